@@ -1,0 +1,306 @@
+"""Pins of the CPU oracle's GKB driver, projected solve and noise convention
+against library routines, brute force, closed forms and invariants."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse.linalg import lsqr
+
+import oracle
+from oracle import dense
+from paper_2606_31153_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_pair(n=6, views=7, bins=None, seed=0):
+    g = synth.par2d(n, views, bins)
+    A, B = dense.dense_A(g), dense.dense_B(g)
+    r = np.random.default_rng(seed)
+    x = r.random(n * n)
+    b = A @ x + 0.01 * r.standard_normal(A.shape[0])
+    return g, A, B, b
+
+
+def krylov_solution(M, rhs, k):
+    """Brute force: min ||M y - rhs|| over K_k(M^T M, M^T rhs)."""
+    v = M.T @ rhs
+    cols = [v]
+    for _ in range(k - 1):
+        v = M.T @ (M @ v)
+        cols.append(v)
+    Qk, _ = np.linalg.qr(np.array(cols).T)
+    z, *_ = np.linalg.lstsq(M @ Qk, rhs, rcond=None)
+    return Qk @ z
+
+
+# ---- G3: AB-/BA-GKB are LSQR on the composite operator (scipy LSQR does not
+# reorthogonalise, so it tracks the exact Krylov iterates only while its
+# bases stay orthogonal: small k)
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+@pytest.mark.parametrize("k", [1, 3, 5, 6])
+def test_g3_equals_lsqr_on_composite(mode, k):
+    g, A, B, b = tiny_pair()
+    op = oracle.Operator(A=A, B=B)
+    res = oracle.gkb(op, mode, b, k)
+    if mode == oracle.MODE_AB:
+        y = lsqr(A @ B, b, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+        x_ref = B @ y
+    else:
+        x_ref = lsqr(B @ A, B @ b, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+    assert res.k_stop == k
+    assert np.linalg.norm(res.x.reshape(-1) - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+# ---- G4: brute-force Krylov subspace solution
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_g4_krylov_brute_force(mode, k):
+    g, A, B, b = tiny_pair(seed=1)
+    op = oracle.Operator(A=A, B=B)
+    res = oracle.gkb(op, mode, b, k)
+    if mode == oracle.MODE_AB:
+        x_ref = B @ krylov_solution(A @ B, b, k)
+    else:
+        x_ref = krylov_solution(B @ A, B @ b, k)
+    assert np.linalg.norm(res.x.reshape(-1) - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+# ---- G5: at k = rank the iteration reaches the least-squares solution
+def test_g5_full_rank_reaches_lstsq():
+    g = synth.par2d(3, 12, 5)
+    A, B = dense.dense_A(g), dense.dense_B(g)
+    r = np.random.default_rng(2)
+    b = r.standard_normal(A.shape[0])
+    op = oracle.Operator(A=A, B=B)
+    M = B @ A
+    assert np.linalg.matrix_rank(M) == 9
+    res = oracle.gkb(op, oracle.MODE_BA, b, 9)
+    x_ref = np.linalg.lstsq(M, B @ b, rcond=None)[0]
+    assert np.linalg.norm(res.x.reshape(-1) - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+
+
+# ---- G6: the matched algorithm is LSQR on A
+@pytest.mark.parametrize("k", [1, 4, 8])
+def test_g6_matched_is_lsqr(k):
+    g, A, B, b = tiny_pair(seed=3)
+    op = oracle.Operator(A=A, B=B)
+    res = oracle.gkb(op, oracle.MODE_GKB, b, k)
+    x_ref = lsqr(A, b, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+    assert np.linalg.norm(res.x.reshape(-1) - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+def test_g6_matched_on_projector_geometry():
+    # the matched path on the geometry operator equals the matched path on its dense matrix
+    g = synth.par2d(8, 6, 13)
+    op_g = oracle.Operator(g)
+    op_d = oracle.Operator(A=dense.dense_A(g), B=dense.dense_B(g))
+    b = np.random.default_rng(4).random(g.m)
+    r1 = oracle.gkb(op_g, oracle.MODE_BA, b, 5)
+    r2 = oracle.gkb(op_d, oracle.MODE_BA, b, 5)
+    assert np.allclose(r1.x.reshape(-1), r2.x.reshape(-1), rtol=1e-10, atol=1e-12)
+
+
+# ---- G7: Tikhonov on the projected problem
+@pytest.mark.parametrize("lam_rel", [1e-3, 1e-1, 1.0])
+def test_g7_tikhonov_normal_equations_and_damped_lsqr(lam_rel):
+    g, A, B, b = tiny_pair(seed=5)
+    op = oracle.Operator(A=A, B=B)
+    k = 5
+    r0 = oracle.gkb(op, oracle.MODE_BA, b, k)
+    lam = lam_rel * r0.alpha1
+    res = oracle.gkb(op, oracle.MODE_BA, b, k, lam=lam)
+    C = np.zeros((k + 1, k))
+    for i in range(k):
+        C[i, i] = res.alpha[i]
+        C[i + 1, i] = res.t[i + 1]
+    rhs = np.zeros(k + 1)
+    rhs[0] = res.t1
+    u_ref = np.linalg.solve(C.T @ C + lam ** 2 * np.eye(k), C.T @ rhs)
+    assert np.allclose(res.u, u_ref, rtol=1e-10, atol=1e-12 * np.abs(u_ref).max())
+    x_ref = lsqr(B @ A, B @ b, damp=lam, atol=0, btol=0, conlim=0, iter_lim=k)[0]
+    assert np.linalg.norm(res.x.reshape(-1) - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+# ---- G1/G2: decomposition and orthogonality invariants
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+def test_g1_g2_invariants(mode):
+    g = synth.par2d(16, 20)
+    op = oracle.Operator(g)
+    xt = synth.ellipse_phantom(16, 7)
+    b = op.A(xt).reshape(-1)
+    k = 12
+    res = oracle.gkb(op, mode, b, k, want_bases=True)
+    Q = res.Q[: k + 1].T
+    S = res.S[: k + 1].T
+    Mq = np.zeros((S.shape[0], k))
+    for i in range(k):
+        if mode == oracle.MODE_AB:
+            Mq[:, i] = op.A(op.B(Q[:, i])).reshape(-1)
+        else:
+            Mq[:, i] = op.B(op.A(Q[:, i])).reshape(-1)
+    C = np.zeros((k + 1, k))
+    for i in range(k):
+        C[i, i] = res.alpha[i]
+        C[i + 1, i] = res.t[i + 1]
+    normM = np.linalg.norm(C, 2)
+    eps = np.finfo(float).eps
+    assert np.linalg.norm(Mq - S @ C) <= 100 * eps * normM * math.sqrt(k)
+    # M^T S_{k+1} = Q_{k+1} [C_k^T ; alpha_{k+1} e_{k+1}^T]^T (upper bidiagonal)
+    Mts = np.zeros((Q.shape[0], k + 1))
+    for i in range(k + 1):
+        if mode == oracle.MODE_AB:
+            Mts[:, i] = op.Bt(op.At(S[:, i])).reshape(-1)
+        else:
+            Mts[:, i] = op.At(op.Bt(S[:, i])).reshape(-1)
+    U = np.zeros((k + 1, k + 1))
+    for i in range(k + 1):
+        U[i, i] = res.alpha[i]
+        if i >= 1:
+            U[i - 1, i] = res.t[i]
+    # alpha_{k+1}, q_{k+1} are not formed at the last iteration: check the first k columns
+    assert np.linalg.norm(Mts[:, :k] - Q[:, :k] @ U[:k, :k]) <= 1e3 * eps * normM * math.sqrt(k)
+    assert np.max(np.abs(Q[:, :k].T @ Q[:, :k] - np.eye(k))) <= 10 * k * eps
+
+
+# ---- G8: projected residual non-increasing
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+def test_g8_projected_residual_monotone(mode):
+    g = synth.par2d(24, 30)
+    op = oracle.Operator(g)
+    b = op.A(synth.ellipse_phantom(24, 8)).reshape(-1)
+    b, en = synth.add_noise(b, synth.noise_direction(b.size, 8), 0.02)
+    res = oracle.gkb(op, mode, b, 20)
+    assert np.all(np.diff(res.pres) <= 1e-12 * res.pres[0])
+    if mode == oracle.MODE_AB:
+        assert np.all(np.diff(res.rho) <= 1e-8 * res.rho[0])
+
+
+# ---- G9: scale invariance of the iterates for lambda = 0
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+def test_g9_scale_invariance(mode):
+    g, A, B, b = tiny_pair(seed=9)
+    x1 = oracle.gkb(oracle.Operator(A=A, B=B), mode, b, 6).x
+    x2 = oracle.gkb(oracle.Operator(A=A, B=3.7 * B), mode, b, 6).x
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x1) * 100
+
+
+# ---- G10: discrepancy principle monotone in tau
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+def test_g10_dp_monotone_in_tau(mode):
+    g = synth.par2d(32, 40)
+    op = oracle.Operator(g)
+    b_true = op.A(synth.ellipse_phantom(32, 10)).reshape(-1)
+    b, en = synth.add_noise(b_true, synth.noise_direction(b_true.size, 10), 0.02)
+    ks = []
+    for tau in (1.5, 1.2, 1.0):
+        r = oracle.gkb(op, mode, b, 60, use_dp=True, tau=tau, noise_norm=en)
+        assert r.reason in (oracle.STOP_DP, oracle.STOP_DP_NOT_REACHED)
+        ks.append(r.k_stop)
+        if r.reason == oracle.STOP_DP:
+            assert r.residual <= tau * en
+            assert np.all(r.rho[:-1] > tau * en)
+    assert ks[0] <= ks[1] <= ks[2]
+
+
+def test_dp_residual_is_literal():
+    g = synth.par2d(16, 20)
+    op = oracle.Operator(g)
+    b = op.A(synth.ellipse_phantom(16, 12)).reshape(-1)
+    b, en = synth.add_noise(b, synth.noise_direction(b.size, 12), 0.05)
+    for mode in (oracle.MODE_AB, oracle.MODE_BA):
+        r = oracle.gkb(op, mode, b, 8, use_dp=True, tau=1.0, noise_norm=en)
+        assert r.residual == pytest.approx(np.linalg.norm(op.A(r.x).reshape(-1) - b), rel=1e-12)
+
+
+# ---- G11: breakdown on an invariant subspace
+def test_g11_breakdown():
+    d = np.array([2.0, 3.0, 5.0, 7.0])
+    A = np.diag(d)
+    B = np.eye(4)
+    b = np.array([1.0, 0.0, 0.0, 0.0])
+    res = oracle.gkb(oracle.Operator(A=A, B=B), oracle.MODE_BA, b, 5)
+    assert res.k_stop == 1 and res.reason == oracle.STOP_BREAKDOWN
+    assert res.t[1] == 0.0
+    assert np.allclose(res.x, [0.5, 0, 0, 0], atol=1e-15)
+
+
+def test_zero_rhs_breakdown():
+    g, A, B, b = tiny_pair()
+    res = oracle.gkb(oracle.Operator(A=A, B=B), oracle.MODE_BA, np.zeros_like(b), 5)
+    assert res.k_stop == 0 and res.reason == oracle.STOP_BREAKDOWN
+    assert not res.x.any()
+
+
+def test_invalid_arguments():
+    g, A, B, b = tiny_pair()
+    with pytest.raises(ValueError):
+        oracle.gkb(oracle.Operator(A=A, B=B), oracle.MODE_BA, b, 0)
+    with pytest.raises(ValueError):
+        oracle.gkb(oracle.Operator(A=A, B=B), oracle.MODE_BA, b, 3, use_dp=True, tau=0.0, noise_norm=1.0)
+
+
+# ---- S1/S2: projected solve against LAPACK and the 1x1 closed form
+@pytest.mark.parametrize("k", [1, 2, 5, 17, 40])
+def test_s1_small_svd(k):
+    r = np.random.default_rng(k)
+    alpha = r.random(k + 1) + 0.1
+    t = r.random(k + 2) + 0.1
+    alpha[k // 2] *= 1e-4  # make it ill-conditioned
+    u, pr, sig = oracle.proj_solve(alpha, t, k)
+    C = np.zeros((k + 1, k))
+    for i in range(k):
+        C[i, i] = alpha[i]
+        C[i + 1, i] = t[i + 1]
+    rhs = np.zeros(k + 1)
+    rhs[0] = t[0]
+    s_ref = np.linalg.svd(C, compute_uv=False)
+    assert np.allclose(np.sort(sig)[::-1], s_ref, rtol=1e-13, atol=1e-13 * s_ref[0])
+    u_ref = np.linalg.lstsq(C, rhs, rcond=None)[0]
+    assert np.allclose(u, u_ref, rtol=1e-10, atol=1e-12 * np.abs(u_ref).max())
+    assert pr == pytest.approx(np.linalg.norm(C @ u_ref - rhs), rel=1e-9, abs=1e-14)
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3, 2.0])
+def test_s2_k1_closed_form(lam):
+    a1, t1, t2 = 1.7, 2.3, 0.9
+    u, pr, sig = oracle.proj_solve([a1, 0.0], [t1, t2, 0.0], 1, lam)
+    assert sig[0] == pytest.approx(math.hypot(a1, t2), rel=1e-15)
+    assert u[0] == pytest.approx(t1 * a1 / (a1 * a1 + t2 * t2 + lam * lam), rel=1e-14)
+
+
+def test_jacobi_svd_reconstructs():
+    M = np.random.default_rng(3).standard_normal((9, 6))
+    U, s, V = oracle.jacobi_svd(M)
+    assert np.allclose(U @ np.diag(s) @ V.T, M, atol=1e-13)
+    assert np.allclose(V.T @ V, np.eye(6), atol=1e-14)
+
+
+# ---- N1: noise convention pinned by the SNR values the paper prints
+def read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def test_n1_snr_matches_paper():
+    for nu_pct, snr_paper in read_golden("paper_noise_snr.txt"):
+        nu = float(nu_pct) / 100.0
+        assert round(synth.snr_db(nu)) == int(snr_paper)
+        assert abs(synth.snr_db(nu) - float(snr_paper)) < 0.2
+    b = np.random.default_rng(0).random(1000)
+    bn, en = synth.add_noise(b, synth.noise_direction(1000, 3), 0.07)
+    assert en == pytest.approx(0.07 * np.linalg.norm(b), rel=1e-14)
+    assert np.linalg.norm(bn - b) == pytest.approx(en, rel=1e-12)
+
+
+def test_paper_problem_shapes():
+    # m = views x bins and n = N^2 for the three examples; bins = N (N_det = N)
+    for n, views, m_paper, n_paper in (map(int, r) for r in read_golden("paper_problem_shapes.txt")):
+        g = synth.par2d(n, views, n)
+        assert (g.m, g.n) == (m_paper, n_paper)

@@ -1,0 +1,244 @@
+"""Pins of the CPU oracle's projectors against facts fixed by the mathematics
+(closed forms, exact special cases, brute force, a second implementation).
+
+Every test runs on the CPU (no GPU marker)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_2606_31153_amd import synth
+
+
+def op_matrix(apply, n_in, n_out):
+    """Dense matrix of a linear map by applying it to unit vectors."""
+    M = np.zeros((n_out, n_in))
+    for c in range(n_in):
+        e = np.zeros(n_in)
+        e[c] = 1.0
+        M[:, c] = np.asarray(apply(e)).reshape(-1)
+    return M
+
+
+def mats(geom):
+    op = oracle.Operator(geom)
+    A = op_matrix(op.A, geom.n, geom.m)
+    At = op_matrix(op.At, geom.m, geom.n)
+    B = op_matrix(op.B, geom.m, geom.n)
+    Bt = op_matrix(op.Bt, geom.n, geom.m)
+    return A, At, B, Bt
+
+
+TINY_PAR = synth.par2d(8, 5, 13, angles=np.deg2rad([0.0, 30.0, 45.0, 90.0, 137.0]))
+TINY_FAN = synth.fan2d(8, 7, 17, src_dist=20.0)
+
+
+# ---- P1: B = A^T exactly when every view is axis aligned; the mismatch elsewhere
+@pytest.mark.parametrize("deg", [0.0, 90.0])
+def test_p1_axis_aligned_view_is_matched(deg):
+    g = synth.par2d(8, 1, 13, angles=[math.radians(deg)])
+    A, At, B, Bt = mats(g)
+    # cos(pi/2) is 6e-17 in floating point, hence the rounding-level tolerance
+    assert np.max(np.abs(B - A.T)) <= 1e-14
+
+
+def test_p1_mismatch_at_45_degrees():
+    # At 45 deg the transpose has a hat of half-width 1/sqrt(2) scaled by sqrt(2);
+    # summed over unit-spaced bins it swings between 2*sqrt(2)*(1-1/sqrt(2)) and sqrt(2)
+    # with the sub-bin position of the pixel, while B applied to ones is exactly 1.
+    g = synth.par2d(16, 1, 40, angles=[math.pi / 4])
+    op = oracle.Operator(g)
+    at1 = op.At(np.ones(g.m))
+    b1 = op.B(np.ones(g.m))
+    lo = 2 * math.sqrt(2) * (1 - 1 / math.sqrt(2))
+    hi = math.sqrt(2)
+    assert np.allclose(b1, 1.0, atol=1e-15)
+    assert at1.min() >= lo - 1e-12 and at1.max() <= hi + 1e-12
+    assert at1.min() < lo + 0.05 and at1.max() > hi - 0.05
+    A, At, B, Bt = mats(TINY_PAR)
+    assert np.linalg.norm(B - A.T) / np.linalg.norm(A) > 0.05
+
+
+# ---- P2/P3: Joseph is exact for linear images on rays that cross every dominant line inside
+@pytest.mark.parametrize("deg", [0.0, 10.0, 33.0, 57.0, 80.0, 100.0, 160.0])
+def test_p2_p3_linear_image_line_integral(deg):
+    n = 32
+    th = math.radians(deg)
+    g = synth.par2d(n, 1, 45, angles=[th])
+    op = oracle.Operator(g)
+    xs = np.arange(n) - (n - 1) / 2.0
+    X, Y = np.meshgrid(xs, xs)
+    al, be, ga = 0.3, -0.7, 2.0
+    for img, lin in ((np.full((n, n), 1.5), (0.0, 0.0, 1.5)), (al * X + be * Y + ga, (al, be, ga))):
+        y = op.A(img).reshape(-1)
+        c, s = math.cos(th), math.sin(th)
+        rowdom = abs(c) >= abs(s)
+        ddom = abs(c) if rowdom else abs(s)
+        checked = 0
+        for k in range(g.n_det_u):
+            sk = k - (g.n_det_u - 1) / 2.0
+            # crossings along the stepping axis
+            if rowdom:
+                cross = (sk - xs * s) / c  # x at each row y_j
+            else:
+                cross = (sk - xs * c) / s  # y at each column x_i
+            if cross.min() < xs[0] or cross.max() > xs[-1]:
+                continue
+            # segment between the planes at -n/2 and n/2 of the stepping axis: length n/|d_dom|,
+            # midpoint is the ray point at stepping coordinate 0
+            mid = (sk / c, 0.0) if rowdom else (0.0, sk / s)
+            fmid = lin[0] * mid[0] + lin[1] * mid[1] + lin[2]
+            assert y[k] == pytest.approx(n / ddom * fmid, rel=1e-12, abs=1e-11)
+            checked += 1
+        assert checked >= 5
+
+
+# ---- P4/P5: B of a constant and of a linear-in-bin sinogram
+@pytest.mark.parametrize("geom", [synth.par2d(24, 17), synth.fan2d(24, 19, 40)])
+def test_p4_constant_sinogram(geom):
+    op = oracle.Operator(geom)
+    x = op.B(np.full(geom.m, 2.5))
+    assert np.allclose(x, 2.5 * geom.n_views, rtol=1e-14)
+
+
+def test_p5_linear_sinogram_par():
+    g = synth.par2d(24, 17)
+    op = oracle.Operator(g)
+    ang = g.view_angles()
+    sk = (np.arange(g.n_det_u) - (g.n_det_u - 1) / 2.0) * g.det_pitch_u
+    y = np.tile(sk, (g.n_views, 1))
+    x = op.B(y)
+    xs = np.arange(24) - 11.5
+    X, Y = np.meshgrid(xs, xs)
+    expect = X * np.cos(ang).sum() + Y * np.sin(ang).sum()
+    assert np.allclose(x, expect, atol=1e-10)
+
+
+def test_p5_linear_sinogram_fan():
+    # y(v, k) = gamma_k  ->  (B y)(p) = sum_v gamma_v(p), the fan angle of p in view v
+    g = synth.fan2d(24, 19, 40)
+    op = oracle.Operator(g)
+    gam = (np.arange(g.n_det_u) - (g.n_det_u - 1) / 2.0) * g.det_pitch_u
+    x = op.B(np.tile(gam, (g.n_views, 1)))
+    xs = np.arange(24) - 11.5
+    X, Y = np.meshgrid(xs, xs)
+    expect = np.zeros_like(X)
+    for b in g.view_angles():
+        sx, sy = g.src_dist * math.cos(b), g.src_dist * math.sin(b)
+        # fan angle: signed angle from the central ray (towards the origin) to p - S
+        ang_c = math.atan2(-sy, -sx)
+        ang_p = np.arctan2(Y - sy, X - sx)
+        expect += np.angle(np.exp(1j * (ang_p - ang_c)))
+    assert np.allclose(x, expect, atol=1e-10)
+
+
+# ---- P6: analytic line integrals of ellipses (geometry conventions)
+def ellipse_sinogram(params, n, lines):
+    """Exact line integrals of a sum of ellipses (pixel units) along lines
+    {p : p.(cos th, sin th) = s} (Kak & Slaney's analytic projection)."""
+    th, s = lines
+    out = np.zeros_like(s)
+    h = n / 2.0
+    for cx, cy, a, b, phi, rho in params:
+        A_, B_ = a * h, b * h
+        t = s - (cx * h * np.cos(th) + cy * h * np.sin(th))
+        tp = th - phi
+        a2 = A_ ** 2 * np.cos(tp) ** 2 + B_ ** 2 * np.sin(tp) ** 2
+        out += np.where(t ** 2 <= a2, 2 * rho * A_ * B_ / a2 * np.sqrt(np.maximum(a2 - t ** 2, 0.0)), 0.0)
+    return out
+
+
+def geom_lines(geom):
+    ang = geom.view_angles()
+    k = np.arange(geom.n_det_u) - (geom.n_det_u - 1) / 2.0
+    if geom.kind == synth.KIND_PAR2D:
+        TH, KK = np.meshgrid(ang, k, indexing="ij")
+        return TH, KK * geom.det_pitch_u
+    B_, KK = np.meshgrid(ang, k, indexing="ij")
+    gam = KK * geom.det_pitch_u
+    dx, dy = -np.cos(B_ + gam), -np.sin(B_ + gam)
+    nx_, ny_ = -dy, dx  # unit normal of the ray
+    sx, sy = geom.src_dist * np.cos(B_), geom.src_dist * np.sin(B_)
+    return np.arctan2(ny_, nx_), sx * nx_ + sy * ny_
+
+
+@pytest.mark.parametrize("kind", ["par", "fan"])
+def test_p6_ellipse_line_integrals(kind):
+    params = synth.ellipse_params(11)
+    errs = []
+    for n in (64, 128):
+        g = synth.par2d(n, 36) if kind == "par" else synth.fan2d(n, 40, int(1.5 * n))
+        op = oracle.Operator(g)
+        sino = op.A(synth.rasterize_ellipses(params, n))
+        ref = ellipse_sinogram(params, n, geom_lines(g))
+        errs.append(np.linalg.norm(sino - ref) / np.linalg.norm(ref))
+    assert errs[0] < 0.03 and errs[1] < errs[0]
+    # a mirrored geometry would be far off: the test is sensitive to orientation
+    g = synth.par2d(64, 36) if kind == "par" else synth.fan2d(64, 40, 96)
+    mirrored = ellipse_sinogram(params[:, [1, 0, 2, 3, 4, 5]], 64, geom_lines(g))
+    sino = oracle.Operator(g).A(synth.rasterize_ellipses(params, 64))
+    assert np.linalg.norm(sino - mirrored) / np.linalg.norm(mirrored) > 0.2
+
+
+# ---- P7: scatter adjoints are exact transposes; P9: second implementation agrees
+@pytest.mark.parametrize("geom", [TINY_PAR, TINY_FAN, synth.par2d(6, 4, 11, ny=5)])
+def test_p7_p9_dense(geom):
+    A, At, B, Bt = mats(geom)
+    assert np.array_equal(At, A.T)
+    assert np.array_equal(Bt, B.T)
+    Ad, Bd = dense.dense_A(geom), dense.dense_B(geom)
+    assert np.max(np.abs(A - Ad)) <= 1e-14 * np.max(np.abs(A))
+    assert np.max(np.abs(B - Bd)) <= 1e-14 * np.max(np.abs(B))
+    assert np.linalg.norm(B - A.T) > 0
+
+
+def test_p7_fan_matrix_fill():
+    # every pixel of the fan geometry is seen by some ray of every view
+    A, At, B, Bt = mats(TINY_FAN)
+    per_view = A.reshape(TINY_FAN.n_views, TINY_FAN.n_det_u, -1).sum(axis=1)
+    assert (per_view > 0).all()
+
+
+# ---- P8: dot-product adjoint test at moderate size
+@pytest.mark.parametrize("geom", [synth.par2d(64, 90, 91), synth.fan2d(64, 60, 128)])
+def test_p8_adjoint_dot(geom):
+    op = oracle.Operator(geom)
+    r = np.random.default_rng(5)
+    x = r.standard_normal(geom.n)
+    y = r.standard_normal(geom.m)
+    for F, Ft in ((op.A, op.At), (op.Bt, op.B)):
+        lhs = float(np.dot(F(x).reshape(-1), y))
+        rhs = float(np.dot(x, Ft(y).reshape(-1)))
+        assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(F(x)) * np.linalg.norm(y)
+
+
+# ---- cone beam: scatter adjoints, second implementation
+TINY_CONE = synth.cone3d(4, 3, 7, 5)
+
+
+def test_cone_dense_and_adjoint():
+    g = TINY_CONE
+    A, At, B, Bt = mats(g)
+    assert np.array_equal(At, A.T)
+    assert np.array_equal(Bt, B.T)
+    Ad, Bd = dense.dense_A(g), dense.dense_B(g)
+    assert np.max(np.abs(A - Ad)) <= 1e-13 * np.max(np.abs(A))
+    assert np.max(np.abs(B - Bd)) <= 1e-13 * np.max(np.abs(B))
+
+
+def test_cone_constant_volume_central_ray():
+    # the central ray of every view runs along the x-y plane through the centre;
+    # for a constant volume its Joseph sum is the number of crossed planes / |d_dom|
+    n = 8
+    g = synth.cone3d(n, 4, 9, 9)
+    op = oracle.Operator(g)
+    y = op.A(np.ones((n, n, n))).reshape(g.n_views, g.n_det_v, g.n_det_u)
+    for v, b in enumerate(g.view_angles()):
+        d = np.array([-math.cos(b), -math.sin(b)])
+        ddom = np.max(np.abs(d))
+        # the central ray crosses all n planes inside the volume only if the
+        # in-plane offset stays within the voxel centres; views at multiples of 90 deg do
+        if abs(ddom - 1.0) < 1e-12:
+            assert y[v, 4, 4] == pytest.approx(n / ddom, rel=1e-12)
