@@ -1,0 +1,208 @@
+"""Benchmark: AB-/BA-GKB on the 512x512 fan-beam workload (720 views over
+360 degrees, 1024 equiangular bins, source at twice the image width), FP32
+projectors and Krylov vectors with FP64 reductions and projected solve,
+150 iterations per solve.
+
+One step = one BA-GKB solve of 150 iterations followed by one AB-GKB solve of
+150 iterations on the same synthetic sinogram (random-ellipse phantom,
+0.5 % Gaussian noise), with the discrepancy test evaluated every iteration.
+value = GKB iterations per second over the timed steps.
+
+Also reported: per-projector device time (HIP events on the library's
+stream), the dominant kernel's roofline position, the projector
+throughput in GB/s against the HBM peak, and the CPU oracle timed on a
+bounded sample of the same workload.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+K_ITERS = 150
+HBM_PEAK_GBS = 8000.0
+# FP32 vector FMA rate without packed math: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# flops per algorithmic unit: ray-driven kernels 2 FMA per dominant-line
+# crossing; pixel-driven kernels 3 FMA per (pixel, view) pair
+FLOPS_PER_UNIT = {"fwd": 4.0, "back_adj": 4.0, "back": 6.0, "fwd_adj": 6.0}
+OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
+
+
+def joseph_crossings(geom) -> int:
+    """Number of (ray, dominant line) pairs with a tap inside the image: the
+    terms of Joseph's sum for this geometry (fan or parallel, 2D)."""
+    from paper_2606_31153_amd import synth
+    nx, ny, nu = geom.nx, geom.ny, geom.n_det_u
+    off = (nu - 1) / 2.0
+    k = np.arange(nu) - off
+    total = 0
+    for ang in geom.view_angles():
+        if geom.kind == synth.KIND_FAN2D:
+            g = k * geom.det_pitch_u
+            dx, dy = -np.cos(ang + g), -np.sin(ang + g)
+            sx = np.full(nu, geom.src_dist * math.cos(ang))
+            sy = np.full(nu, geom.src_dist * math.sin(ang))
+        else:
+            dx = np.full(nu, -math.sin(ang))
+            dy = np.full(nu, math.cos(ang))
+            s = k * geom.det_pitch_u
+            sx, sy = s * math.cos(ang), s * math.sin(ang)
+        rowdom = np.abs(dy) >= np.abs(dx)
+        # crossings with rows (row-dominant rays) or columns
+        lines_r = np.arange(ny) - (ny - 1) / 2.0
+        lines_c = np.arange(nx) - (nx - 1) / 2.0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xr = (sx[:, None] + (lines_r[None, :] - sy[:, None]) * (dx / dy)[:, None]) + (nx - 1) / 2.0
+            yc = (sy[:, None] + (lines_c[None, :] - sx[:, None]) * (dy / dx)[:, None]) + (ny - 1) / 2.0
+        inr = ((xr > -1.0) & (xr < nx)).sum(axis=1)
+        inc = ((yc > -1.0) & (yc < ny)).sum(axis=1)
+        total += int(np.where(rowdom, inr, inc).sum())
+    return total
+
+
+def make_problem(geom, seed: int, nu: float):
+    """Phantom and noisy sinogram on the GPU (forward projector of the
+    library), noise scaled to nu*||b_true||."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    from paper_2606_31153_amd import synth
+    dev = torch.device("cuda:0")
+    ctx = gk.Context(0)
+    x_true = torch.tensor(synth.ellipse_phantom(geom.nx, seed), dtype=torch.float32, device=dev).reshape(-1)
+    b_true = torch.empty(geom.m, dtype=torch.float32, device=dev)
+    gk.gkb_forward(ctx, geom, x_true, b_true)
+    torch.cuda.synchronize()
+    bt = b_true.double().cpu().numpy()
+    b, enorm = synth.add_noise(bt, synth.noise_direction(geom.m, seed), nu)
+    ctx.close()
+    return x_true, torch.tensor(b, dtype=torch.float32, device=dev), enorm
+
+
+def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int):
+    import oracle
+    op = oracle.Operator(geom)
+    t0 = time.perf_counter()
+    res = oracle.gkb(op, oracle.MODE_BA, b_host, iters, use_dp=True, tau=1.0, noise_norm=enorm)
+    dt = time.perf_counter() - t0
+    return {"value": res.k_stop / dt, "unit": "GKB iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "FP64 CPU oracle, BA-GKB, %d iterations of the same fan-beam 512^2/720/1024 problem "
+                      "(residual evaluated literally), %.1f s" % (res.k_stop, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=K_ITERS)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2606_31153_amd as gk
+    from paper_2606_31153_amd import synth
+
+    geom = synth.workload_fan512()
+    dev = torch.device("cuda:0")
+    print("bench: building problem", file=sys.stderr, flush=True)
+    x_true, b, enorm = make_problem(geom, 2000, 0.005)
+    x = torch.zeros(geom.n, dtype=torch.float32, device=dev)
+    ctx = gk.Context(0)
+    kw = dict(use_dp=False, tau=1.0, noise_norm=enorm)
+
+    def step():
+        r1 = gk.gkb_ba_solve(ctx, geom, b, x, args.iters, **kw)
+        r2 = gk.gkb_ab_solve(ctx, geom, b, x, args.iters, **kw)
+        return r1, r2
+
+    for i in range(args.warmup):
+        step()
+        print("bench: warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.trace_enable(True)
+    ctx.trace_reset()
+    t0 = time.perf_counter()
+    ba_s = ab_s = 0.0
+    for i in range(args.steps):
+        r1, r2 = step()
+        ba_s += r1.seconds
+        ab_s += r2.seconds
+        print("bench: step %d done (BA %.3f s, AB %.3f s)" % (i, r1.seconds, r2.seconds), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.trace_enable(False)
+    kernels = {}
+    for name in ("fwd", "back", "fwd_adj", "back_adj", "reorth", "gram", "small_solve"):
+        cnt, ms = ctx.trace_get(name)
+        if cnt:
+            kernels[name] = {"launches": cnt, "avg_ms": ms / cnt, "total_ms": ms}
+
+    # algorithmic units per launch
+    cross = joseph_crossings(geom)
+    pv = geom.n * geom.n_views
+    units = {"fwd": cross, "back_adj": cross, "back": pv, "fwd_adj": pv}
+    proj = {k: v for k, v in kernels.items() if k in units}
+    dom = max(proj, key=lambda k: proj[k]["total_ms"])
+    t_dom = proj[dom]["avg_ms"] / 1e3
+    ach = units[dom] * FLOPS_PER_UNIT[dom] / t_dom / 1e12
+    gbps = {}
+    for k, v in proj.items():
+        t = v["avg_ms"] / 1e3
+        comp = 4.0 * (geom.n + geom.m) / t / 1e9
+        oper = units[k] * OPERAND_BYTES_PER_UNIT / t / 1e9
+        gbps[k] = {"avg_us": v["avg_ms"] * 1e3, "units": units[k], "compulsory_GBs": comp,
+                   "compulsory_pct_hbm": 100 * comp / HBM_PEAK_GBS, "operand_GBs": oper,
+                   "operand_pct_hbm": 100 * oper / HBM_PEAK_GBS}
+
+    iters = 2 * args.iters * args.steps
+    out = {
+        "metric": "GKB iters/s and projector GB/s (% HBM roofline) at 512^2; s/slice to discrepancy",
+        "value": iters / elapsed,
+        "unit": "GKB iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 vectors/projectors, f64 reductions and projected solve",
+        "data": "synthetic: seeded random-ellipse phantom, 0.5% Gaussian noise",
+        "config": {"workload": "fan-beam 512x512, 720 views over 360 deg, 1024 equiangular bins, D=1024; "
+                               "BA-GKB then AB-GKB, %d iterations each" % args.iters,
+                   "iterations_per_step": 2 * args.iters},
+        "ba_iters_per_s": args.iters * args.steps / ba_s,
+        "ab_iters_per_s": args.iters * args.steps / ab_s,
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": VALU_FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / VALU_FP32_PEAK_TFLOPS, "traffic": None,
+                     "work_per_launch": "%d units x %g flop" % (units[dom], FLOPS_PER_UNIT[dom])},
+        "projector_gbps": gbps,
+        "kernels": kernels,
+    }
+    if not args.no_cpu:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(geom, b.double().cpu().numpy(), enorm, args.cpu_iters)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

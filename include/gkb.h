@@ -1,0 +1,152 @@
+/*
+ * gkb.h -- C ABI of the MI355X (gfx950) implementation of AB-GKB and BA-GKB
+ * for X-ray CT with an unmatched projector pair.
+ *
+ * The problem (Sec. 1, eq. (1)): A x ~= b with A in R^{m x n} a forward
+ * projector and B in R^{n x m} a back projector built from a different
+ * discretisation, B != A^T.  AB-GKB (Sec. 3.2, Alg. "AB-GKB") runs the
+ * Golub-Kahan bidiagonalisation on M = AB from b and returns x = B Q_k u_k;
+ * BA-GKB (Alg. "BA-GKB") runs it on M = BA from B b and returns x = Q_k u_k.
+ * Both need the exact transposes A^T and B^T (Sec. 5, where the projector
+ * library is modified to provide them), so all four operators are exported.
+ *
+ * Discretisation (pixel pitch 1; pixel (i, j) has centre
+ * (i - (nx-1)/2, j - (ny-1)/2) and is stored at x[j*nx + i]; sinograms are
+ * stored y[(v*n_det_v + r)*n_det_u + k]):
+ *   A  -- Joseph's ray-driven projector: along every ray, at each crossing
+ *         of a pixel row (column) along the ray's dominant axis, linear
+ *         interpolation between the two nearest pixel centres of that row
+ *         (column); the sum is multiplied by 1/|d_dom| (d the unit ray
+ *         direction; ties step along rows).  3D: bilinear interpolation in
+ *         the voxel plane crossed.
+ *   B  -- pixel (voxel) driven back projection: every pixel centre is
+ *         projected onto each view's detector and the sinogram interpolated
+ *         linearly (bilinearly on a 2D detector) between the nearest bins.
+ *   A^T, B^T -- the exact transposes of those matrices.
+ * Geometries:
+ *   GKB_PAR2D: view angle th, ray (v,k) = { p : p.(cos th, sin th) = s_k },
+ *              s_k = (k - (n_det_u-1)/2) * det_pitch_u.
+ *   GKB_FAN2D: source S = src_dist*(cos b, sin b); curved equiangular
+ *              detector, bin k at fan angle g_k = (k - (n_det_u-1)/2) *
+ *              det_pitch_u (radians) counter-clockwise from the central ray
+ *              -S/|S|; no distance weighting.
+ *   GKB_CONE3D: source S = src_dist*(cos b, sin b, 0); flat detector
+ *              perpendicular to -S at src_det_dist from the source, u axis
+ *              (-sin b, cos b, 0), v axis z; pitches det_pitch_u/v.
+ * View angles: angles[v] if given, else v*angle_span/n_views.
+ *
+ * Conventions:
+ *  - Every data pointer is a DEVICE pointer owned by the caller, holding
+ *    float (GKB_F32) or double (GKB_F64) elements, contiguous.
+ *  - Projector calls are asynchronous on the context's stream.  Solves block
+ *    until the result is in x and fill *info on the host.
+ *  - Errors are negative gkb_status values; gkb_last_error() gives the text
+ *    (thread-local).  On GKB_EINVAL / GKB_ENONFINITE nothing is written to
+ *    the outputs.
+ *  - A context is not thread-safe: one context per host thread.
+ */
+#ifndef GKB_H
+#define GKB_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gkb_ctx gkb_ctx;
+typedef struct gkb_net gkb_net;
+
+typedef enum {
+  GKB_OK = 0,
+  GKB_EINVAL = -1,        /* invalid argument */
+  GKB_ENOMEM = -2,        /* device allocation failed */
+  GKB_EDEVICE = -3,       /* HIP runtime error */
+  GKB_ENONFINITE = -4,    /* NaN or Inf in the data */
+  GKB_EUNSUPPORTED = -5   /* combination not implemented */
+} gkb_status;
+
+typedef enum {
+  GKB_STOP_NONE = 0,
+  GKB_STOP_DP = 1,              /* discrepancy principle met (eq. DP) */
+  GKB_STOP_KMAX = 2,            /* k_max iterations, DP off */
+  GKB_STOP_BREAKDOWN = 3,       /* t_{k+1} or alpha_{k+1} vanished: invariant subspace, x exact there */
+  GKB_STOP_DP_NOT_REACHED = 4,  /* DP on but not met by k_max; x = x_{k_max} */
+  GKB_STOP_FALLBACK = 5         /* learned preconditioner rejected; plain BA-GKB result returned */
+} gkb_stop_reason;
+
+typedef enum { GKB_PAR2D = 0, GKB_FAN2D = 1, GKB_CONE3D = 2 } gkb_geom_kind;
+typedef enum { GKB_F32 = 0, GKB_F64 = 1 } gkb_dtype;
+
+typedef struct {
+  int kind;                 /* gkb_geom_kind */
+  int nx, ny, nz;           /* image size; nz = 1 in 2D */
+  int n_views;
+  const double *angles;     /* HOST array [n_views] (radians) or NULL */
+  double angle_span;        /* used when angles == NULL */
+  int n_det_u, n_det_v;     /* detector bins; n_det_v = 1 in 2D */
+  double det_pitch_u;       /* PAR2D/CONE3D: length; FAN2D: radians */
+  double det_pitch_v;
+  double src_dist;          /* source to rotation centre (FAN2D, CONE3D) */
+  double src_det_dist;      /* source to detector (CONE3D) */
+} gkb_geometry;
+
+typedef struct {
+  int k_max;                /* >= 1 iterations */
+  double lambda;            /* Tikhonov weight on ||u|| in the projected problem; 0 = the paper's */
+  int use_dp;               /* 1: stop at the first k with ||A x_k - b|| <= tau*noise_norm (eq. DP) */
+  double tau;               /* > 0 when use_dp; the paper uses 1 */
+  double noise_norm;        /* ||e||, the noise norm the discrepancy principle compares against */
+  int reorth;               /* 1 = one-sided reorthogonalisation of q (two classical Gram-Schmidt passes); 0 = none */
+  const gkb_net *precond;   /* BA only: learned sinogram filter F inside B (M = B F A); NULL = plain */
+  double *residual_history; /* optional HOST [k_max]: ||A x_k - b||, k = 1..k_stop */
+  double *alpha_history;    /* optional HOST [k_max+1]: alpha_1.. */
+  double *t_history;        /* optional HOST [k_max+1]: t_1.. */
+} gkb_solve_opts;
+
+typedef struct {
+  int k_stop;               /* iterations whose solution is returned (0 if breakdown at start) */
+  int reason;               /* gkb_stop_reason */
+  double residual;          /* ||A x - b|| at k_stop */
+  double proj_residual;     /* ||C_k u_k - t_1 e_1|| (the Tikhonov rows not included) */
+  double t1, alpha1;        /* t_1 = ||rhs||, alpha_1 */
+  double seconds;           /* wall time of the solve */
+} gkb_solve_info;
+
+/* Creates a context on `device` that launches on `hip_stream` (a hipStream_t;
+ * NULL = a stream the context creates).  The context owns geometry tables,
+ * Krylov bases and scratch; it frees them in gkb_destroy. */
+gkb_status gkb_create(gkb_ctx **ctx, int device, void *hip_stream);
+void gkb_destroy(gkb_ctx *ctx);
+gkb_status gkb_set_stream(gkb_ctx *ctx, void *hip_stream);
+const char *gkb_last_error(void);
+
+/* The four projectors (Sec. 1; transposes as in Sec. 5).  x has n = nx*ny*nz
+ * elements, y has m = n_views*n_det_v*n_det_u. */
+gkb_status gkb_forward(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *x, void *y);          /* y = A x   */
+gkb_status gkb_back(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *y, void *x);             /* x = B y   */
+gkb_status gkb_forward_adjoint(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *y, void *x);  /* x = A^T y */
+gkb_status gkb_back_adjoint(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *x, void *y);     /* y = B^T x */
+
+/* AB-GKB (Alg. "AB-GKB"): GKB on M = AB from b; x = B Q_k u_k.
+ * BA-GKB (Alg. "BA-GKB"): GKB on M = BA from B b; x = Q_k u_k.
+ * Matched GKB (Alg. "GKB"): M = A, M^T = A^T; x = Q_k u_k (equivalent to LSQR).
+ * u_k = argmin ||C_k u - t_1 e_1||^2 + lambda^2 ||u||^2 (eq. proj GKB).
+ * GKB_F32 keeps projectors and Krylov vectors in float and every reduction,
+ * alpha, t, the projected solve and the discrepancy test in double. */
+gkb_status gkb_ab_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                        void *x, gkb_solve_info *info);
+gkb_status gkb_ba_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                        void *x, gkb_solve_info *info);
+gkb_status gkb_gkb_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                         void *x, gkb_solve_info *info);
+
+/* Kernel timing.  While enabled, every launch of the named kernels is
+ * bracketed by HIP events on the context's stream; gkb_trace_get returns the
+ * launch count and summed device milliseconds since the last reset. */
+gkb_status gkb_trace_enable(gkb_ctx *ctx, int on);
+gkb_status gkb_trace_reset(gkb_ctx *ctx);
+gkb_status gkb_trace_get(gkb_ctx *ctx, const char *kernel, int *count, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKB_H */

@@ -1,0 +1,254 @@
+"""MI355X-native AB-/BA-GKB for X-ray CT with an unmatched back projector.
+
+A thin ctypes binding over ``libgkb.so`` (HIP kernels for gfx950 behind the C
+ABI of ``include/gkb.h``).  The binding only marshals arguments: tensors are
+allocated by PyTorch on the GPU and their device pointers are handed to the
+library together with the current HIP stream; every step of the projectors
+and of the GKB iteration runs in the library's kernels.
+
+There is no CPU fallback: if ``libgkb.so`` has not been built, importing the
+binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import synth  # noqa: F401  (seeded input generators)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgkb.so")
+
+GKB_OK, GKB_EINVAL, GKB_ENOMEM, GKB_EDEVICE, GKB_ENONFINITE, GKB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STOP_NONE, STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED, STOP_FALLBACK = 0, 1, 2, 3, 4, 5
+GKB_PAR2D, GKB_FAN2D, GKB_CONE3D = 0, 1, 2
+GKB_F32, GKB_F64 = 0, 1
+
+STATUS_NAMES = {0: "GKB_OK", -1: "GKB_EINVAL", -2: "GKB_ENOMEM", -3: "GKB_EDEVICE", -4: "GKB_ENONFINITE",
+                -5: "GKB_EUNSUPPORTED"}
+EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gkb_forward", "gkb_back",
+            "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve",
+            "gkb_trace_enable", "gkb_trace_reset", "gkb_trace_get")
+
+
+class GkbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("n_views", ctypes.c_int), ("angles", ctypes.POINTER(ctypes.c_double)),
+                ("angle_span", ctypes.c_double), ("n_det_u", ctypes.c_int), ("n_det_v", ctypes.c_int),
+                ("det_pitch_u", ctypes.c_double), ("det_pitch_v", ctypes.c_double),
+                ("src_dist", ctypes.c_double), ("src_det_dist", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("k_max", ctypes.c_int), ("lam", ctypes.c_double), ("use_dp", ctypes.c_int),
+                ("tau", ctypes.c_double), ("noise_norm", ctypes.c_double), ("reorth", ctypes.c_int),
+                ("precond", ctypes.c_void_p), ("residual_history", ctypes.POINTER(ctypes.c_double)),
+                ("alpha_history", ctypes.POINTER(ctypes.c_double)),
+                ("t_history", ctypes.POINTER(ctypes.c_double))]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("k_stop", ctypes.c_int), ("reason", ctypes.c_int), ("residual", ctypes.c_double),
+                ("proj_residual", ctypes.c_double), ("t1", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgkb.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_2606_31153_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, cp = ctypes.c_void_p, ctypes.c_int
+        G = ctypes.POINTER(Geometry)
+        L.gkb_create.argtypes = [ctypes.POINTER(vp), cp, vp]
+        L.gkb_destroy.argtypes = [vp]
+        L.gkb_destroy.restype = None
+        L.gkb_set_stream.argtypes = [vp, vp]
+        L.gkb_last_error.restype = ctypes.c_char_p
+        for name in ("gkb_forward", "gkb_back", "gkb_forward_adjoint", "gkb_back_adjoint"):
+            getattr(L, name).argtypes = [vp, G, cp, vp, vp]
+        for name in ("gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve"):
+            getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
+        L.gkb_trace_enable.argtypes = [vp, cp]
+        L.gkb_trace_reset.argtypes = [vp]
+        L.gkb_trace_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(cp), ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != GKB_OK:
+        raise GkbError(status, lib().gkb_last_error().decode())
+
+
+def make_geometry(geom) -> tuple:
+    """C geometry struct from ``synth.Geometry``; returns (struct, keep-alive)."""
+    keep = []
+    g = Geometry()
+    g.kind, g.nx, g.ny, g.nz = geom.kind, geom.nx, geom.ny, geom.nz
+    g.n_views = geom.n_views
+    if geom.angles is not None:
+        a = np.ascontiguousarray(geom.angles, dtype=np.float64)
+        keep.append(a)
+        g.angles = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    g.angle_span = geom.angle_span
+    g.n_det_u, g.n_det_v = geom.n_det_u, geom.n_det_v
+    g.det_pitch_u, g.det_pitch_v = geom.det_pitch_u, geom.det_pitch_v
+    g.src_dist, g.src_det_dist = geom.src_dist, geom.src_det_dist
+    return g, keep
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return GKB_F32
+    if t.dtype == torch.float64:
+        return GKB_F64
+    raise TypeError("tensors must be float32 or float64")
+
+
+def _dev_ptr(t, numel: int):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if t.numel() != numel:
+        raise ValueError("tensor has %d elements, expected %d" % (t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A gkb_ctx bound to one GPU; launches on PyTorch's current stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        import torch
+        self.device = device
+        if stream is None:
+            with torch.cuda.device(device):
+                stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib().gkb_create(ctypes.byref(h), device, ctypes.c_void_p(stream)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gkb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream: int):
+        _check(lib().gkb_set_stream(self.handle, ctypes.c_void_p(stream)))
+
+    # ---- tracing ----
+    def trace_enable(self, on: bool = True):
+        _check(lib().gkb_trace_enable(self.handle, 1 if on else 0))
+
+    def trace_reset(self):
+        _check(lib().gkb_trace_reset(self.handle))
+
+    def trace_get(self, kernel: str):
+        cnt = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().gkb_trace_get(self.handle, kernel.encode(), ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value
+
+
+def _proj(name: str, ctx: Context, geom, inp, out, n_in: int, n_out: int):
+    g, keep = make_geometry(geom)
+    code = _dtype_code(inp)
+    if out.dtype != inp.dtype:
+        raise TypeError("input and output dtypes differ")
+    _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(inp, n_in), _dev_ptr(out, n_out)))
+    return out
+
+
+def gkb_forward(ctx: Context, geom, x, y):
+    """y = A x (Joseph forward projector)."""
+    return _proj("gkb_forward", ctx, geom, x, y, geom.n, geom.m)
+
+
+def gkb_back(ctx: Context, geom, y, x):
+    """x = B y (pixel-driven back projector)."""
+    return _proj("gkb_back", ctx, geom, y, x, geom.m, geom.n)
+
+
+def gkb_forward_adjoint(ctx: Context, geom, y, x):
+    """x = A^T y (exact transpose of A)."""
+    return _proj("gkb_forward_adjoint", ctx, geom, y, x, geom.m, geom.n)
+
+
+def gkb_back_adjoint(ctx: Context, geom, x, y):
+    """y = B^T x (exact transpose of B)."""
+    return _proj("gkb_back_adjoint", ctx, geom, x, y, geom.n, geom.m)
+
+
+@dataclass
+class SolveResult:
+    k_stop: int
+    reason: int
+    residual: float
+    proj_residual: float
+    t1: float
+    alpha1: float
+    seconds: float
+    rho: np.ndarray
+    alpha: np.ndarray
+    t: np.ndarray
+
+
+def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, use_dp: bool = False,
+           tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True) -> SolveResult:
+    g, keep = make_geometry(geom)
+    code = _dtype_code(b)
+    if x.dtype != b.dtype:
+        raise TypeError("b and x dtypes differ")
+    rho = np.zeros(max(k_max, 1))
+    alpha = np.zeros(k_max + 1)
+    t = np.zeros(k_max + 1)
+    P = ctypes.POINTER(ctypes.c_double)
+    o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0, None,
+                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P))
+    info = SolveInfo()
+    _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(b, geom.m), ctypes.byref(o),
+                                _dev_ptr(x, geom.n), ctypes.byref(info)))
+    k = info.k_stop
+    return SolveResult(k_stop=k, reason=info.reason, residual=info.residual, proj_residual=info.proj_residual,
+                       t1=info.t1, alpha1=info.alpha1, seconds=info.seconds, rho=rho[:k], alpha=alpha[:k + 1],
+                       t=t[:k + 1])
+
+
+def gkb_ab_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """AB-GKB: GKB on M = AB from b; x = B Q_k u_k."""
+    return _solve("gkb_ab_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def gkb_ba_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """BA-GKB: GKB on M = BA from B b; x = Q_k u_k."""
+    return _solve("gkb_ba_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def gkb_gkb_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """Matched GKB (B := A^T), equivalent to LSQR."""
+    return _solve("gkb_gkb_solve", ctx, geom, b, x, k_max, **kw)

@@ -1,0 +1,969 @@
+// Host side of libgkb: the C ABI declared in include/gkb.h, geometry tables,
+// workspaces, kernel tracing and the AB-/BA-/matched GKB drivers.
+//
+// The drivers follow the Golub-Kahan bidiagonalisation of Sec. 3 (Algs.
+// "GKB", "AB-GKB", "BA-GKB") read as the Paige-Saunders recurrence:
+// iteration k forms s_{k+1}, t_{k+1} from M q_k, then q_{k+1}, alpha_{k+1}
+// from M^T s_{k+1} with one-sided reorthogonalisation, and finally solves the
+// projected problem (eq. proj GKB) for u_k and applies the discrepancy
+// principle (eq. DP) to ||A x_k - b||.  Every quantity that changes from one
+// iteration to the next lives in device memory (the iteration counter
+// included), so one iteration is a fixed sequence of kernel launches; the
+// host only reads the stop flag, a few iterations behind the device.
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gkb.h"
+#include "internal.h"
+
+using namespace gkb;
+
+namespace {
+
+thread_local std::string g_err;
+
+gkb_status fail(gkb_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPC(expr)                                                                          \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess) return fail(GKB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// --------------------------------------------------------------------------
+// device buffer
+// --------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+// --------------------------------------------------------------------------
+// geometry tables
+// --------------------------------------------------------------------------
+struct HostTables {
+  // per ray
+  std::vector<double> base, slope, w, h, t0, dt, dperp, dpar;
+  std::vector<int> meta;
+  // per view
+  std::vector<double> p0, p1, p2, p3, p4;
+  // per bin (fan)
+  std::vector<double> gcos, gsin;
+  bool has_coldom = false;
+  GeomDev gd{};
+};
+
+struct DevTables {
+  DevBuf buf;
+  RayTab<float> rt32{};
+  ViewTab<float> vt32{};
+  RayTab<double> rt64{};
+  ViewTab<double> vt64{};
+  bool has_coldom = false;
+  GeomDev gd{};
+};
+
+std::vector<double> view_angles(const gkb_geometry *g) {
+  std::vector<double> a(g->n_views);
+  for (int v = 0; v < g->n_views; ++v) a[v] = g->angles ? g->angles[v] : v * (g->angle_span / g->n_views);
+  return a;
+}
+
+// Line range [lo, hi] of a ray whose crossing coordinate on line L is
+// c(L) = c_mid + (L - mid) * slope, restricted to c in [-1-h, len+h].
+void line_range(double c_mid, double slope, double mid, int nlines, int len, double h, int &lo, int &hi) {
+  const double cmin = -1.0 - h - 1.0, cmax = len + h + 1.0;
+  double Llo, Lhi;
+  if (std::fabs(slope) < 1e-300) {
+    if (c_mid < cmin || c_mid > cmax) {
+      lo = 1;
+      hi = 0;
+      return;
+    }
+    Llo = 0;
+    Lhi = nlines - 1;
+  } else {
+    double a = mid + (cmin - c_mid) / slope, b = mid + (cmax - c_mid) / slope;
+    if (a > b) std::swap(a, b);
+    Llo = std::floor(a) - 1;
+    Lhi = std::ceil(b) + 1;
+  }
+  lo = (int)std::max(0.0, Llo);
+  hi = (int)std::min((double)nlines - 1, Lhi);
+  if (lo > hi) {
+    lo = 1;
+    hi = 0;
+  }
+}
+
+void build_tables(const gkb_geometry *g, HostTables &t) {
+  const int nx = g->nx, ny = g->ny, nv = g->n_views, nu = g->n_det_u;
+  const long long m = (long long)nv * nu;
+  const double du = g->det_pitch_u;
+  const double off = 0.5 * (nu - 1);
+  const bool fan = g->kind == GKB_FAN2D;
+  const std::vector<double> ang = view_angles(g);
+  t.base.resize(m);
+  t.slope.resize(m);
+  t.w.resize(m);
+  t.h.resize(m);
+  t.meta.resize(m);
+  if (fan) {
+    t.t0.resize(m);
+    t.dt.resize(m);
+    t.dperp.resize(m);
+    t.dpar.resize(m);
+    t.gcos.resize(nu);
+    t.gsin.resize(nu);
+    for (int k = 0; k < nu; ++k) {
+      const double gam = (k - off) * du;
+      t.gcos[k] = std::cos(gam);
+      t.gsin[k] = std::sin(gam);
+    }
+  }
+  t.p0.resize(nv);
+  t.p1.resize(nv);
+  t.p2.resize(nv);
+  t.p3.resize(nv);
+  t.p4.resize(nv);
+  const double midy = 0.5 * (ny - 1), midx = 0.5 * (nx - 1);
+  const double tan_dg = std::tan(du);
+  for (int v = 0; v < nv; ++v) {
+    const double th = ang[v];
+    const double c = std::cos(th), s = std::sin(th);
+    if (!fan) {
+      const double dd = std::max(std::fabs(c), std::fabs(s));
+      t.p0[v] = c / du;
+      t.p1[v] = s / du;
+      t.p2[v] = 1.0 / dd;
+      t.p3[v] = du / dd;
+      t.p4[v] = dd / du;
+    } else {
+      t.p0[v] = c;
+      t.p1[v] = s;
+      t.p2[v] = t.p3[v] = t.p4[v] = 0.0;
+    }
+    const double Sx = g->src_dist * c, Sy = g->src_dist * s;
+    for (int k = 0; k < nu; ++k) {
+      const long long r = (long long)v * nu + k;
+      double cmid, slope, w, h;
+      bool rowdom;
+      if (!fan) {
+        const double sk = (k - off) * du;
+        rowdom = std::fabs(c) >= std::fabs(s);
+        if (rowdom) {
+          cmid = sk / c + midx;
+          slope = -s / c;
+          w = 1.0 / std::fabs(c);
+        } else {
+          cmid = sk / s + midy;
+          slope = -c / s;
+          w = 1.0 / std::fabs(s);
+        }
+        h = du * w;
+      } else {
+        const double gam = (k - off) * du;
+        const double dx = -std::cos(th + gam), dy = -std::sin(th + gam);
+        rowdom = std::fabs(dy) >= std::fabs(dx);
+        double t0, dt, dperp, dpar;
+        if (rowdom) {
+          cmid = Sx - Sy * dx / dy + midx;
+          slope = dx / dy;
+          w = 1.0 / std::fabs(dy);
+          t0 = -Sy / dy;
+          dt = 1.0 / dy;
+          dperp = -dy;
+          dpar = dx;
+        } else {
+          cmid = Sy - Sx * dy / dx + midy;
+          slope = dy / dx;
+          w = 1.0 / std::fabs(dx);
+          t0 = -Sx / dx;
+          dt = 1.0 / dx;
+          dperp = dx;
+          dpar = dy;
+        }
+        t.t0[r] = t0;
+        t.dt[r] = dt;
+        t.dperp[r] = dperp;
+        t.dpar[r] = dpar;
+        // B^T candidates: |delta| < tan(dg) * along, |delta| = |dperp| |d|
+        const int nl = rowdom ? ny : nx;
+        const double mid = rowdom ? midy : midx;
+        const double al = std::max(std::fabs(t0 + (0 - mid) * dt), std::fabs(t0 + (nl - 1 - mid) * dt)) + 4.0;
+        h = tan_dg * al / (std::fabs(dperp) - tan_dg) * 1.0001 + 1e-6;
+      }
+      int lo, hi;
+      if (rowdom)
+        line_range(cmid, slope, midy, ny, nx, std::max(h, 1.0), lo, hi);
+      else
+        line_range(cmid, slope, midx, nx, ny, std::max(h, 1.0), lo, hi);
+      if (!rowdom) t.has_coldom = true;
+      t.base[r] = cmid;
+      t.slope[r] = slope;
+      t.w[r] = w;
+      t.h[r] = h;
+      t.meta[r] = lo | (hi << 15) | ((rowdom ? 1 : 0) << 30);
+    }
+  }
+  GeomDev &gd = t.gd;
+  gd.kind = g->kind;
+  gd.nx = nx;
+  gd.ny = ny;
+  gd.nv = nv;
+  gd.nu = nu;
+  gd.n = (long long)nx * ny;
+  gd.m = m;
+  gd.du = du;
+  gd.D = g->src_dist;
+  gd.off = off;
+  gd.inv_du = 1.0 / du;
+  gd.hmax_fan = (1.0 / du) * (1.0 + 1e-5);
+}
+
+template <typename T>
+hipError_t upload_tables(const HostTables &h, DevTables &d) {
+  const long long m = h.gd.m;
+  const int nv = h.gd.nv, nu = h.gd.nu;
+  const bool fan = h.gd.kind == GKB_FAN2D;
+  // layout: 8 per-ray T arrays, meta, 5 per-view arrays, 2 per-bin arrays
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t rayT = al(sizeof(T) * m), rayI = al(sizeof(int) * m), viewT = al(sizeof(T) * nv),
+               binT = al(sizeof(T) * nu);
+  const size_t total = 8 * rayT + rayI + 5 * viewT + 2 * binT;
+  hipError_t e = d.buf.ensure(total);
+  if (e != hipSuccess) return e;
+  char *p = d.buf.as<char>();
+  std::vector<T> tmp;
+  auto put = [&](const std::vector<double> &src, size_t stride, size_t count) -> const T * {
+    T *dst = reinterpret_cast<T *>(p);
+    p += stride;
+    if (src.empty()) return dst;
+    tmp.assign(count, T(0));
+    for (size_t i = 0; i < count; ++i) tmp[i] = (T)src[i];
+    (void)hipMemcpy(dst, tmp.data(), sizeof(T) * count, hipMemcpyHostToDevice);
+    return dst;
+  };
+  RayTab<T> rt{};
+  ViewTab<T> vt{};
+  rt.base = put(h.base, rayT, m);
+  rt.slope = put(h.slope, rayT, m);
+  rt.w = put(h.w, rayT, m);
+  rt.h = put(h.h, rayT, m);
+  rt.t0 = put(h.t0, rayT, fan ? m : 0);
+  rt.dt = put(h.dt, rayT, fan ? m : 0);
+  rt.dperp = put(h.dperp, rayT, fan ? m : 0);
+  rt.dpar = put(h.dpar, rayT, fan ? m : 0);
+  int *meta = reinterpret_cast<int *>(p);
+  p += rayI;
+  e = hipMemcpy(meta, h.meta.data(), sizeof(int) * m, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  rt.meta = meta;
+  vt.p0 = put(h.p0, viewT, nv);
+  vt.p1 = put(h.p1, viewT, nv);
+  vt.p2 = put(h.p2, viewT, nv);
+  vt.p3 = put(h.p3, viewT, nv);
+  vt.p4 = put(h.p4, viewT, nv);
+  vt.gcos = put(h.gcos, binT, fan ? nu : 0);
+  vt.gsin = put(h.gsin, binT, fan ? nu : 0);
+  if constexpr (sizeof(T) == 4) {
+    d.rt32 = rt;
+    d.vt32 = vt;
+  } else {
+    d.rt64 = rt;
+    d.vt64 = vt;
+  }
+  d.has_coldom = h.has_coldom;
+  d.gd = h.gd;
+  return hipGetLastError();
+}
+
+std::string geom_key(const gkb_geometry *g, int dtype) {
+  std::string k;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%.17g|%.17g|%d|", g->kind, g->nx, g->ny,
+           g->nz, g->n_views, g->n_det_u, g->n_det_v, dtype, g->angle_span, g->det_pitch_u, g->det_pitch_v,
+           g->src_dist, g->src_det_dist, g->angles ? 1 : 0);
+  k = buf;
+  if (g->angles) {
+    k.append(reinterpret_cast<const char *>(g->angles), sizeof(double) * g->n_views);
+  }
+  return k;
+}
+
+// --------------------------------------------------------------------------
+// tracing
+// --------------------------------------------------------------------------
+struct TraceStat {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  int count = 0;
+  double ms = 0.0;
+};
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// context
+// --------------------------------------------------------------------------
+struct gkb_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::map<std::string, std::unique_ptr<DevTables>> tables;
+  // scratch for standalone projector calls and reductions
+  DevBuf xT, partials, counters;
+  // solve workspace
+  DevBuf Q, Y, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
+  int *host_flag = nullptr;      // host-mapped
+  int *host_flag_dev = nullptr;  // its device address
+  // tracing
+  bool trace = false;
+  std::map<std::string, TraceStat> stats;
+  std::vector<hipEvent_t> event_pool;
+
+  hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void flush_trace() {
+    for (auto &kv : stats) {
+      for (auto &pr : kv.second.pending) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(pr.second);
+        (void)hipEventElapsedTime(&ms, pr.first, pr.second);
+        kv.second.ms += ms;
+        kv.second.count += 1;
+        event_pool.push_back(pr.first);
+        event_pool.push_back(pr.second);
+      }
+      kv.second.pending.clear();
+    }
+  }
+};
+
+namespace {
+
+struct TraceScope {
+  gkb_ctx *c;
+  const char *name;
+  hipEvent_t a = nullptr;
+  TraceScope(gkb_ctx *ctx, const char *n) : c(ctx), name(n) {
+    if (c->trace) {
+      a = c->get_event();
+      (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~TraceScope() {
+    if (a) {
+      hipEvent_t b = c->get_event();
+      (void)hipEventRecord(b, c->stream);
+      c->stats[name].pending.emplace_back(a, b);
+    }
+  }
+};
+
+gkb_status validate_geom(const gkb_geometry *g, int dtype) {
+  if (!g) return fail(GKB_EINVAL, "geometry is NULL");
+  if (dtype != GKB_F32 && dtype != GKB_F64) return fail(GKB_EINVAL, "dtype must be GKB_F32 or GKB_F64");
+  if (g->kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "cone-beam geometry is not built in this library");
+  if (g->kind != GKB_PAR2D && g->kind != GKB_FAN2D) return fail(GKB_EINVAL, "unknown geometry kind");
+  if (g->nx < 1 || g->ny < 1 || g->nx > 16384 || g->ny > 16384)
+    return fail(GKB_EINVAL, "nx, ny must be in [1, 16384]");
+  if (g->nz != 1 && g->nz != 0) return fail(GKB_EINVAL, "nz must be 1 for 2D geometry");
+  if (g->n_views < 1) return fail(GKB_EINVAL, "n_views must be >= 1");
+  if (g->n_det_u < 1 || (g->n_det_v != 1 && g->n_det_v != 0))
+    return fail(GKB_EINVAL, "n_det_u must be >= 1 and n_det_v 1 for 2D geometry");
+  if (!(g->det_pitch_u > 0.0) || !std::isfinite(g->det_pitch_u)) return fail(GKB_EINVAL, "det_pitch_u must be > 0");
+  if (!g->angles && !std::isfinite(g->angle_span)) return fail(GKB_EINVAL, "angle_span must be finite");
+  if (g->angles)
+    for (int v = 0; v < g->n_views; ++v)
+      if (!std::isfinite(g->angles[v])) return fail(GKB_EINVAL, "angles must be finite");
+  if (g->kind == GKB_FAN2D) {
+    const double half_diag = 0.5 * std::sqrt((double)g->nx * g->nx + (double)g->ny * g->ny);
+    if (!(g->src_dist > half_diag + 2.0))
+      return fail(GKB_EINVAL, "fan beam: src_dist must exceed the image half-diagonal + 2");
+    if (!(g->det_pitch_u * g->n_det_u < 3.0)) return fail(GKB_EINVAL, "fan beam: fan angle must be < 3 rad");
+  }
+  return GKB_OK;
+}
+
+gkb_status get_tables(gkb_ctx *c, const gkb_geometry *g, int dtype, DevTables **out) {
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  const std::string key = geom_key(g, dtype);
+  auto it = c->tables.find(key);
+  if (it != c->tables.end()) {
+    *out = it->second.get();
+    return GKB_OK;
+  }
+  HostTables h;
+  build_tables(g, h);
+  auto d = std::make_unique<DevTables>();
+  hipError_t e = (dtype == GKB_F32) ? upload_tables<float>(h, *d) : upload_tables<double>(h, *d);
+  if (e == hipErrorOutOfMemory) return fail(GKB_ENOMEM, "out of device memory for geometry tables");
+  if (e != hipSuccess) return fail(GKB_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  *out = d.get();
+  c->tables.emplace(key, std::move(d));
+  return GKB_OK;
+}
+
+template <typename T>
+const RayTab<T> &rt_of(const DevTables &d);
+template <>
+const RayTab<float> &rt_of<float>(const DevTables &d) {
+  return d.rt32;
+}
+template <>
+const RayTab<double> &rt_of<double>(const DevTables &d) {
+  return d.rt64;
+}
+template <typename T>
+const ViewTab<T> &vt_of(const DevTables &d);
+template <>
+const ViewTab<float> &vt_of<float>(const DevTables &d) {
+  return d.vt32;
+}
+template <>
+const ViewTab<double> &vt_of<double>(const DevTables &d) {
+  return d.vt64;
+}
+
+template <typename T>
+Col<T> col(T *p) {
+  return Col<T>{p, 0, 0, nullptr};
+}
+template <typename T>
+Col<T> colk(T *base, long long ld, int off, const int *kptr) {
+  return Col<T>{base, ld, off, kptr};
+}
+
+template <typename T>
+Epi<T> plain_epi() {
+  Epi<T> e{};
+  e.use_ctl = 0;
+  e.in_sel = IN_ONE;
+  e.prev_sel = PREV_NONE;
+  e.norm_to_t = 0;
+  e.prev = Col<const T>{nullptr, 0, 0, nullptr};
+  e.out_raw = Col<T>{nullptr, 0, 0, nullptr};
+  return e;
+}
+
+gkb_status ensure_scratch(gkb_ctx *c, size_t xT_bytes, long long nblocks_times_cols) {
+  HIPC(c->xT.ensure(std::max<size_t>(xT_bytes, 256)));
+  HIPC(c->partials.ensure(sizeof(double) * std::max<long long>(nblocks_times_cols, 1024)));
+  if (!c->counters.p) {
+    HIPC(c->counters.ensure(256 * sizeof(unsigned)));
+    HIPC(hipMemset(c->counters.p, 0, 256 * sizeof(unsigned)));
+  }
+  return GKB_OK;
+}
+
+// ----- standalone projector application -----
+enum Op { OP_A = 0, OP_B = 1, OP_AT = 2, OP_BT = 3 };
+
+template <typename T>
+gkb_status apply_op(gkb_ctx *c, const DevTables &d, int op, const void *in, void *out) {
+  const GeomDev &g = d.gd;
+  const long long nb = std::max<long long>(std::max(ray_blocks(g), pixel_blocks(g)), 1);
+  gkb_status st = ensure_scratch(c, sizeof(T) * (size_t)g.n, nb);
+  if (st != GKB_OK) return st;
+  Epi<T> e = plain_epi<T>();
+  const T *xi = static_cast<const T *>(in);
+  T *xo = static_cast<T *>(out);
+  T *xT = c->xT.as<T>();
+  switch (op) {
+    case OP_A: {
+      if (d.has_coldom) launch_transpose<T>(col<const T>(xi), xT, g.nx, g.ny, nullptr, c->stream);
+      TraceScope ts(c, "fwd");
+      launch_fwd<T>(g, rt_of<T>(d), col<const T>(xi), xT, col<T>(xo), e, nullptr, c->stream);
+      break;
+    }
+    case OP_BT: {
+      if (d.has_coldom) launch_transpose<T>(col<const T>(xi), xT, g.nx, g.ny, nullptr, c->stream);
+      TraceScope ts(c, "back_adj");
+      launch_back_adj<T>(g, rt_of<T>(d), col<const T>(xi), xT, col<T>(xo), e, nullptr, c->stream);
+      break;
+    }
+    case OP_B: {
+      TraceScope ts(c, "back");
+      launch_back<T>(g, vt_of<T>(d), rt_of<T>(d), col<const T>(xi), xo, e, nullptr, c->stream);
+      break;
+    }
+    case OP_AT: {
+      TraceScope ts(c, "fwd_adj");
+      launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), col<const T>(xi), xo, e, nullptr, c->stream);
+      break;
+    }
+  }
+  HIPC(hipGetLastError());
+  return GKB_OK;
+}
+
+gkb_status projector_call(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *in, void *out, int op) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!in || !out) return fail(GKB_EINVAL, "data pointer is NULL");
+  DevTables *d = nullptr;
+  gkb_status st = get_tables(c, g, dtype, &d);
+  if (st != GKB_OK) return st;
+  HIPC(hipSetDevice(c->device));
+  return dtype == GKB_F32 ? apply_op<float>(c, *d, op, in, out) : apply_op<double>(c, *d, op, in, out);
+}
+
+// --------------------------------------------------------------------------
+// GKB driver
+// --------------------------------------------------------------------------
+enum Mode { MODE_AB = 0, MODE_BA = 1, MODE_GKB = 2 };
+
+template <typename T>
+struct Solver {
+  gkb_ctx *c;
+  const DevTables &d;
+  const GeomDev &g;
+  int mode;
+  int K;
+  long long n, m, dimq, dims;
+  T *Q = nullptr, *Y = nullptr, *s = nullptr, *w = nullptr, *tn = nullptr, *tm = nullptr, *xT = nullptr;
+  Ctl ctl{};
+  double *partials = nullptr;
+  unsigned *counters = nullptr;
+  hipStream_t st;
+  const int *stop = nullptr;
+  const int *kp = nullptr;
+
+  Solver(gkb_ctx *ctx, const DevTables &dt, int md, int kmax) : c(ctx), d(dt), g(dt.gd), mode(md), K(kmax) {
+    n = g.n;
+    m = g.m;
+    dimq = (mode == MODE_AB) ? m : n;
+    dims = (mode == MODE_BA) ? n : m;
+    st = c->stream;
+  }
+
+  gkb_status alloc() {
+    const long long ldG = K + 2;
+    HIPC(c->Q.ensure(sizeof(T) * (size_t)dimq * (K + 1)));
+    HIPC(c->Y.ensure(sizeof(T) * (size_t)m * (K + 1)));
+    HIPC(c->s.ensure(sizeof(T) * (size_t)dims));
+    HIPC(c->w.ensure(sizeof(T) * (size_t)dimq));
+    HIPC(c->tmp_n.ensure(sizeof(T) * (size_t)n));
+    HIPC(c->tmp_m.ensure(sizeof(T) * (size_t)m));
+    const size_t nd = CD_COUNT + 9 * (size_t)(K + 2) + (size_t)ldG * ldG;
+    HIPC(c->ctl_d.ensure(sizeof(double) * nd));
+    HIPC(c->ctl_i.ensure(sizeof(int) * CI_COUNT));
+    const long long vb = std::max<long long>(
+        {(long long)vec_blocks(dimq), (long long)vec_blocks(m), (long long)vec_blocks(dims)});
+    const long long pb = std::max<long long>({(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2)});
+    gkb_status stt = ensure_scratch(c, sizeof(T) * (size_t)n, pb);
+    if (stt != GKB_OK) return stt;
+    if (!c->host_flag) {
+      HIPC(hipHostMalloc((void **)&c->host_flag, sizeof(int) * 4, hipHostMallocMapped));
+      HIPC(hipHostGetDevicePointer((void **)&c->host_flag_dev, c->host_flag, 0));
+    }
+    Q = c->Q.as<T>();
+    Y = c->Y.as<T>();
+    s = c->s.as<T>();
+    w = c->w.as<T>();
+    tn = c->tmp_n.as<T>();
+    tm = c->tmp_m.as<T>();
+    xT = c->xT.as<T>();
+    double *dp = c->ctl_d.as<double>();
+    ctl.ip = c->ctl_i.as<int>();
+    ctl.dp = dp;
+    dp += CD_COUNT;
+    double **arrs[] = {&ctl.alpha, &ctl.t, &ctl.rho, &ctl.pres, &ctl.u, &ctl.Rd, &ctl.Rth, &ctl.Rphi, &ctl.c};
+    for (double **a : arrs) {
+      *a = dp;
+      dp += K + 2;
+    }
+    ctl.G = dp;
+    ctl.K = K;
+    ctl.ldG = (int)ldG;
+    ctl.host_stop = c->host_flag_dev;
+    partials = c->partials.as<double>();
+    counters = c->counters.as<unsigned>();
+    stop = ctl.ip + CI_STOP;
+    kp = ctl.ip + CI_K;
+    return GKB_OK;
+  }
+
+  Epi<T> epi() const {
+    Epi<T> e = plain_epi<T>();
+    e.ctl = ctl;
+    e.use_ctl = 1;
+    e.partials = partials;
+    e.counter = counters;
+    return e;
+  }
+
+  // column i (0-based, shifted by the device counter k) of Q / Y
+  Col<const T> qcol(int off) const { return colk<const T>(Q, dimq, off, kp); }
+  Col<T> ycol(int off) const { return colk<T>(Y, m, off, kp); }
+
+  // ----- the four projectors with device-addressed operands -----
+  void A(Col<const T> in, Col<T> out, const Epi<T> &e) {
+    if (d.has_coldom) launch_transpose<T>(in, xT, g.nx, g.ny, stop, st);
+    TraceScope ts(c, "fwd");
+    launch_fwd<T>(g, rt_of<T>(d), in, xT, out, e, stop, st);
+  }
+  void Bt(Col<const T> in, Col<T> out, const Epi<T> &e) {
+    if (d.has_coldom) launch_transpose<T>(in, xT, g.nx, g.ny, stop, st);
+    TraceScope ts(c, "back_adj");
+    launch_back_adj<T>(g, rt_of<T>(d), in, xT, out, e, stop, st);
+  }
+  void B(Col<const T> in, T *out, const Epi<T> &e) {
+    TraceScope ts(c, "back");
+    launch_back<T>(g, vt_of<T>(d), rt_of<T>(d), in, out, e, stop, st);
+  }
+  void At(Col<const T> in, T *out, const Epi<T> &e) {
+    TraceScope ts(c, "fwd_adj");
+    launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), in, out, e, stop, st);
+  }
+
+  // s~ <- M q_k - alpha_k/t_k s~ (s stored unnormalised, s_k = s~/t_k); t_{k+1}; Y_k
+  void apply_M() {
+    Epi<T> e = epi();
+    e.prev_sel = PREV_NEG_ALPHA_OVER_T;
+    e.prev = col<const T>(s);
+    e.norm_to_t = 1;
+    if (mode == MODE_BA) {  // Y_k = A q_k ; s~ = B Y_k - ...
+      A(qcol(-1), ycol(0), plain_epi<T>());
+      B(colk<const T>(Y, m, 0, kp), s, e);
+    } else if (mode == MODE_AB) {  // Y_k = A B q_k ; s~ = Y_k - ...
+      B(qcol(-1), tn, plain_epi<T>());
+      e.out_raw = ycol(0);
+      A(col<const T>(tn), col<T>(s), e);
+    } else {  // matched: Y_k = A q_k ; s~ = Y_k - ...
+      e.out_raw = ycol(0);
+      A(qcol(-1), col<T>(s), e);
+    }
+  }
+
+  // w <- M^T s_{k+1} - t_{k+1} q_k   (k = 0: w <- M^T s_1)
+  void apply_Mt(bool first) {
+    Epi<T> e0 = epi();
+    e0.in_sel = IN_INV_TNEXT;  // s_{k+1} = s~ / t_{k+1}
+    Epi<T> e1 = epi();
+    if (!first) {
+      e1.prev_sel = PREV_NEG_TNEXT;
+      e1.prev = qcol(-1);
+    }
+    if (mode == MODE_BA) {  // A^T (B^T s)
+      Bt(col<const T>(s), col<T>(tm), e0);
+      At(col<const T>(tm), w, e1);
+    } else if (mode == MODE_AB) {  // B^T (A^T s)
+      At(col<const T>(s), tn, e0);
+      Bt(col<const T>(tn), col<T>(w), e1);
+    } else {  // A^T s
+      Epi<T> e = e1;
+      e.in_sel = IN_INV_TNEXT;
+      At(col<const T>(s), w, e);
+    }
+  }
+
+  void iteration(bool reorth) {
+    apply_M();
+    apply_Mt(false);
+    reorth_and_normalize_impl(reorth);
+    {
+      TraceScope ts(c, "gram");
+      launch_gram<T>(ctl, Y, m, m, 0, partials, counters, st);
+    }
+    {
+      TraceScope ts(c, "small_solve");
+      launch_small_solve(ctl, st);
+    }
+  }
+
+  void reorth_and_normalize_impl(bool reorth) {
+    TraceScope ts(c, "reorth");
+    if (reorth) {
+      launch_cgs_dots<T>(ctl, Q, dimq, w, dimq, partials, counters, st);
+      launch_cgs_update<T>(ctl, Q, dimq, w, dimq, 0, partials, counters, st);
+      launch_cgs_update<T>(ctl, Q, dimq, w, dimq, 1, partials, counters, st);
+    } else {
+      // no reorthogonalisation: only the norm (zero previous columns)
+      launch_norm_to<T>(ctl, w, dimq, NORM_ALPHA1, partials, counters, st);
+    }
+    launch_normalize<T>(ctl, w, Q, dimq, dimq, st);
+  }
+};
+
+template <typename T>
+gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const void *bv, const gkb_solve_opts *o,
+                      void *xv, gkb_solve_info *info, int mode) {
+  auto t_start = std::chrono::steady_clock::now();
+  DevTables *d = nullptr;
+  gkb_status stt = get_tables(c, geom, dtype, &d);
+  if (stt != GKB_OK) return stt;
+  Solver<T> S(c, *d, mode, o->k_max);
+  stt = S.alloc();
+  if (stt != GKB_OK) return stt;
+  const T *b = static_cast<const T *>(bv);
+  T *x = static_cast<T *>(xv);
+  hipStream_t st = c->stream;
+  const GeomDev &g = d->gd;
+
+  // control block
+  int hip_[CI_COUNT] = {0};
+  double hdp[CD_COUNT] = {0};
+  hdp[CD_TAUE] = o->use_dp ? o->tau * o->noise_norm : 0.0;
+  hdp[CD_LAMBDA] = o->lambda;
+  hdp[CD_ETAEPS] = 100.0 * (sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16) * 2.0;
+  hdp[CD_USEDP] = o->use_dp ? 1.0 : 0.0;
+  hdp[CD_KMAX] = o->k_max;
+  HIPC(hipMemcpyAsync(S.ctl.ip, hip_, sizeof hip_, hipMemcpyHostToDevice, st));
+  HIPC(hipMemcpyAsync(S.ctl.dp, hdp, sizeof hdp, hipMemcpyHostToDevice, st));
+  *c->host_flag = 0;
+
+  // start-up (k = 0): Y_0 = b, G_00 = ||b||^2; s~_1 = rhs, t_1; q_1, alpha_1
+  launch_copy<T>(b, S.Y, g.m, st);
+  launch_gram<T>(S.ctl, S.Y, g.m, g.m, 1, S.partials, S.counters, st);
+  if (mode == MODE_BA) {
+    Epi<T> e = S.epi();
+    e.norm_to_t = 1;
+    S.B(col<const T>(b), S.s, e);
+  } else {
+    launch_copy<T>(b, S.s, g.m, st);
+    launch_norm_to<T>(S.ctl, S.s, g.m, NORM_T1, S.partials, S.counters, st);
+  }
+  S.apply_Mt(true);
+  launch_norm_to<T>(S.ctl, S.w, S.dimq, NORM_ALPHA1, S.partials, S.counters, st);
+  launch_normalize<T>(S.ctl, S.w, S.Q, S.dimq, S.dimq, st);
+  HIPC(hipGetLastError());
+  double h3[3];
+  HIPC(hipMemcpyAsync(&h3[0], S.ctl.t + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(&h3[1], S.ctl.alpha + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(&h3[2], S.ctl.G, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  const double t1 = h3[0], bb = h3[2];
+  const double a1 = (t1 > 0.0) ? h3[1] : 0.0;  // M^T (s/t_1) is 0/0 when t_1 = 0
+  if (!std::isfinite(bb) || !std::isfinite(t1) || !std::isfinite(a1))
+    return fail(GKB_ENONFINITE, "non-finite value in b (or in the start-up vectors)");
+  gkb_solve_info inf{};
+  inf.t1 = t1;
+  inf.alpha1 = a1;
+  int k_stop = 0, reason = 0;
+  if (!(t1 > 0.0) || !(a1 > 0.0)) {
+    // rhs = 0 or M^T rhs = 0: x = 0 is the least-squares solution in the (empty) Krylov space
+    HIPC(hipMemsetAsync(x, 0, sizeof(T) * (size_t)g.n, st));
+    HIPC(hipStreamSynchronize(st));
+    reason = GKB_STOP_BREAKDOWN;
+    inf.residual = std::sqrt(bb);
+    inf.proj_residual = t1;
+  } else {
+    launch_set_int(S.ctl.ip + CI_K, 1, st);
+    const int L = 4;
+    std::vector<hipEvent_t> evs(L, nullptr);
+    for (auto &e : evs) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const bool reorth = o->reorth != 0;
+    int launched = 0;
+    for (int k = 1; k <= o->k_max; ++k) {
+      S.iteration(reorth);
+      HIPC(hipEventRecord(evs[k % L], st));
+      ++launched;
+      if (k >= L) {
+        HIPC(hipEventSynchronize(evs[(k - L + 1) % L]));
+        if (*(volatile int *)c->host_flag) break;
+      }
+    }
+    HIPC(hipGetLastError());
+    // solution x = Q_k u_k (BA, matched) or B (Q_k u_k) (AB)
+    if (mode == MODE_AB) {
+      launch_solution<T>(S.ctl, S.Q, S.dimq, S.dimq, S.tm, st);
+      Epi<T> e = plain_epi<T>();
+      TraceScope ts(c, "back");
+      launch_back<T>(g, vt_of<T>(*d), rt_of<T>(*d), col<const T>(S.tm), x, e, nullptr, st);
+    } else {
+      launch_solution<T>(S.ctl, S.Q, S.dimq, S.dimq, x, st);
+    }
+    HIPC(hipGetLastError());
+    int hi[CI_COUNT];
+    HIPC(hipMemcpyAsync(hi, S.ctl.ip, sizeof hi, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    for (auto &e : evs) (void)hipEventDestroy(e);
+    k_stop = hi[CI_KSTOP];
+    reason = hi[CI_REASON];
+    std::vector<double> rho(o->k_max + 2), pres(o->k_max + 2);
+    HIPC(hipMemcpy(rho.data(), S.ctl.rho, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(pres.data(), S.ctl.pres, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    inf.residual = rho[k_stop];
+    inf.proj_residual = pres[k_stop];
+    if (o->residual_history)
+      for (int k = 1; k <= k_stop; ++k) o->residual_history[k - 1] = rho[k];
+    (void)launched;
+  }
+  if (o->alpha_history || o->t_history) {
+    std::vector<double> al(o->k_max + 2), tt(o->k_max + 2);
+    HIPC(hipMemcpy(al.data(), S.ctl.alpha, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(tt.data(), S.ctl.t, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    for (int k = 1; k <= o->k_max + 1; ++k) {
+      if (o->alpha_history) o->alpha_history[k - 1] = (k <= k_stop + 1) ? al[k] : 0.0;
+      if (o->t_history) o->t_history[k - 1] = (k <= k_stop + 1) ? tt[k] : 0.0;
+    }
+  }
+  inf.k_stop = k_stop;
+  inf.reason = reason;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (info) *info = inf;
+  return GKB_OK;
+}
+
+gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                       void *x, gkb_solve_info *info, int mode) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!o) return fail(GKB_EINVAL, "options are NULL");
+  if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  if (o->k_max < 1 || o->k_max > 4096) return fail(GKB_EINVAL, "k_max must be in [1, 4096]");
+  if (!(o->lambda >= 0.0) || !std::isfinite(o->lambda)) return fail(GKB_EINVAL, "lambda must be finite and >= 0");
+  if (o->use_dp && (!(o->tau > 0.0) || !std::isfinite(o->tau)))
+    return fail(GKB_EINVAL, "tau must be > 0 when the discrepancy principle is on");
+  if (o->use_dp && (!(o->noise_norm >= 0.0) || !std::isfinite(o->noise_norm)))
+    return fail(GKB_EINVAL, "noise_norm must be finite and >= 0");
+  if (o->precond) return fail(GKB_EUNSUPPORTED, "learned preconditioner is not available in this build");
+  HIPC(hipSetDevice(c->device));
+  return dtype == GKB_F32 ? solve_impl<float>(c, g, dtype, b, o, x, info, mode)
+                          : solve_impl<double>(c, g, dtype, b, o, x, info, mode);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// C ABI
+// --------------------------------------------------------------------------
+extern "C" {
+
+gkb_status gkb_create(gkb_ctx **ctx, int device, void *hip_stream) {
+  if (!ctx) return fail(GKB_EINVAL, "ctx out-pointer is NULL");
+  *ctx = nullptr;
+  int ndev = 0;
+  HIPC(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(GKB_EINVAL, "device index out of range");
+  HIPC(hipSetDevice(device));
+  auto *c = new gkb_ctx();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(GKB_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  *ctx = c;
+  return GKB_OK;
+}
+
+void gkb_destroy(gkb_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->flush_trace();
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->host_flag) (void)hipHostFree(c->host_flag);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+gkb_status gkb_set_stream(gkb_ctx *c, void *hip_stream) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (c->own_stream) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamDestroy(c->stream);
+    c->own_stream = false;
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  return GKB_OK;
+}
+
+const char *gkb_last_error(void) { return g_err.c_str(); }
+
+gkb_status gkb_forward(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *x, void *y) {
+  return projector_call(c, g, dtype, x, y, OP_A);
+}
+gkb_status gkb_back(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y, void *x) {
+  return projector_call(c, g, dtype, y, x, OP_B);
+}
+gkb_status gkb_forward_adjoint(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y, void *x) {
+  return projector_call(c, g, dtype, y, x, OP_AT);
+}
+gkb_status gkb_back_adjoint(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *x, void *y) {
+  return projector_call(c, g, dtype, x, y, OP_BT);
+}
+
+gkb_status gkb_ab_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                        void *x, gkb_solve_info *info) {
+  return solve_entry(c, g, dtype, b, o, x, info, MODE_AB);
+}
+gkb_status gkb_ba_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                        void *x, gkb_solve_info *info) {
+  return solve_entry(c, g, dtype, b, o, x, info, MODE_BA);
+}
+gkb_status gkb_gkb_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                         void *x, gkb_solve_info *info) {
+  return solve_entry(c, g, dtype, b, o, x, info, MODE_GKB);
+}
+
+gkb_status gkb_trace_enable(gkb_ctx *c, int on) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  c->trace = on != 0;
+  return GKB_OK;
+}
+gkb_status gkb_trace_reset(gkb_ctx *c) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  c->flush_trace();
+  c->stats.clear();
+  return GKB_OK;
+}
+gkb_status gkb_trace_get(gkb_ctx *c, const char *kernel, int *count, double *total_ms) {
+  if (!c || !kernel) return fail(GKB_EINVAL, "NULL argument");
+  c->flush_trace();
+  auto it = c->stats.find(kernel);
+  if (count) *count = it == c->stats.end() ? 0 : it->second.count;
+  if (total_ms) *total_ms = it == c->stats.end() ? 0.0 : it->second.ms;
+  return GKB_OK;
+}
+
+}  // extern "C"

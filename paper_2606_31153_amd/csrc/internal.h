@@ -1,0 +1,173 @@
+// Internal declarations shared by the HIP translation units of libgkb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gkb {
+
+constexpr int kBlock = 256;
+
+// Integer fields of the device control block.
+enum CtlInt : int {
+  CI_K = 0,       // current iteration k (0 during the start-up step)
+  CI_STOP = 1,    // 1 once the iteration has stopped
+  CI_KSTOP = 2,   // iteration whose solution is returned
+  CI_REASON = 3,  // gkb_stop_reason
+  CI_COUNT = 8
+};
+
+// Double fields of the device control block.
+enum CtlDbl : int {
+  CD_TAUE = 0,     // tau * ||e||
+  CD_LAMBDA = 1,   // Tikhonov weight
+  CD_ETAEPS = 2,   // breakdown threshold factor: 100 * unit roundoff of the vector type
+  CD_BSCALE = 3,   // max_i sqrt(alpha_i^2 + t_{i+1}^2)
+  CD_RHOBAR = 4,   // Givens QR state of [C_k; lambda I]
+  CD_PHIBAR = 5,
+  CD_CPREV = 6,
+  CD_SPREV = 7,
+  CD_PSI2 = 8,
+  CD_PRES = 9,     // projected residual at k
+  CD_USEDP = 10,
+  CD_KMAX = 11,
+  CD_COUNT = 16
+};
+
+// Views into the control block (device memory).  Arrays indexed 1-based by
+// iteration: alpha[1..K+1], t[1..K+1], rho[1..K], ...
+struct Ctl {
+  int *ip;
+  double *dp;
+  double *alpha;
+  double *t;
+  double *rho;
+  double *pres;
+  double *u;      // [K+1], u[1..k]
+  double *Rd;     // diagonal of R
+  double *Rth;    // superdiagonal of R (Rth[i] couples columns i-1, i)
+  double *Rphi;   // rotated right-hand side
+  double *G;      // (K+2) x (K+2) Gram of [b, Y_1, ..., Y_K], row-major
+  double *c;      // CGS coefficients [K+1]
+  int *host_stop; // host-mapped mirror of ip[CI_STOP] (may be null)
+  int K;
+  int ldG;
+};
+
+// A vector selected by the device-side iteration counter:
+// address = base + (k + off) * ld (k read from ip[CI_K]); kptr == nullptr -> base.
+template <typename T>
+struct Col {
+  T *base;
+  long long ld;
+  int off;
+  const int *kptr;
+  __host__ __device__ T *get() const {
+    return kptr ? base + (long long)(*kptr + off) * ld : base;
+  }
+};
+
+// Epilogue of a projector kernel:
+//   out = raw * in_scale + prev_coef * prev
+// in_scale: 1 or 1/t[k+1]; prev_coef: 0, -alpha[k]/t[k] or -t[k+1].
+// Optionally stores raw to out_raw and reduces ||out||^2 into t[k+1].
+enum EpiIn : int { IN_ONE = 0, IN_INV_TNEXT = 1 };
+enum EpiPrev : int { PREV_NONE = 0, PREV_NEG_ALPHA_OVER_T = 1, PREV_NEG_TNEXT = 2 };
+
+template <typename T>
+struct Epi {
+  Ctl ctl;             // valid when use_ctl
+  int use_ctl;
+  int in_sel;
+  int prev_sel;
+  int norm_to_t;       // 1: reduce ||out||^2 into t[k+1]
+  Col<const T> prev;
+  Col<T> out_raw;      // base == nullptr: not stored
+  double *partials;    // per-block partial sums
+  unsigned *counter;
+};
+
+// Geometry tables kept in device memory (one set per geometry and dtype).
+template <typename T>
+struct RayTab {        // per ray, m entries: ray-driven kernels (A, B^T)
+  const T *base;       // crossing coordinate (pixel index units) at the middle line
+  const T *slope;      // d(crossing)/d(line)
+  const T *w;          // 1/|d_dom|
+  const int *meta;     // lo | hi << 15 | rowdom << 30
+  const T *h;          // B^T candidate half-width (pixel index units)
+  // fan-beam B^T
+  const T *t0;         // distance from the source to the crossing at the middle line
+  const T *dt;         // its change per line
+  const T *dperp;      // signed perpendicular-distance change per unit offset along the line
+  const T *dpar;       // along-ray distance change per unit offset along the line
+};
+
+template <typename T>
+struct ViewTab {       // per view (pixel-driven kernels B, A^T)
+  const T *p0;         // PAR: cos/du            FAN: cos(beta)
+  const T *p1;         // PAR: sin/du            FAN: sin(beta)
+  const T *p2;         // PAR: 1/|d_dom|
+  const T *p3;         // PAR: du/|d_dom| (A^T hat slope in bins)
+  const T *p4;         // PAR: |d_dom|/du (A^T hat half-width in bins)
+  const T *gcos;       // FAN: cos(gamma_k) [n_det]
+  const T *gsin;       // FAN: sin(gamma_k) [n_det]
+};
+
+struct GeomDev {
+  int kind;
+  int nx, ny, nv, nu;
+  long long n, m;
+  double du;           // bin pitch (length or radians)
+  double D;            // source distance (fan)
+  double off;          // (nu-1)/2
+  double inv_du;
+  double hmax_fan;     // fan A^T candidate half-width numerator bound
+};
+
+// ---- launchers (proj2d.hip) ----
+template <typename T>
+void launch_transpose(Col<const T> x, T *xT, int nx, int ny, const int *stop, hipStream_t s);
+template <typename T>
+void launch_fwd(const GeomDev &g, const RayTab<T> &rt, Col<const T> x, const T *xT, Col<T> y, const Epi<T> &e,
+                const int *stop, hipStream_t s);
+template <typename T>
+void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, Col<const T> x, const T *xT, Col<T> y,
+                     const Epi<T> &e, const int *stop, hipStream_t s);
+template <typename T>
+void launch_back(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, Col<const T> y, T *x,
+                 const Epi<T> &e, const int *stop, hipStream_t s);
+template <typename T>
+void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, Col<const T> y, T *x,
+                    const Epi<T> &e, const int *stop, hipStream_t s);
+int pixel_blocks(const GeomDev &g);
+int ray_blocks(const GeomDev &g);
+
+// ---- Krylov vector kernels (krylov.hip) ----
+int vec_blocks(long long dim);
+template <typename T>
+void launch_copy(const T *src, T *dst, long long n, hipStream_t s);
+template <typename T>
+void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *partials, unsigned *counter,
+                    hipStream_t s);
+template <typename T>
+void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
+                     unsigned *counter, hipStream_t s);
+template <typename T>
+void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
+                       unsigned *counter, hipStream_t s);
+template <typename T>
+void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s);
+template <typename T>
+void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials,
+                 unsigned *counter, hipStream_t s);
+void launch_small_solve(Ctl ctl, hipStream_t s);
+template <typename T>
+void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, hipStream_t s);
+void launch_set_int(int *p, int v, hipStream_t s);
+
+// norm targets for launch_norm_to
+enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1 };
+
+}  // namespace gkb

@@ -1,0 +1,59 @@
+// Deterministic reductions for wave64 / 256-thread workgroups.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gkb {
+
+// Butterfly sum across the 64 lanes of a wavefront (fixed order).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a workgroup of NT threads; the result is valid in thread 0.
+// `lds` holds NT/64 doubles.  Fixed order: lane butterfly, then waves 0..NT/64-1.
+template <int NT>
+__device__ inline double block_sum(double v, double *lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) r += lds[i];
+  }
+  return r;
+}
+
+// Result broadcast to every thread of the block.
+template <int NT>
+__device__ inline double block_sum_all(double v, double *lds) {
+  double r = block_sum<NT>(v, lds);
+  __syncthreads();
+  if (threadIdx.x == 0) lds[0] = r;
+  __syncthreads();
+  r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+// Called by every thread after the block has published its partial results
+// (ordinary stores followed by this call).  Returns true in exactly one
+// block: the last one to arrive, which may then read every block's partials.
+// The last block must reset *counter to 0 before it exits.
+__device__ inline bool arrive_last(unsigned *counter, unsigned nblocks) {
+  __shared__ unsigned s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(counter, 1u) == nblocks - 1u) ? 1u : 0u;
+  __syncthreads();
+  const bool last = s_last != 0u;
+  if (last) __threadfence();
+  return last;
+}
+
+}  // namespace gkb
