@@ -72,11 +72,12 @@ struct DevBuf {
 struct HostTables {
   // per ray
   std::vector<double> base, slope, w, h, t0, dt, dperp, dpar;
-  std::vector<int> meta;
+  std::vector<int> meta, meta_bt;
+  std::vector<double> wpad;  // fan: 1/|d_dom| in padded sinogram layout
   // per view
   std::vector<double> p0, p1, p2, p3, p4;
-  // per bin (fan)
-  std::vector<double> gcos, gsin;
+  // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
+  std::vector<double> gcs;
   bool has_coldom = false;
   GeomDev gd{};
 };
@@ -97,10 +98,9 @@ std::vector<double> view_angles(const gkb_geometry *g) {
   return a;
 }
 
-// Line range [lo, hi] of a ray whose crossing coordinate on line L is
-// c(L) = c_mid + (L - mid) * slope, restricted to c in [-1-h, len+h].
-void line_range(double c_mid, double slope, double mid, int nlines, int len, double h, int &lo, int &hi) {
-  const double cmin = -1.0 - h - 1.0, cmax = len + h + 1.0;
+// Lines [lo, hi] of a ray whose crossing coordinate on line L is
+// c(L) = c_mid + (L - mid) * slope: the lines with c in [cmin, cmax].
+void line_range(double c_mid, double slope, double mid, int nlines, double cmin, double cmax, int &lo, int &hi) {
   double Llo, Lhi;
   if (std::fabs(slope) < 1e-300) {
     if (c_mid < cmin || c_mid > cmax) {
@@ -113,8 +113,8 @@ void line_range(double c_mid, double slope, double mid, int nlines, int len, dou
   } else {
     double a = mid + (cmin - c_mid) / slope, b = mid + (cmax - c_mid) / slope;
     if (a > b) std::swap(a, b);
-    Llo = std::floor(a) - 1;
-    Lhi = std::ceil(b) + 1;
+    Llo = std::ceil(a - 1e-9);
+    Lhi = std::floor(b + 1e-9);
   }
   lo = (int)std::max(0.0, Llo);
   hi = (int)std::min((double)nlines - 1, Lhi);
@@ -124,6 +124,8 @@ void line_range(double c_mid, double slope, double mid, int nlines, int len, dou
   }
 }
 
+// Ray geometry in pixel index coordinates (crossing at the middle line and
+// its slope per line), filled for every ray of a 2D geometry.
 void build_tables(const gkb_geometry *g, HostTables &t) {
   const int nx = g->nx, ny = g->ny, nv = g->n_views, nu = g->n_det_u;
   const long long m = (long long)nv * nu;
@@ -136,18 +138,12 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   t.w.resize(m);
   t.h.resize(m);
   t.meta.resize(m);
+  t.meta_bt.resize(m);
   if (fan) {
     t.t0.resize(m);
     t.dt.resize(m);
     t.dperp.resize(m);
     t.dpar.resize(m);
-    t.gcos.resize(nu);
-    t.gsin.resize(nu);
-    for (int k = 0; k < nu; ++k) {
-      const double gam = (k - off) * du;
-      t.gcos[k] = std::cos(gam);
-      t.gsin[k] = std::sin(gam);
-    }
   }
   t.p0.resize(nv);
   t.p1.resize(nv);
@@ -156,6 +152,7 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   t.p4.resize(nv);
   const double midy = 0.5 * (ny - 1), midx = 0.5 * (nx - 1);
   const double tan_dg = std::tan(du);
+  double hmax_bt = 0.0, hmax_at = 0.0;
   for (int v = 0; v < nv; ++v) {
     const double th = ang[v];
     const double c = std::cos(th), s = std::sin(th);
@@ -166,6 +163,7 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
       t.p2[v] = 1.0 / dd;
       t.p3[v] = du / dd;
       t.p4[v] = dd / du;
+      hmax_at = std::max(hmax_at, dd / du);
     } else {
       t.p0[v] = c;
       t.p1[v] = s;
@@ -215,23 +213,25 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
         t.dt[r] = dt;
         t.dperp[r] = dperp;
         t.dpar[r] = dpar;
-        // B^T candidates: |delta| < tan(dg) * along, |delta| = |dperp| |d|
+        // B^T candidates on a line: |delta| < tan(dg) * along, |delta| = |dperp| |d|
         const int nl = rowdom ? ny : nx;
         const double mid = rowdom ? midy : midx;
         const double al = std::max(std::fabs(t0 + (0 - mid) * dt), std::fabs(t0 + (nl - 1 - mid) * dt)) + 4.0;
-        h = tan_dg * al / (std::fabs(dperp) - tan_dg) * 1.0001 + 1e-6;
+        h = tan_dg * al / (std::fabs(dperp) - tan_dg) * 1.0001 + 1e-3;
       }
+      const int nl = rowdom ? ny : nx, len = rowdom ? nx : ny;
+      const double mid = rowdom ? midy : midx;
       int lo, hi;
-      if (rowdom)
-        line_range(cmid, slope, midy, ny, nx, std::max(h, 1.0), lo, hi);
-      else
-        line_range(cmid, slope, midx, nx, ny, std::max(h, 1.0), lo, hi);
+      line_range(cmid, slope, mid, nl, -1.0, (double)len, lo, hi);
+      t.meta[r] = lo | (hi << 15) | ((rowdom ? 1 : 0) << 30);
+      line_range(cmid, slope, mid, nl, -h, len - 1 + h, lo, hi);
+      t.meta_bt[r] = lo | (hi << 15) | ((rowdom ? 1 : 0) << 30);
       if (!rowdom) t.has_coldom = true;
       t.base[r] = cmid;
       t.slope[r] = slope;
       t.w[r] = w;
       t.h[r] = h;
-      t.meta[r] = lo | (hi << 15) | ((rowdom ? 1 : 0) << 30);
+      hmax_bt = std::max(hmax_bt, h);
     }
   }
   GeomDev &gd = t.gd;
@@ -246,54 +246,90 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   gd.D = g->src_dist;
   gd.off = off;
   gd.inv_du = 1.0 / du;
+  gd.tan_dg = tan_dg;
   gd.hmax_fan = (1.0 / du) * (1.0 + 1e-5);
+  if (fan) {
+    // A^T candidates: within asin(|d_dom| / |p - S|) of the pixel's fan angle
+    const double rc = std::sqrt(midx * midx + midy * midy);
+    const double z = 1.0 / (g->src_dist - rc);
+    hmax_at = gd.hmax_fan * z * (1.0 + z * z) + 1e-3;
+    gd.dd_spread = (hmax_at + 2.0) * du;
+    // |tan| of the largest pixel fan angle (pixel centres within rc of the centre)
+    const double tmax = rc / std::sqrt(g->src_dist * g->src_dist - rc * rc);
+    gd.fast_atan = tmax <= 0.5 ? 1 : 0;
+  }
+  gd.nc_bt = (int)std::floor(2.0 * hmax_bt) + 1;
+  gd.nc_at = (int)std::floor(2.0 * hmax_at) + 1;
+  gd.pad = gd.nc_bt + (int)std::ceil(hmax_bt) + 2;
+  gd.ldR = nx + 2 * gd.pad;
+  gd.ldT = ny + 2 * gd.pad;
+  gd.offT = (long long)ny * gd.ldR;
+  gd.pad_elems = gd.offT + (long long)nx * gd.ldT;
+  gd.uclamp_at = hmax_at + 1.0;
+  gd.padY = std::max(4, gd.nc_at + (int)std::ceil(2.0 * hmax_at) + 3);
+  gd.ldY = nu + 2 * gd.padY;
+  gd.ypad_elems = (long long)nv * gd.ldY;
+  if (fan) {
+    t.gcs.assign(2 * (size_t)gd.ldY, 0.0);
+    for (int k = 0; k < gd.ldY; ++k) t.gcs[2 * k] = 1.0;
+    for (int k = 0; k < nu; ++k) {
+      const double gam = (k - off) * du;
+      t.gcs[2 * (gd.padY + k)] = std::cos(gam);
+      t.gcs[2 * (gd.padY + k) + 1] = std::sin(gam);
+    }
+    t.wpad.assign(gd.ypad_elems, 0.0);
+    for (int v = 0; v < nv; ++v)
+      for (int k = 0; k < nu; ++k) t.wpad[(long long)v * gd.ldY + gd.padY + k] = t.w[(long long)v * nu + k];
+  }
 }
 
 template <typename T>
 hipError_t upload_tables(const HostTables &h, DevTables &d) {
   const long long m = h.gd.m;
-  const int nv = h.gd.nv, nu = h.gd.nu;
+  const int nv = h.gd.nv;
   const bool fan = h.gd.kind == GKB_FAN2D;
-  // layout: 8 per-ray T arrays, meta, 5 per-view arrays, 2 per-bin arrays
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t rayT = al(sizeof(T) * m), rayI = al(sizeof(int) * m), viewT = al(sizeof(T) * nv),
-               binT = al(sizeof(T) * nu);
-  const size_t total = 8 * rayT + rayI + 5 * viewT + 2 * binT;
+               binT = al(sizeof(T) * 2 * h.gd.ldY), wpT = al(sizeof(T) * (fan ? h.gd.ypad_elems : 1));
+  const size_t total = 8 * rayT + 2 * rayI + 5 * viewT + binT + wpT;
   hipError_t e = d.buf.ensure(total);
   if (e != hipSuccess) return e;
   char *p = d.buf.as<char>();
   std::vector<T> tmp;
-  auto put = [&](const std::vector<double> &src, size_t stride, size_t count) -> const T * {
+  auto put = [&](const std::vector<double> &src, size_t stride) -> const T * {
     T *dst = reinterpret_cast<T *>(p);
     p += stride;
     if (src.empty()) return dst;
-    tmp.assign(count, T(0));
-    for (size_t i = 0; i < count; ++i) tmp[i] = (T)src[i];
-    (void)hipMemcpy(dst, tmp.data(), sizeof(T) * count, hipMemcpyHostToDevice);
+    tmp.assign(src.size(), T(0));
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+    (void)hipMemcpy(dst, tmp.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return dst;
+  };
+  auto put_i = [&](const std::vector<int> &src) -> const int * {
+    int *dst = reinterpret_cast<int *>(p);
+    p += rayI;
+    (void)hipMemcpy(dst, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice);
     return dst;
   };
   RayTab<T> rt{};
   ViewTab<T> vt{};
-  rt.base = put(h.base, rayT, m);
-  rt.slope = put(h.slope, rayT, m);
-  rt.w = put(h.w, rayT, m);
-  rt.h = put(h.h, rayT, m);
-  rt.t0 = put(h.t0, rayT, fan ? m : 0);
-  rt.dt = put(h.dt, rayT, fan ? m : 0);
-  rt.dperp = put(h.dperp, rayT, fan ? m : 0);
-  rt.dpar = put(h.dpar, rayT, fan ? m : 0);
-  int *meta = reinterpret_cast<int *>(p);
-  p += rayI;
-  e = hipMemcpy(meta, h.meta.data(), sizeof(int) * m, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return e;
-  rt.meta = meta;
-  vt.p0 = put(h.p0, viewT, nv);
-  vt.p1 = put(h.p1, viewT, nv);
-  vt.p2 = put(h.p2, viewT, nv);
-  vt.p3 = put(h.p3, viewT, nv);
-  vt.p4 = put(h.p4, viewT, nv);
-  vt.gcos = put(h.gcos, binT, fan ? nu : 0);
-  vt.gsin = put(h.gsin, binT, fan ? nu : 0);
+  rt.base = put(h.base, rayT);
+  rt.slope = put(h.slope, rayT);
+  rt.w = put(h.w, rayT);
+  rt.h = put(h.h, rayT);
+  rt.t0 = put(h.t0, rayT);
+  rt.dt = put(h.dt, rayT);
+  rt.dperp = put(h.dperp, rayT);
+  rt.dpar = put(h.dpar, rayT);
+  rt.meta = put_i(h.meta);
+  rt.meta_bt = put_i(h.meta_bt);
+  vt.p0 = put(h.p0, viewT);
+  vt.p1 = put(h.p1, viewT);
+  vt.p2 = put(h.p2, viewT);
+  vt.p3 = put(h.p3, viewT);
+  vt.p4 = put(h.p4, viewT);
+  vt.gcos = put(h.gcs, binT);
+  rt.wpad = put(h.wpad, wpT);
   if constexpr (sizeof(T) == 4) {
     d.rt32 = rt;
     d.vt32 = vt;
@@ -339,7 +375,7 @@ struct gkb_ctx {
   bool own_stream = false;
   std::map<std::string, std::unique_ptr<DevTables>> tables;
   // scratch for standalone projector calls and reductions
-  DevBuf xT, partials, counters;
+  DevBuf xpad, ypad, partials, counters;
   // solve workspace
   DevBuf Q, Y, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
   int *host_flag = nullptr;      // host-mapped
@@ -432,6 +468,11 @@ gkb_status get_tables(gkb_ctx *c, const gkb_geometry *g, int dtype, DevTables **
   }
   HostTables h;
   build_tables(g, h);
+  if (h.gd.nc_bt > 8 || h.gd.nc_at > 8)
+    return fail(GKB_EUNSUPPORTED, "detector pitch too fine relative to the pixel pitch (more than 8 "
+                                  "interpolation candidates per line)");
+  if (h.gd.pad_elems >= (1LL << 31) || h.gd.ypad_elems >= (1LL << 31))
+    return fail(GKB_EUNSUPPORTED, "image or sinogram too large for 32-bit offsets");
   auto d = std::make_unique<DevTables>();
   hipError_t e = (dtype == GKB_F32) ? upload_tables<float>(h, *d) : upload_tables<double>(h, *d);
   if (e == hipErrorOutOfMemory) return fail(GKB_ENOMEM, "out of device memory for geometry tables");
@@ -483,8 +524,9 @@ Epi<T> plain_epi() {
   return e;
 }
 
-gkb_status ensure_scratch(gkb_ctx *c, size_t xT_bytes, long long nblocks_times_cols) {
-  HIPC(c->xT.ensure(std::max<size_t>(xT_bytes, 256)));
+gkb_status ensure_scratch(gkb_ctx *c, const GeomDev &g, size_t elem, long long nblocks_times_cols) {
+  HIPC(c->xpad.ensure(elem * (size_t)g.pad_elems));
+  HIPC(c->ypad.ensure(2 * elem * (size_t)g.ypad_elems));
   HIPC(c->partials.ensure(sizeof(double) * std::max<long long>(nblocks_times_cols, 1024)));
   if (!c->counters.p) {
     HIPC(c->counters.ensure(256 * sizeof(unsigned)));
@@ -500,33 +542,36 @@ template <typename T>
 gkb_status apply_op(gkb_ctx *c, const DevTables &d, int op, const void *in, void *out) {
   const GeomDev &g = d.gd;
   const long long nb = std::max<long long>(std::max(ray_blocks(g), pixel_blocks(g)), 1);
-  gkb_status st = ensure_scratch(c, sizeof(T) * (size_t)g.n, nb);
+  gkb_status st = ensure_scratch(c, g, sizeof(T), nb);
   if (st != GKB_OK) return st;
   Epi<T> e = plain_epi<T>();
   const T *xi = static_cast<const T *>(in);
   T *xo = static_cast<T *>(out);
-  T *xT = c->xT.as<T>();
+  T *xpad = c->xpad.as<T>();
+  T *ypad = c->ypad.as<T>();
   switch (op) {
     case OP_A: {
-      if (d.has_coldom) launch_transpose<T>(col<const T>(xi), xT, g.nx, g.ny, nullptr, c->stream);
+      launch_pad_image<T>(g, col<const T>(xi), xpad, d.has_coldom, nullptr, c->stream);
       TraceScope ts(c, "fwd");
-      launch_fwd<T>(g, rt_of<T>(d), col<const T>(xi), xT, col<T>(xo), e, nullptr, c->stream);
+      launch_fwd<T>(g, rt_of<T>(d), xpad, col<T>(xo), e, nullptr, c->stream);
       break;
     }
     case OP_BT: {
-      if (d.has_coldom) launch_transpose<T>(col<const T>(xi), xT, g.nx, g.ny, nullptr, c->stream);
+      launch_pad_image<T>(g, col<const T>(xi), xpad, d.has_coldom, nullptr, c->stream);
       TraceScope ts(c, "back_adj");
-      launch_back_adj<T>(g, rt_of<T>(d), col<const T>(xi), xT, col<T>(xo), e, nullptr, c->stream);
+      launch_back_adj<T>(g, rt_of<T>(d), xpad, col<T>(xo), e, nullptr, c->stream);
       break;
     }
     case OP_B: {
+      launch_pad_sino<T>(g, col<const T>(xi), ypad, nullptr, c->stream);
       TraceScope ts(c, "back");
-      launch_back<T>(g, vt_of<T>(d), rt_of<T>(d), col<const T>(xi), xo, e, nullptr, c->stream);
+      launch_back<T>(g, vt_of<T>(d), ypad, xo, e, nullptr, c->stream);
       break;
     }
     case OP_AT: {
+      launch_pad_sino_adj<T>(g, rt_of<T>(d), col<const T>(xi), ypad, nullptr, c->stream);
       TraceScope ts(c, "fwd_adj");
-      launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), col<const T>(xi), xo, e, nullptr, c->stream);
+      launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), ypad, xo, e, nullptr, c->stream);
       break;
     }
   }
@@ -557,7 +602,9 @@ struct Solver {
   int mode;
   int K;
   long long n, m, dimq, dims;
-  T *Q = nullptr, *Y = nullptr, *s = nullptr, *w = nullptr, *tn = nullptr, *tm = nullptr, *xT = nullptr;
+  long long ldq, ldy;  // column strides of Q and Y (multiples of 4)
+  T *Q = nullptr, *Y = nullptr, *s = nullptr, *w = nullptr, *tn = nullptr, *tm = nullptr;
+  T *xpad = nullptr, *ypad = nullptr;
   Ctl ctl{};
   double *partials = nullptr;
   unsigned *counters = nullptr;
@@ -569,14 +616,16 @@ struct Solver {
     n = g.n;
     m = g.m;
     dimq = (mode == MODE_AB) ? m : n;
+    ldq = (dimq + 3) / 4 * 4;
+    ldy = (m + 3) / 4 * 4;
     dims = (mode == MODE_BA) ? n : m;
     st = c->stream;
   }
 
   gkb_status alloc() {
     const long long ldG = K + 2;
-    HIPC(c->Q.ensure(sizeof(T) * (size_t)dimq * (K + 1)));
-    HIPC(c->Y.ensure(sizeof(T) * (size_t)m * (K + 1)));
+    HIPC(c->Q.ensure(sizeof(T) * (size_t)ldq * (K + 1)));
+    HIPC(c->Y.ensure(sizeof(T) * (size_t)ldy * (K + 1)));
     HIPC(c->s.ensure(sizeof(T) * (size_t)dims));
     HIPC(c->w.ensure(sizeof(T) * (size_t)dimq));
     HIPC(c->tmp_n.ensure(sizeof(T) * (size_t)n));
@@ -587,7 +636,7 @@ struct Solver {
     const long long vb = std::max<long long>(
         {(long long)vec_blocks(dimq), (long long)vec_blocks(m), (long long)vec_blocks(dims)});
     const long long pb = std::max<long long>({(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2)});
-    gkb_status stt = ensure_scratch(c, sizeof(T) * (size_t)n, pb);
+    gkb_status stt = ensure_scratch(c, g, sizeof(T), pb);
     if (stt != GKB_OK) return stt;
     if (!c->host_flag) {
       HIPC(hipHostMalloc((void **)&c->host_flag, sizeof(int) * 4, hipHostMallocMapped));
@@ -599,7 +648,8 @@ struct Solver {
     w = c->w.as<T>();
     tn = c->tmp_n.as<T>();
     tm = c->tmp_m.as<T>();
-    xT = c->xT.as<T>();
+    xpad = c->xpad.as<T>();
+    ypad = c->ypad.as<T>();
     double *dp = c->ctl_d.as<double>();
     ctl.ip = c->ctl_i.as<int>();
     ctl.dp = dp;
@@ -630,27 +680,29 @@ struct Solver {
   }
 
   // column i (0-based, shifted by the device counter k) of Q / Y
-  Col<const T> qcol(int off) const { return colk<const T>(Q, dimq, off, kp); }
-  Col<T> ycol(int off) const { return colk<T>(Y, m, off, kp); }
+  Col<const T> qcol(int off) const { return colk<const T>(Q, ldq, off, kp); }
+  Col<T> ycol(int off) const { return colk<T>(Y, ldy, off, kp); }
 
   // ----- the four projectors with device-addressed operands -----
   void A(Col<const T> in, Col<T> out, const Epi<T> &e) {
-    if (d.has_coldom) launch_transpose<T>(in, xT, g.nx, g.ny, stop, st);
+    launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
     TraceScope ts(c, "fwd");
-    launch_fwd<T>(g, rt_of<T>(d), in, xT, out, e, stop, st);
+    launch_fwd<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
   }
   void Bt(Col<const T> in, Col<T> out, const Epi<T> &e) {
-    if (d.has_coldom) launch_transpose<T>(in, xT, g.nx, g.ny, stop, st);
+    launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
     TraceScope ts(c, "back_adj");
-    launch_back_adj<T>(g, rt_of<T>(d), in, xT, out, e, stop, st);
+    launch_back_adj<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
   }
   void B(Col<const T> in, T *out, const Epi<T> &e) {
+    launch_pad_sino<T>(g, in, ypad, stop, st);
     TraceScope ts(c, "back");
-    launch_back<T>(g, vt_of<T>(d), rt_of<T>(d), in, out, e, stop, st);
+    launch_back<T>(g, vt_of<T>(d), ypad, out, e, stop, st);
   }
   void At(Col<const T> in, T *out, const Epi<T> &e) {
+    launch_pad_sino_adj<T>(g, rt_of<T>(d), in, ypad, stop, st);
     TraceScope ts(c, "fwd_adj");
-    launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), in, out, e, stop, st);
+    launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), ypad, out, e, stop, st);
   }
 
   // s~ <- M q_k - alpha_k/t_k s~ (s stored unnormalised, s_k = s~/t_k); t_{k+1}; Y_k
@@ -661,7 +713,7 @@ struct Solver {
     e.norm_to_t = 1;
     if (mode == MODE_BA) {  // Y_k = A q_k ; s~ = B Y_k - ...
       A(qcol(-1), ycol(0), plain_epi<T>());
-      B(colk<const T>(Y, m, 0, kp), s, e);
+      B(colk<const T>(Y, ldy, 0, kp), s, e);
     } else if (mode == MODE_AB) {  // Y_k = A B q_k ; s~ = Y_k - ...
       B(qcol(-1), tn, plain_epi<T>());
       e.out_raw = ycol(0);
@@ -700,7 +752,7 @@ struct Solver {
     reorth_and_normalize_impl(reorth);
     {
       TraceScope ts(c, "gram");
-      launch_gram<T>(ctl, Y, m, m, 0, partials, counters, st);
+      launch_gram<T>(ctl, Y, ldy, m, 0, partials, counters, st);
     }
     {
       TraceScope ts(c, "small_solve");
@@ -711,14 +763,15 @@ struct Solver {
   void reorth_and_normalize_impl(bool reorth) {
     TraceScope ts(c, "reorth");
     if (reorth) {
-      launch_cgs_dots<T>(ctl, Q, dimq, w, dimq, partials, counters, st);
-      launch_cgs_update<T>(ctl, Q, dimq, w, dimq, 0, partials, counters, st);
-      launch_cgs_update<T>(ctl, Q, dimq, w, dimq, 1, partials, counters, st);
+      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, counters, st);
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, counters, st);
+      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, counters, st);
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, counters, st);
     } else {
       // no reorthogonalisation: only the norm (zero previous columns)
       launch_norm_to<T>(ctl, w, dimq, NORM_ALPHA1, partials, counters, st);
     }
-    launch_normalize<T>(ctl, w, Q, dimq, dimq, st);
+    launch_normalize<T>(ctl, w, Q, ldq, dimq, st);
   }
 };
 
@@ -751,7 +804,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
 
   // start-up (k = 0): Y_0 = b, G_00 = ||b||^2; s~_1 = rhs, t_1; q_1, alpha_1
   launch_copy<T>(b, S.Y, g.m, st);
-  launch_gram<T>(S.ctl, S.Y, g.m, g.m, 1, S.partials, S.counters, st);
+  launch_gram<T>(S.ctl, S.Y, S.ldy, g.m, 1, S.partials, S.counters, st);
   if (mode == MODE_BA) {
     Epi<T> e = S.epi();
     e.norm_to_t = 1;
@@ -762,7 +815,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   }
   S.apply_Mt(true);
   launch_norm_to<T>(S.ctl, S.w, S.dimq, NORM_ALPHA1, S.partials, S.counters, st);
-  launch_normalize<T>(S.ctl, S.w, S.Q, S.dimq, S.dimq, st);
+  launch_normalize<T>(S.ctl, S.w, S.Q, S.ldq, S.dimq, st);
   HIPC(hipGetLastError());
   double h3[3];
   HIPC(hipMemcpyAsync(&h3[0], S.ctl.t + 1, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -803,12 +856,13 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     HIPC(hipGetLastError());
     // solution x = Q_k u_k (BA, matched) or B (Q_k u_k) (AB)
     if (mode == MODE_AB) {
-      launch_solution<T>(S.ctl, S.Q, S.dimq, S.dimq, S.tm, st);
+      launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, S.tm, st);
       Epi<T> e = plain_epi<T>();
+      launch_pad_sino<T>(g, col<const T>(S.tm), S.ypad, nullptr, st);
       TraceScope ts(c, "back");
-      launch_back<T>(g, vt_of<T>(*d), rt_of<T>(*d), col<const T>(S.tm), x, e, nullptr, st);
+      launch_back<T>(g, vt_of<T>(*d), S.ypad, x, e, nullptr, st);
     } else {
-      launch_solution<T>(S.ctl, S.Q, S.dimq, S.dimq, x, st);
+      launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, x, st);
     }
     HIPC(hipGetLastError());
     int hi[CI_COUNT];

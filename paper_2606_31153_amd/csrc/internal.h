@@ -95,13 +95,16 @@ struct RayTab {        // per ray, m entries: ray-driven kernels (A, B^T)
   const T *base;       // crossing coordinate (pixel index units) at the middle line
   const T *slope;      // d(crossing)/d(line)
   const T *w;          // 1/|d_dom|
-  const int *meta;     // lo | hi << 15 | rowdom << 30
+  const int *meta;     // lines of A: lo | hi << 15 | rowdom << 30
+  const int *meta_bt;  // lines of B^T: lo | hi << 15 | rowdom << 30
   const T *h;          // B^T candidate half-width (pixel index units)
   // fan-beam B^T
   const T *t0;         // distance from the source to the crossing at the middle line
   const T *dt;         // its change per line
   const T *dperp;      // signed perpendicular-distance change per unit offset along the line
   const T *dpar;       // along-ray distance change per unit offset along the line
+  // fan-beam A^T: 1/|d_dom| per ray in padded sinogram layout (zeros in the pads)
+  const T *wpad;
 };
 
 template <typename T>
@@ -111,8 +114,7 @@ struct ViewTab {       // per view (pixel-driven kernels B, A^T)
   const T *p2;         // PAR: 1/|d_dom|
   const T *p3;         // PAR: du/|d_dom| (A^T hat slope in bins)
   const T *p4;         // PAR: |d_dom|/du (A^T hat half-width in bins)
-  const T *gcos;       // FAN: cos(gamma_k) [n_det]
-  const T *gsin;       // FAN: sin(gamma_k) [n_det]
+  const T *gcos;       // FAN: (cos(gamma_k), sin(gamma_k)) pairs, padded like a sinogram row [2 (n_det + 2 padY)]
 };
 
 struct GeomDev {
@@ -123,23 +125,43 @@ struct GeomDev {
   double D;            // source distance (fan)
   double off;          // (nu-1)/2
   double inv_du;
-  double hmax_fan;     // fan A^T candidate half-width numerator bound
+  double hmax_fan;     // fan A^T: candidate half-width per unit asin(|d_dom|/|p-S|), in bins
+  double tan_dg;       // fan B^T: tan(bin pitch)
+  double dd_spread;    // fan A^T: bound on the |d_dom| change across the candidate rays
+  int fast_atan;       // fan, float: every pixel's fan angle has |tan| <= 0.5
+  // padded image: row-major region (ny lines of ldR = nx + 2 pad), then the
+  // column-major region at offT (nx lines of ldT = ny + 2 pad)
+  int pad, ldR, ldT;
+  long long offT;
+  long long pad_elems;
+  // padded sinogram: nv lines of ldY = nu + 2 padY
+  int padY, ldY;
+  long long ypad_elems;
+  int nc_bt;           // B^T candidates per line
+  int nc_at;           // A^T candidate bins per view
+  double uclamp_at;    // A^T: detector coordinates are clamped to [-uclamp_at, nu-1+uclamp_at]
 };
 
 // ---- launchers (proj2d.hip) ----
 template <typename T>
-void launch_transpose(Col<const T> x, T *xT, int nx, int ny, const int *stop, hipStream_t s);
+void launch_pad_image(const GeomDev &g, Col<const T> x, T *pad, bool cols, const int *stop, hipStream_t s);
 template <typename T>
-void launch_fwd(const GeomDev &g, const RayTab<T> &rt, Col<const T> x, const T *xT, Col<T> y, const Epi<T> &e,
-                const int *stop, hipStream_t s);
+void launch_pad_sino(const GeomDev &g, Col<const T> y, T *pad, const int *stop, hipStream_t s);
+// input of A^T: the padded sinogram, or for fan beam (w y, w) pairs (2x the elements)
 template <typename T>
-void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, Col<const T> x, const T *xT, Col<T> y,
-                     const Epi<T> &e, const int *stop, hipStream_t s);
+void launch_pad_sino_adj(const GeomDev &g, const RayTab<T> &rt, Col<const T> y, T *pad, const int *stop,
+                         hipStream_t s);
 template <typename T>
-void launch_back(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, Col<const T> y, T *x,
-                 const Epi<T> &e, const int *stop, hipStream_t s);
+void launch_fwd(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e, const int *stop,
+                hipStream_t s);
 template <typename T>
-void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, Col<const T> y, T *x,
+void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e,
+                     const int *stop, hipStream_t s);
+template <typename T>
+void launch_back(const GeomDev &g, const ViewTab<T> &vt, const T *ypad, T *x, const Epi<T> &e, const int *stop,
+                 hipStream_t s);
+template <typename T>
+void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, const T *ypad, T *x,
                     const Epi<T> &e, const int *stop, hipStream_t s);
 int pixel_blocks(const GeomDev &g);
 int ray_blocks(const GeomDev &g);

@@ -20,6 +20,8 @@
 // for lambda); this gives the same minimiser as the SVD route of the paper
 // in O(k) work per iteration.
 
+#include <algorithm>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -27,9 +29,9 @@ namespace gkb {
 
 namespace {
 
-constexpr int CH = 8;  // columns per pass of the multi-dot loops
-
-int g_max_vec_blocks = 512;
+constexpr int CH = 16;  // columns per workgroup in the multi-dot kernels
+constexpr int RPT = 4;  // rows per thread (one 4-wide vector load)
+constexpr int ROWS_PER_BLOCK = kBlock * RPT;
 
 // Sum CH values over the block; results valid in threads 0..CH-1 (value j in thread j).
 __device__ inline double block_sum_vec(double (&v)[CH], double *lds /* [4][CH] */) {
@@ -50,87 +52,136 @@ __device__ inline double block_sum_vec(double (&v)[CH], double *lds /* [4][CH] *
   return r;
 }
 
-// Partial inner products of w with columns [0, ncol) of V over this block's
-// rows, written to partials[blockIdx.x * ldp + c].
+// Rows r..r+3 of a column (zeros past dim).  Columns are stored with a
+// leading dimension that is a multiple of 4, so full quads are aligned.
 template <typename T>
-__device__ inline void block_dots(const T *__restrict__ V, long long ld, int ncol, const T *__restrict__ w,
-                                  long long dim, double *partials, int ldp, double *lds) {
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (int c0 = 0; c0 < ncol; c0 += CH) {
-    double acc[CH];
+__device__ inline void load_quad(const T *__restrict__ p, long long r, long long dim, double (&q)[RPT]) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  if (r + RPT <= dim) {
+    const v4 v = *reinterpret_cast<const v4 *>(p + r);
+    q[0] = (double)v.x;
+    q[1] = (double)v.y;
+    q[2] = (double)v.z;
+    q[3] = (double)v.w;
+  } else {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) acc[j] = 0.0;
-    for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < dim; r += stride) {
-      const double wv = (double)w[r];
-#pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (c0 + j < ncol) acc[j] = fma((double)V[(long long)(c0 + j) * ld + r], wv, acc[j]);
-    }
-    const double s = block_sum_vec(acc, lds);
-    if (threadIdx.x < CH && c0 + (int)threadIdx.x < ncol) partials[(long long)blockIdx.x * ldp + c0 + threadIdx.x] = s;
+    for (int i = 0; i < RPT; ++i) q[i] = (r + i < dim) ? (double)p[r + i] : 0.0;
   }
 }
 
-// Last block: out[c] = sum over blocks of partials[b*ldp + c], fixed order.
-__device__ inline void finish_dots(int ncol, const double *partials, int ldp, double *out, long long out_stride,
-                                   double *out2, long long out2_stride) {
-  const unsigned nb = gridDim.x;
-  for (int c = threadIdx.x; c < ncol; c += kBlock) {
-    double acc = 0.0;
-    for (unsigned b = 0; b < nb; ++b) acc += partials[(long long)b * ldp + c];
-    out[(long long)c * out_stride] = acc;
-    if (out2) out2[(long long)c * out2_stride] = acc;
+template <typename T>
+__device__ inline void store_quad(T *__restrict__ p, long long r, long long dim, const T (&q)[RPT]) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  if (r + RPT <= dim) {
+    v4 v;
+    v.x = q[0];
+    v.y = q[1];
+    v.z = q[2];
+    v.w = q[3];
+    *reinterpret_cast<v4 *>(p + r) = v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (r + i < dim) p[r + i] = q[i];
   }
 }
 
-// ---- c = Q[:, 0..k-1]^T w -------------------------------------------------
+// ---- partial inner products: workgroup (x, y) covers rows [x*1024, x*1024+1024)
+// and columns [16 y, 16 y + 16) of V, against w.  gram == 0: columns 0..k-1 of
+// Q against w (reorthogonalisation); gram == 1: columns 0..k of Y against
+// Y_k (Gram row k).  Result: partials[x * ldp + column].
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cgs_dots(Ctl ctl, const T *__restrict__ Q, long long ld,
-                                                     const T *__restrict__ w, long long dim, double *partials,
-                                                     unsigned *counter) {
+__global__ __launch_bounds__(kBlock) void k_dots(Ctl ctl, const T *__restrict__ V, long long ld,
+                                                 const T *__restrict__ w, long long dim, double *partials, int gram) {
   if (ctl.ip[CI_STOP]) return;
-  __shared__ double lds[(kBlock / 64) * CH];
   const int k = ctl.ip[CI_K];
+  const int ncol = gram ? k + 1 : k;
+  const int c0 = blockIdx.y * CH;
+  if (c0 >= ncol) return;
+  __shared__ double lds[(kBlock / 64) * CH];
+  const T *__restrict__ wv = gram ? V + (long long)k * ld : w;
+  const long long r = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  double wq[RPT];
+  load_quad(wv, r, dim, wq);
+  double acc[CH];
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    acc[j] = 0.0;
+    if (c0 + j < ncol) {
+      double q[RPT];
+      load_quad(V + (long long)(c0 + j) * ld, r, dim, q);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) acc[j] = fma(q[i], wq[i], acc[j]);
+    }
+  }
+  const double sum = block_sum_vec(acc, lds);
+  if (threadIdx.x < CH && c0 + (int)threadIdx.x < ncol)
+    partials[(long long)blockIdx.x * (ctl.K + 2) + c0 + threadIdx.x] = sum;
+}
+
+// ---- column sums of the per-workgroup partials: one workgroup per column ----
+// which == 0: c[col] (col < k);  which == 1: Gram row k, G[k][col] = G[col][k] (col <= k)
+__global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *__restrict__ partials, int nb,
+                                                        int which) {
+  if (ctl.ip[CI_STOP]) return;
+  __shared__ double lds[kBlock / 64];
+  const int k = ctl.ip[CI_K];
+  const int col = blockIdx.x;
+  const int ncol = which == 0 ? k : k + 1;
+  if (col >= ncol) return;
   const int ldp = ctl.K + 2;
-  block_dots(Q, ld, k, w, dim, partials, ldp, lds);
-  if (arrive_last(counter, gridDim.x)) {
-    finish_dots(k, partials, ldp, ctl.c, 1, nullptr, 0);
-    if (threadIdx.x == 0) *counter = 0u;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += partials[(long long)b * ldp + col];
+  const double tot = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) {
+    if (which == 0) {
+      ctl.c[col] = tot;
+    } else {
+      ctl.G[(long long)k * ctl.ldG + col] = tot;
+      ctl.G[(long long)col * ctl.ldG + k] = tot;
+    }
   }
 }
 
-// ---- w -= Q c; then (last == 0) c = Q^T w, or (last == 1) alpha[k+1] = ||w|| ----
+// ---- w -= Q[:, 0..k-1] c (FP64 per element); last == 1: alpha[k+1] = ||w|| ----
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restrict__ Q, long long ld,
                                                        T *__restrict__ w, long long dim, int last,
                                                        double *partials, unsigned *counter) {
   if (ctl.ip[CI_STOP]) return;
-  __shared__ double lds[(kBlock / 64) * CH];
+  __shared__ double lds[kBlock / 64];
   const int k = ctl.ip[CI_K];
-  const int ldp = ctl.K + 2;
-  const long long stride = (long long)gridDim.x * kBlock;
   const double *__restrict__ cc = ctl.c;
-  double nrm = 0.0;
-  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < dim; r += stride) {
-    double acc = (double)w[r];
-    for (int c = 0; c < k; ++c) acc = fma(-cc[c], (double)Q[(long long)c * ld + r], acc);
-    const T v = (T)acc;
-    w[r] = v;
-    nrm = fma((double)v, (double)v, nrm);
-  }
-  if (!last) {
-    block_dots(Q, ld, k, (const T *)w, dim, partials, ldp, lds);
-    if (arrive_last(counter, gridDim.x)) {
-      finish_dots(k, partials, ldp, ctl.c, 1, nullptr, 0);
-      if (threadIdx.x == 0) *counter = 0u;
+  const long long r = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  double acc[RPT];
+  load_quad(w, r, dim, acc);
+  for (int c0 = 0; c0 < k; c0 += CH) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if (c0 + j < k) {
+        double q[RPT];
+        load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
+        const double cj = cc[c0 + j];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) acc[i] = fma(-cj, q[i], acc[i]);
+      }
     }
-  } else {
+  }
+  T out[RPT];
+  double nrm = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    out[i] = (T)acc[i];
+    nrm = fma((double)out[i], (double)out[i], nrm);
+  }
+  if (r < dim) store_quad(w, r, dim, out);
+  if (last) {
     const double s = block_sum<kBlock>(nrm, lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
     if (arrive_last(counter, gridDim.x)) {
-      double acc = 0.0;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock) acc += partials[b];
-      const double tot = block_sum<kBlock>(acc, lds);
+      double a = 0.0;
+      for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock) a += partials[b];
+      const double tot = block_sum<kBlock>(a, lds);
       if (threadIdx.x == 0) {
         ctl.alpha[k + 1] = sqrt(tot);
         *counter = 0u;
@@ -147,34 +198,32 @@ __global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restri
   const int k = ctl.ip[CI_K];
   const double inv = 1.0 / ctl.alpha[k + 1];
   T *q = Q + (long long)k * ld;
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < dim; r += stride)
-    q[r] = (T)((double)w[r] * inv);
-}
-
-// ---- Gram row k: G[k][c] = G[c][k] = Y_k . Y_c, c = 0..k (Y_0 = b) ------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gram(Ctl ctl, const T *__restrict__ Y, long long ld, long long dim,
-                                                 double *partials, unsigned *counter) {
-  if (ctl.ip[CI_STOP]) return;
-  __shared__ double lds[(kBlock / 64) * CH];
-  const int k = ctl.ip[CI_K];
-  const int ldp = ctl.K + 2;
-  block_dots(Y, ld, k + 1, Y + (long long)k * ld, dim, partials, ldp, lds);
-  if (arrive_last(counter, gridDim.x)) {
-    finish_dots(k + 1, partials, ldp, ctl.G + (long long)k * ctl.ldG, 1, ctl.G + k, ctl.ldG);
-    if (threadIdx.x == 0) *counter = 0u;
-  }
+  const long long r = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  if (r >= dim) return;
+  double v[RPT];
+  load_quad(w, r, dim, v);
+  T out[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) out[i] = (T)(v[i] * inv);
+  store_quad(q, r, dim, out);
 }
 
 // ---- projected solve, discrepancy test, advance --------------------------------
-// One wavefront.  Iteration k has alpha[1..k], t[1..k+1] (and alpha[k+1]
-// unless k == K).  Givens rotations G = [[c, s], [-s, c]] reduce
-// [C_k; lambda I] to upper bidiagonal R (diagonal Rd, superdiagonal Rth) with
-// right-hand side Rphi; u_k solves R u = Rphi.
-__global__ __launch_bounds__(64) void k_small_solve(Ctl ctl) {
+// Iteration k has alpha[1..k], t[1..k+1] (and alpha[k+1] unless k == K).
+// Givens rotations G = [[c, s], [-s, c]] reduce [C_k; lambda I] to upper
+// bidiagonal R (diagonal Rd, superdiagonal Rth) with right-hand side Rphi;
+// u_k solves R u = Rphi.  The quantities the serial steps touch are staged in
+// LDS; the quadratic form of the residual is spread over the workgroup.
+constexpr int kSolveThreads = 256;
+constexpr int kMaxKLds = 4096;
+
+__global__ __launch_bounds__(kSolveThreads) void k_small_solve(Ctl ctl) {
   if (ctl.ip[CI_STOP]) return;
-  __shared__ double s_u[1];
+  __shared__ double s_u[kMaxKLds + 2];
+  __shared__ double s_rd[kMaxKLds + 2];
+  __shared__ double s_rth[kMaxKLds + 2];
+  __shared__ double s_rphi[kMaxKLds + 2];
+  __shared__ double s_red[kSolveThreads / 64];
   const int k = ctl.ip[CI_K];
   double *dp = ctl.dp;
   if (threadIdx.x == 0) {
@@ -204,39 +253,49 @@ __global__ __launch_bounds__(64) void k_small_solve(Ctl ctl) {
     const double c = rhat / rk, s = tk1 / rk;
     ctl.Rd[k] = rk;
     ctl.Rphi[k] = c * phibar;
-    const double phibar_next = -s * phibar;
     dp[CD_CPREV] = c;
     dp[CD_SPREV] = s;
-    dp[CD_PHIBAR] = phibar_next;
-    // back substitution
-    double un = ctl.Rphi[k] / ctl.Rd[k];
-    ctl.u[k] = un;
-    for (int i = k - 1; i >= 1; --i) {
-      un = (ctl.Rphi[i] - ctl.Rth[i + 1] * un) / ctl.Rd[i];
-      ctl.u[i] = un;
-    }
-    // projected residual ||C_k u - t_1 e_1|| (without the Tikhonov rows):
-    // row i of C_k u is alpha_i u_i + t_i u_{i-1}
-    double pr = 0.0;
-    for (int i = 1; i <= k + 1; ++i) {
-      double r = (i <= k ? ctl.alpha[i] * ctl.u[i] : 0.0) + (i >= 2 ? ctl.t[i] * ctl.u[i - 1] : 0.0);
-      if (i == 1) r -= ctl.t[1];
-      pr = fma(r, r, pr);
-    }
-    dp[CD_PRES] = sqrt(pr);
-    ctl.pres[k] = dp[CD_PRES];
+    dp[CD_PHIBAR] = -s * phibar;
   }
   __syncthreads();
-  // ||Y u - b||^2 = sum_ij u_i u_j G_ij - 2 sum_i u_i G_i0 + G_00  (i, j = 1..k)
-  double part = 0.0;
-  for (int i = 1 + threadIdx.x; i <= k; i += 64) {
-    const double *Gi = ctl.G + (long long)i * ctl.ldG;
-    double acc = -2.0 * Gi[0];
-    for (int j = 1; j <= k; ++j) acc = fma(Gi[j], ctl.u[j], acc);
-    part = fma(ctl.u[i], acc, part);
+  for (int i = 1 + threadIdx.x; i <= k; i += kSolveThreads) {
+    s_rd[i] = ctl.Rd[i];
+    s_rth[i] = ctl.Rth[i];
+    s_rphi[i] = ctl.Rphi[i];
   }
-  part = wave_sum(part);
+  __syncthreads();
+  // back substitution R u = Rphi (serial, operands in LDS)
   if (threadIdx.x == 0) {
+    double un = s_rphi[k] / s_rd[k];
+    s_u[k] = un;
+    for (int i = k - 1; i >= 1; --i) {
+      un = (s_rphi[i] - s_rth[i + 1] * un) / s_rd[i];
+      s_u[i] = un;
+    }
+    s_u[0] = 0.0;
+    s_u[k + 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = 1 + threadIdx.x; i <= k; i += kSolveThreads) ctl.u[i] = s_u[i];
+  // projected residual ||C_k u - t_1 e_1||: row i of C_k u is alpha_i u_i + t_i u_{i-1}
+  double pr = 0.0;
+  for (int i = 1 + threadIdx.x; i <= k + 1; i += kSolveThreads) {
+    double r = (i <= k ? ctl.alpha[i] * s_u[i] : 0.0) + (i >= 2 ? ctl.t[i] * s_u[i - 1] : 0.0);
+    if (i == 1) r -= ctl.t[1];
+    pr = fma(r, r, pr);
+  }
+  pr = block_sum<kSolveThreads>(pr, s_red);
+  // ||Y u - b||^2 = sum_j u_j (sum_i u_i G_ij) - 2 sum_j u_j G_0j + G_00 (i, j = 1..k)
+  double part = 0.0;
+  for (int j = 1 + threadIdx.x; j <= k; j += kSolveThreads) {
+    double sj = -2.0 * ctl.G[j];
+    for (int i = 1; i <= k; ++i) sj = fma(s_u[i], ctl.G[(long long)i * ctl.ldG + j], sj);
+    part = fma(s_u[j], sj, part);
+  }
+  part = block_sum<kSolveThreads>(part, s_red);
+  if (threadIdx.x == 0) {
+    dp[CD_PRES] = sqrt(pr);
+    ctl.pres[k] = dp[CD_PRES];
     const double rho2 = part + ctl.G[0];
     const double rho = sqrt(fmax(rho2, 0.0));
     ctl.rho[k] = rho;
@@ -263,7 +322,6 @@ __global__ __launch_bounds__(64) void k_small_solve(Ctl ctl) {
       ctl.ip[CI_K] = k + 1;
     }
   }
-  (void)s_u;
 }
 
 // ---- out = sum_{i=1..k_stop} u_i Q[:, i-1] -------------------------------------
@@ -321,10 +379,8 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
 void launch_set_int(int *p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v); }
 
 int vec_blocks(long long dim) {
-  long long b = (dim + kBlock - 1) / kBlock;
-  if (b > g_max_vec_blocks) b = g_max_vec_blocks;
-  if (b < 1) b = 1;
-  return (int)b;
+  long long b = (dim + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+  return (int)std::max<long long>(b, 1);
 }
 
 template <typename T>
@@ -340,14 +396,17 @@ void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *parti
 template <typename T>
 void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
                      unsigned *counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_cgs_dots<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials,
-                     counter);
+  (void)counter;
+  const int nb = vec_blocks(dim);
+  const dim3 grid(nb, (ctl.K + CH) / CH);
+  hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials, 0);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 1), dim3(kBlock), 0, s, ctl, (const double *)partials, nb, 0);
 }
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        unsigned *counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_cgs_update<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last,
-                     partials, counter);
+  const int nb = vec_blocks(dim);
+  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, counter);
 }
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s) {
@@ -357,10 +416,14 @@ template <typename T>
 void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials, unsigned *counter,
                  hipStream_t s) {
   (void)init;
-  hipLaunchKernelGGL(k_gram<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, Y, ld, dim, partials, counter);
+  (void)counter;
+  const int nb = vec_blocks(dim);
+  const dim3 grid(nb, (ctl.K + 1 + CH) / CH);
+  hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Y, ld, (const T *)nullptr, dim, partials, 1);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 2), dim3(kBlock), 0, s, ctl, (const double *)partials, nb, 1);
 }
 void launch_small_solve(Ctl ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(64), 0, s, ctl);
+  hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl);
 }
 template <typename T>
 void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, hipStream_t s) {

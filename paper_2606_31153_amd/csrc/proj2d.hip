@@ -9,17 +9,23 @@
 // Mapping:
 //  * ray-driven kernels (A, B^T): one thread per ray (view, bin), bins of a
 //    view on consecutive lanes; the loop runs over the lines of the ray's
-//    dominant image axis.  Row-stepping rays read the image row-major,
-//    column-stepping rays read a transposed copy, so the taps of a wavefront
-//    stay within a few cache lines of one image line.
+//    dominant image axis.  They read a zero-padded copy of the image that
+//    holds both a row-major and a column-major layout, so row-stepping and
+//    column-stepping rays both read along one padded line, every tap is in
+//    bounds without a test, and the two taps of a crossing are one 8-byte
+//    load addressed by a 32-bit offset from a uniform base.
 //  * pixel-driven kernels (B, A^T): one thread per pixel, 32x8 pixel tiles
 //    per 256-thread workgroup, loop over views; per-view constants are
-//    uniform across the workgroup (scalar loads).
+//    uniform across the workgroup (scalar loads).  They read a zero-padded
+//    copy of the sinogram; the detector coordinate is clamped into the padded
+//    range (taps outside the detector read zeros).
 //  * gathers only: every output element is written by one thread, the sum
 //    order is fixed, results are bitwise reproducible.
 //  * epilogue: out = raw * in_scale + coef * prev, optional copy of raw, and
 //    a deterministic FP64 reduction of ||out||^2 (last-arriving workgroup
 //    finalises).
+
+#include <algorithm>
 
 #include "internal.h"
 #include "reduce.h"
@@ -28,22 +34,58 @@ namespace gkb {
 
 namespace {
 
+// two consecutive elements, 4-byte (float) or 8-byte (double) aligned
 template <typename T>
-__device__ inline T load_or_zero(const T *line, int i, int len) {
-  const int ic = min(max(i, 0), len - 1);
-  const T v = line[ic];
-  return ((unsigned)i < (unsigned)len) ? v : T(0);
+struct Pair;
+template <>
+struct Pair<float> {
+  typedef float v2 __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <>
+struct Pair<double> {
+  typedef double v2 __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <typename T>
+__device__ inline typename Pair<T>::v2 load_pair(const T *p) {
+  return *reinterpret_cast<const typename Pair<T>::v2 *>(p);
+}
+
+// atan of |z| <= 0.5: z * P(z^2), P a degree-5 polynomial fitted to atan(z)/z
+// on [0, 0.5] (relative error 5.4e-9, below float rounding).
+__device__ inline float atan_poly(float z) {
+  const float t = z * z;
+  float p = -0.05129426f;
+  p = fmaf(p, t, 0.10156788f);
+  p = fmaf(p, t, -0.14173856f);
+  p = fmaf(p, t, 0.19994047f);
+  p = fmaf(p, t, -0.33333223f);
+  p = fmaf(p, t, 1.0f);
+  return z * p;
+}
+
+// Fan angle of a pixel from its coordinates (a along, b across the central ray).
+template <typename T>
+__device__ inline T fan_angle(T bb, T a, bool fast);
+template <>
+__device__ inline float fan_angle<float>(float bb, float a, bool fast) {
+  return fast ? atan_poly(bb * __builtin_amdgcn_rcpf(a)) : atan2f(bb, a);
+}
+template <>
+__device__ inline double fan_angle<double>(double bb, double a, bool) {
+  return atan2(bb, a);
 }
 
 // atan of the small angle between a ray and the direction to a pixel
-// (|z| <= tan of one bin pitch).  float: the series z - z^3/3 + z^5/5, whose
-// relative error z^6/7 stays below float rounding for |z| < 0.05; double:
-// the library atan.
+// (|z| <= tan of one bin pitch).  float: z - z^3/3 + z^5/5, relative error
+// z^6/7 (below float rounding for |z| < 0.05); double: the library atan.
 __device__ inline float small_atan(float z) {
   const float z2 = z * z;
   return z * fmaf(z2, fmaf(z2, 0.2f, -1.0f / 3.0f), 1.0f);
 }
 __device__ inline double small_atan(double z) { return atan(z); }
+
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fast_rcp(double x) { return 1.0 / x; }
 
 // Epilogue shared by all projector kernels.  Every thread of the block calls
 // it (the norm reduction needs the whole block).
@@ -84,14 +126,61 @@ __device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T ra
 }
 
 // ---------------------------------------------------------------------------
+// padded copies
+// ---------------------------------------------------------------------------
+// row-major region: ny lines of ldR = nx + 2P (image row j at line j)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_rows(Col<const T> xc, T *__restrict__ pad, int nx, int ny, int P,
+                                                  int ldR, const int *stop) {
+  if (stop && *stop) return;
+  const T *__restrict__ x = xc.get();
+  const long long total = (long long)ny * ldR;
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    const int j = (int)(idx / ldR), i = (int)(idx - (long long)j * ldR) - P;
+    pad[idx] = ((unsigned)i < (unsigned)nx) ? x[(long long)j * nx + i] : T(0);
+  }
+}
+
+// column-major region at offset offT: nx lines of ldT = ny + 2P (image column i at line i)
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_cols(Col<const T> xc, T *__restrict__ pad, int nx, int ny, int P,
+                                                  int ldT, long long offT, const int *stop) {
+  if (stop && *stop) return;
+  const T *__restrict__ x = xc.get();
+  __shared__ T tile[32][33];
+  const int jp0 = blockIdx.x * 32, i0 = blockIdx.y * 32;  // tile of the padded column-major image
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int j = jp0 + r - P, i = i0 + tx;  // source pixel (i, j)
+    tile[r][tx] = ((unsigned)j < (unsigned)ny && i < nx) ? x[(long long)j * nx + i] : T(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, jp = jp0 + tx;
+    if (i < nx && jp < ldT) pad[offT + (long long)i * ldT + jp] = tile[tx][r];
+  }
+}
+
+// sinogram rows padded by PY zeros on both sides: nv lines of ldY = nu + 2 PY
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_sino(Col<const T> yc, T *__restrict__ pad, int nv, int nu, int PY,
+                                                  int ldY, const int *stop) {
+  if (stop && *stop) return;
+  const T *__restrict__ y = yc.get();
+  const long long total = (long long)nv * ldY;
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    const int v = (int)(idx / ldY), k = (int)(idx - (long long)v * ldY) - PY;
+    pad[idx] = ((unsigned)k < (unsigned)nu) ? y[(long long)v * nu + k] : T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // ray-driven: A (Joseph forward)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, Col<const T> xc,
-                                                const T *__restrict__ xT, Col<T> yc, Epi<T> e,
-                                                const int *stop) {
+__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
+                                                Epi<T> e, const int *stop) {
   if (stop && *stop) return;
-  const T *__restrict__ x = xc.get();
   const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = r < g.m;
   T acc = T(0);
@@ -100,20 +189,44 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, Col<con
     const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
     const bool rowdom = (meta >> 30) & 1;
     const T base = rt.base[r], slope = rt.slope[r];
-    const T *img = rowdom ? x : xT;
-    const int len = rowdom ? g.nx : g.ny;
+    const int ld = rowdom ? g.ldR : g.ldT;
     const T mid = rowdom ? T(0.5) * T(g.ny - 1) : T(0.5) * T(g.nx - 1);
-    for (int j = lo; j <= hi; ++j) {
-      const T c = fma(T(j) - mid, slope, base);
-      const T fl = floor(c);
-      const int i0 = (int)fl;
-      const T f = c - fl;
-      const T *line = img + (long long)j * len;
-      const T v0 = load_or_zero(line, i0, len);
-      const T v1 = load_or_zero(line, i0 + 1, len);
-      acc += fma(f, v1 - v0, v0);
+    unsigned off = (rowdom ? 0u : (unsigned)g.offT) + (unsigned)(lo * ld + g.pad);
+    T jf = T(lo) - mid;
+    // crossings outside [-1, len] only meet the zero padding; the clamp keeps
+    // every tap inside the padded line whatever the rounding of c
+    const T clo = T(-1.5), chi = T(rowdom ? g.nx : g.ny) + T(0.5);
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+    int j = lo;
+    // four lines per step: the eight taps are in flight together
+    for (; j + 3 <= hi; j += 4) {
+      T c[4], fl[4];
+      typename Pair<T>::v2 p[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = fmin(fmax(fma(jf + T(q), slope, base), clo), chi);
+        fl[q] = floor(c[q]);
+        p[q] = load_pair(pad + (off + (unsigned)(q * ld) + (unsigned)(int)fl[q]));
+      }
+      a0 += fma(c[0] - fl[0], p[0].y - p[0].x, p[0].x);
+      a1 += fma(c[1] - fl[1], p[1].y - p[1].x, p[1].x);
+      a2 += fma(c[2] - fl[2], p[2].y - p[2].x, p[2].x);
+      a3 += fma(c[3] - fl[3], p[3].y - p[3].x, p[3].x);
+      jf += T(4);
+      off += 4u * (unsigned)ld;
     }
-    acc *= rt.w[r];
+    for (; j <= hi; ++j) {
+      const T c0 = fmin(fmax(fma(jf, slope, base), clo), chi);
+      const T f0l = floor(c0);
+      const auto p0 = load_pair(pad + (off + (unsigned)(int)f0l));
+      a0 += fma(c0 - f0l, p0.y - p0.x, p0.x);
+      jf += T(1);
+      off += (unsigned)ld;
+    }
+    a0 += a1;
+    a2 += a3;
+    a0 += a2;
+    acc = a0 * rt.w[r];
   }
   epilogue(e, r, valid, acc, yc.get());
 }
@@ -122,53 +235,72 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, Col<con
 // ray-driven: B^T (transpose of the pixel-driven back projector)
 // Ray (v,k) collects every pixel whose detector coordinate is within one bin
 // of k, with the hat weight 1 - |u(p) - k|.  On each line the candidates lie
-// within h of the ray's crossing.
+// within h of the ray's crossing: NC consecutive pixels from ceil(c - h).
 // ---------------------------------------------------------------------------
-template <typename T, bool FAN>
-__global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, Col<const T> xc,
-                                                     const T *__restrict__ xT, Col<T> yc, Epi<T> e,
-                                                     const int *stop) {
+template <typename T, bool FAN, int NC>
+__global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
+                                                     Epi<T> e, const int *stop) {
   if (stop && *stop) return;
-  const T *__restrict__ x = xc.get();
   const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = r < g.m;
   T acc = T(0);
   if (valid) {
-    const int meta = rt.meta[r];
+    const int meta = rt.meta_bt[r];
     const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
     const bool rowdom = (meta >> 30) & 1;
     const T base = rt.base[r], slope = rt.slope[r];
-    const T h = rt.h[r];
-    const T *img = rowdom ? x : xT;
-    const int len = rowdom ? g.nx : g.ny;
+    const int ld = rowdom ? g.ldR : g.ldT;
     const T mid = rowdom ? T(0.5) * T(g.ny - 1) : T(0.5) * T(g.nx - 1);
+    unsigned off = (rowdom ? 0u : (unsigned)g.offT) + (unsigned)(lo * ld + g.pad);
+    T jf = T(lo) - mid;
+    // crossings farther than h from the image only meet zero weights; the
+    // clamp keeps every candidate inside the padded line
+    const T hr = rt.h[r];
+    const T clo = -hr - T(0.5), chi = T((rowdom ? g.nx : g.ny) - 1) + hr + T(0.5);
     if (!FAN) {
+      const T h = hr;
       const T inv_h = T(1) / h;
       for (int j = lo; j <= hi; ++j) {
-        const T c = fma(T(j) - mid, slope, base);
-        const int ilo = (int)ceil(c - h), ihi = (int)floor(c + h);
-        const T *line = img + (long long)j * len;
-        for (int i = ilo; i <= ihi; ++i) {
-          const T wt = T(1) - fabs(c - T(i)) * inv_h;
-          const T v = load_or_zero(line, i, len);
-          acc += (wt > T(0)) ? wt * v : T(0);
+        const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
+        const T i0f = ceil(c - h);
+        const int cnt = (int)(floor(c + h) - i0f) + 1;
+        const T *p = pad + (off + (unsigned)(int)i0f);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          if (q < cnt) {
+            const T wt = T(1) - fabs(c - (i0f + T(q))) * inv_h;
+            const T v = p[q];
+            acc += (wt > T(0)) ? wt * v : T(0);
+          }
         }
+        jf += T(1);
+        off += (unsigned)ld;
       }
     } else {
       const T t0 = rt.t0[r], dt = rt.dt[r], dperp = rt.dperp[r], dpar = rt.dpar[r];
       const T inv_dg = T(g.inv_du);
+      // candidate half-width on a line at distance `along` from the source
+      const T hfac = T(g.tan_dg) / (fabs(dperp) - T(g.tan_dg));
       for (int j = lo; j <= hi; ++j) {
-        const T c = fma(T(j) - mid, slope, base);
-        const T along0 = fma(T(j) - mid, dt, t0);
-        const int ilo = (int)ceil(c - h), ihi = (int)floor(c + h);
-        const T *line = img + (long long)j * len;
-        for (int i = ilo; i <= ihi; ++i) {
-          const T d = T(i) - c;
-          const T z = (dperp * d) / fma(dpar, d, along0);
-          const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
-          const T v = load_or_zero(line, i, len);
-          acc += (wt > T(0)) ? wt * v : T(0);
+        const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
+        const T along0 = fma(jf, dt, t0);
+        const T h = fmin(hfac * along0 * T(1.0001) + T(1e-4), hr);
+        const T i0f = ceil(c - h);
+        const int cnt = (int)(floor(c + h) - i0f) + 1;
+        const T *p = pad + (off + (unsigned)(int)i0f);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          if (q < cnt) {
+            const T d = (i0f + T(q)) - c;
+            // tangent of the angle between the ray and the pixel, seen from the source
+            const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
+            const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
+            const T v = p[q];
+            acc += (wt > T(0)) ? wt * v : T(0);
+          }
         }
+        jf += T(1);
+        off += (unsigned)ld;
       }
     }
   }
@@ -186,45 +318,75 @@ __device__ inline void tile_pixel(const GeomDev &g, int &i, int &j) {
 }
 
 template <typename T, bool FAN>
-__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, Col<const T> yc, T *__restrict__ xo,
-                                                 Epi<T> e, const int *stop) {
+__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
+                                                 T *__restrict__ xo, Epi<T> e, const int *stop) {
   if (stop && *stop) return;
   int i, j;
   tile_pixel(g, i, j);
   const bool valid = i < g.nx && j < g.ny;
-  const T *__restrict__ y = yc.get();
   T acc = T(0);
   if (valid) {
     const T px = T(i) - T(0.5) * T(g.nx - 1);
     const T py = T(j) - T(0.5) * T(g.ny - 1);
     const T off = T(g.off);
-    const int nu = g.nu;
+    const T ulo = T(-2), uhi = T(g.nu + 1);
+    const unsigned ldY = (unsigned)g.ldY;
+    unsigned roff = (unsigned)g.padY;
     if (!FAN) {
-      for (int v = 0; v < g.nv; ++v) {
-        const T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
-        const T fl = floor(u);
-        const int k0 = (int)fl;
-        const T f = u - fl;
-        const T *row = y + (long long)v * nu;
-        const T y0 = load_or_zero(row, k0, nu);
-        const T y1 = load_or_zero(row, k0 + 1, nu);
-        acc += fma(f, y1 - y0, y0);
+      T a[4] = {T(0), T(0), T(0), T(0)};
+      int v = 0;
+      for (; v + 3 < g.nv; v += 4) {
+        T u[4], fl[4];
+        typename Pair<T>::v2 p[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          u[q] = fmin(fmax(fma(px, vt.p0[v + q], fma(py, vt.p1[v + q], off)), ulo), uhi);
+          fl[q] = floor(u[q]);
+          p[q] = load_pair(ypad + (roff + (unsigned)q * ldY + (unsigned)(int)fl[q]));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] += fma(u[q] - fl[q], p[q].y - p[q].x, p[q].x);
+        roff += 4u * ldY;
       }
+      for (; v < g.nv; ++v) {
+        const T u0 = fmin(fmax(fma(px, vt.p0[v], fma(py, vt.p1[v], off)), ulo), uhi);
+        const T f0l = floor(u0);
+        const auto p0 = load_pair(ypad + (roff + (unsigned)(int)f0l));
+        a[0] += fma(u0 - f0l, p0.y - p0.x, p0.x);
+        roff += ldY;
+      }
+      acc = (a[0] + a[1]) + (a[2] + a[3]);
     } else {
       const T D = T(g.D), inv_dg = T(g.inv_du);
-      for (int v = 0; v < g.nv; ++v) {
+      const bool fast = g.fast_atan != 0;
+      T a0 = T(0), a1 = T(0);
+      int v = 0;
+      for (; v + 1 < g.nv; v += 2) {
+        T u[2], fl[2];
+        typename Pair<T>::v2 p[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const T cb = vt.p0[v + q], sb = vt.p1[v + q];
+          const T a = D - fma(px, cb, py * sb);
+          const T bb = fma(px, sb, -py * cb);
+          u[q] = fmin(fmax(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo), uhi);
+          fl[q] = floor(u[q]);
+          p[q] = load_pair(ypad + (roff + (unsigned)q * ldY + (unsigned)(int)fl[q]));
+        }
+        a0 += fma(u[0] - fl[0], p[0].y - p[0].x, p[0].x);
+        a1 += fma(u[1] - fl[1], p[1].y - p[1].x, p[1].x);
+        roff += 2u * ldY;
+      }
+      if (v < g.nv) {
         const T cb = vt.p0[v], sb = vt.p1[v];
         const T a = D - fma(px, cb, py * sb);
         const T bb = fma(px, sb, -py * cb);
-        const T u = fma(atan2(bb, a), inv_dg, off);
+        const T u = fmin(fmax(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo), uhi);
         const T fl = floor(u);
-        const int k0 = (int)fl;
-        const T f = u - fl;
-        const T *row = y + (long long)v * nu;
-        const T y0 = load_or_zero(row, k0, nu);
-        const T y1 = load_or_zero(row, k0 + 1, nu);
-        acc += fma(f, y1 - y0, y0);
+        const auto p = load_pair(ypad + (roff + (unsigned)(int)fl));
+        a0 += fma(u - fl, p.y - p.x, p.x);
       }
+      acc = a0 + a1;
     }
   }
   epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo);
@@ -237,77 +399,100 @@ __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, Col<c
 // Parallel beam: delta = (s_k - s(p)), so the candidates are the bins within
 // |d_dom|/du of u(p).  Fan beam: delta = b cos(g_k) - a sin(g_k) with (a, b)
 // the coordinates of p - S along and across the central ray; the candidates
-// are the bins within asin(1/|p - S|) of the pixel's fan angle.
+// are the bins within asin(|d_dom|/|p - S|) of the pixel's fan angle, with
+// |d_dom| bounded by that of the pixel's own ray plus the fan spread of the
+// candidates.
 // ---------------------------------------------------------------------------
-template <typename T, bool FAN>
-__global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, RayTab<T> rt, Col<const T> yc,
+template <typename T, bool FAN, int NC>
+__global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
                                                     T *__restrict__ xo, Epi<T> e, const int *stop) {
   if (stop && *stop) return;
   int i, j;
   tile_pixel(g, i, j);
   const bool valid = i < g.nx && j < g.ny;
-  const T *__restrict__ y = yc.get();
   T acc = T(0);
   if (valid) {
     const T px = T(i) - T(0.5) * T(g.nx - 1);
     const T py = T(j) - T(0.5) * T(g.ny - 1);
     const T off = T(g.off);
-    const int nu = g.nu;
+    const unsigned ldY = (unsigned)g.ldY;
+    unsigned roff = (unsigned)g.padY;
+    // bins farther than the candidate half-width from the detector have zero
+    // weight; the clamp keeps every candidate inside the padded row
+    const T ulo = -T(g.uclamp_at), uhi = T(g.nu - 1) + T(g.uclamp_at);
     if (!FAN) {
       for (int v = 0; v < g.nv; ++v) {
-        const T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
+        T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
+        u = fmin(fmax(u, ulo), uhi);
         const T w = vt.p2[v], slope = vt.p3[v], h = vt.p4[v];
-        const int klo = max((int)ceil(u - h), 0), khi = min((int)floor(u + h), nu - 1);
-        const T *row = y + (long long)v * nu;
-        for (int k = klo; k <= khi; ++k) {
-          const T wt = T(1) - fabs(u - T(k)) * slope;
-          acc += (wt > T(0)) ? w * wt * row[k] : T(0);
+        const T k0f = ceil(u - h);
+        const int cnt = (int)(floor(u + h) - k0f) + 1;
+        const T *row = ypad + (roff + (unsigned)(int)k0f);
+        T part = T(0);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          if (q < cnt) {
+            const T wt = T(1) - fabs(u - (k0f + T(q))) * slope;
+            const T yv = row[q];
+            part += (wt > T(0)) ? wt * yv : T(0);
+          }
         }
+        acc = fma(w, part, acc);
+        roff += ldY;
       }
     } else {
-      const T D = T(g.D), inv_dg = T(g.inv_du), hfac = T(g.hmax_fan);
+      // ypad holds (w y, w) per padded bin, w = 1/|d_dom| of the ray (0 in the pads);
+      // vt.gcos holds (cos g_k, sin g_k) per padded bin
+      const T D = T(g.D), inv_dg = T(g.inv_du), hfac = T(g.hmax_fan), spread = T(g.dd_spread);
+      const bool fast = g.fast_atan != 0;
       for (int v = 0; v < g.nv; ++v) {
         const T cb = vt.p0[v], sb = vt.p1[v];
         const T a = D - fma(px, cb, py * sb);
         const T bb = fma(px, sb, -py * cb);
-        const T up = fma(atan2(bb, a), inv_dg, off);
-        // candidates: |g_k - g_p| < asin(1/|p-S|) <= z/sqrt(1-z^2), z = 1/|p-S|
-        const T z = rsqrt(fma(a, a, bb * bb));
-        const T h = hfac * z * rsqrt(T(1) - z * z) + T(1e-3);
-        const int klo = max((int)ceil(up - h), 0), khi = min((int)floor(up + h), nu - 1);
-        const T *row = y + (long long)v * nu;
-        const T *wv = rt.w + (long long)v * nu;
-        for (int k = klo; k <= khi; ++k) {
-          const T delta = fma(bb, vt.gcos[k], -a * vt.gsin[k]);
-          const T w = wv[k];
-          const T wt = T(1) - fabs(delta) * w;
-          acc += (wt > T(0)) ? w * wt * row[k] : T(0);
+        T up = fma(fan_angle<T>(bb, a, fast), inv_dg, off);
+        up = fmin(fmax(up, ulo), uhi);
+        // |d_dom| of the pixel's ray: (p - S) = a c + b c_perp, c = -(cos b, sin b)
+        const T wx = fma(bb, sb, -a * cb), wy = -fma(a, sb, bb * cb);
+        const T rinv = rsqrt(fma(a, a, bb * bb));
+        const T ddm = fmin(fmax(fabs(wx), fabs(wy)) * rinv + spread, T(1));
+        // candidates: |g_k - g_p| < asin(|d_dom| / |p - S|) <= z (1 + z^2)
+        const T z = ddm * rinv;
+        const T h = hfac * z * fma(z, z, T(1)) + T(1e-3);
+        const T k0f = ceil(up - h);
+        const int cnt = (int)(floor(up + h) - k0f) + 1;
+        const unsigned k0 = (unsigned)((int)g.padY + (int)k0f);
+        const typename Pair<T>::v2 *yw = reinterpret_cast<const typename Pair<T>::v2 *>(ypad) + (roff - g.padY + k0);
+        const typename Pair<T>::v2 *cs = reinterpret_cast<const typename Pair<T>::v2 *>(vt.gcos) + k0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          if (q < cnt) {
+            const auto gq = cs[q];
+            const auto pq = yw[q];
+            const T delta = fma(bb, gq.x, -a * gq.y);
+            const T wt = T(1) - fabs(delta) * pq.y;
+            acc += (wt > T(0)) ? wt * pq.x : T(0);
+          }
         }
+        roff += ldY;
       }
     }
   }
   epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo);
 }
 
-// ---------------------------------------------------------------------------
-// transpose (32x32 LDS tiles) for column-stepping rays
-// ---------------------------------------------------------------------------
+// (w y, w) per padded bin for the fan-beam A^T: w = 1/|d_dom| per ray in padded layout
 template <typename T>
-__global__ __launch_bounds__(256) void k_transpose(Col<const T> xc, T *__restrict__ xT, int nx, int ny,
-                                                   const int *stop) {
+__global__ __launch_bounds__(256) void k_pad_sino_w(Col<const T> yc, const T *__restrict__ wpad, T *__restrict__ out,
+                                                    int nv, int nu, int PY, int ldY, const int *stop) {
   if (stop && *stop) return;
-  const T *__restrict__ x = xc.get();
-  __shared__ T tile[32][33];
-  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    const int i = bx + tx, j = by + r;
-    if (i < nx && j < ny) tile[r][tx] = x[(long long)j * nx + i];
-  }
-  __syncthreads();
-  for (int r = ty; r < 32; r += 8) {
-    const int j = by + tx, i = bx + r;
-    if (i < nx && j < ny) xT[(long long)i * ny + j] = tile[tx][r];
+  const T *__restrict__ y = yc.get();
+  const long long total = (long long)nv * ldY;
+  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+    const int v = (int)(idx / ldY), k = (int)(idx - (long long)v * ldY) - PY;
+    const T yv = ((unsigned)k < (unsigned)nu) ? y[(long long)v * nu + k] : T(0);
+    const T w = wpad[idx];
+    out[2 * idx] = w * yv;
+    out[2 * idx + 1] = w;
   }
 }
 
@@ -317,54 +502,110 @@ int pixel_blocks(const GeomDev &g) { return ((g.nx + 31) / 32) * ((g.ny + 7) / 8
 int ray_blocks(const GeomDev &g) { return (int)((g.m + kBlock - 1) / kBlock); }
 
 template <typename T>
-void launch_transpose(Col<const T> x, T *xT, int nx, int ny, const int *stop, hipStream_t s) {
-  dim3 grid((nx + 31) / 32, (ny + 31) / 32);
-  hipLaunchKernelGGL(k_transpose<T>, grid, dim3(256), 0, s, x, xT, nx, ny, stop);
+void launch_pad_image(const GeomDev &g, Col<const T> x, T *pad, bool cols, const int *stop, hipStream_t s) {
+  const long long totR = (long long)g.ny * g.ldR;
+  const int nbR = (int)std::min<long long>((totR + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_pad_rows<T>, dim3(nbR), dim3(256), 0, s, x, pad, g.nx, g.ny, g.pad, g.ldR, stop);
+  if (cols) {
+    dim3 grid((g.ldT + 31) / 32, (g.nx + 31) / 32);
+    hipLaunchKernelGGL(k_pad_cols<T>, grid, dim3(256), 0, s, x, pad, g.nx, g.ny, g.pad, g.ldT, g.offT, stop);
+  }
 }
 
 template <typename T>
-void launch_fwd(const GeomDev &g, const RayTab<T> &rt, Col<const T> x, const T *xT, Col<T> y, const Epi<T> &e,
-                const int *stop, hipStream_t s) {
-  hipLaunchKernelGGL(k_fwd<T>, dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, x, xT, y, e, stop);
+void launch_pad_sino(const GeomDev &g, Col<const T> y, T *pad, const int *stop, hipStream_t s) {
+  const long long tot = (long long)g.nv * g.ldY;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pad_sino<T>, dim3(nb), dim3(256), 0, s, y, pad, g.nv, g.nu, g.padY, g.ldY, stop);
 }
 
 template <typename T>
-void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, Col<const T> x, const T *xT, Col<T> y,
-                     const Epi<T> &e, const int *stop, hipStream_t s) {
+void launch_pad_sino_adj(const GeomDev &g, const RayTab<T> &rt, Col<const T> y, T *pad, const int *stop,
+                         hipStream_t s) {
+  if (g.kind != 1) {
+    launch_pad_sino<T>(g, y, pad, stop, s);
+    return;
+  }
+  const long long tot = (long long)g.nv * g.ldY;
+  const int nb = (int)std::min<long long>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pad_sino_w<T>, dim3(nb), dim3(256), 0, s, y, rt.wpad, pad, g.nv, g.nu, g.padY, g.ldY, stop);
+}
+
+template <typename T>
+void launch_fwd(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e, const int *stop,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_fwd<T>, dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, pad, y, e, stop);
+}
+
+template <typename T, bool FAN>
+static void back_adj_nc(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e,
+                        const int *stop, hipStream_t s) {
+  const dim3 grid(ray_blocks(g)), blk(kBlock);
+  switch (g.nc_bt) {
+    case 2: hipLaunchKernelGGL((k_back_adj<T, FAN, 2>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+    case 3: hipLaunchKernelGGL((k_back_adj<T, FAN, 3>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+    case 4: hipLaunchKernelGGL((k_back_adj<T, FAN, 4>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+    case 5: hipLaunchKernelGGL((k_back_adj<T, FAN, 5>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+    case 6: hipLaunchKernelGGL((k_back_adj<T, FAN, 6>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+    case 7: hipLaunchKernelGGL((k_back_adj<T, FAN, 7>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+    default: hipLaunchKernelGGL((k_back_adj<T, FAN, 8>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
+  }
+}
+
+template <typename T>
+void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e,
+                     const int *stop, hipStream_t s) {
   if (g.kind == 1)
-    hipLaunchKernelGGL((k_back_adj<T, true>), dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, x, xT, y, e, stop);
+    back_adj_nc<T, true>(g, rt, pad, y, e, stop, s);
   else
-    hipLaunchKernelGGL((k_back_adj<T, false>), dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, x, xT, y, e, stop);
+    back_adj_nc<T, false>(g, rt, pad, y, e, stop, s);
 }
 
 template <typename T>
-void launch_back(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, Col<const T> y, T *x,
-                 const Epi<T> &e, const int *stop, hipStream_t s) {
-  (void)rt;
+void launch_back(const GeomDev &g, const ViewTab<T> &vt, const T *ypad, T *x, const Epi<T> &e, const int *stop,
+                 hipStream_t s) {
   if (g.kind == 1)
-    hipLaunchKernelGGL((k_back<T, true>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, y, x, e, stop);
+    hipLaunchKernelGGL((k_back<T, true>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
   else
-    hipLaunchKernelGGL((k_back<T, false>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, y, x, e, stop);
+    hipLaunchKernelGGL((k_back<T, false>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
+}
+
+template <typename T, bool FAN>
+static void fwd_adj_nc(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, const T *ypad, T *x,
+                       const Epi<T> &e, const int *stop, hipStream_t s) {
+  const dim3 grid(pixel_blocks(g)), blk(kBlock);
+  switch (g.nc_at) {
+    case 2: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 2>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    case 3: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 3>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    case 4: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 4>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    case 5: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 5>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    case 6: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 6>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    case 7: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 7>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    default: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 8>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+  }
 }
 
 template <typename T>
-void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, Col<const T> y, T *x,
+void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, const T *ypad, T *x,
                     const Epi<T> &e, const int *stop, hipStream_t s) {
   if (g.kind == 1)
-    hipLaunchKernelGGL((k_fwd_adj<T, true>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, rt, y, x, e, stop);
+    fwd_adj_nc<T, true>(g, vt, rt, ypad, x, e, stop, s);
   else
-    hipLaunchKernelGGL((k_fwd_adj<T, false>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, rt, y, x, e, stop);
+    fwd_adj_nc<T, false>(g, vt, rt, ypad, x, e, stop, s);
 }
 
-#define GKB_INST(T)                                                                                             \
-  template void launch_transpose<T>(Col<const T>, T *, int, int, const int *, hipStream_t);                   \
-  template void launch_fwd<T>(const GeomDev &, const RayTab<T> &, Col<const T>, const T *, Col<T>,              \
-                              const Epi<T> &, const int *, hipStream_t);                                       \
-  template void launch_back_adj<T>(const GeomDev &, const RayTab<T> &, Col<const T>, const T *, Col<T>,         \
-                                   const Epi<T> &, const int *, hipStream_t);                                  \
-  template void launch_back<T>(const GeomDev &, const ViewTab<T> &, const RayTab<T> &, Col<const T>, T *,       \
-                               const Epi<T> &, const int *, hipStream_t);                                      \
-  template void launch_fwd_adj<T>(const GeomDev &, const ViewTab<T> &, const RayTab<T> &, Col<const T>, T *,    \
+#define GKB_INST(T)                                                                                               \
+  template void launch_pad_image<T>(const GeomDev &, Col<const T>, T *, bool, const int *, hipStream_t);         \
+  template void launch_pad_sino<T>(const GeomDev &, Col<const T>, T *, const int *, hipStream_t);                \
+  template void launch_pad_sino_adj<T>(const GeomDev &, const RayTab<T> &, Col<const T>, T *, const int *,       \
+                                       hipStream_t);                                                             \
+  template void launch_fwd<T>(const GeomDev &, const RayTab<T> &, const T *, Col<T>, const Epi<T> &,             \
+                              const int *, hipStream_t);                                                         \
+  template void launch_back_adj<T>(const GeomDev &, const RayTab<T> &, const T *, Col<T>, const Epi<T> &,        \
+                                   const int *, hipStream_t);                                                    \
+  template void launch_back<T>(const GeomDev &, const ViewTab<T> &, const T *, T *, const Epi<T> &, const int *, \
+                               hipStream_t);                                                                     \
+  template void launch_fwd_adj<T>(const GeomDev &, const ViewTab<T> &, const RayTab<T> &, const T *, T *,        \
                                   const Epi<T> &, const int *, hipStream_t);
 GKB_INST(float)
 GKB_INST(double)
