@@ -38,6 +38,10 @@ VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # crossing; pixel-driven kernels 3 FMA per (pixel, view) pair
 FLOPS_PER_UNIT = {"fwd": 4.0, "back_adj": 4.0, "back": 6.0, "fwd_adj": 6.0}
 OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each
+# scaled by the plain-copy calibration), profiles/fan512_gkb_hbm_traffic.txt.
+# An entry must be removed when its kernel changes.
+MEASURED_TRAFFIC = {"back_adj": (18239.4 * 1.9814 + 2880.0 * 1.0) * 1024.0}
 
 
 def joseph_crossings(geom) -> int:
@@ -192,7 +196,8 @@ def main():
         "ba_iters_per_s": args.iters * args.steps / ba_s,
         "ab_iters_per_s": args.iters * args.steps / ab_s,
         "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": VALU_FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": ach / VALU_FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": ach / VALU_FP32_PEAK_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get(dom),
                      "work_per_launch": "%d units x %g flop" % (units[dom], FLOPS_PER_UNIT[dom])},
         "projector_gbps": gbps,
         "kernels": kernels,
