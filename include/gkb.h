@@ -139,6 +139,23 @@ gkb_status gkb_ba_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const vo
 gkb_status gkb_gkb_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
                          void *x, gkb_solve_info *info);
 
+/* Batched multi-slice solve: n_slices independent problems, each with its own
+ * geometry, b, options (k_max, lambda, tau, noise_norm, reorth, histories)
+ * and discrepancy stop, solved by AB-GKB (method GKB_METHOD_AB) or BA-GKB
+ * (GKB_METHOD_BA) exactly as gkb_ab_solve / gkb_ba_solve would solve each
+ * one (same kernels and workgroup partitions per slice, hence the same
+ * results bit for bit), but with every kernel launch covering all slices
+ * that have not yet stopped.  geoms[s], b[s] (DEVICE, m_s elements), opts[s], x[s] (DEVICE,
+ * n_s elements) and info[s] describe slice s; info may be NULL.
+ * Constraints: 1 <= n_slices <= 1024; all geometries 2D and of one kind
+ * (all GKB_PAR2D or all GKB_FAN2D); opts[s].precond must be NULL.
+ * Errors: GKB_EINVAL for a bad argument in any slice (the message names the
+ * slice); GKB_ENONFINITE if any b[s] holds NaN/Inf (no x is written).
+ * info[s].seconds is the wall time of the whole batched call. */
+typedef enum { GKB_METHOD_AB = 0, GKB_METHOD_BA = 1 } gkb_method;
+gkb_status gkb_batch_solve(gkb_ctx *ctx, int method, int n_slices, const gkb_geometry *geoms, int dtype,
+                           const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info);
+
 /* Kernel timing.  While enabled, every launch of the named kernels is
  * bracketed by HIP events on the context's stream; gkb_trace_get returns the
  * launch count and summed device milliseconds since the last reset. */

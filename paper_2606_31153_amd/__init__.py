@@ -27,12 +27,13 @@ GKB_OK, GKB_EINVAL, GKB_ENOMEM, GKB_EDEVICE, GKB_ENONFINITE, GKB_EUNSUPPORTED = 
 STOP_NONE, STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED, STOP_FALLBACK = 0, 1, 2, 3, 4, 5
 GKB_PAR2D, GKB_FAN2D, GKB_CONE3D = 0, 1, 2
 GKB_F32, GKB_F64 = 0, 1
+GKB_METHOD_AB, GKB_METHOD_BA = 0, 1
 
 STATUS_NAMES = {0: "GKB_OK", -1: "GKB_EINVAL", -2: "GKB_ENOMEM", -3: "GKB_EDEVICE", -4: "GKB_ENONFINITE",
                 -5: "GKB_EUNSUPPORTED"}
 EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gkb_forward", "gkb_back",
             "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve",
-            "gkb_trace_enable", "gkb_trace_reset", "gkb_trace_get")
+            "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_reset", "gkb_trace_get")
 
 
 class GkbError(RuntimeError):
@@ -85,6 +86,8 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [vp, G, cp, vp, vp]
         for name in ("gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve"):
             getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
+        L.gkb_batch_solve.argtypes = [vp, cp, cp, G, cp, ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
+                                      ctypes.POINTER(vp), ctypes.POINTER(SolveInfo)]
         L.gkb_trace_enable.argtypes = [vp, cp]
         L.gkb_trace_reset.argtypes = [vp]
         L.gkb_trace_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(cp), ctypes.POINTER(ctypes.c_double)]
@@ -252,3 +255,57 @@ def gkb_ba_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
 def gkb_gkb_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
     """Matched GKB (B := A^T), equivalent to LSQR."""
     return _solve("gkb_gkb_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def _opts(k_max: int, lam: float = 0.0, use_dp: bool = False, tau: float = 1.0, noise_norm: float = 0.0,
+          reorth: bool = True):
+    """(SolveOpts, history arrays) for one problem."""
+    rho = np.zeros(max(k_max, 1))
+    alpha = np.zeros(k_max + 1)
+    t = np.zeros(k_max + 1)
+    P = ctypes.POINTER(ctypes.c_double)
+    o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0, None,
+                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P))
+    return o, (rho, alpha, t)
+
+
+def gkb_batch_solve(ctx: Context, method: int, geoms, bs, xs, opts) -> list:
+    """Batched solve of independent slices (AB-GKB or BA-GKB per ``method``):
+    ``geoms``, ``bs``, ``xs`` are per-slice geometries and device tensors;
+    ``opts`` is a list of per-slice keyword dicts (k_max, lam, use_dp, tau,
+    noise_norm, reorth).  Returns one SolveResult per slice."""
+    ns = len(geoms)
+    if not (len(bs) == len(xs) == len(opts) == ns):
+        raise ValueError("geoms, bs, xs and opts must have one entry per slice")
+    G = (Geometry * ns)()
+    O = (SolveOpts * ns)()
+    I = (SolveInfo * ns)()
+    Bp = (ctypes.c_void_p * ns)()
+    Xp = (ctypes.c_void_p * ns)()
+    keep, hist = [], []
+    code = None
+    for s in range(ns):
+        g, k = make_geometry(geoms[s])
+        keep.append(k)
+        G[s] = g
+        o, h = _opts(**opts[s])
+        O[s] = o
+        hist.append(h)
+        c = _dtype_code(bs[s])
+        if code is None:
+            code = c
+        if c != code or xs[s].dtype != bs[s].dtype:
+            raise TypeError("all slices must share one dtype")
+        Bp[s] = _dev_ptr(bs[s], geoms[s].m).value
+        Xp[s] = _dev_ptr(xs[s], geoms[s].n).value
+    if code is None:  # no slices: the library reports the invalid count
+        code = GKB_F32
+    _check(lib().gkb_batch_solve(ctx.handle, method, ns, G, code, Bp, O, Xp, I))
+    out = []
+    for s in range(ns):
+        rho, alpha, t = hist[s]
+        k = I[s].k_stop
+        out.append(SolveResult(k_stop=k, reason=I[s].reason, residual=I[s].residual,
+                               proj_residual=I[s].proj_residual, t1=I[s].t1, alpha1=I[s].alpha1,
+                               seconds=I[s].seconds, rho=rho[:k], alpha=alpha[:k + 1], t=t[:k + 1]))
+    return out

@@ -380,6 +380,13 @@ struct gkb_ctx {
   DevBuf Q, Y, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
   int *host_flag = nullptr;      // host-mapped
   int *host_flag_dev = nullptr;  // its device address
+  // batched solves: vectors, control blocks, slice descriptors, launch maps
+  DevBuf bws, bwd, bwi, bsd, bmap, brep;
+  int *bflags = nullptr, *bflags_dev = nullptr;  // host-mapped stop mirrors, one per slice
+  int bflags_n = 0;
+  int *bpin = nullptr;  // pinned staging of launch maps: two slots
+  size_t bpin_slot = 0;
+  hipEvent_t bpin_ev[2] = {nullptr, nullptr};
   // tracing
   bool trace = false;
   std::map<std::string, TraceStat> stats;
@@ -768,8 +775,8 @@ struct Solver {
       launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, counters, st);
       launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, counters, st);
     } else {
-      // no reorthogonalisation: only the norm (zero previous columns)
-      launch_norm_to<T>(ctl, w, dimq, NORM_ALPHA1, partials, counters, st);
+      // no reorthogonalisation: only the norm alpha_{k+1} = ||w|| (no columns)
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, counters, st, 0);
     }
     launch_normalize<T>(ctl, w, Q, ldq, dimq, st);
   }
@@ -884,6 +891,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     std::vector<double> al(o->k_max + 2), tt(o->k_max + 2);
     HIPC(hipMemcpy(al.data(), S.ctl.alpha, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
     HIPC(hipMemcpy(tt.data(), S.ctl.t, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    al[1] = inf.alpha1;  // 0 (not 0/0) when t_1 = 0
     for (int k = 1; k <= o->k_max + 1; ++k) {
       if (o->alpha_history) o->alpha_history[k - 1] = (k <= k_stop + 1) ? al[k] : 0.0;
       if (o->t_history) o->t_history[k - 1] = (k <= k_stop + 1) ? tt[k] : 0.0;
@@ -896,13 +904,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   return GKB_OK;
 }
 
-gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
-                       void *x, gkb_solve_info *info, int mode) {
-  if (!c) return fail(GKB_EINVAL, "context is NULL");
-  if (!o) return fail(GKB_EINVAL, "options are NULL");
-  if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
-  gkb_status st = validate_geom(g, dtype);
-  if (st != GKB_OK) return st;
+gkb_status validate_opts(const gkb_solve_opts *o) {
   if (o->k_max < 1 || o->k_max > 4096) return fail(GKB_EINVAL, "k_max must be in [1, 4096]");
   if (!(o->lambda >= 0.0) || !std::isfinite(o->lambda)) return fail(GKB_EINVAL, "lambda must be finite and >= 0");
   if (o->use_dp && (!(o->tau > 0.0) || !std::isfinite(o->tau)))
@@ -910,9 +912,419 @@ gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void 
   if (o->use_dp && (!(o->noise_norm >= 0.0) || !std::isfinite(o->noise_norm)))
     return fail(GKB_EINVAL, "noise_norm must be finite and >= 0");
   if (o->precond) return fail(GKB_EUNSUPPORTED, "learned preconditioner is not available in this build");
+  return GKB_OK;
+}
+
+gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                       void *x, gkb_solve_info *info, int mode) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!o) return fail(GKB_EINVAL, "options are NULL");
+  if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  st = validate_opts(o);
+  if (st != GKB_OK) return st;
   HIPC(hipSetDevice(c->device));
   return dtype == GKB_F32 ? solve_impl<float>(c, g, dtype, b, o, x, info, mode)
                           : solve_impl<double>(c, g, dtype, b, o, x, info, mode);
+}
+
+// --------------------------------------------------------------------------
+// batched multi-slice driver: every launch covers all active slices
+// --------------------------------------------------------------------------
+inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct SliceHost {
+  const DevTables *d;
+  long long n, m, dimq, dims, ldq, ldy;
+  int K;
+  int cnt[BF_COUNT];
+  // byte offsets into the vector workspace
+  size_t oQ, oY, os, ow, otn, otm, oxp, oyp;
+  // element offsets into the double workspace (control arrays, partials)
+  size_t oarr, opart;
+};
+
+// Launch map of the slices in `active` (slice ids): the active list followed
+// by the per-family prefix sums.
+void build_map(const std::vector<SliceHost> &sh, const std::vector<int> &active, std::vector<int> &buf,
+               BatchLaunch &bl) {
+  const int na = (int)active.size();
+  buf.assign(na + BF_COUNT * (na + 1), 0);
+  for (int a = 0; a < na; ++a) buf[a] = active[a];
+  for (int f = 0; f < BF_COUNT; ++f) {
+    int *pre = buf.data() + na + f * (na + 1);
+    pre[0] = 0;
+    for (int a = 0; a < na; ++a) pre[a + 1] = pre[a] + sh[active[a]].cnt[f];
+    bl.tot[f] = pre[na];
+  }
+  bl.na = na;
+}
+
+// Stages a launch map through one of two pinned slots and copies it to the
+// device map buffer, ordered on the stream after every earlier launch.
+gkb_status upload_map(gkb_ctx *c, const std::vector<int> &buf) {
+  const int j = (int)(c->bpin_slot++ & 1);
+  const size_t slot_ints = c->bmap.bytes / sizeof(int);
+  if (buf.size() > slot_ints) return fail(GKB_EINVAL, "internal: launch map larger than its buffer");
+  if (c->bpin_ev[j]) HIPC(hipEventSynchronize(c->bpin_ev[j]));
+  int *h = c->bpin + (size_t)j * slot_ints;
+  std::memcpy(h, buf.data(), sizeof(int) * buf.size());
+  HIPC(hipMemcpyAsync(c->bmap.p, h, sizeof(int) * buf.size(), hipMemcpyHostToDevice, c->stream));
+  if (!c->bpin_ev[j]) HIPC(hipEventCreateWithFlags(&c->bpin_ev[j], hipEventDisableTiming));
+  HIPC(hipEventRecord(c->bpin_ev[j], c->stream));
+  return GKB_OK;
+}
+
+template <typename T>
+gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, int dtype, const void *const *bv,
+                      const gkb_solve_opts *opts, void *const *xv, gkb_solve_info *info) {
+  auto t_start = std::chrono::steady_clock::now();
+  hipStream_t st = c->stream;
+  std::vector<SliceHost> sh(ns);
+  BatchLaunch bl{};
+  bl.nc_bt = 2;
+  bl.nc_at = 2;
+  bl.kmax = 1;
+  size_t bytesT = 0, ndbl = (size_t)ns * CD_COUNT;
+  for (int s = 0; s < ns; ++s) {
+    DevTables *d = nullptr;
+    gkb_status stt = get_tables(c, &geoms[s], dtype, &d);
+    if (stt != GKB_OK) return stt;
+    const GeomDev &g = d->gd;
+    if (s == 0) bl.fan = g.kind == GKB_FAN2D;
+    if ((g.kind == GKB_FAN2D) != (bl.fan != 0))
+      return fail(GKB_EINVAL, "all slices of a batch must share the geometry kind");
+    SliceHost &h = sh[s];
+    h.d = d;
+    h.n = g.n;
+    h.m = g.m;
+    h.K = opts[s].k_max;
+    h.dimq = mode == MODE_AB ? g.m : g.n;
+    h.dims = mode == MODE_BA ? g.n : g.m;
+    h.ldq = (h.dimq + 3) / 4 * 4;
+    h.ldy = (g.m + 3) / 4 * 4;
+    bl.nc_bt = std::max(bl.nc_bt, g.nc_bt);
+    bl.nc_at = std::max(bl.nc_at, g.nc_at);
+    bl.kmax = std::max(bl.kmax, h.K);
+    h.cnt[BF_RAY] = ray_blocks(g);
+    h.cnt[BF_PIX] = pixel_blocks(g);
+    h.cnt[BF_VQ] = vec_blocks(h.dimq);
+    h.cnt[BF_VM] = vec_blocks(g.m);
+    h.cnt[BF_PADR] = (int)std::min<long long>(((long long)g.ny * g.ldR + 255) / 256, 2048);
+    h.cnt[BF_PADC] = d->has_coldom ? ((g.ldT + 31) / 32) * ((g.nx + 31) / 32) : 0;
+    h.cnt[BF_PADS] = (int)std::min<long long>(((long long)g.nv * g.ldY + 255) / 256, 4096);
+    auto take = [&](size_t elems) {
+      const size_t o = bytesT;
+      bytesT += al256(sizeof(T) * elems);
+      return o;
+    };
+    h.oQ = take((size_t)h.ldq * (h.K + 1));
+    h.oY = take((size_t)h.ldy * (h.K + 1));
+    h.os = take((size_t)h.dims);
+    h.ow = take((size_t)h.dimq);
+    h.otn = take((size_t)g.n);
+    h.otm = take((size_t)g.m);
+    h.oxp = take((size_t)g.pad_elems);
+    h.oyp = take(2 * (size_t)g.ypad_elems);
+    h.oarr = ndbl;
+    ndbl += 9 * (size_t)(h.K + 2) + (size_t)(h.K + 2) * (h.K + 2);
+    h.opart = ndbl;
+    ndbl += (size_t)std::max<long long>(
+        {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
+         (long long)h.cnt[BF_VM] * (h.K + 2), 1024LL});
+    ndbl = (ndbl + 31) / 32 * 32;
+  }
+  // workspaces
+  HIPC(c->bws.ensure(bytesT));
+  HIPC(c->bwd.ensure(sizeof(double) * ndbl));
+  HIPC(c->bwi.ensure(sizeof(int) * (size_t)ns * (CI_COUNT + 16)));
+  HIPC(c->bsd.ensure(sizeof(SliceDev<T>) * (size_t)ns));
+  const size_t slot_ints = (size_t)ns + BF_COUNT * (size_t)(ns + 1);
+  if (c->bmap.bytes < sizeof(int) * slot_ints) {
+    HIPC(hipStreamSynchronize(st));
+    HIPC(c->bmap.ensure(sizeof(int) * slot_ints));
+    if (c->bpin) HIPC(hipHostFree(c->bpin));
+    c->bpin = nullptr;
+    HIPC(hipHostMalloc((void **)&c->bpin, 2 * c->bmap.bytes, hipHostMallocDefault));
+  }
+  HIPC(c->brep.ensure(sizeof(double) * 4 * (size_t)ns));
+  if (c->bflags_n < ns) {
+    HIPC(hipStreamSynchronize(st));
+    if (c->bflags) HIPC(hipHostFree(c->bflags));
+    c->bflags = nullptr;
+    HIPC(hipHostMalloc((void **)&c->bflags, sizeof(int) * ns, hipHostMallocMapped));
+    HIPC(hipHostGetDevicePointer((void **)&c->bflags_dev, c->bflags, 0));
+    c->bflags_n = ns;
+  }
+  char *wsT = c->bws.as<char>();
+  double *wsD = c->bwd.as<double>();
+  int *wsI = c->bwi.as<int>();
+  unsigned *cnt0 = reinterpret_cast<unsigned *>(wsI + (size_t)ns * CI_COUNT);
+  // counters start at zero; each last-arriving workgroup resets its own
+  HIPC(hipMemsetAsync(cnt0, 0, sizeof(unsigned) * 16 * (size_t)ns, st));
+
+  // slice descriptors and control headers
+  std::vector<SliceDev<T>> hsd(ns);
+  std::vector<double> hdp((size_t)ns * CD_COUNT, 0.0);
+  std::vector<int> hip_((size_t)ns * CI_COUNT, 0);
+  for (int s = 0; s < ns; ++s) {
+    const SliceHost &h = sh[s];
+    const gkb_solve_opts &o = opts[s];
+    SliceDev<T> &d = hsd[s];
+    d.g = h.d->gd;
+    d.rt = rt_of<T>(*h.d);
+    d.vt = vt_of<T>(*h.d);
+    Ctl &ctl = d.ctl;
+    ctl.ip = wsI + (size_t)s * CI_COUNT;
+    ctl.dp = wsD + (size_t)s * CD_COUNT;
+    double *dp = wsD + h.oarr;
+    double **arrs[] = {&ctl.alpha, &ctl.t, &ctl.rho, &ctl.pres, &ctl.u, &ctl.Rd, &ctl.Rth, &ctl.Rphi, &ctl.c};
+    for (double **a : arrs) {
+      *a = dp;
+      dp += h.K + 2;
+    }
+    ctl.G = dp;
+    ctl.K = h.K;
+    ctl.ldG = h.K + 2;
+    ctl.host_stop = c->bflags_dev + s;
+    d.xpad = reinterpret_cast<T *>(wsT + h.oxp);
+    d.ypad = reinterpret_cast<T *>(wsT + h.oyp);
+    d.Q = reinterpret_cast<T *>(wsT + h.oQ);
+    d.Y = reinterpret_cast<T *>(wsT + h.oY);
+    d.s = reinterpret_cast<T *>(wsT + h.os);
+    d.w = reinterpret_cast<T *>(wsT + h.ow);
+    d.tn = reinterpret_cast<T *>(wsT + h.otn);
+    d.tm = reinterpret_cast<T *>(wsT + h.otm);
+    d.b = static_cast<const T *>(bv[s]);
+    d.x = static_cast<T *>(xv[s]);
+    d.ldq = h.ldq;
+    d.ldy = h.ldy;
+    d.dimq = h.dimq;
+    d.dims = h.dims;
+    d.partials = wsD + h.opart;
+    d.counter = cnt0 + 16 * (size_t)s;
+    d.has_coldom = h.d->has_coldom ? 1 : 0;
+    d.reorth = o.reorth != 0;
+    double *hd = hdp.data() + (size_t)s * CD_COUNT;
+    hd[CD_TAUE] = o.use_dp ? o.tau * o.noise_norm : 0.0;
+    hd[CD_LAMBDA] = o.lambda;
+    hd[CD_ETAEPS] = 100.0 * (sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16) * 2.0;
+    hd[CD_USEDP] = o.use_dp ? 1.0 : 0.0;
+    hd[CD_KMAX] = o.k_max;
+    c->bflags[s] = 0;
+  }
+  HIPC(hipMemcpyAsync(c->bsd.p, hsd.data(), sizeof(SliceDev<T>) * ns, hipMemcpyHostToDevice, st));
+  HIPC(hipMemcpyAsync(wsD, hdp.data(), sizeof(double) * hdp.size(), hipMemcpyHostToDevice, st));
+  HIPC(hipMemcpyAsync(wsI, hip_.data(), sizeof(int) * hip_.size(), hipMemcpyHostToDevice, st));
+  const SliceDev<T> *sd = c->bsd.as<const SliceDev<T>>();
+
+  std::vector<int> active(ns), mapbuf;
+  for (int s = 0; s < ns; ++s) active[s] = s;
+  build_map(sh, active, mapbuf, bl);
+  gkb_status stt = upload_map(c, mapbuf);
+  if (stt != GKB_OK) return stt;
+  BatchDev<T> bd{sd, c->bmap.as<const int>(), c->bmap.as<const int>() + bl.na, bl.na, 0};
+
+  const EpiCfg plain{IN_ONE, PREV_NONE, BS_NONE, 0, BS_NONE};
+  auto opA = [&](int in, int out, EpiCfg e) {
+    launch_b_pad_image<T>(bd, bl, in, st);
+    TraceScope ts(c, "fwd");
+    launch_b_fwd<T>(bd, bl, out, e, st);
+  };
+  auto opBt = [&](int in, int out, EpiCfg e) {
+    launch_b_pad_image<T>(bd, bl, in, st);
+    TraceScope ts(c, "back_adj");
+    launch_b_back_adj<T>(bd, bl, out, e, st);
+  };
+  auto opB = [&](int in, int out, EpiCfg e) {
+    launch_b_pad_sino<T>(bd, bl, in, 0, st);
+    TraceScope ts(c, "back");
+    launch_b_back<T>(bd, bl, out, e, st);
+  };
+  auto opAt = [&](int in, int out, EpiCfg e) {
+    launch_b_pad_sino<T>(bd, bl, in, 1, st);
+    TraceScope ts(c, "fwd_adj");
+    launch_b_fwd_adj<T>(bd, bl, out, e, st);
+  };
+  // w <- M^T s_{k+1} - t_{k+1} q_k   (first: w <- M^T s_1)
+  auto apply_Mt = [&](bool first) {
+    const EpiCfg e0{IN_INV_TNEXT, PREV_NONE, BS_NONE, 0, BS_NONE};
+    const EpiCfg e1 = first ? plain : EpiCfg{IN_ONE, PREV_NEG_TNEXT, BS_Q_PREV, 0, BS_NONE};
+    if (mode == MODE_BA) {
+      opBt(BS_S, BS_TM, e0);
+      opAt(BS_TM, BS_W, e1);
+    } else {
+      opAt(BS_S, BS_TN, e0);
+      opBt(BS_TN, BS_W, e1);
+    }
+  };
+
+  // start-up (k = 0 in every slice): Y_0 = b, G_00; s~_1 = rhs, t_1; q_1, alpha_1
+  launch_b_copy<T>(bd, bl, BS_B, BS_Y_CUR, st);
+  launch_b_gram<T>(bd, bl, st);
+  if (mode == MODE_BA) {
+    opB(BS_B, BS_S, EpiCfg{IN_ONE, PREV_NONE, BS_NONE, 1, BS_NONE});
+  } else {
+    launch_b_copy<T>(bd, bl, BS_B, BS_S, st);
+    launch_b_norm_to<T>(bd, bl, BS_S, BF_VM, NORM_T1, st);
+  }
+  apply_Mt(true);
+  launch_b_norm_to<T>(bd, bl, BS_W, BF_VQ, NORM_ALPHA1, st);
+  launch_b_normalize<T>(bd, bl, st);
+  launch_b_report<T>(sd, ns, 0, c->brep.as<double>(), st);
+  HIPC(hipGetLastError());
+  std::vector<double> rep(4 * (size_t)ns);
+  HIPC(hipMemcpyAsync(rep.data(), c->brep.p, sizeof(double) * rep.size(), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  std::vector<gkb_solve_info> inf(ns);
+  std::vector<int> loop;
+  for (int s = 0; s < ns; ++s) {
+    const double t1 = rep[4 * s], bb = rep[4 * s + 2];
+    const double a1 = t1 > 0.0 ? rep[4 * s + 1] : 0.0;
+    if (!std::isfinite(bb) || !std::isfinite(t1) || !std::isfinite(a1))
+      return fail(GKB_ENONFINITE, "non-finite value in b of slice " + std::to_string(s));
+    inf[s] = gkb_solve_info{};
+    inf[s].t1 = t1;
+    inf[s].alpha1 = a1;
+    int *hi = hip_.data() + (size_t)s * CI_COUNT;
+    if (!(t1 > 0.0) || !(a1 > 0.0)) {
+      hi[CI_STOP] = 1;
+      hi[CI_REASON] = GKB_STOP_BREAKDOWN;
+      inf[s].reason = GKB_STOP_BREAKDOWN;
+      inf[s].residual = std::sqrt(bb);
+      inf[s].proj_residual = t1;
+    } else {
+      hi[CI_K] = 1;
+      loop.push_back(s);
+    }
+  }
+  for (int s = 0; s < ns; ++s)
+    if (inf[s].reason == GKB_STOP_BREAKDOWN) HIPC(hipMemsetAsync(xv[s], 0, sizeof(T) * (size_t)sh[s].n, st));
+  HIPC(hipMemcpyAsync(wsI, hip_.data(), sizeof(int) * hip_.size(), hipMemcpyHostToDevice, st));
+
+  if (!loop.empty()) {
+    active = loop;
+    build_map(sh, active, mapbuf, bl);
+    stt = upload_map(c, mapbuf);
+    if (stt != GKB_OK) return stt;
+    bd = BatchDev<T>{sd, c->bmap.as<const int>(), c->bmap.as<const int>() + bl.na, bl.na, 0};
+    const int L = 4;
+    std::vector<hipEvent_t> evs(L, nullptr);
+    for (auto &e : evs) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (int k = 1; k <= bl.kmax; ++k) {
+      // s~ <- M q_k - alpha_k/t_k s~, t_{k+1}, Y_k
+      if (mode == MODE_BA) {
+        opA(BS_Q_PREV, BS_Y_CUR, plain);
+        opB(BS_Y_CUR, BS_S, EpiCfg{IN_ONE, PREV_NEG_ALPHA_OVER_T, BS_S, 1, BS_NONE});
+      } else {
+        opB(BS_Q_PREV, BS_TN, plain);
+        opA(BS_TN, BS_S, EpiCfg{IN_ONE, PREV_NEG_ALPHA_OVER_T, BS_S, 1, BS_Y_CUR});
+      }
+      apply_Mt(false);
+      {
+        TraceScope ts(c, "reorth");
+        launch_b_cgs_dots<T>(bd, bl, st);
+        launch_b_cgs_update<T>(bd, bl, 0, st);
+        launch_b_cgs_dots<T>(bd, bl, st);
+        launch_b_cgs_update<T>(bd, bl, 1, st);
+        launch_b_normalize<T>(bd, bl, st);
+      }
+      {
+        TraceScope ts(c, "gram");
+        launch_b_gram<T>(bd, bl, st);
+      }
+      {
+        TraceScope ts(c, "small_solve");
+        launch_b_small_solve<T>(bd, bl, st);
+      }
+      HIPC(hipEventRecord(evs[k % L], st));
+      if (k >= L) {
+        HIPC(hipEventSynchronize(evs[(k - L + 1) % L]));
+        std::vector<int> still;
+        for (int s : active)
+          if (!*(volatile int *)(c->bflags + s)) still.push_back(s);
+        if (still.empty()) break;
+        if (still.size() != active.size()) {
+          active.swap(still);
+          build_map(sh, active, mapbuf, bl);
+          stt = upload_map(c, mapbuf);
+          if (stt != GKB_OK) return stt;
+          bd = BatchDev<T>{sd, c->bmap.as<const int>(), c->bmap.as<const int>() + bl.na, bl.na, 0};
+        }
+      }
+    }
+    HIPC(hipGetLastError());
+    // solutions of every slice that iterated: x = Q u (BA) or B (Q u) (AB)
+    active = loop;
+    build_map(sh, active, mapbuf, bl);
+    stt = upload_map(c, mapbuf);
+    if (stt != GKB_OK) return stt;
+    bd = BatchDev<T>{sd, c->bmap.as<const int>(), c->bmap.as<const int>() + bl.na, bl.na, 1};
+    if (mode == MODE_BA) {
+      launch_b_solution<T>(bd, bl, BS_X, st);
+    } else {
+      launch_b_solution<T>(bd, bl, BS_TM, st);
+      opB(BS_TM, BS_X, plain);
+    }
+    launch_b_report<T>(sd, ns, 1, c->brep.as<double>(), st);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(rep.data(), c->brep.p, sizeof(double) * rep.size(), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    for (auto &e : evs) (void)hipEventDestroy(e);
+    for (int s : loop) {
+      inf[s].k_stop = (int)rep[4 * s];
+      inf[s].reason = (int)rep[4 * s + 1];
+      inf[s].residual = rep[4 * s + 2];
+      inf[s].proj_residual = rep[4 * s + 3];
+    }
+  }
+  // optional histories
+  for (int s = 0; s < ns; ++s) {
+    const gkb_solve_opts &o = opts[s];
+    if (!o.residual_history && !o.alpha_history && !o.t_history) continue;
+    const Ctl &ctl = hsd[s].ctl;
+    const int K = sh[s].K, ks = inf[s].k_stop;
+    std::vector<double> buf(K + 2);
+    if (o.residual_history) {
+      HIPC(hipMemcpy(buf.data(), ctl.rho, sizeof(double) * (K + 2), hipMemcpyDeviceToHost));
+      for (int k = 1; k <= ks; ++k) o.residual_history[k - 1] = buf[k];
+    }
+    if (o.alpha_history) {
+      HIPC(hipMemcpy(buf.data(), ctl.alpha, sizeof(double) * (K + 2), hipMemcpyDeviceToHost));
+      buf[1] = inf[s].alpha1;  // 0 (not 0/0) when t_1 = 0
+      for (int k = 1; k <= K + 1; ++k) o.alpha_history[k - 1] = k <= ks + 1 ? buf[k] : 0.0;
+    }
+    if (o.t_history) {
+      HIPC(hipMemcpy(buf.data(), ctl.t, sizeof(double) * (K + 2), hipMemcpyDeviceToHost));
+      for (int k = 1; k <= K + 1; ++k) o.t_history[k - 1] = k <= ks + 1 ? buf[k] : 0.0;
+    }
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  for (int s = 0; s < ns; ++s) {
+    inf[s].seconds = secs;
+    if (info) info[s] = inf[s];
+  }
+  return GKB_OK;
+}
+
+gkb_status batch_entry(gkb_ctx *c, int method, int ns, const gkb_geometry *geoms, int dtype,
+                       const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (method != GKB_METHOD_AB && method != GKB_METHOD_BA) return fail(GKB_EINVAL, "method must be AB or BA");
+  if (ns < 1 || ns > 1024) return fail(GKB_EINVAL, "n_slices must be in [1, 1024]");
+  if (!geoms || !b || !opts || !x) return fail(GKB_EINVAL, "NULL array argument");
+  for (int s = 0; s < ns; ++s) {
+    gkb_status st = validate_geom(&geoms[s], dtype);
+    if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
+    st = validate_opts(&opts[s]);
+    if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
+    if (!b[s] || !x[s]) return fail(GKB_EINVAL, "slice " + std::to_string(s) + ": data pointer is NULL");
+  }
+  HIPC(hipSetDevice(c->device));
+  const int mode = method == GKB_METHOD_AB ? MODE_AB : MODE_BA;
+  return dtype == GKB_F32 ? batch_impl<float>(c, mode, ns, geoms, dtype, b, opts, x, info)
+                          : batch_impl<double>(c, mode, ns, geoms, dtype, b, opts, x, info);
 }
 
 }  // namespace
@@ -952,6 +1364,10 @@ void gkb_destroy(gkb_ctx *c) {
   c->flush_trace();
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   if (c->host_flag) (void)hipHostFree(c->host_flag);
+  if (c->bflags) (void)hipHostFree(c->bflags);
+  if (c->bpin) (void)hipHostFree(c->bpin);
+  for (hipEvent_t e : c->bpin_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -998,6 +1414,11 @@ gkb_status gkb_ba_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void
 gkb_status gkb_gkb_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
                          void *x, gkb_solve_info *info) {
   return solve_entry(c, g, dtype, b, o, x, info, MODE_GKB);
+}
+
+gkb_status gkb_batch_solve(gkb_ctx *c, int method, int n_slices, const gkb_geometry *geoms, int dtype,
+                           const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info) {
+  return batch_entry(c, method, n_slices, geoms, dtype, b, opts, x, info);
 }
 
 gkb_status gkb_trace_enable(gkb_ctx *c, int on) {

@@ -142,6 +142,86 @@ struct GeomDev {
   double uclamp_at;    // A^T: detector coordinates are clamped to [-uclamp_at, nu-1+uclamp_at]
 };
 
+// Workgroup index and count within one slice's share of a launch.
+struct Blk {
+  unsigned id;
+  unsigned n;
+};
+
+// ---- batched multi-slice solves ----
+// Vector operands of a batched launch, resolved per slice on the device
+// (k = the slice's iteration counter).
+enum BufSel : int {
+  BS_NONE = 0,
+  BS_B,       // right-hand side b
+  BS_X,       // solution x
+  BS_S,       // s~ (unnormalised s)
+  BS_W,       // w (q~ before normalisation)
+  BS_TN,      // n-vector temporary
+  BS_TM,      // m-vector temporary
+  BS_Q_PREV,  // Q[:, k-1] = q_k
+  BS_Y_CUR    // Y[:, k]
+};
+
+// Everything one slice of a batch needs on the device.
+template <typename T>
+struct SliceDev {
+  GeomDev g;
+  RayTab<T> rt;
+  ViewTab<T> vt;
+  Ctl ctl;
+  T *xpad, *ypad;
+  T *Q, *Y, *s, *w, *tn, *tm;
+  const T *b;
+  T *x;
+  long long ldq, ldy, dimq, dims;
+  double *partials;
+  unsigned *counter;
+  int has_coldom;
+  int reorth;
+};
+
+// Families of per-slice workgroup counts.  pre[f * (na + 1) + a] is the first
+// workgroup of active slice a in a launch of family f; pre[f * (na + 1) + na]
+// is the launch's total.
+enum BlockFam : int {
+  BF_RAY = 0,  // ray-driven projectors: ceil(m / 256)
+  BF_PIX,      // pixel-driven projectors: 32x8 tiles
+  BF_VQ,       // vector kernels over Q's dimension
+  BF_VM,       // vector kernels over m
+  BF_PADR,     // row-major image padding
+  BF_PADC,     // column-major image padding (32x32 tiles)
+  BF_PADS,     // sinogram padding
+  BF_COUNT
+};
+
+template <typename T>
+struct BatchDev {
+  const SliceDev<T> *sd;  // [n_slices]
+  const int *active;      // [na] slice ids
+  const int *pre;         // [BF_COUNT][na + 1]
+  int na;
+  int ignore_stop;        // 1: run on stopped slices too
+};
+
+// Host-side summary of a batched launch configuration.
+struct BatchLaunch {
+  int na;
+  int tot[BF_COUNT];
+  int kmax;      // largest k_max over the slices
+  int fan;       // all slices fan beam (else all parallel beam)
+  int nc_bt, nc_at;
+};
+
+// Epilogue selection of a batched projector launch (see Epi).
+struct EpiCfg {
+  int in_sel;
+  int prev_sel;
+  int prev_buf;     // BufSel of prev
+  int norm_to_t;
+  int out_raw_buf;  // BufSel of out_raw or BS_NONE
+};
+
 // ---- launchers (proj2d.hip) ----
 template <typename T>
 void launch_pad_image(const GeomDev &g, Col<const T> x, T *pad, bool cols, const int *stop, hipStream_t s);
@@ -178,7 +258,7 @@ void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long di
                      unsigned *counter, hipStream_t s);
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
-                       unsigned *counter, hipStream_t s);
+                       unsigned *counter, hipStream_t s, int reorth = 1);
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s);
 template <typename T>
@@ -191,5 +271,39 @@ void launch_set_int(int *p, int v, hipStream_t s);
 
 // norm targets for launch_norm_to
 enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1 };
+
+// ---- batched launchers: one launch covers every active slice ----
+template <typename T>
+void launch_b_pad_image(const BatchDev<T> &bd, const BatchLaunch &bl, int in_sel, hipStream_t s);
+template <typename T>
+void launch_b_pad_sino(const BatchDev<T> &bd, const BatchLaunch &bl, int in_sel, int adj, hipStream_t s);
+template <typename T>
+void launch_b_fwd(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s);
+template <typename T>
+void launch_b_back_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s);
+template <typename T>
+void launch_b_back(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s);
+template <typename T>
+void launch_b_fwd_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s);
+template <typename T>
+void launch_b_copy(const BatchDev<T> &bd, const BatchLaunch &bl, int src_sel, int dst_sel, hipStream_t s);
+template <typename T>
+void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int fam, int which, hipStream_t s);
+template <typename T>
+void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+template <typename T>
+void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s);
+template <typename T>
+void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+template <typename T>
+void launch_b_gram(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+template <typename T>
+void launch_b_small_solve(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+template <typename T>
+void launch_b_solution(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, hipStream_t s);
+template <typename T>
+void launch_b_set_k(const BatchDev<T> &bd, const BatchLaunch &bl, int k, hipStream_t s);
+template <typename T>
+void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipStream_t s);
 
 }  // namespace gkb

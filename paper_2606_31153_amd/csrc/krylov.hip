@@ -22,6 +22,7 @@
 
 #include <algorithm>
 
+#include "batch.h"
 #include "internal.h"
 #include "reduce.h"
 
@@ -91,16 +92,14 @@ __device__ inline void store_quad(T *__restrict__ p, long long r, long long dim,
 // Q against w (reorthogonalisation); gram == 1: columns 0..k of Y against
 // Y_k (Gram row k).  Result: partials[x * ldp + column].
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dots(Ctl ctl, const T *__restrict__ V, long long ld,
-                                                 const T *__restrict__ w, long long dim, double *partials, int gram) {
-  if (ctl.ip[CI_STOP]) return;
+__device__ inline void dots_body(const Ctl &ctl, const T *__restrict__ V, long long ld, const T *__restrict__ w,
+                                 long long dim, double *partials, int gram, unsigned bx, unsigned by, int ncol) {
   const int k = ctl.ip[CI_K];
-  const int ncol = gram ? k + 1 : k;
-  const int c0 = blockIdx.y * CH;
+  const int c0 = by * CH;
   if (c0 >= ncol) return;
   __shared__ double lds[(kBlock / 64) * CH];
   const T *__restrict__ wv = gram ? V + (long long)k * ld : w;
-  const long long r = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  const long long r = ((long long)bx * kBlock + threadIdx.x) * RPT;
   double wq[RPT];
   load_quad(wv, r, dim, wq);
   double acc[CH];
@@ -116,18 +115,23 @@ __global__ __launch_bounds__(kBlock) void k_dots(Ctl ctl, const T *__restrict__ 
   }
   const double sum = block_sum_vec(acc, lds);
   if (threadIdx.x < CH && c0 + (int)threadIdx.x < ncol)
-    partials[(long long)blockIdx.x * (ctl.K + 2) + c0 + threadIdx.x] = sum;
+    partials[(long long)bx * (ctl.K + 2) + c0 + threadIdx.x] = sum;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dots(Ctl ctl, const T *__restrict__ V, long long ld,
+                                                 const T *__restrict__ w, long long dim, double *partials, int gram) {
+  if (ctl.ip[CI_STOP]) return;
+  const int k = ctl.ip[CI_K];
+  dots_body(ctl, V, ld, w, dim, partials, gram, blockIdx.x, blockIdx.y, gram ? k + 1 : k);
 }
 
 // ---- column sums of the per-workgroup partials: one workgroup per column ----
 // which == 0: c[col] (col < k);  which == 1: Gram row k, G[k][col] = G[col][k] (col <= k)
-__global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *__restrict__ partials, int nb,
-                                                        int which) {
-  if (ctl.ip[CI_STOP]) return;
+__device__ inline void reduce_cols_body(const Ctl &ctl, const double *__restrict__ partials, int nb, int which,
+                                        int col, int ncol) {
   __shared__ double lds[kBlock / 64];
   const int k = ctl.ip[CI_K];
-  const int col = blockIdx.x;
-  const int ncol = which == 0 ? k : k + 1;
   if (col >= ncol) return;
   const int ldp = ctl.K + 2;
   double acc = 0.0;
@@ -143,22 +147,28 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *_
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *__restrict__ partials, int nb,
+                                                        int which) {
+  if (ctl.ip[CI_STOP]) return;
+  const int k = ctl.ip[CI_K];
+  reduce_cols_body(ctl, partials, nb, which, blockIdx.x, which == 0 ? k : k + 1);
+}
+
 // ---- w -= Q[:, 0..k-1] c (FP64 per element); last == 1: alpha[k+1] = ||w|| ----
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restrict__ Q, long long ld,
-                                                       T *__restrict__ w, long long dim, int last,
-                                                       double *partials, unsigned *counter) {
-  if (ctl.ip[CI_STOP]) return;
+__device__ inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q, long long ld, T *__restrict__ w,
+                                       long long dim, int last, double *partials, unsigned *counter, Blk b,
+                                       int ncols) {
   __shared__ double lds[kBlock / 64];
   const int k = ctl.ip[CI_K];
   const double *__restrict__ cc = ctl.c;
-  const long long r = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  const long long r = ((long long)b.id * kBlock + threadIdx.x) * RPT;
   double acc[RPT];
   load_quad(w, r, dim, acc);
-  for (int c0 = 0; c0 < k; c0 += CH) {
+  for (int c0 = 0; c0 < ncols; c0 += CH) {
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
-      if (c0 + j < k) {
+      if (c0 + j < ncols) {
         double q[RPT];
         load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
         const double cj = cc[c0 + j];
@@ -177,10 +187,10 @@ __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restr
   if (r < dim) store_quad(w, r, dim, out);
   if (last) {
     const double s = block_sum<kBlock>(nrm, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    if (arrive_last(counter, gridDim.x)) {
+    if (threadIdx.x == 0) partials[b.id] = s;
+    if (arrive_last(counter, b.n)) {
       double a = 0.0;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock) a += partials[b];
+      for (unsigned i = threadIdx.x; i < b.n; i += kBlock) a += partials[i];
       const double tot = block_sum<kBlock>(a, lds);
       if (threadIdx.x == 0) {
         ctl.alpha[k + 1] = sqrt(tot);
@@ -190,15 +200,24 @@ __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restr
   }
 }
 
+// reorth == 0: no columns, only alpha[k+1] = ||w|| (with last == 1)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restrict__ Q, long long ld,
+                                                       T *__restrict__ w, long long dim, int last,
+                                                       double *partials, unsigned *counter, int reorth) {
+  if (ctl.ip[CI_STOP]) return;
+  cgs_update_body(ctl, Q, ld, w, dim, last, partials, counter, Blk{blockIdx.x, gridDim.x},
+                  reorth ? ctl.ip[CI_K] : 0);
+}
+
 // ---- Q[:, k] = w / alpha[k+1] ------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restrict__ w, T *__restrict__ Q,
-                                                      long long ld, long long dim) {
-  if (ctl.ip[CI_STOP]) return;
+__device__ inline void normalize_body(const Ctl &ctl, const T *__restrict__ w, T *__restrict__ Q, long long ld,
+                                      long long dim, unsigned blk) {
   const int k = ctl.ip[CI_K];
   const double inv = 1.0 / ctl.alpha[k + 1];
   T *q = Q + (long long)k * ld;
-  const long long r = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  const long long r = ((long long)blk * kBlock + threadIdx.x) * RPT;
   if (r >= dim) return;
   double v[RPT];
   load_quad(w, r, dim, v);
@@ -206,6 +225,13 @@ __global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restri
 #pragma unroll
   for (int i = 0; i < RPT; ++i) out[i] = (T)(v[i] * inv);
   store_quad(q, r, dim, out);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restrict__ w, T *__restrict__ Q,
+                                                      long long ld, long long dim) {
+  if (ctl.ip[CI_STOP]) return;
+  normalize_body(ctl, w, Q, ld, dim, blockIdx.x);
 }
 
 // ---- projected solve, discrepancy test, advance --------------------------------
@@ -217,8 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restri
 constexpr int kSolveThreads = 256;
 constexpr int kMaxKLds = 4096;
 
-__global__ __launch_bounds__(kSolveThreads) void k_small_solve(Ctl ctl) {
-  if (ctl.ip[CI_STOP]) return;
+__device__ inline void small_solve_body(const Ctl &ctl) {
   __shared__ double s_u[kMaxKLds + 2];
   __shared__ double s_rd[kMaxKLds + 2];
   __shared__ double s_rth[kMaxKLds + 2];
@@ -324,13 +349,18 @@ __global__ __launch_bounds__(kSolveThreads) void k_small_solve(Ctl ctl) {
   }
 }
 
+__global__ __launch_bounds__(kSolveThreads) void k_small_solve(Ctl ctl) {
+  if (ctl.ip[CI_STOP]) return;
+  small_solve_body(ctl);
+}
+
 // ---- out = sum_{i=1..k_stop} u_i Q[:, i-1] -------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_solution(Ctl ctl, const T *__restrict__ Q, long long ld,
-                                                     long long dim, T *__restrict__ out) {
+__device__ inline void solution_body(const Ctl &ctl, const T *__restrict__ Q, long long ld, long long dim,
+                                     T *__restrict__ out, Blk b) {
   const int ks = ctl.ip[CI_KSTOP];
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < dim; r += stride) {
+  const long long stride = (long long)b.n * kBlock;
+  for (long long r = (long long)b.id * kBlock + threadIdx.x; r < dim; r += stride) {
     double acc = 0.0;
     for (int i = 1; i <= ks; ++i) acc = fma(ctl.u[i], (double)Q[(long long)(i - 1) * ld + r], acc);
     out[r] = (T)acc;
@@ -338,28 +368,38 @@ __global__ __launch_bounds__(kBlock) void k_solution(Ctl ctl, const T *__restric
 }
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void k_solution(Ctl ctl, const T *__restrict__ Q, long long ld,
+                                                     long long dim, T *__restrict__ out) {
+  solution_body(ctl, Q, ld, dim, out, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__device__ inline void copy_body(const T *__restrict__ a, T *__restrict__ b, long long n, Blk blk) {
+  const long long stride = (long long)blk.n * kBlock;
+  for (long long r = (long long)blk.id * kBlock + threadIdx.x; r < n; r += stride) b[r] = a[r];
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ a, T *__restrict__ b, long long n) {
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < n; r += stride) b[r] = a[r];
+  copy_body(a, b, n, Blk{blockIdx.x, gridDim.x});
 }
 
 // ||v|| into t[k+1] (which == NORM_T1) or alpha[k+1] (NORM_ALPHA1)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_norm_to(Ctl ctl, const T *__restrict__ v, long long dim, int which,
-                                                    double *partials, unsigned *counter) {
-  if (ctl.ip[CI_STOP]) return;
+__device__ inline void norm_to_body(const Ctl &ctl, const T *__restrict__ v, long long dim, int which,
+                                    double *partials, unsigned *counter, Blk b) {
   __shared__ double lds[kBlock / 64];
-  const long long stride = (long long)gridDim.x * kBlock;
+  const long long stride = (long long)b.n * kBlock;
   double acc = 0.0;
-  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < dim; r += stride) {
+  for (long long r = (long long)b.id * kBlock + threadIdx.x; r < dim; r += stride) {
     const double x = (double)v[r];
     acc = fma(x, x, acc);
   }
   const double s = block_sum<kBlock>(acc, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (arrive_last(counter, gridDim.x)) {
+  if (threadIdx.x == 0) partials[b.id] = s;
+  if (arrive_last(counter, b.n)) {
     double a = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock) a += partials[b];
+    for (unsigned i = threadIdx.x; i < b.n; i += kBlock) a += partials[i];
     const double tot = block_sum<kBlock>(a, lds);
     if (threadIdx.x == 0) {
       const int k = ctl.ip[CI_K];
@@ -372,7 +412,119 @@ __global__ __launch_bounds__(kBlock) void k_norm_to(Ctl ctl, const T *__restrict
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_norm_to(Ctl ctl, const T *__restrict__ v, long long dim, int which,
+                                                    double *partials, unsigned *counter) {
+  if (ctl.ip[CI_STOP]) return;
+  norm_to_body(ctl, v, dim, which, partials, counter, Blk{blockIdx.x, gridDim.x});
+}
+
 __global__ void k_set_int(int *p, int v) { *p = v; }
+
+// ---- batched launches (see proj2d.hip): one grid over every active slice ----
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_copy(BatchDev<T> bd, int src_sel, int dst_sel) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_VM, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  copy_body<T>(resolve(d, src_sel, k), resolve(d, dst_sel, k), d.g.m, b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_norm_to(BatchDev<T> bd, int sel, int fam, int which) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, fam, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  norm_to_body<T>(d.ctl, resolve(d, sel, k), fam == BF_VM ? d.g.m : d.dimq, which, d.partials, d.counter, b);
+}
+
+// gram == 0: Q^T w for reorthogonalisation (no columns when the slice does
+// not reorthogonalise); gram == 1: Gram row k of Y
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_dots(BatchDev<T> bd, int gram) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, gram ? BF_VM : BF_VQ, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  if (gram)
+    dots_body<T>(d.ctl, d.Y, d.ldy, nullptr, d.g.m, d.partials, 1, b.id, blockIdx.y, k + 1);
+  else
+    dots_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, d.partials, 0, b.id, blockIdx.y, d.reorth ? k : 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_reduce_cols(BatchDev<T> bd, int which) {
+  const int a = blockIdx.y;
+  const SliceDev<T> &d = bd.sd[bd.active[a]];
+  if (skip(bd, d)) return;
+  const int fam = which == 0 ? BF_VQ : BF_VM;
+  const int *pre = bd.pre + fam * (bd.na + 1);
+  const int k = d.ctl.ip[CI_K];
+  const int ncol = which == 0 ? (d.reorth ? k : 0) : k + 1;
+  reduce_cols_body(d.ctl, d.partials, pre[a + 1] - pre[a], which, blockIdx.x, ncol);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_cgs_update(BatchDev<T> bd, int last) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  cgs_update_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, last, d.partials, d.counter, b, d.reorth ? k : 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_normalize(BatchDev<T> bd) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  normalize_body<T>(d.ctl, d.w, d.Q, d.ldq, d.dimq, b.id);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSolveThreads) void kb_small_solve(BatchDev<T> bd) {
+  const SliceDev<T> &d = bd.sd[bd.active[blockIdx.x]];
+  if (skip(bd, d)) return;
+  small_solve_body(d.ctl);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_solution(BatchDev<T> bd, int out_sel) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
+  solution_body<T>(d.ctl, d.Q, d.ldq, d.dimq, resolve(d, out_sel, 0), b);
+}
+
+// Per-slice scalars for the host, 4 per slice.  phase 0: t_1, alpha_1,
+// ||b||^2; phase 1: k_stop, reason, rho[k_stop], pres[k_stop].
+template <typename T>
+__global__ void kb_report(const SliceDev<T> *sd, int ns, int phase, double *out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  const Ctl &c = sd[s].ctl;
+  if (phase == 0) {
+    out[4 * s] = c.t[1];
+    out[4 * s + 1] = c.alpha[1];
+    out[4 * s + 2] = c.G[0];
+    out[4 * s + 3] = 0.0;
+  } else {
+    const int ks = c.ip[CI_KSTOP];
+    out[4 * s] = ks;
+    out[4 * s + 1] = c.ip[CI_REASON];
+    out[4 * s + 2] = ks > 0 ? c.rho[ks] : 0.0;
+    out[4 * s + 3] = ks > 0 ? c.pres[ks] : 0.0;
+  }
+}
+
+template <typename T>
+__global__ void kb_set_k(BatchDev<T> bd, int k) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= bd.na) return;
+  const SliceDev<T> &d = bd.sd[bd.active[a]];
+  if (!d.ctl.ip[CI_STOP]) d.ctl.ip[CI_K] = k;
+}
 
 }  // namespace
 
@@ -404,9 +556,10 @@ void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long di
 }
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
-                       unsigned *counter, hipStream_t s) {
+                       unsigned *counter, hipStream_t s, int reorth) {
   const int nb = vec_blocks(dim);
-  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, counter);
+  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, counter,
+                     reorth);
 }
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s) {
@@ -430,16 +583,73 @@ void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, h
   hipLaunchKernelGGL(k_solution<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, Q, ld, dim, out);
 }
 
+// ---- batched launchers ----
+template <typename T>
+void launch_b_copy(const BatchDev<T> &bd, const BatchLaunch &bl, int src_sel, int dst_sel, hipStream_t s) {
+  if (bl.tot[BF_VM] > 0) hipLaunchKernelGGL(kb_copy<T>, dim3(bl.tot[BF_VM]), dim3(kBlock), 0, s, bd, src_sel, dst_sel);
+}
+template <typename T>
+void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int fam, int which, hipStream_t s) {
+  if (bl.tot[fam] > 0)
+    hipLaunchKernelGGL(kb_norm_to<T>, dim3(bl.tot[fam]), dim3(kBlock), 0, s, bd, sel, fam, which);
+}
+template <typename T>
+void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+  if (bl.tot[BF_VQ] <= 0) return;
+  hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VQ], (bl.kmax + CH) / CH), dim3(kBlock), 0, s, bd, 0);
+  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 1, bl.na), dim3(kBlock), 0, s, bd, 0);
+}
+template <typename T>
+void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s) {
+  if (bl.tot[BF_VQ] > 0) hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd, last);
+}
+template <typename T>
+void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+  if (bl.tot[BF_VQ] > 0) hipLaunchKernelGGL(kb_normalize<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd);
+}
+template <typename T>
+void launch_b_gram(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+  if (bl.tot[BF_VM] <= 0) return;
+  hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VM], (bl.kmax + 1 + CH) / CH), dim3(kBlock), 0, s, bd, 1);
+  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 2, bl.na), dim3(kBlock), 0, s, bd, 1);
+}
+template <typename T>
+void launch_b_small_solve(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+  if (bl.na > 0) hipLaunchKernelGGL(kb_small_solve<T>, dim3(bl.na), dim3(kSolveThreads), 0, s, bd);
+}
+template <typename T>
+void launch_b_solution(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, hipStream_t s) {
+  if (bl.tot[BF_VQ] > 0) hipLaunchKernelGGL(kb_solution<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd, out_sel);
+}
+template <typename T>
+void launch_b_set_k(const BatchDev<T> &bd, const BatchLaunch &bl, int k, hipStream_t s) {
+  if (bl.na > 0) hipLaunchKernelGGL(kb_set_k<T>, dim3((bl.na + 255) / 256), dim3(256), 0, s, bd, k);
+}
+template <typename T>
+void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipStream_t s) {
+  if (ns > 0) hipLaunchKernelGGL(kb_report<T>, dim3((ns + 255) / 256), dim3(256), 0, s, sd, ns, phase, out);
+}
+
 #define GKB_INST(T)                                                                                         \
   template void launch_copy<T>(const T *, T *, long long, hipStream_t);                                    \
   template void launch_norm_to<T>(Ctl, const T *, long long, int, double *, unsigned *, hipStream_t);      \
   template void launch_cgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, unsigned *,  \
                                    hipStream_t);                                                           \
   template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, unsigned *, \
-                                     hipStream_t);                                                         \
+                                     hipStream_t, int);                                                         \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t);               \
   template void launch_gram<T>(Ctl, const T *, long long, long long, int, double *, unsigned *, hipStream_t); \
-  template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);
+  template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
+  template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
+  template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
+  template void launch_b_cgs_dots<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                \
+  template void launch_b_cgs_update<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);         \
+  template void launch_b_normalize<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);               \
+  template void launch_b_gram<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                    \
+  template void launch_b_small_solve<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);             \
+  template void launch_b_solution<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);           \
+  template void launch_b_set_k<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);              \
+  template void launch_b_report<T>(const SliceDev<T> *, int, int, double *, hipStream_t);
 GKB_INST(float)
 GKB_INST(double)
 #undef GKB_INST

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 
+#include "batch.h"
 #include "internal.h"
 #include "reduce.h"
 
@@ -90,7 +91,7 @@ __device__ inline double fast_rcp(double x) { return 1.0 / x; }
 // Epilogue shared by all projector kernels.  Every thread of the block calls
 // it (the norm reduction needs the whole block).
 template <typename T>
-__device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T raw, T *outp) {
+__device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T raw, T *outp, Blk b) {
   __shared__ double red[kBlock / 64];
   double out = (double)raw;
   int k = 0;
@@ -111,8 +112,8 @@ __device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T ra
   if (e.norm_to_t) {
     const double v = valid ? (double)outT * (double)outT : 0.0;
     const double bs = block_sum<kBlock>(v, red);
-    const unsigned nb = gridDim.x;
-    if (threadIdx.x == 0) e.partials[blockIdx.x] = bs;
+    const unsigned nb = b.n;
+    if (threadIdx.x == 0) e.partials[b.id] = bs;
     if (arrive_last(e.counter, nb)) {
       double acc = 0.0;
       for (unsigned b = threadIdx.x; b < nb; b += kBlock) acc += e.partials[b];
@@ -130,25 +131,22 @@ __device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T ra
 // ---------------------------------------------------------------------------
 // row-major region: ny lines of ldR = nx + 2P (image row j at line j)
 template <typename T>
-__global__ __launch_bounds__(256) void k_pad_rows(Col<const T> xc, T *__restrict__ pad, int nx, int ny, int P,
-                                                  int ldR, const int *stop) {
-  if (stop && *stop) return;
-  const T *__restrict__ x = xc.get();
+__device__ inline void pad_rows_body(const T *__restrict__ x, T *__restrict__ pad, int nx, int ny, int P, int ldR,
+                                     Blk b) {
   const long long total = (long long)ny * ldR;
-  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+  for (long long idx = (long long)b.id * 256 + threadIdx.x; idx < total; idx += (long long)b.n * 256) {
     const int j = (int)(idx / ldR), i = (int)(idx - (long long)j * ldR) - P;
     pad[idx] = ((unsigned)i < (unsigned)nx) ? x[(long long)j * nx + i] : T(0);
   }
 }
 
-// column-major region at offset offT: nx lines of ldT = ny + 2P (image column i at line i)
+// column-major region at offset offT: nx lines of ldT = ny + 2P (image column
+// i at line i); tile (bx, by) covers padded rows 32 bx.. and columns 32 by..
 template <typename T>
-__global__ __launch_bounds__(256) void k_pad_cols(Col<const T> xc, T *__restrict__ pad, int nx, int ny, int P,
-                                                  int ldT, long long offT, const int *stop) {
-  if (stop && *stop) return;
-  const T *__restrict__ x = xc.get();
+__device__ inline void pad_cols_body(const T *__restrict__ x, T *__restrict__ pad, int nx, int ny, int P, int ldT,
+                                     long long offT, int bx, int by) {
   __shared__ T tile[32][33];
-  const int jp0 = blockIdx.x * 32, i0 = blockIdx.y * 32;  // tile of the padded column-major image
+  const int jp0 = bx * 32, i0 = by * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r = ty; r < 32; r += 8) {
     const int j = jp0 + r - P, i = i0 + tx;  // source pixel (i, j)
@@ -163,25 +161,64 @@ __global__ __launch_bounds__(256) void k_pad_cols(Col<const T> xc, T *__restrict
 
 // sinogram rows padded by PY zeros on both sides: nv lines of ldY = nu + 2 PY
 template <typename T>
-__global__ __launch_bounds__(256) void k_pad_sino(Col<const T> yc, T *__restrict__ pad, int nv, int nu, int PY,
-                                                  int ldY, const int *stop) {
-  if (stop && *stop) return;
-  const T *__restrict__ y = yc.get();
+__device__ inline void pad_sino_body(const T *__restrict__ y, T *__restrict__ pad, int nv, int nu, int PY, int ldY,
+                                     Blk b) {
   const long long total = (long long)nv * ldY;
-  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
+  for (long long idx = (long long)b.id * 256 + threadIdx.x; idx < total; idx += (long long)b.n * 256) {
     const int v = (int)(idx / ldY), k = (int)(idx - (long long)v * ldY) - PY;
     pad[idx] = ((unsigned)k < (unsigned)nu) ? y[(long long)v * nu + k] : T(0);
   }
+}
+
+// (w y, w) per padded bin for the fan-beam A^T: w = 1/|d_dom| per ray in padded layout
+template <typename T>
+__device__ inline void pad_sino_w_body(const T *__restrict__ y, const T *__restrict__ wpad, T *__restrict__ out,
+                                       int nv, int nu, int PY, int ldY, Blk b) {
+  const long long total = (long long)nv * ldY;
+  for (long long idx = (long long)b.id * 256 + threadIdx.x; idx < total; idx += (long long)b.n * 256) {
+    const int v = (int)(idx / ldY), k = (int)(idx - (long long)v * ldY) - PY;
+    const T yv = ((unsigned)k < (unsigned)nu) ? y[(long long)v * nu + k] : T(0);
+    const T w = wpad[idx];
+    out[2 * idx] = w * yv;
+    out[2 * idx + 1] = w;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_rows(Col<const T> xc, T *__restrict__ pad, int nx, int ny, int P,
+                                                  int ldR, const int *stop) {
+  if (stop && *stop) return;
+  pad_rows_body(xc.get(), pad, nx, ny, P, ldR, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_cols(Col<const T> xc, T *__restrict__ pad, int nx, int ny, int P,
+                                                  int ldT, long long offT, const int *stop) {
+  if (stop && *stop) return;
+  pad_cols_body(xc.get(), pad, nx, ny, P, ldT, offT, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_sino(Col<const T> yc, T *__restrict__ pad, int nv, int nu, int PY,
+                                                  int ldY, const int *stop) {
+  if (stop && *stop) return;
+  pad_sino_body(yc.get(), pad, nv, nu, PY, ldY, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_sino_w(Col<const T> yc, const T *__restrict__ wpad, T *__restrict__ out,
+                                                    int nv, int nu, int PY, int ldY, const int *stop) {
+  if (stop && *stop) return;
+  pad_sino_w_body(yc.get(), wpad, out, nv, nu, PY, ldY, Blk{blockIdx.x, gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
 // ray-driven: A (Joseph forward)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
-                                                Epi<T> e, const int *stop) {
-  if (stop && *stop) return;
-  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+__device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
+                                const Epi<T> &e, Blk b) {
+  const long long r = (long long)b.id * kBlock + threadIdx.x;
   const bool valid = r < g.m;
   T acc = T(0);
   if (valid) {
@@ -228,7 +265,14 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
     a0 += a2;
     acc = a0 * rt.w[r];
   }
-  epilogue(e, r, valid, acc, yc.get());
+  epilogue(e, r, valid, acc, yo, b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
+                                                Epi<T> e, const int *stop) {
+  if (stop && *stop) return;
+  fwd_body(g, rt, pad, yc.get(), e, Blk{blockIdx.x, gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -238,10 +282,9 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // within h of the ray's crossing: NC consecutive pixels from ceil(c - h).
 // ---------------------------------------------------------------------------
 template <typename T, bool FAN, int NC>
-__global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
-                                                     Epi<T> e, const int *stop) {
-  if (stop && *stop) return;
-  const long long r = (long long)blockIdx.x * kBlock + threadIdx.x;
+__device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
+                                     const Epi<T> &e, Blk b) {
+  const long long r = (long long)b.id * kBlock + threadIdx.x;
   const bool valid = r < g.m;
   T acc = T(0);
   if (valid) {
@@ -304,25 +347,31 @@ __global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, co
       }
     }
   }
-  epilogue(e, r, valid, acc, yc.get());
+  epilogue(e, r, valid, acc, yo, b);
+}
+
+template <typename T, bool FAN, int NC>
+__global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
+                                                     Epi<T> e, const int *stop) {
+  if (stop && *stop) return;
+  back_adj_body<T, FAN, NC>(g, rt, pad, yc.get(), e, Blk{blockIdx.x, gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
 // pixel-driven: B (back projection by linear interpolation on the detector)
 // ---------------------------------------------------------------------------
-__device__ inline void tile_pixel(const GeomDev &g, int &i, int &j) {
+__device__ inline void tile_pixel(const GeomDev &g, unsigned blk, int &i, int &j) {
   const int tiles_x = (g.nx + 31) >> 5;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = (int)blk % tiles_x, ty = (int)blk / tiles_x;
   i = tx * 32 + (threadIdx.x & 31);
   j = ty * 8 + (threadIdx.x >> 5);
 }
 
 template <typename T, bool FAN>
-__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
-                                                 T *__restrict__ xo, Epi<T> e, const int *stop) {
-  if (stop && *stop) return;
+__device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
+                                 const Epi<T> &e, Blk b) {
   int i, j;
-  tile_pixel(g, i, j);
+  tile_pixel(g, b.id, i, j);
   const bool valid = i < g.nx && j < g.ny;
   T acc = T(0);
   if (valid) {
@@ -389,7 +438,14 @@ __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const
       acc = a0 + a1;
     }
   }
-  epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo);
+  epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo, b);
+}
+
+template <typename T, bool FAN>
+__global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
+                                                 T *__restrict__ xo, Epi<T> e, const int *stop) {
+  if (stop && *stop) return;
+  back_body<T, FAN>(g, vt, ypad, xo, e, Blk{blockIdx.x, gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -404,11 +460,10 @@ __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const
 // candidates.
 // ---------------------------------------------------------------------------
 template <typename T, bool FAN, int NC>
-__global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
-                                                    T *__restrict__ xo, Epi<T> e, const int *stop) {
-  if (stop && *stop) return;
+__device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
+                                    const Epi<T> &e, Blk b) {
   int i, j;
-  tile_pixel(g, i, j);
+  tile_pixel(g, b.id, i, j);
   const bool valid = i < g.nx && j < g.ny;
   T acc = T(0);
   if (valid) {
@@ -496,23 +551,112 @@ __global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, co
       }
     }
   }
-  epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo);
+  epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo, b);
 }
 
-// (w y, w) per padded bin for the fan-beam A^T: w = 1/|d_dom| per ray in padded layout
-template <typename T>
-__global__ __launch_bounds__(256) void k_pad_sino_w(Col<const T> yc, const T *__restrict__ wpad, T *__restrict__ out,
-                                                    int nv, int nu, int PY, int ldY, const int *stop) {
+template <typename T, bool FAN, int NC>
+__global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
+                                                    T *__restrict__ xo, Epi<T> e, const int *stop) {
   if (stop && *stop) return;
-  const T *__restrict__ y = yc.get();
-  const long long total = (long long)nv * ldY;
-  for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (long long)gridDim.x * 256) {
-    const int v = (int)(idx / ldY), k = (int)(idx - (long long)v * ldY) - PY;
-    const T yv = ((unsigned)k < (unsigned)nu) ? y[(long long)v * nu + k] : T(0);
-    const T w = wpad[idx];
-    out[2 * idx] = w * yv;
-    out[2 * idx + 1] = w;
-  }
+  fwd_adj_body<T, FAN, NC>(g, vt, ypad, xo, e, Blk{blockIdx.x, gridDim.x});
+}
+
+
+// ---------------------------------------------------------------------------
+// batched launches: every active slice of a batch in one grid; workgroup ->
+// (slice, local workgroup) by a search over the per-slice prefix sums, then
+// the same bodies as the single-slice kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline Epi<T> make_epi(const SliceDev<T> &d, const EpiCfg &ec, int k) {
+  Epi<T> e;
+  e.ctl = d.ctl;
+  e.use_ctl = 1;
+  e.in_sel = ec.in_sel;
+  e.prev_sel = ec.prev_sel;
+  e.norm_to_t = ec.norm_to_t;
+  e.prev = Col<const T>{resolve(d, ec.prev_buf, k), 0, 0, nullptr};
+  e.out_raw = Col<T>{resolve(d, ec.out_raw_buf, k), 0, 0, nullptr};
+  e.partials = d.partials;
+  e.counter = d.counter;
+  return e;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_pad_rows(BatchDev<T> bd, int in_sel) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_PADR, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  pad_rows_body(resolve(d, in_sel, k), d.xpad, d.g.nx, d.g.ny, d.g.pad, d.g.ldR, b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_pad_cols(BatchDev<T> bd, int in_sel) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_PADC, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  const int tiles_x = (d.g.ldT + 31) / 32;
+  pad_cols_body(resolve(d, in_sel, k), d.xpad, d.g.nx, d.g.ny, d.g.pad, d.g.ldT, d.g.offT, (int)b.id % tiles_x,
+                (int)b.id / tiles_x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_pad_sino(BatchDev<T> bd, int in_sel, int adj) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_PADS, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  const T *y = resolve(d, in_sel, k);
+  if (adj && d.g.kind == 1)
+    pad_sino_w_body(y, d.rt.wpad, d.ypad, d.g.nv, d.g.nu, d.g.padY, d.g.ldY, b);
+  else
+    pad_sino_body(y, d.ypad, d.g.nv, d.g.nu, d.g.padY, d.g.ldY, b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_fwd(BatchDev<T> bd, int out_sel, EpiCfg ec) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_RAY, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  const GeomDev g = d.g;
+  const RayTab<T> rt = d.rt;
+  fwd_body(g, rt, d.xpad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
+}
+
+template <typename T, bool FAN, int NC>
+__global__ __launch_bounds__(kBlock) void kb_back_adj(BatchDev<T> bd, int out_sel, EpiCfg ec) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_RAY, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  const GeomDev g = d.g;
+  const RayTab<T> rt = d.rt;
+  back_adj_body<T, FAN, NC>(g, rt, d.xpad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
+}
+
+template <typename T, bool FAN>
+__global__ __launch_bounds__(kBlock) void kb_back(BatchDev<T> bd, int out_sel, EpiCfg ec) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_PIX, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  const GeomDev g = d.g;
+  const ViewTab<T> vt = d.vt;
+  back_body<T, FAN>(g, vt, d.ypad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
+}
+
+template <typename T, bool FAN, int NC>
+__global__ __launch_bounds__(kBlock) void kb_fwd_adj(BatchDev<T> bd, int out_sel, EpiCfg ec) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_PIX, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  const int k = d.ctl.ip[CI_K];
+  const GeomDev g = d.g;
+  const ViewTab<T> vt = d.vt;
+  fwd_adj_body<T, FAN, NC>(g, vt, d.ypad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
 }
 
 }  // namespace
@@ -613,6 +757,82 @@ void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt,
     fwd_adj_nc<T, false>(g, vt, rt, ypad, x, e, stop, s);
 }
 
+// ---- batched launchers ----
+template <typename T>
+void launch_b_pad_image(const BatchDev<T> &bd, const BatchLaunch &bl, int in_sel, hipStream_t s) {
+  if (bl.tot[BF_PADR] > 0)
+    hipLaunchKernelGGL(kb_pad_rows<T>, dim3(bl.tot[BF_PADR]), dim3(256), 0, s, bd, in_sel);
+  if (bl.tot[BF_PADC] > 0)
+    hipLaunchKernelGGL(kb_pad_cols<T>, dim3(bl.tot[BF_PADC]), dim3(256), 0, s, bd, in_sel);
+}
+
+template <typename T>
+void launch_b_pad_sino(const BatchDev<T> &bd, const BatchLaunch &bl, int in_sel, int adj, hipStream_t s) {
+  if (bl.tot[BF_PADS] > 0)
+    hipLaunchKernelGGL(kb_pad_sino<T>, dim3(bl.tot[BF_PADS]), dim3(256), 0, s, bd, in_sel, adj);
+}
+
+template <typename T>
+void launch_b_fwd(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
+  if (bl.tot[BF_RAY] > 0)
+    hipLaunchKernelGGL(kb_fwd<T>, dim3(bl.tot[BF_RAY]), dim3(kBlock), 0, s, bd, out_sel, ec);
+}
+
+template <typename T, bool FAN>
+static void b_back_adj_nc(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
+  const dim3 grid(bl.tot[BF_RAY]), blk(kBlock);
+  switch (bl.nc_bt) {
+    case 2: hipLaunchKernelGGL((kb_back_adj<T, FAN, 2>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 3: hipLaunchKernelGGL((kb_back_adj<T, FAN, 3>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 4: hipLaunchKernelGGL((kb_back_adj<T, FAN, 4>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 5: hipLaunchKernelGGL((kb_back_adj<T, FAN, 5>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 6: hipLaunchKernelGGL((kb_back_adj<T, FAN, 6>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 7: hipLaunchKernelGGL((kb_back_adj<T, FAN, 7>), grid, blk, 0, s, bd, out_sel, ec); break;
+    default: hipLaunchKernelGGL((kb_back_adj<T, FAN, 8>), grid, blk, 0, s, bd, out_sel, ec); break;
+  }
+}
+
+template <typename T>
+void launch_b_back_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
+  if (bl.tot[BF_RAY] <= 0) return;
+  if (bl.fan)
+    b_back_adj_nc<T, true>(bd, bl, out_sel, ec, s);
+  else
+    b_back_adj_nc<T, false>(bd, bl, out_sel, ec, s);
+}
+
+template <typename T>
+void launch_b_back(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
+  if (bl.tot[BF_PIX] <= 0) return;
+  if (bl.fan)
+    hipLaunchKernelGGL((kb_back<T, true>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  else
+    hipLaunchKernelGGL((kb_back<T, false>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
+}
+
+template <typename T, bool FAN>
+static void b_fwd_adj_nc(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
+  const dim3 grid(bl.tot[BF_PIX]), blk(kBlock);
+  switch (bl.nc_at) {
+    case 2: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 2>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 3: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 3>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 4: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 4>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 5: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 5>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 6: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 6>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 7: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 7>), grid, blk, 0, s, bd, out_sel, ec); break;
+    default: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 8>), grid, blk, 0, s, bd, out_sel, ec); break;
+  }
+}
+
+template <typename T>
+void launch_b_fwd_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
+  if (bl.tot[BF_PIX] <= 0) return;
+  if (bl.fan)
+    b_fwd_adj_nc<T, true>(bd, bl, out_sel, ec, s);
+  else
+    b_fwd_adj_nc<T, false>(bd, bl, out_sel, ec, s);
+}
+
 #define GKB_INST(T)                                                                                               \
   template void launch_pad_image<T>(const GeomDev &, Col<const T>, T *, bool, const int *, hipStream_t);         \
   template void launch_pad_sino<T>(const GeomDev &, Col<const T>, T *, const int *, hipStream_t);                \
@@ -625,7 +845,13 @@ void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt,
   template void launch_back<T>(const GeomDev &, const ViewTab<T> &, const T *, T *, const Epi<T> &, const int *, \
                                hipStream_t);                                                                     \
   template void launch_fwd_adj<T>(const GeomDev &, const ViewTab<T> &, const RayTab<T> &, const T *, T *,        \
-                                  const Epi<T> &, const int *, hipStream_t);
+                                  const Epi<T> &, const int *, hipStream_t);                             \
+  template void launch_b_pad_image<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);               \
+  template void launch_b_pad_sino<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);           \
+  template void launch_b_fwd<T>(const BatchDev<T> &, const BatchLaunch &, int, EpiCfg, hipStream_t);             \
+  template void launch_b_back_adj<T>(const BatchDev<T> &, const BatchLaunch &, int, EpiCfg, hipStream_t);        \
+  template void launch_b_back<T>(const BatchDev<T> &, const BatchLaunch &, int, EpiCfg, hipStream_t);            \
+  template void launch_b_fwd_adj<T>(const BatchDev<T> &, const BatchLaunch &, int, EpiCfg, hipStream_t);
 GKB_INST(float)
 GKB_INST(double)
 #undef GKB_INST

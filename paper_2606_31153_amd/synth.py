@@ -165,14 +165,21 @@ def rasterize_ellipses(params: np.ndarray, nx: int, ny: Optional[int] = None, ss
     half = max(nx, ny) / 2.0
     xs = _supersample_axis(nx, ss) * (nx / 2.0) / half
     ys = _supersample_axis(ny, ss) * (ny / 2.0) / half
-    X, Y = np.meshgrid(xs, ys)
-    img = np.zeros_like(X)
+    img = np.zeros((ys.size, xs.size))
     for cx, cy, a, b, phi, rho in params:
         c, s = math.cos(phi), math.sin(phi)
+        # samples outside the ellipse's bounding box (plus a margin) are outside it
+        ex = math.hypot(a * c, b * s) * 1.001 + 1e-9
+        ey = math.hypot(a * s, b * c) * 1.001 + 1e-9
+        i0, i1 = np.searchsorted(xs, cx - ex), np.searchsorted(xs, cx + ex, side="right")
+        j0, j1 = np.searchsorted(ys, cy - ey), np.searchsorted(ys, cy + ey, side="right")
+        if i0 >= i1 or j0 >= j1:
+            continue
+        X, Y = np.meshgrid(xs[i0:i1], ys[j0:j1])
         dx, dy = X - cx, Y - cy
         u = dx * c + dy * s
         v = -dx * s + dy * c
-        img += rho * ((u / a) ** 2 + (v / b) ** 2 <= 1.0)
+        img[j0:j1, i0:i1] += rho * ((u / a) ** 2 + (v / b) ** 2 <= 1.0)
     return img.reshape(ny, ss, nx, ss).mean(axis=(1, 3))
 
 

@@ -196,6 +196,8 @@ def test_zero_rhs_is_breakdown_with_zero_solution(ctx):
     res, x = gpu_solve(ctx, geom, "ba", np.zeros(geom.m), torch.float32, 10)
     assert res.k_stop == 0 and res.reason == gk.STOP_BREAKDOWN
     assert not x.any()
+    assert res.alpha1 == 0.0 and res.t1 == 0.0
+    assert np.array_equal(res.alpha, [0.0]) and np.array_equal(res.t, [0.0])
 
 
 def test_nonfinite_rhs_rejected(ctx):

@@ -33,7 +33,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def test_binding_names_match_c_abi():
     for name in ("gkb_forward", "gkb_back", "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve",
-                 "gkb_ba_solve", "gkb_gkb_solve"):
+                 "gkb_ba_solve", "gkb_gkb_solve", "gkb_batch_solve"):
         assert callable(getattr(gk, name))
 
 
