@@ -13,7 +13,14 @@ stream), the dominant kernel's roofline position, the projector
 throughput in GB/s against the HBM peak, and the CPU oracle timed on a
 bounded sample of the same workload.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Batched workload (the "s/slice to discrepancy" part of the metric): 64
+parallel-beam slices, n = 128 + 32 U{0..12}, 180 + 30 U{0..18} views,
+ceil(n sqrt 2) bins, 0.5-5 % noise, BA-GKB with the discrepancy stop
+(tau = 1, k_max = 150) per slice; timed once solved one slice after another
+and once as one batched call, after an untimed pass of each that builds the
+geometry tables.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
 """
 from __future__ import annotations
 
@@ -95,6 +102,65 @@ def make_problem(geom, seed: int, nu: float):
     return x_true, torch.tensor(b, dtype=torch.float32, device=dev), enorm
 
 
+def batch_problems(count: int = 64):
+    """The 64-slice workload: per-slice geometry, device b (FP32) and ||e||."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    from paper_2606_31153_amd import synth
+    dev = torch.device("cuda:0")
+    ctx = gk.Context(0)
+    geoms, bs, ens = [], [], []
+    for (n, v, nu, seed) in synth.batch_slices(3000, count):
+        g = synth.par2d(n, v)
+        x = torch.tensor(synth.ellipse_phantom(n, seed).reshape(-1), dtype=torch.float32, device=dev)
+        y = torch.empty(g.m, dtype=torch.float32, device=dev)
+        gk.gkb_forward(ctx, g, x, y)
+        torch.cuda.synchronize()
+        b, en = synth.add_noise(y.double().cpu().numpy(), synth.noise_direction(g.m, seed), nu)
+        geoms.append(g)
+        bs.append(torch.tensor(b, dtype=torch.float32, device=dev))
+        ens.append(en)
+    ctx.close()
+    return geoms, bs, ens
+
+
+def batch_bench(ctx):
+    import torch
+
+    import paper_2606_31153_amd as gk
+    geoms, bs, ens = batch_problems()
+    xs = [torch.zeros(g.n, dtype=torch.float32, device=b.device) for g, b in zip(geoms, bs)]
+    opts = [dict(k_max=150, use_dp=True, tau=1.0, noise_norm=e) for e in ens]
+
+    def sequential():
+        return [gk.gkb_ba_solve(ctx, g, b, x, **o) for g, b, x, o in zip(geoms, bs, xs, opts)]
+
+    def batched():
+        return gk.gkb_batch_solve(ctx, gk.GKB_METHOD_BA, geoms, bs, xs, opts)
+
+    sequential()
+    batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = sequential()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rb = batched()
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    ks = [r.k_stop for r in rb]
+    assert ks == [r.k_stop for r in rs]
+    ns = len(geoms)
+    return {"workload": "64 parallel-beam slices, n 128..512, 180..720 views, 0.5-5% noise, BA-GKB, DP tau=1",
+            "slices": ns, "s_per_slice_batched": t_bat / ns, "s_per_slice_sequential": t_seq / ns,
+            "batched_speedup": t_seq / t_bat, "iterations_mean": float(np.mean(ks)),
+            "iterations_min": int(min(ks)), "iterations_max": int(max(ks)),
+            "stopped_by_dp": sum(1 for r in rb if r.reason == gk.STOP_DP),
+            "pixels_total": int(sum(g.n for g in geoms)), "bins_total": int(sum(g.m for g in geoms))}
+
+
 def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int):
     import oracle
     op = oracle.Operator(geom)
@@ -112,8 +178,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=K_ITERS)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -202,6 +269,9 @@ def main():
         "projector_gbps": gbps,
         "kernels": kernels,
     }
+    if not args.no_batch:
+        print("bench: 64-slice batched workload", file=sys.stderr, flush=True)
+        out["s_per_slice_to_discrepancy"] = batch_bench(ctx)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(geom, b.double().cpu().numpy(), enorm, args.cpu_iters)
