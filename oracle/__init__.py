@@ -80,6 +80,10 @@ def lib():
         L.or_proj_solve.restype = None
         L.or_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
         L.or_jacobi_svd.restype = ctypes.c_int
+        for name in ("or_cone_forward_sampled", "or_cone_back_sampled"):
+            f = getattr(L, name)
+            f.argtypes = [G, P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_longlong, P]
+            f.restype = ctypes.c_int
         L.or_num_threads.restype = ctypes.c_int
         L.or_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -133,6 +137,25 @@ class Operator:
 
     def A(self, x):
         return self._call("or_forward", x, self.m, self.sino_shape)
+
+    def _sampled(self, name, inp, ids, size):
+        a = np.ascontiguousarray(np.asarray(inp, dtype=np.float64).reshape(-1))
+        assert a.size == size
+        idx = np.ascontiguousarray(np.asarray(ids, dtype=np.int64).reshape(-1))
+        out = np.zeros(idx.size, dtype=np.float64)
+        rc = getattr(lib(), name)(ctypes.byref(self.g), _ptr(a),
+                                  idx.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), idx.size, _ptr(out))
+        if rc != 0:
+            raise ValueError("%s: not a cone-beam geometry or index out of range" % name)
+        return out
+
+    def A_at(self, x, ray_ids):
+        """(A x) at the listed detector pixels (cone beam only)."""
+        return self._sampled("or_cone_forward_sampled", x, ray_ids, self.n)
+
+    def B_at(self, y, voxel_ids):
+        """(B y) at the listed voxels (cone beam only)."""
+        return self._sampled("or_cone_back_sampled", y, voxel_ids, self.m)
 
     def At(self, y):
         return self._call("or_forward_adjoint", y, self.n, self.image_shape)

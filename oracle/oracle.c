@@ -470,6 +470,27 @@ static void cone_pixel_coords(const or_geom *g, int v, double xi, double yj, dou
   *w = pz * mag / g->dw + (g->nw - 1) / 2.0;
 }
 
+/* (B y) at voxel (i, j, l): the sum over views of the bilinear interpolation
+   of y at the voxel's detector coordinates. */
+static double cone_back_voxel(const or_geom *g, const double *yin, int i, int j, int l) {
+  const int nx = g->nx, ny = g->ny, nz = g->nz, nu = g->nu, nw = g->nw, nv = g->nv;
+  double acc = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    double u, w;
+    cone_pixel_coords(g, v, i - (nx - 1) / 2.0, j - (ny - 1) / 2.0, l - (nz - 1) / 2.0, &u, &w);
+    const double fu = floor(u), fw = floor(w);
+    const int k0 = (int)fu, r0 = (int)fw;
+    const double a = u - fu, c = w - fw;
+    for (int e2 = 0; e2 < 2; ++e2)
+      for (int e1 = 0; e1 < 2; ++e1) {
+        const int kk = k0 + e1, rr = r0 + e2;
+        if (kk < 0 || kk >= nu || rr < 0 || rr >= nw) continue;
+        acc += (e1 ? a : 1.0 - a) * (e2 ? c : 1.0 - c) * yin[((size_t)v * nw + rr) * nu + kk];
+      }
+  }
+  return acc;
+}
+
 static void cone_pixel(const or_geom *g, const double *yin, double *xout, const double *xin, double *yout,
                        int adjoint) {
   const int nx = g->nx, ny = g->ny, nz = g->nz, nu = g->nu, nw = g->nw, nv = g->nv;
@@ -477,23 +498,7 @@ static void cone_pixel(const or_geom *g, const double *yin, double *xout, const 
 #pragma omp parallel for collapse(2) schedule(static)
     for (int l = 0; l < nz; ++l)
       for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-          double acc = 0.0;
-          for (int v = 0; v < nv; ++v) {
-            double u, w;
-            cone_pixel_coords(g, v, i - (nx - 1) / 2.0, j - (ny - 1) / 2.0, l - (nz - 1) / 2.0, &u, &w);
-            const double fu = floor(u), fw = floor(w);
-            const int k0 = (int)fu, r0 = (int)fw;
-            const double a = u - fu, c = w - fw;
-            for (int e2 = 0; e2 < 2; ++e2)
-              for (int e1 = 0; e1 < 2; ++e1) {
-                const int kk = k0 + e1, rr = r0 + e2;
-                if (kk < 0 || kk >= nu || rr < 0 || rr >= nw) continue;
-                acc += (e1 ? a : 1.0 - a) * (e2 ? c : 1.0 - c) * yin[((size_t)v * nw + rr) * nu + kk];
-              }
-          }
-          xout[((size_t)l * ny + j) * nx + i] = acc;
-        }
+        for (int i = 0; i < nx; ++i) xout[((size_t)l * ny + j) * nx + i] = cone_back_voxel(g, yin, i, j, l);
   } else {
 #pragma omp parallel for schedule(static)
     for (int v = 0; v < nv; ++v) {
@@ -517,6 +522,40 @@ static void cone_pixel(const or_geom *g, const double *yin, double *xout, const 
           }
     }
   }
+}
+
+/* Cone beam at sampled outputs: the same definitions as cone_joseph (A) and
+   cone_pixel (B), evaluated only at the listed detector pixels (A, index
+   (v * nw + r) * nu + k) or voxels (B, index (l * ny + j) * nx + i), for
+   checks at sizes where the whole operator is too slow on the CPU.
+   Returns -1 for a geometry that is not a cone beam or an index out of range. */
+int or_cone_forward_sampled(const or_geom *g, const double *x, const long long *ids, long long count,
+                            double *out) {
+  if (g->kind != OR_CONE3D) return -1;
+  const long long m = g_m(g);
+  for (long long s = 0; s < count; ++s)
+    if (ids[s] < 0 || ids[s] >= m) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long s = 0; s < count; ++s) {
+    const long long id = ids[s];
+    const int k = (int)(id % g->nu), r = (int)((id / g->nu) % g->nw), v = (int)(id / ((long long)g->nu * g->nw));
+    cone_ray(g, v, r, k, x, NULL, 0.0, &out[s]);
+  }
+  return 0;
+}
+
+int or_cone_back_sampled(const or_geom *g, const double *y, const long long *ids, long long count, double *out) {
+  if (g->kind != OR_CONE3D) return -1;
+  const long long n = g_n(g);
+  for (long long s = 0; s < count; ++s)
+    if (ids[s] < 0 || ids[s] >= n) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long long s = 0; s < count; ++s) {
+    const long long id = ids[s];
+    const int i = (int)(id % g->nx), j = (int)((id / g->nx) % g->ny), l = (int)(id / ((long long)g->nx * g->ny));
+    out[s] = cone_back_voxel(g, y, i, j, l);
+  }
+  return 0;
 }
 
 /* ---------------------------------------------------------------------- */

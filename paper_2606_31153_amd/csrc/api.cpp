@@ -79,6 +79,11 @@ struct HostTables {
   // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
   std::vector<double> gcs;
   bool has_coldom = false;
+  // cone beam, per (view, column)
+  std::vector<double> cbase1, cslope1, clmid, clslope, cdxy2, ch1, cpk;
+  std::vector<int> cmeta, cmeta_bt;
+  bool has_xdom = false, has_ydom = false;
+  double min_ddom = 0.0;
   GeomDev gd{};
 };
 
@@ -88,7 +93,10 @@ struct DevTables {
   ViewTab<float> vt32{};
   RayTab<double> rt64{};
   ViewTab<double> vt64{};
+  ConeTab<float> ct32{};
+  ConeTab<double> ct64{};
   bool has_coldom = false;
+  bool has_xdom = false, has_ydom = false;
   GeomDev gd{};
 };
 
@@ -283,6 +291,175 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   }
 }
 
+// Cone beam: per (view, column) the ray's dominant axis and its crossings
+// (see ConeTab), formed in double; the direction is built from the detector
+// point exactly as P - S with P = S + SDD c + u_k e_u.
+void build_cone_tables(const gkb_geometry *g, HostTables &t) {
+  const int nx = g->nx, ny = g->ny, nz = g->nz, nv = g->n_views, nu = g->n_det_u, nw = g->n_det_v;
+  const double du = g->det_pitch_u, dw = g->det_pitch_v, D = g->src_dist, SDD = g->src_det_dist;
+  const double offu = 0.5 * (nu - 1), offw = 0.5 * (nw - 1);
+  const double midx = 0.5 * (nx - 1), midy = 0.5 * (ny - 1);
+  const std::vector<double> ang = view_angles(g);
+  const size_t nvk = (size_t)nv * nu;
+  t.cbase1.resize(nvk);
+  t.cslope1.resize(nvk);
+  t.clmid.resize(nvk);
+  t.clslope.resize(nvk);
+  t.cdxy2.resize(nvk);
+  t.ch1.resize(nvk);
+  t.cpk.resize(2 * nvk);
+  t.cmeta.resize(nvk);
+  t.cmeta_bt.resize(nvk);
+  t.p0.resize(nv);
+  t.p1.resize(nv);
+  t.p2.assign(nv, 0.0);
+  t.p3.assign(nv, 0.0);
+  t.p4.assign(nv, 0.0);
+  double min_ddom = 1e300;
+  for (int v = 0; v < nv; ++v) {
+    const double cb = std::cos(ang[v]), sb = std::sin(ang[v]);
+    t.p0[v] = cb;
+    t.p1[v] = sb;
+    const double Sx = D * cb, Sy = D * sb;
+    for (int k = 0; k < nu; ++k) {
+      const size_t vk = (size_t)v * nu + k;
+      const double uu = (k - offu) * du;
+      const double dx = (Sx + SDD * (-cb) + uu * (-sb)) - Sx;
+      const double dy = (Sy + SDD * (-sb) + uu * cb) - Sy;
+      const bool ydom = std::fabs(dy) > std::fabs(dx);
+      const double Sax = ydom ? Sy : Sx, So = ydom ? Sx : Sy, dax = ydom ? dy : dx, dob = ydom ? dx : dy;
+      const int nax = ydom ? ny : nx, n1 = ydom ? nx : ny;
+      const double midax = ydom ? midy : midx, mid1 = ydom ? midx : midy;
+      min_ddom = std::min(min_ddom, std::fabs(dax));
+      const double slope1 = dob / dax;
+      const double base1 = So + (0.0 - Sax) / dax * dob + mid1;
+      t.cslope1[vk] = slope1;
+      t.cbase1[vk] = base1;
+      t.clmid[vk] = -Sax / dax;
+      t.clslope[vk] = 1.0 / dax;
+      t.cdxy2[vk] = dx * dx + dy * dy;
+      t.cpk[2 * vk] = 1.0 / dax;
+      t.cpk[2 * vk + 1] = ydom ? 1.0 : 0.0;
+      // B^T half-width: the in-plane interval whose voxels project within one
+      // column of k, evaluated exactly at the first and last plane (it grows
+      // monotonically with the depth along the ray)
+      double h = 0.0;
+      for (int e = 0; e < 2; ++e) {
+        const double a = (e ? nax - 1 : 0) - midax;
+        const double oc = base1 + a * slope1 - mid1;
+        for (int sg = -1; sg <= 1; sg += 2) {
+          const double U = (k + sg - offu) * du / SDD;
+          const double den = ydom ? (-sb + U * cb) : (cb + U * sb);
+          if (std::fabs(den) < 1e-12) {
+            h = std::max(h, (double)n1 + 2.0);
+            continue;
+          }
+          const double o = ydom ? (U * (D - a * sb) - a * cb) / den : (U * (D - a * cb) + a * sb) / den;
+          h = std::max(h, std::fabs(o - oc));
+        }
+      }
+      h = std::min(h * 1.0001 + 1e-3, (double)n1 + 2.0);
+      t.ch1[vk] = h;
+      int lo, hi;
+      line_range(base1, slope1, midax, nax, -1.0, (double)n1, lo, hi);
+      t.cmeta[vk] = lo | (hi << 15) | ((ydom ? 1 : 0) << 30);
+      line_range(base1, slope1, midax, nax, -h, n1 - 1 + h, lo, hi);
+      t.cmeta_bt[vk] = lo | (hi << 15) | ((ydom ? 1 : 0) << 30);
+      if (ydom)
+        t.has_ydom = true;
+      else
+        t.has_xdom = true;
+    }
+  }
+  t.min_ddom = min_ddom;
+  GeomDev &gd = t.gd;
+  gd.kind = GKB_CONE3D;
+  gd.nx = nx;
+  gd.ny = ny;
+  gd.nz = nz;
+  gd.nv = nv;
+  gd.nu = nu;
+  gd.nw = nw;
+  gd.n = (long long)nx * ny * nz;
+  gd.m = (long long)nv * nw * nu;
+  gd.du = du;
+  gd.dw = dw;
+  gd.D = D;
+  gd.SDD = SDD;
+  gd.off = offu;
+  gd.offw = offw;
+  gd.inv_du = 1.0 / du;
+  gd.Su = SDD / du;
+  gd.Sw = SDD / dw;
+  gd.hk_fac = std::sqrt(SDD * SDD + (offu * du) * (offu * du)) / du * (1.0 + 1e-6);
+  gd.nc_bt = 2;
+  gd.nc_at = 2;
+  gd.P3 = 2;
+  gd.ldX = ny + 2 * gd.P3;
+  gd.ldV = nx + 2 * gd.P3;
+  gd.planeX = (long long)(nz + 2 * gd.P3) * gd.ldX;
+  gd.planeY = (long long)(nz + 2 * gd.P3) * gd.ldV;
+  gd.offYD = (long long)nx * gd.planeX;
+  gd.vol_pad_elems = gd.offYD + (long long)ny * gd.planeY;
+  gd.PY3 = 2;
+  gd.ldSu = nu + 2 * gd.PY3;
+  gd.sliceY = (long long)(nw + 2 * gd.PY3) * gd.ldSu;
+  gd.sino_pad_elems = (long long)nv * gd.sliceY;
+  gd.pad_elems = gd.vol_pad_elems;
+  gd.ypad_elems = std::max(gd.sino_pad_elems, gd.m);
+}
+
+template <typename T>
+hipError_t upload_cone_tables(const HostTables &h, DevTables &d) {
+  const size_t nvk = h.cbase1.size();
+  const int nv = h.gd.nv;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t aT = al(sizeof(T) * nvk), aI = al(sizeof(int) * nvk), aV = al(sizeof(T) * nv);
+  const size_t total = 6 * aT + 2 * aT + 2 * aI + 2 * aV;
+  hipError_t e = d.buf.ensure(total);
+  if (e != hipSuccess) return e;
+  char *p = d.buf.as<char>();
+  std::vector<T> tmp;
+  auto put = [&](const std::vector<double> &src, size_t stride) -> const T * {
+    T *dst = reinterpret_cast<T *>(p);
+    p += stride;
+    tmp.assign(src.size(), T(0));
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+    (void)hipMemcpy(dst, tmp.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return dst;
+  };
+  auto put_i = [&](const std::vector<int> &src) -> const int * {
+    int *dst = reinterpret_cast<int *>(p);
+    p += aI;
+    (void)hipMemcpy(dst, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice);
+    return dst;
+  };
+  ConeTab<T> ct{};
+  ViewTab<T> vt{};
+  ct.base1 = put(h.cbase1, aT);
+  ct.slope1 = put(h.cslope1, aT);
+  ct.lmid = put(h.clmid, aT);
+  ct.lslope = put(h.clslope, aT);
+  ct.dxy2 = put(h.cdxy2, aT);
+  ct.h1 = put(h.ch1, aT);
+  ct.pk = put(h.cpk, 2 * aT);
+  ct.meta = put_i(h.cmeta);
+  ct.meta_bt = put_i(h.cmeta_bt);
+  vt.p0 = put(h.p0, aV);
+  vt.p1 = put(h.p1, aV);
+  if constexpr (sizeof(T) == 4) {
+    d.ct32 = ct;
+    d.vt32 = vt;
+  } else {
+    d.ct64 = ct;
+    d.vt64 = vt;
+  }
+  d.has_xdom = h.has_xdom;
+  d.has_ydom = h.has_ydom;
+  d.gd = h.gd;
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t upload_tables(const HostTables &h, DevTables &d) {
   const long long m = h.gd.m;
@@ -442,7 +619,25 @@ struct TraceScope {
 gkb_status validate_geom(const gkb_geometry *g, int dtype) {
   if (!g) return fail(GKB_EINVAL, "geometry is NULL");
   if (dtype != GKB_F32 && dtype != GKB_F64) return fail(GKB_EINVAL, "dtype must be GKB_F32 or GKB_F64");
-  if (g->kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "cone-beam geometry is not built in this library");
+  if (g->kind == GKB_CONE3D) {
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nx > 16384 || g->ny > 16384 || g->nz > 16384)
+      return fail(GKB_EINVAL, "nx, ny, nz must be in [1, 16384]");
+    if (g->n_views < 1) return fail(GKB_EINVAL, "n_views must be >= 1");
+    if (g->n_det_u < 1 || g->n_det_v < 1) return fail(GKB_EINVAL, "n_det_u and n_det_v must be >= 1");
+    if (!(g->det_pitch_u > 0.0) || !std::isfinite(g->det_pitch_u) || !(g->det_pitch_v > 0.0) ||
+        !std::isfinite(g->det_pitch_v))
+      return fail(GKB_EINVAL, "detector pitches must be > 0");
+    if (!g->angles && !std::isfinite(g->angle_span)) return fail(GKB_EINVAL, "angle_span must be finite");
+    if (g->angles)
+      for (int v = 0; v < g->n_views; ++v)
+        if (!std::isfinite(g->angles[v])) return fail(GKB_EINVAL, "angles must be finite");
+    const double half_diag = 0.5 * std::sqrt((double)g->nx * g->nx + (double)g->ny * g->ny);
+    if (!(g->src_dist > half_diag + 2.0) || !std::isfinite(g->src_dist))
+      return fail(GKB_EINVAL, "cone beam: src_dist must exceed the volume's half-diagonal + 2");
+    if (!(g->src_det_dist > 0.0) || !std::isfinite(g->src_det_dist))
+      return fail(GKB_EINVAL, "cone beam: src_det_dist must be > 0");
+    return GKB_OK;
+  }
   if (g->kind != GKB_PAR2D && g->kind != GKB_FAN2D) return fail(GKB_EINVAL, "unknown geometry kind");
   if (g->nx < 1 || g->ny < 1 || g->nx > 16384 || g->ny > 16384)
     return fail(GKB_EINVAL, "nx, ny must be in [1, 16384]");
@@ -474,6 +669,21 @@ gkb_status get_tables(gkb_ctx *c, const gkb_geometry *g, int dtype, DevTables **
     return GKB_OK;
   }
   HostTables h;
+  if (g->kind == GKB_CONE3D) {
+    build_cone_tables(g, h);
+    if (!(h.min_ddom > 0.5 * (g->n_det_v - 1) * g->det_pitch_v))
+      return fail(GKB_EUNSUPPORTED, "cone beam: some ray would step along z (detector too tall for the "
+                                    "source-detector distance)");
+    if (h.gd.vol_pad_elems >= (1LL << 32) || h.gd.sino_pad_elems >= (1LL << 32))
+      return fail(GKB_EUNSUPPORTED, "volume or sinogram too large for 32-bit offsets");
+    auto d = std::make_unique<DevTables>();
+    hipError_t e = (dtype == GKB_F32) ? upload_cone_tables<float>(h, *d) : upload_cone_tables<double>(h, *d);
+    if (e == hipErrorOutOfMemory) return fail(GKB_ENOMEM, "out of device memory for geometry tables");
+    if (e != hipSuccess) return fail(GKB_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    *out = d.get();
+    c->tables.emplace(key, std::move(d));
+    return GKB_OK;
+  }
   build_tables(g, h);
   if (h.gd.nc_bt > 8 || h.gd.nc_at > 8)
     return fail(GKB_EUNSUPPORTED, "detector pitch too fine relative to the pixel pitch (more than 8 "
@@ -508,6 +718,17 @@ const ViewTab<float> &vt_of<float>(const DevTables &d) {
 template <>
 const ViewTab<double> &vt_of<double>(const DevTables &d) {
   return d.vt64;
+}
+
+template <typename T>
+const ConeTab<T> &ct_of(const DevTables &d);
+template <>
+const ConeTab<float> &ct_of<float>(const DevTables &d) {
+  return d.ct32;
+}
+template <>
+const ConeTab<double> &ct_of<double>(const DevTables &d) {
+  return d.ct64;
 }
 
 template <typename T>
@@ -556,6 +777,37 @@ gkb_status apply_op(gkb_ctx *c, const DevTables &d, int op, const void *in, void
   T *xo = static_cast<T *>(out);
   T *xpad = c->xpad.as<T>();
   T *ypad = c->ypad.as<T>();
+  if (g.kind == GKB_CONE3D) {
+    hipStream_t st = c->stream;
+    switch (op) {
+      case OP_A: {
+        launch_cone_pad_volume<T>(g, col<const T>(xi), xpad, d.has_xdom, d.has_ydom, nullptr, st);
+        TraceScope ts(c, "fwd");
+        launch_cone_fwd<T>(g, ct_of<T>(d), xpad, col<T>(xo), e, nullptr, st);
+        break;
+      }
+      case OP_BT: {
+        launch_cone_pad_volume<T>(g, col<const T>(xi), xpad, d.has_xdom, d.has_ydom, nullptr, st);
+        TraceScope ts(c, "back_adj");
+        launch_cone_back_adj<T>(g, ct_of<T>(d), vt_of<T>(d), xpad, col<T>(xo), e, nullptr, st);
+        break;
+      }
+      case OP_B: {
+        launch_cone_pad_sino<T>(g, col<const T>(xi), ypad, nullptr, st);
+        TraceScope ts(c, "back");
+        launch_cone_back<T>(g, vt_of<T>(d), ypad, xo, e, nullptr, st);
+        break;
+      }
+      case OP_AT: {
+        launch_cone_weight_sino<T>(g, ct_of<T>(d), col<const T>(xi), ypad, nullptr, st);
+        TraceScope ts(c, "fwd_adj");
+        launch_cone_fwd_adj<T>(g, ct_of<T>(d), vt_of<T>(d), ypad, xo, e, nullptr, st);
+        break;
+      }
+    }
+    HIPC(hipGetLastError());
+    return GKB_OK;
+  }
   switch (op) {
     case OP_A: {
       launch_pad_image<T>(g, col<const T>(xi), xpad, d.has_coldom, nullptr, c->stream);
@@ -691,22 +943,49 @@ struct Solver {
   Col<T> ycol(int off) const { return colk<T>(Y, ldy, off, kp); }
 
   // ----- the four projectors with device-addressed operands -----
+  bool cone() const { return g.kind == GKB_CONE3D; }
   void A(Col<const T> in, Col<T> out, const Epi<T> &e) {
+    if (cone()) {
+      launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stop, st);
+      TraceScope ts(c, "fwd");
+      launch_cone_fwd<T>(g, ct_of<T>(d), xpad, out, e, stop, st);
+      return;
+    }
     launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
     TraceScope ts(c, "fwd");
     launch_fwd<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
   }
   void Bt(Col<const T> in, Col<T> out, const Epi<T> &e) {
+    if (cone()) {
+      launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stop, st);
+      TraceScope ts(c, "back_adj");
+      launch_cone_back_adj<T>(g, ct_of<T>(d), vt_of<T>(d), xpad, out, e, stop, st);
+      return;
+    }
     launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
     TraceScope ts(c, "back_adj");
     launch_back_adj<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
   }
-  void B(Col<const T> in, T *out, const Epi<T> &e) {
-    launch_pad_sino<T>(g, in, ypad, stop, st);
+  // stp: the stop flag the launches test (nullptr: run unconditionally)
+  void B(Col<const T> in, T *out, const Epi<T> &e, const int *stp) {
+    if (cone()) {
+      launch_cone_pad_sino<T>(g, in, ypad, stp, st);
+      TraceScope ts(c, "back");
+      launch_cone_back<T>(g, vt_of<T>(d), ypad, out, e, stp, st);
+      return;
+    }
+    launch_pad_sino<T>(g, in, ypad, stp, st);
     TraceScope ts(c, "back");
-    launch_back<T>(g, vt_of<T>(d), ypad, out, e, stop, st);
+    launch_back<T>(g, vt_of<T>(d), ypad, out, e, stp, st);
   }
+  void B(Col<const T> in, T *out, const Epi<T> &e) { B(in, out, e, stop); }
   void At(Col<const T> in, T *out, const Epi<T> &e) {
+    if (cone()) {
+      launch_cone_weight_sino<T>(g, ct_of<T>(d), in, ypad, stop, st);
+      TraceScope ts(c, "fwd_adj");
+      launch_cone_fwd_adj<T>(g, ct_of<T>(d), vt_of<T>(d), ypad, out, e, stop, st);
+      return;
+    }
     launch_pad_sino_adj<T>(g, rt_of<T>(d), in, ypad, stop, st);
     TraceScope ts(c, "fwd_adj");
     launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), ypad, out, e, stop, st);
@@ -864,10 +1143,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     // solution x = Q_k u_k (BA, matched) or B (Q_k u_k) (AB)
     if (mode == MODE_AB) {
       launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, S.tm, st);
-      Epi<T> e = plain_epi<T>();
-      launch_pad_sino<T>(g, col<const T>(S.tm), S.ypad, nullptr, st);
-      TraceScope ts(c, "back");
-      launch_back<T>(g, vt_of<T>(*d), S.ypad, x, e, nullptr, st);
+      S.B(col<const T>(S.tm), x, plain_epi<T>(), nullptr);
     } else {
       launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, x, st);
     }
@@ -1317,6 +1593,7 @@ gkb_status batch_entry(gkb_ctx *c, int method, int ns, const gkb_geometry *geoms
   for (int s = 0; s < ns; ++s) {
     gkb_status st = validate_geom(&geoms[s], dtype);
     if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
+    if (geoms[s].kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "batched solves take 2D slices");
     st = validate_opts(&opts[s]);
     if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
     if (!b[s] || !x[s]) return fail(GKB_EINVAL, "slice " + std::to_string(s) + ": data pointer is NULL");

@@ -1,0 +1,28 @@
+// Small device helpers shared by the projector kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gkb {
+
+// two consecutive elements, 4-byte (float) or 8-byte (double) aligned
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  typedef float v2 __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <>
+struct Pair<double> {
+  typedef double v2 __attribute__((ext_vector_type(2), aligned(8)));
+};
+template <typename T>
+__device__ inline typename Pair<T>::v2 load_pair(const T *p) {
+  return *reinterpret_cast<const typename Pair<T>::v2 *>(p);
+}
+
+// reciprocal: hardware approximation (1 ulp) in float, exact division in double
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fast_rcp(double x) { return 1.0 / x; }
+
+}  // namespace gkb

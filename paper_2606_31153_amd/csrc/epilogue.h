@@ -1,0 +1,47 @@
+// Epilogue shared by the projector kernels (2D and 3D).
+#pragma once
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace gkb {
+
+// Epilogue shared by all projector kernels.  Every thread of the block calls
+// it (the norm reduction needs the whole block).
+template <typename T>
+__device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T raw, T *outp, Blk b) {
+  __shared__ double red[kBlock / 64];
+  double out = (double)raw;
+  int k = 0;
+  if (e.use_ctl) {
+    k = e.ctl.ip[CI_K];
+    if (e.in_sel == IN_INV_TNEXT) out = out / e.ctl.t[k + 1];
+    if (e.prev_sel != PREV_NONE && valid) {
+      const double pc =
+          (e.prev_sel == PREV_NEG_ALPHA_OVER_T) ? -e.ctl.alpha[k] / e.ctl.t[k] : -e.ctl.t[k + 1];
+      out = fma(pc, (double)e.prev.get()[idx], out);
+    }
+  }
+  const T outT = (T)out;
+  if (valid) {
+    outp[idx] = outT;
+    if (e.out_raw.base) e.out_raw.get()[idx] = raw;
+  }
+  if (e.norm_to_t) {
+    const double v = valid ? (double)outT * (double)outT : 0.0;
+    const double bs = block_sum<kBlock>(v, red);
+    const unsigned nb = b.n;
+    if (threadIdx.x == 0) e.partials[b.id] = bs;
+    if (arrive_last(e.counter, nb)) {
+      double acc = 0.0;
+      for (unsigned b = threadIdx.x; b < nb; b += kBlock) acc += e.partials[b];
+      const double tot = block_sum<kBlock>(acc, red);
+      if (threadIdx.x == 0) {
+        e.ctl.t[k + 1] = sqrt(tot);
+        *e.counter = 0u;
+      }
+    }
+  }
+}
+
+}  // namespace gkb

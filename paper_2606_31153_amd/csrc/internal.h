@@ -140,6 +140,38 @@ struct GeomDev {
   int nc_bt;           // B^T candidates per line
   int nc_at;           // A^T candidate bins per view
   double uclamp_at;    // A^T: detector coordinates are clamped to [-uclamp_at, nu-1+uclamp_at]
+  // ---- cone beam (kind 2) ----
+  int nz, nw;          // volume depth, detector rows
+  double dw;           // detector row pitch
+  double SDD;          // source to detector
+  double offw;         // (nw-1)/2
+  double Su, Sw;       // SDD/du, SDD/dw
+  double hk_fac;       // A^T: candidate columns within hk_fac/depth of the voxel's detector coordinate
+  // padded volume: x-dominant copy [i][l+P][j+P] (planes of (nz+2P) x ldX),
+  // then at offYD the y-dominant copy [j][l+P][i+P] (planes of (nz+2P) x ldV)
+  int P3, ldX, ldV;
+  long long planeX, planeY, offYD, vol_pad_elems;
+  // padded sinogram for B: [v][r+PY][k+PY], rows of ldSu, views of sliceY
+  int PY3, ldSu;
+  long long sliceY, sino_pad_elems;
+};
+
+// Cone-beam ray tables, one entry per (view, detector column): the ray's
+// dominant axis (x or y; the z axis never dominates), its crossing of the
+// in-plane coordinate at the middle plane and the slope, the source-distance
+// parameter lambda at the middle plane and per plane (lambda * d_z gives z),
+// |d_xy|^2, and the plane ranges of A and B^T.
+template <typename T>
+struct ConeTab {
+  const T *base1;      // in-plane index coordinate of the crossing at the middle plane
+  const T *slope1;     // its change per plane
+  const T *lmid;       // lambda at the middle plane (= -S_ax / d_ax)
+  const T *lslope;     // lambda per plane (= 1 / d_ax)
+  const T *dxy2;       // d_x^2 + d_y^2 (unnormalised direction, detector at SDD)
+  const T *h1;         // B^T: in-plane candidate half-width
+  const int *meta;     // planes of A: lo | hi << 15 | ydom << 30
+  const int *meta_bt;  // planes of B^T
+  const T *pk;         // (1/d_ax, ydom) pairs for A^T
 };
 
 // Workgroup index and count within one slice's share of a launch.
@@ -245,6 +277,29 @@ void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt,
                     const Epi<T> &e, const int *stop, hipStream_t s);
 int pixel_blocks(const GeomDev &g);
 int ray_blocks(const GeomDev &g);
+
+// ---- cone-beam launchers (cone3d.hip) ----
+template <typename T>
+void launch_cone_pad_volume(const GeomDev &g, Col<const T> x, T *pad, int want_x, int want_y, const int *stop,
+                            hipStream_t s);
+template <typename T>
+void launch_cone_pad_sino(const GeomDev &g, Col<const T> y, T *pad, const int *stop, hipStream_t s);
+template <typename T>
+void launch_cone_weight_sino(const GeomDev &g, const ConeTab<T> &ct, Col<const T> y, T *wy, const int *stop,
+                             hipStream_t s);
+template <typename T>
+void launch_cone_fwd(const GeomDev &g, const ConeTab<T> &ct, const T *pad, Col<T> y, const Epi<T> &e,
+                     const int *stop, hipStream_t s);
+template <typename T>
+void launch_cone_back_adj(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt, const T *pad, Col<T> y,
+                          const Epi<T> &e, const int *stop, hipStream_t s);
+template <typename T>
+void launch_cone_back(const GeomDev &g, const ViewTab<T> &vt, const T *ypad, T *x, const Epi<T> &e,
+                      const int *stop, hipStream_t s);
+template <typename T>
+void launch_cone_fwd_adj(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt, const T *wy, T *x,
+                         const Epi<T> &e, const int *stop, hipStream_t s);
+int cone_voxel_blocks(const GeomDev &g);
 
 // ---- Krylov vector kernels (krylov.hip) ----
 int vec_blocks(long long dim);

@@ -28,28 +28,14 @@
 #include <algorithm>
 
 #include "batch.h"
+#include "devmath.h"
+#include "epilogue.h"
 #include "internal.h"
 #include "reduce.h"
 
 namespace gkb {
 
 namespace {
-
-// two consecutive elements, 4-byte (float) or 8-byte (double) aligned
-template <typename T>
-struct Pair;
-template <>
-struct Pair<float> {
-  typedef float v2 __attribute__((ext_vector_type(2), aligned(4)));
-};
-template <>
-struct Pair<double> {
-  typedef double v2 __attribute__((ext_vector_type(2), aligned(8)));
-};
-template <typename T>
-__device__ inline typename Pair<T>::v2 load_pair(const T *p) {
-  return *reinterpret_cast<const typename Pair<T>::v2 *>(p);
-}
 
 // atan of |z| <= 0.5: z * P(z^2), P a degree-5 polynomial fitted to atan(z)/z
 // on [0, 0.5] (relative error 5.4e-9, below float rounding).
@@ -85,46 +71,6 @@ __device__ inline float small_atan(float z) {
 }
 __device__ inline double small_atan(double z) { return atan(z); }
 
-__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double fast_rcp(double x) { return 1.0 / x; }
-
-// Epilogue shared by all projector kernels.  Every thread of the block calls
-// it (the norm reduction needs the whole block).
-template <typename T>
-__device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T raw, T *outp, Blk b) {
-  __shared__ double red[kBlock / 64];
-  double out = (double)raw;
-  int k = 0;
-  if (e.use_ctl) {
-    k = e.ctl.ip[CI_K];
-    if (e.in_sel == IN_INV_TNEXT) out = out / e.ctl.t[k + 1];
-    if (e.prev_sel != PREV_NONE && valid) {
-      const double pc =
-          (e.prev_sel == PREV_NEG_ALPHA_OVER_T) ? -e.ctl.alpha[k] / e.ctl.t[k] : -e.ctl.t[k + 1];
-      out = fma(pc, (double)e.prev.get()[idx], out);
-    }
-  }
-  const T outT = (T)out;
-  if (valid) {
-    outp[idx] = outT;
-    if (e.out_raw.base) e.out_raw.get()[idx] = raw;
-  }
-  if (e.norm_to_t) {
-    const double v = valid ? (double)outT * (double)outT : 0.0;
-    const double bs = block_sum<kBlock>(v, red);
-    const unsigned nb = b.n;
-    if (threadIdx.x == 0) e.partials[b.id] = bs;
-    if (arrive_last(e.counter, nb)) {
-      double acc = 0.0;
-      for (unsigned b = threadIdx.x; b < nb; b += kBlock) acc += e.partials[b];
-      const double tot = block_sum<kBlock>(acc, red);
-      if (threadIdx.x == 0) {
-        e.ctl.t[k + 1] = sqrt(tot);
-        *e.counter = 0u;
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // padded copies
@@ -661,7 +607,9 @@ __global__ __launch_bounds__(kBlock) void kb_fwd_adj(BatchDev<T> bd, int out_sel
 
 }  // namespace
 
-int pixel_blocks(const GeomDev &g) { return ((g.nx + 31) / 32) * ((g.ny + 7) / 8); }
+int pixel_blocks(const GeomDev &g) {
+  return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * (g.kind == 2 ? g.nz : 1);
+}
 int ray_blocks(const GeomDev &g) { return (int)((g.m + kBlock - 1) / kBlock); }
 
 template <typename T>

@@ -242,3 +242,23 @@ def test_cone_constant_volume_central_ray():
         # in-plane offset stays within the voxel centres; views at multiples of 90 deg do
         if abs(ddom - 1.0) < 1e-12:
             assert y[v, 4, 4] == pytest.approx(n / ddom, rel=1e-12)
+
+
+def test_cone_sampled_outputs_equal_the_full_operators():
+    # the sampled evaluations (used for checks at full size) reproduce the
+    # whole-operator loops exactly at the listed indices
+    g = synth.Geometry(kind=synth.KIND_CONE3D, nx=9, ny=7, nz=5, n_views=6, n_det_u=15, n_det_v=11,
+                       det_pitch_u=1.3, det_pitch_v=1.1, src_dist=20.0, src_det_dist=37.0,
+                       angle_span=2 * math.pi)
+    op = oracle.Operator(g)
+    r = np.random.default_rng(11)
+    x = r.standard_normal(g.n)
+    y = r.standard_normal(g.m)
+    rays = r.choice(g.m, 50, replace=False)
+    vox = r.choice(g.n, 40, replace=False)
+    assert np.array_equal(op.A_at(x, rays), op.A(x).reshape(-1)[rays])
+    assert np.array_equal(op.B_at(y, vox), op.B(y).reshape(-1)[vox])
+    with pytest.raises(ValueError):
+        op.A_at(x, [g.m])
+    with pytest.raises(ValueError):
+        oracle.Operator(synth.par2d(8, 4)).A_at(np.zeros(64), [0])
