@@ -161,6 +161,116 @@ def batch_bench(ctx):
             "pixels_total": int(sum(g.n for g in geoms)), "bins_total": int(sum(g.m for g in geoms))}
 
 
+def cone_units(geom) -> int:
+    """Joseph-3D samples of A (= nonzero bilinear stencils of A and A^T): the
+    (ray, plane) pairs whose crossing lies inside the volume.  Per ray the
+    planes with the in-plane crossing inside and those with the height inside
+    are two intervals; the count is the length of their intersection."""
+    nx, ny, nz, nu, nw = geom.nx, geom.ny, geom.nz, geom.n_det_u, geom.n_det_v
+    D, SDD, du, dw = geom.src_dist, geom.src_det_dist, geom.det_pitch_u, geom.det_pitch_v
+    uu = (np.arange(nu) - (nu - 1) / 2.0) * du
+    vv = (np.arange(nw) - (nw - 1) / 2.0) * dw
+    total = 0
+
+    def interval(c0, c1, lo, hi):
+        # integers t with lo < c0 + c1 t < hi
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ta, tb = (lo - c0) / c1, (hi - c0) / c1
+        a, b = np.minimum(ta, tb), np.maximum(ta, tb)
+        flat = c1 == 0
+        inside = (c0 > lo) & (c0 < hi)
+        a = np.where(flat, np.where(inside, -np.inf, np.inf), a)
+        b = np.where(flat, np.where(inside, np.inf, -np.inf), b)
+        return np.floor(a) + 1, np.ceil(b) - 1
+
+    for b in geom.view_angles():
+        cb, sb = math.cos(b), math.sin(b)
+        Sx, Sy = D * cb, D * sb
+        dx = -SDD * cb - uu * sb
+        dy = -SDD * sb + uu * cb
+        ydom = np.abs(dy) > np.abs(dx)
+        dax = np.where(ydom, dy, dx)
+        dob = np.where(ydom, dx, dy)
+        nax = np.where(ydom, ny, nx)
+        n1 = np.where(ydom, nx, ny)
+        lam0 = (-(nax - 1) / 2.0 - np.where(ydom, Sy, Sx)) / dax  # lambda at plane 0
+        p10 = np.where(ydom, Sx, Sy) + lam0 * dob + (n1 - 1) / 2.0
+        p1s = dob / dax
+        lo1, hi1 = interval(p10, p1s, -1.0, n1)
+        lo1 = np.maximum(lo1, 0)
+        hi1 = np.minimum(hi1, nax - 1)
+        lo2, hi2 = interval(lam0[:, None] * vv[None, :] + (nz - 1) / 2.0, (1.0 / dax)[:, None] * vv[None, :],
+                            -1.0, nz)
+        lo = np.maximum(lo1[:, None], lo2)
+        hi = np.minimum(hi1[:, None], hi2)
+        total += int(np.clip(hi - lo + 1, 0, None).sum())
+    return total
+
+
+def cone_main(args):
+    """512^3 cone beam (720 views, 1024 x 768 flat detector, D = 1024,
+    SDD = 2048): the four projectors and BA-GKB iterations."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    from paper_2606_31153_amd import synth
+    dev = torch.device("cuda:0")
+    geom = synth.cone3d(512, 720, 1024, 768)
+    print("bench: cone phantom", file=sys.stderr, flush=True)
+    xt = torch.from_numpy(synth.rasterize_ellipsoids(synth.ellipsoid_params(5000), 512).reshape(-1)).to(dev)
+    ctx = gk.Context(0)
+    bt = torch.empty(geom.m, dtype=torch.float32, device=dev)
+    gk.gkb_forward(ctx, geom, xt, bt)
+    torch.cuda.synchronize()
+    print("bench: cone noise", file=sys.stderr, flush=True)
+    b, enorm = synth.add_noise(bt.double().cpu().numpy(), synth.noise_direction(geom.m, 5000), 0.01)
+    bd = torch.from_numpy(b.astype(np.float32)).to(dev)
+    del b
+    x = torch.empty(geom.n, dtype=torch.float32, device=dev)
+    y = torch.empty(geom.m, dtype=torch.float32, device=dev)
+    calls = {"fwd": lambda: gk.gkb_forward(ctx, geom, xt, y), "back": lambda: gk.gkb_back(ctx, geom, bd, x),
+             "fwd_adj": lambda: gk.gkb_forward_adjoint(ctx, geom, bd, x),
+             "back_adj": lambda: gk.gkb_back_adjoint(ctx, geom, xt, y)}
+    for f in calls.values():
+        f()
+    torch.cuda.synchronize()
+    ctx.trace_enable(True)
+    ctx.trace_reset()
+    for _ in range(args.steps):
+        for f in calls.values():
+            f()
+    torch.cuda.synchronize()
+    kernels = {}
+    for name in calls:
+        cnt, ms = ctx.trace_get(name)
+        kernels[name] = {"launches": cnt, "avg_ms": ms / cnt}
+    ctx.trace_enable(False)
+    print("bench: cone BA-GKB", file=sys.stderr, flush=True)
+    iters = args.cone_iters
+    t0 = time.perf_counter()
+    r = gk.gkb_ba_solve(ctx, geom, bd, x, iters, use_dp=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print("bench: cone units", file=sys.stderr, flush=True)
+    units = cone_units(geom)
+    pv = geom.n * geom.n_views
+    u = {"fwd": units, "fwd_adj": units, "back": pv, "back_adj": pv}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    ach = u[dom] * 8.0 / (kernels[dom]["avg_ms"] / 1e3) / 1e12
+    out = {"metric": "cone 512^3: BA-GKB iters/s; projector time per call", "value": r.k_stop / el,
+           "unit": "GKB iters/s", "n_gpus": 1, "iterations": r.k_stop, "seconds": el,
+           "higher_is_better": True, "dtype": "f32 vectors/projectors, f64 reductions and projected solve",
+           "data": "synthetic: seeded 8-ellipsoid phantom, 1% Gaussian noise",
+           "config": {"workload": "cone beam 512^3, 720 views over 360 deg, 1024x768 flat detector, D=1024, "
+                                  "SDD=2048; BA-GKB %d iterations" % iters},
+           "kernels": kernels, "units": {"joseph_samples": units, "voxel_views": pv},
+           "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": VALU_FP32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / VALU_FP32_PEAK_TFLOPS,
+                        "work_per_launch": "%d units x 8 flop (bilinear: 3 lerps + accumulate)" % u[dom]}}
+    ctx.close()
+    print(json.dumps(out))
+
+
 def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int):
     import oracle
     op = oracle.Operator(geom)
@@ -181,10 +291,16 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cone", action="store_true", help="measure the 512^3 cone-beam workload instead")
+    ap.add_argument("--cone-iters", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.cone:
+        cone_main(args)
+        return
 
     import torch
 

@@ -218,23 +218,32 @@ def rasterize_ellipsoids(params: np.ndarray, n: int, ss: int = 2, zchunk: int = 
     """Mean of ss^3 point samples per voxel; float32 [n][n][n] (z, y, x)."""
     ax = _supersample_axis(n, ss)
     out = np.zeros((n, n, n), dtype=np.float32)
-    Y, X = np.meshgrid(ax, ax, indexing="ij")
+    # per ellipsoid: its axis-aligned bounding box (samples outside it are outside)
+    boxes = []
+    for row in params:
+        R = _quat_rot(row[6:10])
+        ext = np.sqrt((R * np.asarray(row[3:6])[None, :]) ** 2 @ np.ones(3)) * 1.001 + 1e-9
+        lo = [int(np.searchsorted(ax, row[i] - ext[i])) for i in range(3)]
+        hi = [int(np.searchsorted(ax, row[i] + ext[i], side="right")) for i in range(3)]
+        boxes.append((R, lo, hi))
     for z0 in range(0, n, zchunk):
         z1 = min(n, z0 + zchunk)
-        zs = ax[z0 * ss:z1 * ss]
-        acc = np.zeros((len(zs), n * ss, n * ss), dtype=np.float32)
-        for row in params:
+        acc = np.zeros(((z1 - z0) * ss, n * ss, n * ss), dtype=np.float32)
+        for row, (R, lo, hi) in zip(params, boxes):
             cx, cy, cz, a, b, c = row[:6]
-            R = _quat_rot(row[6:10])
             rho = row[10]
-            dz = (zs - cz)[:, None, None]
-            dx = (X - cx)[None]
-            dy = (Y - cy)[None]
+            k0, k1 = max(lo[2], z0 * ss), min(hi[2], z1 * ss)
+            if k0 >= k1 or lo[1] >= hi[1] or lo[0] >= hi[0]:
+                continue
+            dz = (ax[k0:k1] - cz)[:, None, None]
+            dy = (ax[lo[1]:hi[1]] - cy)[None, :, None]
+            dx = (ax[lo[0]:hi[0]] - cx)[None, None, :]
             # body coordinates = R^T (p - c)
             u = R[0, 0] * dx + R[1, 0] * dy + R[2, 0] * dz
             v = R[0, 1] * dx + R[1, 1] * dy + R[2, 1] * dz
             w = R[0, 2] * dx + R[1, 2] * dy + R[2, 2] * dz
-            acc += np.float32(rho) * ((u / a) ** 2 + (v / b) ** 2 + (w / c) ** 2 <= 1.0)
+            acc[k0 - z0 * ss:k1 - z0 * ss, lo[1]:hi[1], lo[0]:hi[0]] += \
+                np.float32(rho) * ((u / a) ** 2 + (v / b) ** 2 + (w / c) ** 2 <= 1.0)
         out[z0:z1] = acc.reshape(z1 - z0, ss, n, ss, n, ss).mean(axis=(1, 3, 5))
     return out
 
