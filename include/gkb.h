@@ -156,6 +156,49 @@ typedef enum { GKB_METHOD_AB = 0, GKB_METHOD_BA = 1 } gkb_method;
 gkb_status gkb_batch_solve(gkb_ctx *ctx, int method, int n_slices, const gkb_geometry *geoms, int dtype,
                            const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info);
 
+/* ---- Learned sinogram filter inside B (BA-GKB only) ----
+ * BA-GKB (Alg. "BA-GKB") applies B and B^T only, so a linear filter F on
+ * the sinogram side of B keeps the algorithm as it is: M = B F A,
+ * M^T = A^T F^T B^T, right-hand side B F b.  F is the frozen-mask
+ * linearisation at the measured b of a bias-free 1D convolutional network N
+ * along the detector axis of every view (every detector row in 3D):
+ * 1 -> 32 -> 32 -> 32 -> 1 channels, kernel 9, zero "same" padding, ReLU
+ * after layers 1-3; with the ReLU masks of b frozen, F is linear, F b = N(b),
+ * and F^T is its exact transpose.  The discrepancy test stays on
+ * ||A x - b||.  Set gkb_solve_opts.precond to a network to use it (GKB_F32,
+ * gkb_ba_solve); if the learned solve does not reach the discrepancy level by
+ * k_max, breaks down before iteration 3 or meets a non-finite value, the
+ * plain BA-GKB result is returned with reason GKB_STOP_FALLBACK.
+ *
+ * Weights: FP32 master copy of 19008 values, W1 [32][1][9], W2 [32][32][9],
+ * W3 [32][32][9], W4 [1][32][9] ([out][in][tap], concatenated); every layer
+ * uses them rounded to bfloat16.  The 32 -> 32 layers run on the matrix cores
+ * (bfloat16 operands, FP32 accumulation); inside GKB each FP32 activation
+ * enters them as three bfloat16 terms, so F is applied at FP32 accuracy.
+ * Training: loss = mean over the batch of ||B N(b_i) - x_i||^2 / ||x_i||^2
+ * (bfloat16 inputs of layers 2, 3 and bfloat16 gradients through them),
+ * Adam (beta 0.9 / 0.999, eps 1e-8) with bias correction.
+ * A network belongs to the device of the context it was created with. */
+gkb_status gkb_net_create(gkb_ctx *ctx, gkb_net **net, int channels, int ksize, int layers,
+                          unsigned long long seed);   /* channels 32, ksize 9, layers 4; He initialisation */
+void gkb_net_destroy(gkb_net *net);
+gkb_status gkb_net_set_weights(gkb_net *net, const float *w, long long count);  /* HOST w[19008]; resets Adam */
+gkb_status gkb_net_get_weights(const gkb_net *net, float *w, long long count);  /* HOST w[19008] */
+gkb_status gkb_net_save(const gkb_net *net, const char *path);  /* "GKBNET1\0", int32 {32, 9, 4, 19008}, FP32 weights */
+gkb_status gkb_net_load(gkb_net *net, const char *path);
+/* out = N(y) for a sinogram y of geometry g (DEVICE, FP32, m elements each). */
+gkb_status gkb_net_apply(gkb_ctx *ctx, const gkb_net *net, const gkb_geometry *g, const void *y, void *out);
+/* out = F y (transpose = 0) or F^T y (transpose = 1), F frozen at b (DEVICE, FP32, m elements each). */
+gkb_status gkb_net_frozen_apply(gkb_ctx *ctx, const gkb_net *net, const gkb_geometry *g, const void *b,
+                                const void *y, void *out, int transpose);
+/* Mean training loss over a batch and its gradient: b DEVICE [batch][m], x DEVICE [batch][n] (FP32, 2D
+ * geometry); *loss and the HOST gradient grad[19008] (may be NULL).  Blocks until done. */
+gkb_status gkb_net_grad(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
+                        const void *x, double *loss, float *grad);
+/* gkb_net_grad followed by one Adam step with learning rate lr. */
+gkb_status gkb_net_train_step(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
+                              const void *x, double lr, double *loss);
+
 /* Kernel timing.  While enabled, every launch of the named kernels is
  * bracketed by HIP events on the context's stream; gkb_trace_get returns the
  * launch count and summed device milliseconds since the last reset. */

@@ -33,7 +33,10 @@ STATUS_NAMES = {0: "GKB_OK", -1: "GKB_EINVAL", -2: "GKB_ENOMEM", -3: "GKB_EDEVIC
                 -5: "GKB_EUNSUPPORTED"}
 EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gkb_forward", "gkb_back",
             "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve",
-            "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_reset", "gkb_trace_get")
+            "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
+            "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
+            "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step")
+NET_PARAMS = 19008
 
 
 class GkbError(RuntimeError):
@@ -88,6 +91,18 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
         L.gkb_batch_solve.argtypes = [vp, cp, cp, G, cp, ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                                       ctypes.POINTER(vp), ctypes.POINTER(SolveInfo)]
+        L.gkb_net_create.argtypes = [vp, ctypes.POINTER(vp), cp, cp, cp, ctypes.c_ulonglong]
+        L.gkb_net_destroy.argtypes = [vp]
+        L.gkb_net_destroy.restype = None
+        FP = ctypes.POINTER(ctypes.c_float)
+        L.gkb_net_set_weights.argtypes = [vp, FP, ctypes.c_longlong]
+        L.gkb_net_get_weights.argtypes = [vp, FP, ctypes.c_longlong]
+        L.gkb_net_save.argtypes = [vp, ctypes.c_char_p]
+        L.gkb_net_load.argtypes = [vp, ctypes.c_char_p]
+        L.gkb_net_apply.argtypes = [vp, vp, G, vp, vp]
+        L.gkb_net_frozen_apply.argtypes = [vp, vp, G, vp, vp, vp, cp]
+        L.gkb_net_grad.argtypes = [vp, vp, G, cp, vp, vp, ctypes.POINTER(ctypes.c_double), FP]
+        L.gkb_net_train_step.argtypes = [vp, vp, G, cp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
         L.gkb_trace_enable.argtypes = [vp, cp]
         L.gkb_trace_reset.argtypes = [vp]
         L.gkb_trace_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(cp), ctypes.POINTER(ctypes.c_double)]
@@ -222,7 +237,7 @@ class SolveResult:
 
 
 def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, use_dp: bool = False,
-           tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True) -> SolveResult:
+           tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True, precond=None) -> SolveResult:
     g, keep = make_geometry(geom)
     code = _dtype_code(b)
     if x.dtype != b.dtype:
@@ -231,7 +246,8 @@ def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, us
     alpha = np.zeros(k_max + 1)
     t = np.zeros(k_max + 1)
     P = ctypes.POINTER(ctypes.c_double)
-    o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0, None,
+    o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0,
+                  None if precond is None else precond.handle,
                   rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P))
     info = SolveInfo()
     _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(b, geom.m), ctypes.byref(o),
@@ -309,3 +325,76 @@ def gkb_batch_solve(ctx: Context, method: int, geoms, bs, xs, opts) -> list:
                                proj_residual=I[s].proj_residual, t1=I[s].t1, alpha1=I[s].alpha1,
                                seconds=I[s].seconds, rho=rho[:k], alpha=alpha[:k + 1], t=t[:k + 1]))
     return out
+
+
+class Net:
+    """The learned sinogram filter (gkb_net): 32 channels, kernel 9, 4 layers,
+    He-initialised from ``seed``; lives on the context's device."""
+
+    def __init__(self, ctx: Context, seed: int = 0, channels: int = 32, ksize: int = 9, layers: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().gkb_net_create(ctx.handle, ctypes.byref(h), channels, ksize, layers, seed))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gkb_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_weights(self) -> np.ndarray:
+        w = np.zeros(NET_PARAMS, dtype=np.float32)
+        _check(lib().gkb_net_get_weights(self.handle, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
+        return w
+
+    def set_weights(self, w) -> None:
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+        _check(lib().gkb_net_set_weights(self.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+
+    def save(self, path: str) -> None:
+        _check(lib().gkb_net_save(self.handle, path.encode()))
+
+    def load(self, path: str) -> None:
+        _check(lib().gkb_net_load(self.handle, path.encode()))
+
+
+def gkb_net_apply(ctx: Context, net: Net, geom, y, out):
+    """out = N(y) (FP32 device tensors of m elements)."""
+    g, keep = make_geometry(geom)
+    _check(lib().gkb_net_apply(ctx.handle, net.handle, ctypes.byref(g), _dev_ptr(y, geom.m), _dev_ptr(out, geom.m)))
+    return out
+
+
+def gkb_net_frozen_apply(ctx: Context, net: Net, geom, b, y, out, transpose: bool = False):
+    """out = F y or F^T y with the masks of b frozen."""
+    g, keep = make_geometry(geom)
+    _check(lib().gkb_net_frozen_apply(ctx.handle, net.handle, ctypes.byref(g), _dev_ptr(b, geom.m),
+                                      _dev_ptr(y, geom.m), _dev_ptr(out, geom.m), 1 if transpose else 0))
+    return out
+
+
+def gkb_net_grad(ctx: Context, net: Net, geom, bs, xs):
+    """(mean loss, gradient [19008]) for a batch: bs [batch, m], xs [batch, n] FP32 device tensors."""
+    g, keep = make_geometry(geom)
+    batch = bs.shape[0]
+    loss = ctypes.c_double()
+    grad = np.zeros(NET_PARAMS, dtype=np.float32)
+    _check(lib().gkb_net_grad(ctx.handle, net.handle, ctypes.byref(g), batch, _dev_ptr(bs, batch * geom.m),
+                              _dev_ptr(xs, batch * geom.n), ctypes.byref(loss),
+                              grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return loss.value, grad
+
+
+def gkb_net_train_step(ctx: Context, net: Net, geom, bs, xs, lr: float) -> float:
+    """One Adam step on a batch; returns the batch loss before the step."""
+    g, keep = make_geometry(geom)
+    batch = bs.shape[0]
+    loss = ctypes.c_double()
+    _check(lib().gkb_net_train_step(ctx.handle, net.handle, ctypes.byref(g), batch, _dev_ptr(bs, batch * geom.m),
+                                    _dev_ptr(xs, batch * geom.n), lr, ctypes.byref(loss)))
+    return loss.value

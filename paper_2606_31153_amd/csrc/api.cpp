@@ -15,11 +15,13 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gkb.h"
@@ -564,6 +566,8 @@ struct gkb_ctx {
   int *bpin = nullptr;  // pinned staging of launch maps: two slots
   size_t bpin_slot = 0;
   hipEvent_t bpin_ev[2] = {nullptr, nullptr};
+  // learned filter: activations, masks, filter output, training buffers
+  DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ncnt;
   // tracing
   bool trace = false;
   std::map<std::string, TraceStat> stats;
@@ -849,6 +853,191 @@ gkb_status projector_call(gkb_ctx *c, const gkb_geometry *g, int dtype, const vo
 }
 
 // --------------------------------------------------------------------------
+// learned sinogram filter: network object, filter chains, training
+// --------------------------------------------------------------------------
+}  // namespace
+
+struct gkb_net {
+  int device = 0;
+  DevBuf W, m, v, grad, prep;  // master weights, Adam state, gradient, derived layouts
+  NetW nw{};
+  int step = 0;
+};
+
+namespace {
+
+constexpr long long kOffW2 = (long long)kNetC * kNetK, kOffW3 = kOffW2 + (long long)kNetC * kNetC * kNetK,
+                    kOffW4 = kOffW3 + (long long)kNetC * kNetC * kNetK;
+
+gkb_status net_prepare(gkb_net *net, hipStream_t st) {
+  launch_net_prep(net->W.as<float>(), net->nw, st);
+  HIPC(hipGetLastError());
+  return GKB_OK;
+}
+
+// rows (views x detector rows) and columns of a geometry's sinogram
+void net_shape(const gkb_geometry *g, long long &rows, int &L) {
+  rows = (long long)g->n_views * (g->kind == GKB_CONE3D ? g->n_det_v : 1);
+  L = g->n_det_u;
+}
+
+// positions per chunk of the filter chains (two activation buffers of
+// 32 floats per position)
+constexpr long long kNetChunk = 1LL << 23;
+
+gkb_status net_scratch(gkb_ctx *c, long long rows, int L) {
+  const long long per = std::min(rows, std::max(1LL, kNetChunk / L)) * L;
+  HIPC(c->na0.ensure(sizeof(float) * kNetC * (size_t)per));
+  HIPC(c->na1.ensure(sizeof(float) * kNetC * (size_t)per));
+  HIPC(c->nmask.ensure(sizeof(unsigned) * 3 * (size_t)(rows * L)));
+  HIPC(c->nout.ensure(sizeof(float) * (size_t)(rows * L)));
+  return GKB_OK;
+}
+
+enum NetOp { NET_MASKS = 0, NET_F = 1, NET_FT = 2 };
+
+// NET_MASKS: out = N(y) and the frozen masks of y; NET_F: out = F y;
+// NET_FT: out = F^T y (the masks as last computed).  Rows in chunks.
+void net_chain(gkb_ctx *c, const gkb_net *net, int op, Col<const float> y, float *out, long long rows, int L,
+               const int *stop, hipStream_t st) {
+  const long long m = rows * L;
+  const long long crow = std::max(1LL, kNetChunk / L);
+  float *a0 = c->na0.as<float>(), *a1 = c->na1.as<float>();
+  unsigned *masks = c->nmask.as<unsigned>();
+  const NetW &w = net->nw;
+  for (long long r0 = 0; r0 < rows; r0 += crow) {
+    const long long nr = std::min(crow, rows - r0);
+    const long long off = r0 * L;
+    Col<const float> yin{y.base + off, y.ld, y.off, y.kptr};
+    unsigned *m0 = masks + off, *m1 = masks + m + off, *m2 = masks + 2 * m + off;
+    if (op == NET_MASKS) {
+      launch_net_c1(yin, a0, m0, w.w1, L, nr, 1, stop, st);
+      launch_net_c32(a0, a1, m1, w.w2b, L, nr, 3, 1, stop, st);
+      launch_net_c32(a1, a0, m2, w.w3b, L, nr, 3, 1, stop, st);
+      launch_net_c4(a0, out + off, w.w4, L, nr, stop, st);
+    } else if (op == NET_F) {
+      launch_net_c1(yin, a0, m0, w.w1, L, nr, 2, stop, st);
+      launch_net_c32(a0, a1, m1, w.w2b, L, nr, 3, 2, stop, st);
+      launch_net_c32(a1, a0, m2, w.w3b, L, nr, 3, 2, stop, st);
+      launch_net_c4(a0, out + off, w.w4, L, nr, stop, st);
+    } else {
+      launch_net_c1(yin, a0, m2, w.w4t, L, nr, 2, stop, st);
+      launch_net_c32(a0, a1, m1, w.w3t, L, nr, 3, 2, stop, st);
+      launch_net_c32(a1, a0, m0, w.w2t, L, nr, 3, 2, stop, st);
+      launch_net_c4(a0, out + off, w.w1t, L, nr, stop, st);
+    }
+  }
+}
+
+// He initialisation N(0, 2 / fan_in) from a counter-based generator:
+// SplitMix64 (Steele, Lea and Flood 2014) for uniform 53-bit numbers,
+// Box-Muller for the normal deviates.
+void he_init(unsigned long long seed, std::vector<float> &w) {
+  auto mix = [](uint64_t z) {
+    z += 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  };
+  auto unif = [&](uint64_t i) { return ((mix(seed * 0x100000001B3ULL + i) >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+  const double pi = 3.14159265358979323846;
+  w.resize(kNetParams);
+  for (int i = 0; i < kNetParams; ++i) {
+    const double fan_in = (i < kOffW2) ? kNetK : (double)kNetC * kNetK;
+    const double u1 = unif(2 * (uint64_t)i), u2 = unif(2 * (uint64_t)i + 1);
+    const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * pi * u2);
+    w[i] = (float)(g * std::sqrt(2.0 / fan_in));
+  }
+}
+
+// gradient of the mean training loss over a batch of S sinograms b [S][m]
+// and targets x [S][n] (2D geometry); optional Adam step
+gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S, const float *b, const float *x,
+                         double *loss_out) {
+  DevTables *d = nullptr;
+  gkb_status stt = get_tables(c, g, GKB_F32, &d);
+  if (stt != GKB_OK) return stt;
+  const GeomDev &gd = d->gd;
+  hipStream_t st = c->stream;
+  const long long mS = gd.m, n = gd.n, rows = (long long)S * gd.nv, M = rows * gd.nu;
+  const int L = gd.nu;
+  const size_t act = sizeof(float) * kNetC * (size_t)M;
+  HIPC(c->na0.ensure(act));
+  HIPC(c->na1.ensure(act));
+  HIPC(c->na2.ensure(act));
+  HIPC(c->nga.ensure(act));
+  HIPC(c->ngb.ensure(act));
+  HIPC(c->nmask.ensure(sizeof(unsigned) * 3 * (size_t)M));
+  HIPC(c->nout.ensure(sizeof(float) * (size_t)M));
+  HIPC(c->ngout.ensure(sizeof(float) * (size_t)M));
+  HIPC(c->nxh.ensure(sizeof(float) * (size_t)n));
+  HIPC(c->nr.ensure(sizeof(float) * (size_t)n));
+  HIPC(c->npart.ensure(sizeof(float) * (size_t)net_wgrad_blocks() * kNetC * kNetC * kNetK));
+  HIPC(c->nsums.ensure(sizeof(double) * 2 * (size_t)S));
+  HIPC(c->nred.ensure(sizeof(double) * 2 * 1024));
+  if (!c->ncnt.p) {
+    HIPC(c->ncnt.ensure(64));
+    HIPC(hipMemset(c->ncnt.p, 0, 64));
+  }
+  const long long nb = std::max<long long>(std::max(ray_blocks(gd), pixel_blocks(gd)), 1);
+  stt = ensure_scratch(c, gd, sizeof(float), nb);
+  if (stt != GKB_OK) return stt;
+  float *a1 = c->na0.as<float>(), *a2 = c->na1.as<float>(), *a3 = c->na2.as<float>();
+  float *ga = c->nga.as<float>(), *gb = c->ngb.as<float>(), *out = c->nout.as<float>(), *gout = c->ngout.as<float>();
+  unsigned *mk = c->nmask.as<unsigned>();
+  unsigned *m0 = mk, *m1 = mk + M, *m2 = mk + 2 * M;
+  float *part = c->npart.as<float>(), *grad = net->grad.as<float>();
+  const NetW &w = net->nw;
+  // forward with the training rounding (bfloat16 operands in layers 2, 3)
+  launch_net_c1(Col<const float>{b, 0, 0, nullptr}, a1, m0, w.w1, L, rows, 1, nullptr, st);
+  launch_net_c32(a1, a2, m1, w.w2b, L, rows, 1, 1, nullptr, st);
+  launch_net_c32(a2, a3, m2, w.w3b, L, rows, 1, 1, nullptr, st);
+  launch_net_c4(a3, out, w.w4, L, rows, nullptr, st);
+  // per sample: xhat = B N(b_s); r = xhat - x_s; gout_s = B^T r * 2 / (||x_s||^2 S)
+  const Epi<float> pe = plain_epi<float>();
+  for (int si = 0; si < S; ++si) {
+    launch_pad_sino<float>(gd, col<const float>(out + si * mS), c->ypad.as<float>(), nullptr, st);
+    launch_back<float>(gd, vt_of<float>(*d), c->ypad.as<float>(), c->nxh.as<float>(), pe, nullptr, st);
+    launch_net_resid(c->nxh.as<float>(), x + si * n, c->nr.as<float>(), n, c->nred.as<double>(),
+                     c->ncnt.as<unsigned>(), c->nsums.as<double>() + 2 * si, st);
+    launch_net_scale(c->nr.as<float>(), n, c->nsums.as<double>() + 2 * si, S, st);
+    launch_pad_image<float>(gd, col<const float>(c->nr.as<float>()), c->xpad.as<float>(), d->has_coldom, nullptr,
+                            st);
+    launch_back_adj<float>(gd, rt_of<float>(*d), c->xpad.as<float>(), col<float>(gout + si * mS), pe, nullptr, st);
+  }
+  // backward
+  const int np = net_wgrad_blocks();
+  launch_net_wgrad_edge(a3, gout, part, L, rows, -1, st);
+  launch_net_reduce(part, np, kNetC * kNetK, grad + kOffW4, 1.0, st);
+  launch_net_c1(Col<const float>{gout, 0, 0, nullptr}, ga, m2, w.w4t, L, rows, 2, nullptr, st);
+  launch_net_wgrad32(ga, a2, part, L, rows, st);
+  launch_net_reduce(part, np, kNetC * kNetC * kNetK, grad + kOffW3, 1.0, st);
+  launch_net_c32(ga, gb, m1, w.w3t, L, rows, 1, 2, nullptr, st);
+  launch_net_wgrad32(gb, a1, part, L, rows, st);
+  launch_net_reduce(part, np, kNetC * kNetC * kNetK, grad + kOffW2, 1.0, st);
+  launch_net_c32(gb, ga, m0, w.w2t, L, rows, 1, 2, nullptr, st);
+  launch_net_wgrad_edge(ga, b, part, L, rows, 1, st);
+  launch_net_reduce(part, np, kNetC * kNetK, grad, 1.0, st);
+  HIPC(hipGetLastError());
+  std::vector<double> sums(2 * (size_t)S);
+  HIPC(hipMemcpyAsync(sums.data(), c->nsums.p, sizeof(double) * sums.size(), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  double loss = 0.0;
+  for (int si = 0; si < S; ++si) loss += sums[2 * si] / sums[2 * si + 1];
+  loss /= S;
+  if (!std::isfinite(loss)) return fail(GKB_ENONFINITE, "non-finite training loss");
+  if (loss_out) *loss_out = loss;
+  return GKB_OK;
+}
+
+gkb_status net_check(gkb_ctx *c, const gkb_net *net) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!net) return fail(GKB_EINVAL, "network is NULL");
+  if (net->device != c->device) return fail(GKB_EINVAL, "network and context are on different devices");
+  return GKB_OK;
+}
+
+// --------------------------------------------------------------------------
 // GKB driver
 // --------------------------------------------------------------------------
 enum Mode { MODE_AB = 0, MODE_BA = 1, MODE_GKB = 2 };
@@ -870,6 +1059,10 @@ struct Solver {
   hipStream_t st;
   const int *stop = nullptr;
   const int *kp = nullptr;
+  // learned filter inside B (BA-GKB, FP32): M = B F A, M^T = A^T F^T B^T
+  const gkb_net *net = nullptr;
+  long long nrows = 0;
+  int nL = 0;
 
   Solver(gkb_ctx *ctx, const DevTables &dt, int md, int kmax) : c(ctx), d(dt), g(dt.gd), mode(md), K(kmax) {
     n = g.n;
@@ -997,9 +1190,14 @@ struct Solver {
     e.prev_sel = PREV_NEG_ALPHA_OVER_T;
     e.prev = col<const T>(s);
     e.norm_to_t = 1;
-    if (mode == MODE_BA) {  // Y_k = A q_k ; s~ = B Y_k - ...
+    if (mode == MODE_BA) {  // Y_k = A q_k ; s~ = B Y_k - ...  (B F Y_k with the filter)
       A(qcol(-1), ycol(0), plain_epi<T>());
-      B(colk<const T>(Y, ldy, 0, kp), s, e);
+      if (filtered()) {
+        filter(NET_F, colk<const T>(Y, ldy, 0, kp));
+        B(col<const T>(c->nout.as<T>()), s, e);
+      } else {
+        B(colk<const T>(Y, ldy, 0, kp), s, e);
+      }
     } else if (mode == MODE_AB) {  // Y_k = A B q_k ; s~ = Y_k - ...
       B(qcol(-1), tn, plain_epi<T>());
       e.out_raw = ycol(0);
@@ -1007,6 +1205,15 @@ struct Solver {
     } else {  // matched: Y_k = A q_k ; s~ = Y_k - ...
       e.out_raw = ycol(0);
       A(qcol(-1), col<T>(s), e);
+    }
+  }
+
+  bool filtered() const { return std::is_same<T, float>::value && net != nullptr; }
+  // filter chain into the context's filter output buffer (FP32 path only)
+  void filter(int op, Col<const T> in) {
+    if constexpr (std::is_same<T, float>::value) {
+      TraceScope ts(c, op == NET_FT ? "filter_t" : "filter");
+      net_chain(c, net, op, in, c->nout.as<float>(), nrows, nL, stop, st);
     }
   }
 
@@ -1019,9 +1226,14 @@ struct Solver {
       e1.prev_sel = PREV_NEG_TNEXT;
       e1.prev = qcol(-1);
     }
-    if (mode == MODE_BA) {  // A^T (B^T s)
+    if (mode == MODE_BA) {  // A^T (B^T s)  (A^T F^T B^T s with the filter)
       Bt(col<const T>(s), col<T>(tm), e0);
-      At(col<const T>(tm), w, e1);
+      if (filtered()) {
+        filter(NET_FT, col<const T>(tm));
+        At(col<const T>(c->nout.as<T>()), w, e1);
+      } else {
+        At(col<const T>(tm), w, e1);
+      }
     } else if (mode == MODE_AB) {  // B^T (A^T s)
       At(col<const T>(s), tn, e0);
       Bt(col<const T>(tn), col<T>(w), e1);
@@ -1071,6 +1283,12 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   Solver<T> S(c, *d, mode, o->k_max);
   stt = S.alloc();
   if (stt != GKB_OK) return stt;
+  if (o->precond) {
+    S.net = o->precond;
+    net_shape(geom, S.nrows, S.nL);
+    stt = net_scratch(c, S.nrows, S.nL);
+    if (stt != GKB_OK) return stt;
+  }
   const T *b = static_cast<const T *>(bv);
   T *x = static_cast<T *>(xv);
   hipStream_t st = c->stream;
@@ -1094,7 +1312,12 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   if (mode == MODE_BA) {
     Epi<T> e = S.epi();
     e.norm_to_t = 1;
-    S.B(col<const T>(b), S.s, e);
+    if (S.filtered()) {  // rhs B F b = B N(b); the masks of b are frozen here
+      S.filter(NET_MASKS, col<const T>(b));
+      S.B(col<const T>(c->nout.as<T>()), S.s, e);
+    } else {
+      S.B(col<const T>(b), S.s, e);
+    }
   } else {
     launch_copy<T>(b, S.s, g.m, st);
     launch_norm_to<T>(S.ctl, S.s, g.m, NORM_T1, S.partials, S.counters, st);
@@ -1187,7 +1410,6 @@ gkb_status validate_opts(const gkb_solve_opts *o) {
     return fail(GKB_EINVAL, "tau must be > 0 when the discrepancy principle is on");
   if (o->use_dp && (!(o->noise_norm >= 0.0) || !std::isfinite(o->noise_norm)))
     return fail(GKB_EINVAL, "noise_norm must be finite and >= 0");
-  if (o->precond) return fail(GKB_EUNSUPPORTED, "learned preconditioner is not available in this build");
   return GKB_OK;
 }
 
@@ -1201,6 +1423,33 @@ gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void 
   st = validate_opts(o);
   if (st != GKB_OK) return st;
   HIPC(hipSetDevice(c->device));
+  if (o->precond) {
+    if (mode != MODE_BA) return fail(GKB_EUNSUPPORTED, "the learned filter sits inside B: BA-GKB only");
+    if (dtype != GKB_F32) return fail(GKB_EUNSUPPORTED, "the learned filter runs in FP32 (GKB_F32)");
+    st = net_check(c, o->precond);
+    if (st != GKB_OK) return st;
+    // learned solve; plain BA-GKB is the fallback when the learned one does
+    // not reach the discrepancy level, breaks down early or meets a
+    // non-finite value
+    gkb_solve_info li{};
+    st = solve_impl<float>(c, g, dtype, b, o, x, &li, mode);
+    const bool bad = st == GKB_ENONFINITE ||
+                     (st == GKB_OK && (li.reason == GKB_STOP_DP_NOT_REACHED || !(li.t1 > 0.0) ||
+                                       (li.reason == GKB_STOP_BREAKDOWN && li.k_stop < 3)));
+    if (!bad) {
+      if (st == GKB_OK && info) *info = li;
+      return st;
+    }
+    gkb_solve_opts po = *o;
+    po.precond = nullptr;
+    gkb_solve_info pi{};
+    st = solve_impl<float>(c, g, dtype, b, &po, x, &pi, mode);
+    if (st != GKB_OK) return st;
+    pi.reason = GKB_STOP_FALLBACK;
+    pi.seconds += li.seconds;
+    if (info) *info = pi;
+    return GKB_OK;
+  }
   return dtype == GKB_F32 ? solve_impl<float>(c, g, dtype, b, o, x, info, mode)
                           : solve_impl<double>(c, g, dtype, b, o, x, info, mode);
 }
@@ -1594,6 +1843,7 @@ gkb_status batch_entry(gkb_ctx *c, int method, int ns, const gkb_geometry *geoms
     gkb_status st = validate_geom(&geoms[s], dtype);
     if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
     if (geoms[s].kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "batched solves take 2D slices");
+    if (opts[s].precond) return fail(GKB_EUNSUPPORTED, "batched solves run without the learned filter");
     st = validate_opts(&opts[s]);
     if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
     if (!b[s] || !x[s]) return fail(GKB_EINVAL, "slice " + std::to_string(s) + ": data pointer is NULL");
@@ -1696,6 +1946,179 @@ gkb_status gkb_gkb_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const voi
 gkb_status gkb_batch_solve(gkb_ctx *c, int method, int n_slices, const gkb_geometry *geoms, int dtype,
                            const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info) {
   return batch_entry(c, method, n_slices, geoms, dtype, b, opts, x, info);
+}
+
+gkb_status gkb_net_create(gkb_ctx *c, gkb_net **net, int channels, int ksize, int layers, unsigned long long seed) {
+  if (!c || !net) return fail(GKB_EINVAL, "NULL argument");
+  *net = nullptr;
+  if (channels != kNetC || ksize != kNetK || layers != 4)
+    return fail(GKB_EUNSUPPORTED, "the built network has 32 channels, kernel 9 and 4 layers");
+  HIPC(hipSetDevice(c->device));
+  auto nt = std::make_unique<gkb_net>();
+  nt->device = c->device;
+  const size_t pb = sizeof(float) * kNetParams;
+  HIPC(nt->W.ensure(pb));
+  HIPC(nt->m.ensure(pb));
+  HIPC(nt->v.ensure(pb));
+  HIPC(nt->grad.ensure(pb));
+  const size_t n1 = (size_t)kNetC * kNetK, n2 = (size_t)kNetC * kNetC * kNetK;
+  HIPC(nt->prep.ensure(4 * sizeof(float) * n1 + 4 * 2 * n2 + 256 * 8));
+  char *p = nt->prep.as<char>();
+  auto take = [&](size_t bytes) {
+    char *q = p;
+    p += (bytes + 255) & ~size_t(255);
+    return q;
+  };
+  nt->nw.w1 = reinterpret_cast<float *>(take(sizeof(float) * n1));
+  nt->nw.w1t = reinterpret_cast<float *>(take(sizeof(float) * n1));
+  nt->nw.w4 = reinterpret_cast<float *>(take(sizeof(float) * n1));
+  nt->nw.w4t = reinterpret_cast<float *>(take(sizeof(float) * n1));
+  nt->nw.w2b = reinterpret_cast<__bf16 *>(take(2 * n2));
+  nt->nw.w3b = reinterpret_cast<__bf16 *>(take(2 * n2));
+  nt->nw.w2t = reinterpret_cast<__bf16 *>(take(2 * n2));
+  nt->nw.w3t = reinterpret_cast<__bf16 *>(take(2 * n2));
+  std::vector<float> w;
+  he_init(seed, w);
+  HIPC(hipMemcpy(nt->W.p, w.data(), pb, hipMemcpyHostToDevice));
+  HIPC(hipMemset(nt->m.p, 0, pb));
+  HIPC(hipMemset(nt->v.p, 0, pb));
+  HIPC(hipMemset(nt->grad.p, 0, pb));
+  gkb_status st = net_prepare(nt.get(), c->stream);
+  if (st != GKB_OK) return st;
+  HIPC(hipStreamSynchronize(c->stream));
+  *net = nt.release();
+  return GKB_OK;
+}
+
+void gkb_net_destroy(gkb_net *net) {
+  if (!net) return;
+  (void)hipSetDevice(net->device);
+  (void)hipDeviceSynchronize();
+  delete net;
+}
+
+gkb_status gkb_net_set_weights(gkb_net *net, const float *w, long long count) {
+  if (!net || !w) return fail(GKB_EINVAL, "NULL argument");
+  if (count != kNetParams) return fail(GKB_EINVAL, "expected 19008 weights");
+  for (long long i = 0; i < count; ++i)
+    if (!std::isfinite(w[i])) return fail(GKB_ENONFINITE, "non-finite weight");
+  HIPC(hipSetDevice(net->device));
+  HIPC(hipMemcpy(net->W.p, w, sizeof(float) * kNetParams, hipMemcpyHostToDevice));
+  HIPC(hipMemset(net->m.p, 0, sizeof(float) * kNetParams));
+  HIPC(hipMemset(net->v.p, 0, sizeof(float) * kNetParams));
+  net->step = 0;
+  gkb_status st = net_prepare(net, nullptr);
+  if (st != GKB_OK) return st;
+  HIPC(hipDeviceSynchronize());
+  return GKB_OK;
+}
+
+gkb_status gkb_net_get_weights(const gkb_net *net, float *w, long long count) {
+  if (!net || !w) return fail(GKB_EINVAL, "NULL argument");
+  if (count != kNetParams) return fail(GKB_EINVAL, "expected 19008 weights");
+  HIPC(hipSetDevice(net->device));
+  HIPC(hipDeviceSynchronize());
+  HIPC(hipMemcpy(w, net->W.p, sizeof(float) * kNetParams, hipMemcpyDeviceToHost));
+  return GKB_OK;
+}
+
+gkb_status gkb_net_save(const gkb_net *net, const char *path) {
+  if (!net || !path) return fail(GKB_EINVAL, "NULL argument");
+  std::vector<float> w(kNetParams);
+  gkb_status st = gkb_net_get_weights(net, w.data(), kNetParams);
+  if (st != GKB_OK) return st;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(GKB_EINVAL, std::string("cannot open ") + path);
+  const char magic[8] = {'G', 'K', 'B', 'N', 'E', 'T', '1', '\0'};
+  const int32_t hdr[4] = {kNetC, kNetK, 4, kNetParams};
+  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int32_t), 4, f) == 4 &&
+            std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size();
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? GKB_OK : fail(GKB_EINVAL, std::string("write failed: ") + path);
+}
+
+gkb_status gkb_net_load(gkb_net *net, const char *path) {
+  if (!net || !path) return fail(GKB_EINVAL, "NULL argument");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(GKB_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t hdr[4];
+  std::vector<float> w(kNetParams);
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "GKBNET1", 8) == 0 &&
+            std::fread(hdr, sizeof(int32_t), 4, f) == 4 && hdr[0] == kNetC && hdr[1] == kNetK && hdr[2] == 4 &&
+            hdr[3] == kNetParams && std::fread(w.data(), sizeof(float), w.size(), f) == w.size();
+  std::fclose(f);
+  if (!ok) return fail(GKB_EINVAL, std::string("not a network file of this architecture: ") + path);
+  return gkb_net_set_weights(net, w.data(), kNetParams);
+}
+
+gkb_status gkb_net_apply(gkb_ctx *c, const gkb_net *net, const gkb_geometry *g, const void *y, void *out) {
+  gkb_status st = net_check(c, net);
+  if (st != GKB_OK) return st;
+  if (!y || !out) return fail(GKB_EINVAL, "data pointer is NULL");
+  st = validate_geom(g, GKB_F32);
+  if (st != GKB_OK) return st;
+  HIPC(hipSetDevice(c->device));
+  long long rows;
+  int L;
+  net_shape(g, rows, L);
+  st = net_scratch(c, rows, L);
+  if (st != GKB_OK) return st;
+  net_chain(c, net, NET_MASKS, Col<const float>{static_cast<const float *>(y), 0, 0, nullptr},
+            static_cast<float *>(out), rows, L, nullptr, c->stream);
+  HIPC(hipGetLastError());
+  return GKB_OK;
+}
+
+gkb_status gkb_net_frozen_apply(gkb_ctx *c, const gkb_net *net, const gkb_geometry *g, const void *b, const void *y,
+                                void *out, int transpose) {
+  gkb_status st = net_check(c, net);
+  if (st != GKB_OK) return st;
+  if (!b || !y || !out) return fail(GKB_EINVAL, "data pointer is NULL");
+  st = validate_geom(g, GKB_F32);
+  if (st != GKB_OK) return st;
+  HIPC(hipSetDevice(c->device));
+  long long rows;
+  int L;
+  net_shape(g, rows, L);
+  st = net_scratch(c, rows, L);
+  if (st != GKB_OK) return st;
+  net_chain(c, net, NET_MASKS, Col<const float>{static_cast<const float *>(b), 0, 0, nullptr}, c->nout.as<float>(),
+            rows, L, nullptr, c->stream);
+  net_chain(c, net, transpose ? NET_FT : NET_F, Col<const float>{static_cast<const float *>(y), 0, 0, nullptr},
+            static_cast<float *>(out), rows, L, nullptr, c->stream);
+  HIPC(hipGetLastError());
+  return GKB_OK;
+}
+
+gkb_status gkb_net_grad(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int batch, const void *b, const void *x,
+                        double *loss, float *grad) {
+  gkb_status st = net_check(c, net);
+  if (st != GKB_OK) return st;
+  if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
+  if (batch < 1) return fail(GKB_EINVAL, "batch must be >= 1");
+  st = validate_geom(g, GKB_F32);
+  if (st != GKB_OK) return st;
+  if (g->kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "training takes 2D geometries");
+  HIPC(hipSetDevice(c->device));
+  st = net_grad_impl(c, net, g, batch, static_cast<const float *>(b), static_cast<const float *>(x), loss);
+  if (st != GKB_OK) return st;
+  if (grad) HIPC(hipMemcpy(grad, net->grad.p, sizeof(float) * kNetParams, hipMemcpyDeviceToHost));
+  return GKB_OK;
+}
+
+gkb_status gkb_net_train_step(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
+                              const void *x, double lr, double *loss) {
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(GKB_EINVAL, "lr must be > 0");
+  gkb_status st = gkb_net_grad(c, net, g, batch, b, x, loss, nullptr);
+  if (st != GKB_OK) return st;
+  net->step += 1;
+  launch_net_adam(net->W.as<float>(), net->m.as<float>(), net->v.as<float>(), net->grad.as<float>(), kNetParams, lr,
+                  0.9, 0.999, 1e-8, net->step, c->stream);
+  st = net_prepare(net, c->stream);
+  if (st != GKB_OK) return st;
+  HIPC(hipGetLastError());
+  return GKB_OK;
 }
 
 gkb_status gkb_trace_enable(gkb_ctx *c, int on) {

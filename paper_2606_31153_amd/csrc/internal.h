@@ -324,6 +324,38 @@ template <typename T>
 void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
 
+// ---- learned sinogram filter (netk.hip) ----
+// Derived weight layouts (see k_net_prep): FP32 for the 1 <-> 32 channel
+// layers, bfloat16 [out][tap][in] for the 32 -> 32 layers; *t: the
+// transposed filter (flipped taps, channels swapped).
+struct NetW {
+  float *w1, *w1t, *w4, *w4t;
+  __bf16 *w2b, *w3b, *w2t, *w3t;
+};
+constexpr int kNetC = 32, kNetK = 9;
+constexpr int kNetParams = 2 * kNetC * kNetK + 2 * kNetC * kNetC * kNetK;  // 19008
+int net_segments(int L, int tile);
+// mode: 0 none, 1 compute (ReLU + mask bits), 2 apply frozen mask bits
+void launch_net_c1(Col<const float> s, float *out, unsigned *mask, const float *w, int L, long long rows, int mode,
+                   const int *stop, hipStream_t st);
+void launch_net_c4(const float *a, float *out, const float *w, int L, long long rows, const int *stop,
+                   hipStream_t st);
+void launch_net_c32(const float *a, float *out, unsigned *mask, const __bf16 *wb, int L, long long rows, int nsplit,
+                    int mode, const int *stop, hipStream_t st);
+int net_wgrad_blocks();
+void launch_net_wgrad32(const float *g, const float *a, float *partials, int L, long long rows, hipStream_t st);
+void launch_net_wgrad_edge(const float *G, const float *S, float *partials, int L, long long rows, int sgn,
+                           hipStream_t st);
+void launch_net_reduce(const float *partials, int nparts, int count, float *out, double scale, hipStream_t st);
+void launch_net_adam(float *w, float *m, float *v, const float *g, int n, double lr, double b1, double b2,
+                     double eps, int step, hipStream_t st);
+void launch_net_prep(const float *W, const NetW &nw, hipStream_t st);
+// training loss of one sample: r = xhat - x; sums[0] = ||r||^2, sums[1] = ||x||^2;
+// then r *= 2 / (||x||^2 * batch)
+void launch_net_resid(const float *xhat, const float *x, float *r, long long n, double *partials, unsigned *counter,
+                      double *sums, hipStream_t st);
+void launch_net_scale(float *r, long long n, const double *sums, int batch, hipStream_t st);
+
 // norm targets for launch_norm_to
 enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1 };
 
