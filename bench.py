@@ -271,6 +271,77 @@ def cone_main(args):
     print(json.dumps(out))
 
 
+def learned_main(args):
+    """Learned filter: train on 256^2 / 360-view parallel-beam samples (1-5 %
+    noise), evaluate on 16 held-out 512^2 / 720-view slices against plain
+    BA-GKB at the same discrepancy stop."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    from paper_2606_31153_amd import learned, synth
+
+    def log(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
+    ctx = gk.Context(0)
+    tg, eg = synth.par2d(256, 360), synth.par2d(512, 720)
+    t0 = time.perf_counter()
+    log("training set (%d samples)" % args.train_samples)
+    bd, xd, _ = learned.make_set(ctx, tg, range(4_000_000, 4_000_000 + args.train_samples), 0.01, 0.05, 4_000_000)
+    if args.textures > 0:
+        log("texture samples (%d)" % args.textures)
+        bt, xt = learned.make_textures(ctx, tg, args.textures, 4_200_000, 0.01, 0.05)
+        bd, xd = torch.cat([bd, bt]), torch.cat([xd, xt])
+        del bt, xt
+    t_data = time.perf_counter() - t0
+    net = gk.Net(ctx, seed=4_000_000)
+    net.set_weights(learned.init_weights(4_000_000, noise=args.init_noise,
+                                         first=learned.ramlak() if args.init == "ramlak" else None))
+    learned.rescale_output(ctx, net, tg, bd, xd)
+    t0 = time.perf_counter()
+    objective = gk.GKB_NET_FROZEN if args.objective == "frozen" else gk.GKB_NET_FBP
+    losses = learned.train(ctx, net, tg, bd, xd, args.epochs, args.batch, args.lr, seed=4_000_000, log=log,
+                           objective=objective)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = args.epochs * (args.train_samples // args.batch)
+    del bd, xd
+    log("evaluation set")
+    eb, ex, en = learned.make_set(ctx, eg, range(4_100_000, 4_100_016), 0.01, 0.05, 4_100_000)
+    ev = learned.evaluate(ctx, net, eg, eb, ex, en)
+    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
+        net.save(os.path.join(ROOT, "gpurun_out", "learned_filter.bin"))
+    # control: the same kernels with the network set to the analytic Ram-Lak
+    # filter (a linear filter, exactly, whatever the masks)
+    log("Ram-Lak control")
+    ctl = gk.Net(ctx, seed=0)
+    ctl.set_weights(learned.linear_pair_weights(learned.ramlak()))
+    evc = learned.evaluate(ctx, ctl, eg, eb, ex, en)
+    ctl.close()
+    out = {"metric": "learned vs plain BA-GKB: s/slice to discrepancy at 512^2, 720 views",
+           "value": ev["speedup_s_per_slice"], "unit": "x (plain s/slice / learned s/slice)",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f32 vectors, bf16-MFMA filter (3-term split)",
+           "data": "synthetic: seeded ellipse phantoms, 1-5% Gaussian noise",
+           "config": {"workload": "train 256^2/360 views/363 bins, %d samples, %d epochs, batch %d, lr %g; "
+                                  "evaluate 16 slices 512^2/720 views/725 bins, DP tau=1, k_max 150; "
+                                  "%d random-texture samples; init %s + %g He noise; objective %s"
+                                  % (args.train_samples, args.epochs, args.batch, args.lr, args.textures, args.init,
+                                     args.init_noise, args.objective)},
+           "training": {"seconds_data": t_data, "seconds_train": t_train, "steps": steps,
+                        "ms_per_step": 1e3 * t_train / max(steps, 1), "loss_per_epoch": losses},
+           "plain": ev["plain"], "learned": ev["learned"],
+           "ramlak_control": {"filter": evc["learned"], "speedup_s_per_slice": evc["speedup_s_per_slice"],
+                              "plain": evc["plain"]},
+           "learned_min_residual_over_e": [r["learned_free"]["min_res_over_e"] for r in ev["slices"]],
+           "target_over_e_mean": ev["target_over_e_mean"],
+           "per_slice": [{k: ({kk: v[kk] for kk in ("k", "seconds", "rre", "res_over_e")}
+                              if isinstance(v, dict) and "k" in v else v) for k, v in r.items()}
+                         for r in ev["slices"]]}
+    net.close()
+    ctx.close()
+    print(json.dumps(out))
+
+
 def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int):
     import oracle
     op = oracle.Operator(geom)
@@ -293,6 +364,15 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cone", action="store_true", help="measure the 512^3 cone-beam workload instead")
     ap.add_argument("--cone-iters", type=int, default=60)
+    ap.add_argument("--learned", action="store_true", help="train and evaluate the learned filter instead")
+    ap.add_argument("--train-samples", type=int, default=20000)
+    ap.add_argument("--textures", type=int, default=0, help="extra random-texture training samples")
+    ap.add_argument("--init", choices=("identity", "ramlak"), default="identity")
+    ap.add_argument("--objective", choices=("fbp", "frozen"), default="frozen")
+    ap.add_argument("--init-noise", type=float, default=0.1)
+    ap.add_argument("--epochs", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -300,6 +380,9 @@ def main():
 
     if args.cone:
         cone_main(args)
+        return
+    if args.learned:
+        learned_main(args)
         return
 
     import torch

@@ -112,8 +112,10 @@ typedef struct {
 } gkb_solve_info;
 
 /* Creates a context on `device` that launches on `hip_stream` (a hipStream_t;
- * NULL = a stream the context creates).  The context owns geometry tables,
- * Krylov bases and scratch; it frees them in gkb_destroy. */
+ * NULL = the default stream), so that its work is ordered with the caller's
+ * other work on that stream.  The context owns geometry tables, Krylov bases
+ * and scratch; it frees them in gkb_destroy.  gkb_set_stream switches the
+ * stream (NULL = the default stream). */
 gkb_status gkb_create(gkb_ctx **ctx, int device, void *hip_stream);
 void gkb_destroy(gkb_ctx *ctx);
 gkb_status gkb_set_stream(gkb_ctx *ctx, void *hip_stream);
@@ -175,9 +177,9 @@ gkb_status gkb_batch_solve(gkb_ctx *ctx, int method, int n_slices, const gkb_geo
  * uses them rounded to bfloat16.  The 32 -> 32 layers run on the matrix cores
  * (bfloat16 operands, FP32 accumulation); inside GKB each FP32 activation
  * enters them as three bfloat16 terms, so F is applied at FP32 accuracy.
- * Training: loss = mean over the batch of ||B N(b_i) - x_i||^2 / ||x_i||^2
- * (bfloat16 inputs of layers 2, 3 and bfloat16 gradients through them),
- * Adam (beta 0.9 / 0.999, eps 1e-8) with bias correction.
+ * Training (bfloat16 inputs of layers 2, 3 and bfloat16 gradients through
+ * them): one of the objectives below, Adam (beta 0.9 / 0.999, eps 1e-8) with
+ * bias correction.
  * A network belongs to the device of the context it was created with. */
 gkb_status gkb_net_create(gkb_ctx *ctx, gkb_net **net, int channels, int ksize, int layers,
                           unsigned long long seed);   /* channels 32, ksize 9, layers 4; He initialisation */
@@ -191,13 +193,19 @@ gkb_status gkb_net_apply(gkb_ctx *ctx, const gkb_net *net, const gkb_geometry *g
 /* out = F y (transpose = 0) or F^T y (transpose = 1), F frozen at b (DEVICE, FP32, m elements each). */
 gkb_status gkb_net_frozen_apply(gkb_ctx *ctx, const gkb_net *net, const gkb_geometry *g, const void *b,
                                 const void *y, void *out, int transpose);
+/* Training objectives, per sample (b_i, x_i), averaged over the batch:
+ *  GKB_NET_FBP:    ||B N(b_i) - x_i||^2 / ||x_i||^2 (learned filtered back projection);
+ *  GKB_NET_FROZEN: ||B F_{b_i} (A x_i) - x_i||^2 / ||x_i||^2, the filter frozen at the measured b_i
+ *                  (masks held fixed) applied to the noise-free data, i.e. the operator M = B F A
+ *                  that BA-GKB iterates with. */
+typedef enum { GKB_NET_FBP = 0, GKB_NET_FROZEN = 1 } gkb_net_objective;
 /* Mean training loss over a batch and its gradient: b DEVICE [batch][m], x DEVICE [batch][n] (FP32, 2D
  * geometry); *loss and the HOST gradient grad[19008] (may be NULL).  Blocks until done. */
 gkb_status gkb_net_grad(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
-                        const void *x, double *loss, float *grad);
+                        const void *x, int objective, double *loss, float *grad);
 /* gkb_net_grad followed by one Adam step with learning rate lr. */
 gkb_status gkb_net_train_step(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
-                              const void *x, double lr, double *loss);
+                              const void *x, int objective, double lr, double *loss);
 
 /* Kernel timing.  While enabled, every launch of the named kernels is
  * bracketed by HIP events on the context's stream; gkb_trace_get returns the

@@ -28,8 +28,10 @@ Precision points mirrored from the GPU path:
   * training: the inputs of layers 2 and 3 (forward) and the gradients
     entering the transposed layers 3 and 2 and the weight gradients of
     layers 2 and 3 are rounded to bfloat16; layers 1 and 4 stay exact.
-Training loss per sample: L = ||B N(b) - x||^2 / ||x||^2 (learned
-filtered back projection), averaged over the batch; Adam with bias
+Training losses per sample, averaged over the batch: the learned filtered
+back projection ||B N(b) - x||^2 / ||x||^2, or the operator objective
+||B F_b (A x) - x||^2 / ||x||^2 of the filter frozen at the measured b and
+applied to the noise-free data A x (what M = B F A needs); Adam with bias
 correction (Kingma and Ba 2015).
 
 Arrays: a sinogram batch is [rows, L] (rows = views (x detector rows),
@@ -141,11 +143,30 @@ def apply_Ft(Ws, masks, z):
     return g[:, 0, :]
 
 
-def net_grad(Ws, y, gout, train: bool = True):
-    """Gradient of <N(y), gout> in the weights (list of arrays), with the
-    training rounding points when train is set."""
+def forward_frozen(Ws, y, masks, train: bool = False):
+    """F y with given masks, in the training precision when train is set.
+    Returns (out, z list, masks)."""
     Wb = [bf16(W) for W in Ws]
-    out, zs, masks = forward(Ws, y, train=train)
+    a = np.asarray(y, dtype=np.float64)[:, None, :]
+    zs = []
+    for l in range(4):
+        inp = bf16(a) if (train and l in (1, 2)) else a
+        z = conv(inp, Wb[l])
+        zs.append(z)
+        if l < 3:
+            a = np.where(masks[l], z, 0.0)
+    return zs[3][:, 0, :], zs, masks
+
+
+def net_grad(Ws, y, gout, train: bool = True, masks=None):
+    """Gradient of <N(y), gout> in the weights (list of arrays), with the
+    training rounding points when train is set; with masks given, of
+    <F y, gout> for the filter frozen at those masks (masks held fixed)."""
+    Wb = [bf16(W) for W in Ws]
+    if masks is None:
+        out, zs, masks = forward(Ws, y, train=train)
+    else:
+        out, zs, masks = forward_frozen(Ws, y, masks, train=train)
     acts = [np.asarray(y, dtype=np.float64)[:, None, :]]
     for l in range(3):
         acts.append(np.where(masks[l], zs[l], 0.0))
@@ -177,6 +198,28 @@ def loss_and_grad(Ws, op_B, op_Bt, bs, xs, train: bool = True):
         total += float(res @ res) / xx
         gout = np.asarray(op_Bt(res)).reshape(out.shape) * (2.0 / xx / nb)
         _, dW = net_grad(Ws, b, gout, train=train)
+        grads = dW if grads is None else [g0 + g1 for g0, g1 in zip(grads, dW)]
+    return total / nb, grads
+
+
+def frozen_loss_and_grad(Ws, op_A, op_B, op_Bt, bs, xs, train: bool = True):
+    """Operator objective of the filter GKB applies: with the masks of the
+    measured b_i frozen, mean over the batch of
+    ||B F_{b_i} (A x_i) - x_i||^2 / ||x_i||^2 and its gradient in the
+    weights (masks held fixed).  bs: [batch, rows, L]; xs: [batch, n]."""
+    nb = len(bs)
+    total = 0.0
+    grads = None
+    for b, x in zip(bs, xs):
+        x = np.asarray(x, dtype=np.float64).reshape(-1)
+        masks = masks_of(Ws, b)
+        y = np.asarray(op_A(x)).reshape(np.shape(b))
+        out = forward_frozen(Ws, y, masks, train=train)[0]
+        res = np.asarray(op_B(out.reshape(-1))).reshape(-1) - x
+        xx = float(x @ x)
+        total += float(res @ res) / xx
+        gout = np.asarray(op_Bt(res)).reshape(out.shape) * (2.0 / xx / nb)
+        _, dW = net_grad(Ws, y, gout, train=train, masks=masks)
         grads = dW if grads is None else [g0 + g1 for g0, g1 in zip(grads, dW)]
     return total / nb, grads
 

@@ -37,6 +37,7 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
             "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step")
 NET_PARAMS = 19008
+GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
 
 class GkbError(RuntimeError):
@@ -101,8 +102,9 @@ def lib() -> ctypes.CDLL:
         L.gkb_net_load.argtypes = [vp, ctypes.c_char_p]
         L.gkb_net_apply.argtypes = [vp, vp, G, vp, vp]
         L.gkb_net_frozen_apply.argtypes = [vp, vp, G, vp, vp, vp, cp]
-        L.gkb_net_grad.argtypes = [vp, vp, G, cp, vp, vp, ctypes.POINTER(ctypes.c_double), FP]
-        L.gkb_net_train_step.argtypes = [vp, vp, G, cp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.gkb_net_grad.argtypes = [vp, vp, G, cp, vp, vp, cp, ctypes.POINTER(ctypes.c_double), FP]
+        L.gkb_net_train_step.argtypes = [vp, vp, G, cp, vp, vp, cp, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_double)]
         L.gkb_trace_enable.argtypes = [vp, cp]
         L.gkb_trace_reset.argtypes = [vp]
         L.gkb_trace_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(cp), ctypes.POINTER(ctypes.c_double)]
@@ -378,23 +380,23 @@ def gkb_net_frozen_apply(ctx: Context, net: Net, geom, b, y, out, transpose: boo
     return out
 
 
-def gkb_net_grad(ctx: Context, net: Net, geom, bs, xs):
+def gkb_net_grad(ctx: Context, net: Net, geom, bs, xs, objective: int = GKB_NET_FBP):
     """(mean loss, gradient [19008]) for a batch: bs [batch, m], xs [batch, n] FP32 device tensors."""
     g, keep = make_geometry(geom)
     batch = bs.shape[0]
     loss = ctypes.c_double()
     grad = np.zeros(NET_PARAMS, dtype=np.float32)
     _check(lib().gkb_net_grad(ctx.handle, net.handle, ctypes.byref(g), batch, _dev_ptr(bs, batch * geom.m),
-                              _dev_ptr(xs, batch * geom.n), ctypes.byref(loss),
+                              _dev_ptr(xs, batch * geom.n), objective, ctypes.byref(loss),
                               grad.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
     return loss.value, grad
 
 
-def gkb_net_train_step(ctx: Context, net: Net, geom, bs, xs, lr: float) -> float:
+def gkb_net_train_step(ctx: Context, net: Net, geom, bs, xs, lr: float, objective: int = GKB_NET_FBP) -> float:
     """One Adam step on a batch; returns the batch loss before the step."""
     g, keep = make_geometry(geom)
     batch = bs.shape[0]
     loss = ctypes.c_double()
     _check(lib().gkb_net_train_step(ctx.handle, net.handle, ctypes.byref(g), batch, _dev_ptr(bs, batch * geom.m),
-                                    _dev_ptr(xs, batch * geom.n), lr, ctypes.byref(loss)))
+                                    _dev_ptr(xs, batch * geom.n), objective, lr, ctypes.byref(loss)))
     return loss.value

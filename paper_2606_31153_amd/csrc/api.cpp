@@ -567,7 +567,7 @@ struct gkb_ctx {
   size_t bpin_slot = 0;
   hipEvent_t bpin_ev[2] = {nullptr, nullptr};
   // learned filter: activations, masks, filter output, training buffers
-  DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ncnt;
+  DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ncnt, ny;
   // tracing
   bool trace = false;
   std::map<std::string, TraceStat> stats;
@@ -953,7 +953,7 @@ void he_init(unsigned long long seed, std::vector<float> &w) {
 // gradient of the mean training loss over a batch of S sinograms b [S][m]
 // and targets x [S][n] (2D geometry); optional Adam step
 gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S, const float *b, const float *x,
-                         double *loss_out) {
+                         int objective, double *loss_out) {
   DevTables *d = nullptr;
   gkb_status stt = get_tables(c, g, GKB_F32, &d);
   if (stt != GKB_OK) return stt;
@@ -988,11 +988,33 @@ gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S,
   unsigned *m0 = mk, *m1 = mk + M, *m2 = mk + 2 * M;
   float *part = c->npart.as<float>(), *grad = net->grad.as<float>();
   const NetW &w = net->nw;
-  // forward with the training rounding (bfloat16 operands in layers 2, 3)
-  launch_net_c1(Col<const float>{b, 0, 0, nullptr}, a1, m0, w.w1, L, rows, 1, nullptr, st);
-  launch_net_c32(a1, a2, m1, w.w2b, L, rows, 1, 1, nullptr, st);
-  launch_net_c32(a2, a3, m2, w.w3b, L, rows, 1, 1, nullptr, st);
-  launch_net_c4(a3, out, w.w4, L, rows, nullptr, st);
+  // input of the trained map: b (learned filtered back projection), or the
+  // noise-free data A x through the filter frozen at b (operator objective)
+  const float *in = b;
+  if (objective == 0) {
+    // forward with the training rounding (bfloat16 operands in layers 2, 3)
+    launch_net_c1(Col<const float>{b, 0, 0, nullptr}, a1, m0, w.w1, L, rows, 1, nullptr, st);
+    launch_net_c32(a1, a2, m1, w.w2b, L, rows, 1, 1, nullptr, st);
+    launch_net_c32(a2, a3, m2, w.w3b, L, rows, 1, 1, nullptr, st);
+    launch_net_c4(a3, out, w.w4, L, rows, nullptr, st);
+  } else {
+    HIPC(c->ny.ensure(sizeof(float) * (size_t)M));
+    float *y = c->ny.as<float>();
+    // masks of b in the precision the solve uses
+    launch_net_c1(Col<const float>{b, 0, 0, nullptr}, a1, m0, w.w1, L, rows, 1, nullptr, st);
+    launch_net_c32(a1, a2, m1, w.w2b, L, rows, 3, 1, nullptr, st);
+    launch_net_c32(a2, a3, m2, w.w3b, L, rows, 3, 1, nullptr, st);
+    for (int si = 0; si < S; ++si) {
+      launch_pad_image<float>(gd, col<const float>(x + si * n), c->xpad.as<float>(), d->has_coldom, nullptr, st);
+      launch_fwd<float>(gd, rt_of<float>(*d), c->xpad.as<float>(), col<float>(y + si * mS), plain_epi<float>(),
+                        nullptr, st);
+    }
+    launch_net_c1(Col<const float>{y, 0, 0, nullptr}, a1, m0, w.w1, L, rows, 2, nullptr, st);
+    launch_net_c32(a1, a2, m1, w.w2b, L, rows, 1, 2, nullptr, st);
+    launch_net_c32(a2, a3, m2, w.w3b, L, rows, 1, 2, nullptr, st);
+    launch_net_c4(a3, out, w.w4, L, rows, nullptr, st);
+    in = y;
+  }
   // per sample: xhat = B N(b_s); r = xhat - x_s; gout_s = B^T r * 2 / (||x_s||^2 S)
   const Epi<float> pe = plain_epi<float>();
   for (int si = 0; si < S; ++si) {
@@ -1016,7 +1038,7 @@ gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S,
   launch_net_wgrad32(gb, a1, part, L, rows, st);
   launch_net_reduce(part, np, kNetC * kNetC * kNetK, grad + kOffW2, 1.0, st);
   launch_net_c32(gb, ga, m0, w.w2t, L, rows, 1, 2, nullptr, st);
-  launch_net_wgrad_edge(ga, b, part, L, rows, 1, st);
+  launch_net_wgrad_edge(ga, in, part, L, rows, 1, st);
   launch_net_reduce(part, np, kNetC * kNetK, grad, 1.0, st);
   HIPC(hipGetLastError());
   std::vector<double> sums(2 * (size_t)S);
@@ -1870,16 +1892,7 @@ gkb_status gkb_create(gkb_ctx **ctx, int device, void *hip_stream) {
   HIPC(hipSetDevice(device));
   auto *c = new gkb_ctx();
   c->device = device;
-  if (hip_stream) {
-    c->stream = static_cast<hipStream_t>(hip_stream);
-  } else {
-    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-      delete c;
-      return fail(GKB_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
-    }
-    c->own_stream = true;
-  }
+  c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the default stream
   *ctx = c;
   return GKB_OK;
 }
@@ -1906,12 +1919,7 @@ gkb_status gkb_set_stream(gkb_ctx *c, void *hip_stream) {
     (void)hipStreamDestroy(c->stream);
     c->own_stream = false;
   }
-  if (hip_stream) {
-    c->stream = static_cast<hipStream_t>(hip_stream);
-  } else {
-    HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-  }
+  c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the default stream
   return GKB_OK;
 }
 
@@ -2092,25 +2100,26 @@ gkb_status gkb_net_frozen_apply(gkb_ctx *c, const gkb_net *net, const gkb_geomet
 }
 
 gkb_status gkb_net_grad(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int batch, const void *b, const void *x,
-                        double *loss, float *grad) {
+                        int objective, double *loss, float *grad) {
   gkb_status st = net_check(c, net);
   if (st != GKB_OK) return st;
   if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
   if (batch < 1) return fail(GKB_EINVAL, "batch must be >= 1");
+  if (objective != GKB_NET_FBP && objective != GKB_NET_FROZEN) return fail(GKB_EINVAL, "unknown objective");
   st = validate_geom(g, GKB_F32);
   if (st != GKB_OK) return st;
   if (g->kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "training takes 2D geometries");
   HIPC(hipSetDevice(c->device));
-  st = net_grad_impl(c, net, g, batch, static_cast<const float *>(b), static_cast<const float *>(x), loss);
+  st = net_grad_impl(c, net, g, batch, static_cast<const float *>(b), static_cast<const float *>(x), objective, loss);
   if (st != GKB_OK) return st;
   if (grad) HIPC(hipMemcpy(grad, net->grad.p, sizeof(float) * kNetParams, hipMemcpyDeviceToHost));
   return GKB_OK;
 }
 
 gkb_status gkb_net_train_step(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
-                              const void *x, double lr, double *loss) {
+                              const void *x, int objective, double lr, double *loss) {
   if (!(lr > 0.0) || !std::isfinite(lr)) return fail(GKB_EINVAL, "lr must be > 0");
-  gkb_status st = gkb_net_grad(c, net, g, batch, b, x, loss, nullptr);
+  gkb_status st = gkb_net_grad(c, net, g, batch, b, x, objective, loss, nullptr);
   if (st != GKB_OK) return st;
   net->step += 1;
   launch_net_adam(net->W.as<float>(), net->m.as<float>(), net->v.as<float>(), net->grad.as<float>(), kNetParams, lr,

@@ -167,8 +167,31 @@ def test_invalid_geometry_rejected(ctx):
     with pytest.raises(gk.GkbError) as e:
         gk.gkb_forward(ctx, g, x, y)
     assert e.value.status == gk.GKB_EINVAL
-    c = synth.cone3d(8, 4, 9, 9)
+    p = synth.par2d(16, 10)
+    p.det_pitch_u = 0.0  # zero detector pitch
     with pytest.raises(gk.GkbError) as e:
-        gk.gkb_forward(ctx, c, torch.zeros(c.n, dtype=torch.float32, device=dev),
-                       torch.zeros(c.m, dtype=torch.float32, device=dev))
-    assert e.value.status == gk.GKB_EUNSUPPORTED
+        gk.gkb_forward(ctx, p, torch.zeros(p.n, dtype=torch.float32, device=dev),
+                       torch.zeros(p.m, dtype=torch.float32, device=dev))
+    assert e.value.status == gk.GKB_EINVAL
+
+
+def test_library_work_is_ordered_with_torch_on_the_default_stream(ctx):
+    # the context launches on PyTorch's current stream: a tensor op issued
+    # right after a projector call (no synchronisation in between) must see
+    # the finished result, and a projector call must see a tensor op issued
+    # just before it
+    geom = synth.workload_fan512()
+    dev = torch.device("cuda:0")
+    x = torch.tensor(synth.ellipse_phantom(512, 3).reshape(-1), dtype=torch.float32, device=dev)
+    y = torch.empty(geom.m, dtype=torch.float32, device=dev)
+    note("stream ordering")
+    for _ in range(3):
+        y.fill_(float("nan"))
+        gk.gkb_forward(ctx, geom, x, y)
+        s1 = y.double().sum()
+        x2 = x * 2.0
+        y2 = torch.empty_like(y)
+        gk.gkb_forward(ctx, geom, x2, y2)
+        s2 = y2.double().sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(s1) and abs(float(s2) - 2.0 * float(s1)) <= 1e-6 * abs(float(s2))

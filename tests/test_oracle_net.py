@@ -134,3 +134,42 @@ def test_training_rounding_points_change_little():
     _, g_train = net.net_grad(Ws, y, gout, train=True)
     for ge, gt in zip(g_exact, g_train):
         assert np.linalg.norm(gt - ge) <= 0.05 * np.linalg.norm(ge)
+
+
+def test_frozen_objective_gradient_against_finite_differences():
+    # masks held fixed: the objective is a smooth function of the weights
+    C, K, L, rows = 2, 3, 16, 3
+    r = np.random.default_rng(12)
+    Ws = [net.bf16(r.standard_normal(s)) for s in net.shapes(C, K)]
+    n = 10
+    Am = r.standard_normal((rows * L, n))
+    Bm = r.standard_normal((n, rows * L))
+    xs = r.standard_normal((2, n))
+    bs = [(Am @ x).reshape(rows, L) + 0.1 * r.standard_normal((rows, L)) for x in xs]
+    val, grads = net.frozen_loss_and_grad(Ws, lambda v: Am @ v, lambda v: Bm @ v, lambda v: Bm.T @ v, bs, xs,
+                                          train=False)
+    masks = [net.masks_of(Ws, b) for b in bs]
+
+    def loss(Wlist):
+        # exact arithmetic (the oracle's weights enter through bfloat16, which
+        # would swallow the finite-difference step)
+        tot = 0.0
+        for b, x, mk in zip(bs, xs, masks):
+            a = (Am @ x).reshape(rows, L)[:, None, :]
+            for l in range(4):
+                z = net.conv(a, Wlist[l])
+                a = np.where(mk[l], z, 0.0) if l < 3 else z
+            res = Bm @ a[:, 0, :].reshape(-1) - x
+            tot += float(res @ res) / float(x @ x)
+        return tot / len(xs)
+
+    assert val == pytest.approx(loss(Ws), rel=1e-12)
+    h = 1e-6
+    for l in range(4):
+        for idx in np.ndindex(*Ws[l].shape):
+            Wp = [W.copy() for W in Ws]
+            Wm = [W.copy() for W in Ws]
+            Wp[l][idx] += h
+            Wm[l][idx] -= h
+            fd = (loss(Wp) - loss(Wm)) / (2 * h)
+            assert abs(fd - grads[l][idx]) <= 1e-6 * max(1.0, abs(fd)), (l, idx)
