@@ -81,6 +81,7 @@ struct HostTables {
   // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
   std::vector<double> gcs;
   bool has_coldom = false;
+  double min_along = 1e300;  // fan: smallest source distance of a B^T crossing
   // cone beam, per (view, column)
   std::vector<double> cbase1, cslope1, clmid, clslope, cdxy2, ch1, cpk;
   std::vector<int> cmeta, cmeta_bt;
@@ -236,6 +237,10 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
       t.meta[r] = lo | (hi << 15) | ((rowdom ? 1 : 0) << 30);
       line_range(cmid, slope, mid, nl, -h, len - 1 + h, lo, hi);
       t.meta_bt[r] = lo | (hi << 15) | ((rowdom ? 1 : 0) << 30);
+      if (fan && lo <= hi) {
+        const double a0 = t.t0[r] + (lo - mid) * t.dt[r], a1 = t.t0[r] + (hi - mid) * t.dt[r];
+        t.min_along = std::min(t.min_along, std::min(std::fabs(a0), std::fabs(a1)));
+      }
       if (!rowdom) t.has_coldom = true;
       t.base[r] = cmid;
       t.slope[r] = slope;
@@ -267,6 +272,12 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     // |tan| of the largest pixel fan angle (pixel centres within rc of the centre)
     const double tmax = rc / std::sqrt(g->src_dist * g->src_dist - rc * rc);
     gd.fast_atan = tmax <= 0.5 ? 1 : 0;
+    // B^T in float: a candidate's source distance differs from the crossing's
+    // by e = dpar d / along with |e| <= (h + 1) / min_along, and the angle to
+    // it has |tan| <= tan(dg): 1/(1 + e) to second order and atan(z) = z are
+    // exact to e^3 + dg^2 / 3 relative
+    const double emax = (hmax_bt + 1.0) / t.min_along;
+    gd.bt_fast = (emax * emax * emax + du * du / 3.0 <= 1e-6) ? 1 : 0;
   }
   gd.nc_bt = (int)std::floor(2.0 * hmax_bt) + 1;
   gd.nc_at = (int)std::floor(2.0 * hmax_at) + 1;

@@ -129,6 +129,7 @@ struct GeomDev {
   double tan_dg;       // fan B^T: tan(bin pitch)
   double dd_spread;    // fan A^T: bound on the |d_dom| change across the candidate rays
   int fast_atan;       // fan, float: every pixel's fan angle has |tan| <= 0.5
+  int bt_fast;         // fan B^T, float: series forms of the candidate weights are exact to FP32
   // padded image: row-major region (ny lines of ldR = nx + 2 pad), then the
   // column-major region at offT (nx lines of ldT = ny + 2 pad)
   int pad, ldR, ldT;

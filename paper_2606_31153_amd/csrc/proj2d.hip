@@ -270,6 +270,7 @@ __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, cons
       const T inv_dg = T(g.inv_du);
       // candidate half-width on a line at distance `along` from the source
       const T hfac = T(g.tan_dg) / (fabs(dperp) - T(g.tan_dg));
+      const bool series = sizeof(T) == 4 && g.bt_fast;
       for (int j = lo; j <= hi; ++j) {
         const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
         const T along0 = fma(jf, dt, t0);
@@ -277,15 +278,31 @@ __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, cons
         const T i0f = ceil(c - h);
         const int cnt = (int)(floor(c + h) - i0f) + 1;
         const T *p = pad + (off + (unsigned)(int)i0f);
+        if (series) {
+          // |angle| / dg = kz |d| (1 - e + e^2), e = kd d: one reciprocal per line
+          const T inv0 = fast_rcp(along0);
+          const T kd = dpar * inv0, kz = fabs(dperp) * inv0 * inv_dg;
 #pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          if (q < cnt) {
-            const T d = (i0f + T(q)) - c;
-            // tangent of the angle between the ray and the pixel, seen from the source
-            const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
-            const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
-            const T v = p[q];
-            acc += (wt > T(0)) ? wt * v : T(0);
+          for (int q = 0; q < NC; ++q) {
+            if (q < cnt) {
+              const T d = (i0f + T(q)) - c;
+              const T e = kd * d;
+              const T wt = T(1) - kz * fabs(d) * fma(e, e - T(1), T(1));
+              const T v = p[q];
+              acc += (wt > T(0)) ? wt * v : T(0);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < NC; ++q) {
+            if (q < cnt) {
+              const T d = (i0f + T(q)) - c;
+              // tangent of the angle between the ray and the pixel, seen from the source
+              const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
+              const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
+              const T v = p[q];
+              acc += (wt > T(0)) ? wt * v : T(0);
+            }
           }
         }
         jf += T(1);

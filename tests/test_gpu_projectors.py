@@ -40,6 +40,7 @@ GEOMS = {
     "fan_tiny": synth.fan2d(8, 7, 17, src_dist=20.0),
     "fan_ragged": synth.fan2d(45, 33, 70),
     "fan128": synth.fan2d(128, 180, 256),
+    "fan_far": synth.fan2d(96, 60, 200, src_dist=1000.0),  # float B^T takes the series form
 }
 
 OPS = {
