@@ -273,10 +273,11 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     const double tmax = rc / std::sqrt(g->src_dist * g->src_dist - rc * rc);
     gd.fast_atan = tmax <= 0.5 ? 1 : 0;
     // B^T in float: a candidate's source distance differs from the crossing's
-    // by e = dpar d / along with |e| <= (h + 1) / min_along, and the angle to
-    // it has |tan| <= tan(dg): 1/(1 + e) to second order and atan(z) = z are
-    // exact to e^3 + dg^2 / 3 relative
-    const double emax = (hmax_bt + 1.0) / t.min_along;
+    // by e = dpar d / along, where the candidate window (floor(2h) + 1 pixels
+    // from ceil(c - h)) gives |d| <= 2h + 1, and the angle to a candidate with
+    // a nonzero weight has |tan| <= tan(dg): 1/(1 + e) to second order and
+    // atan(z) = z are exact to e^3 + dg^2 / 3 relative
+    const double emax = (2.0 * hmax_bt + 1.0) / t.min_along;
     gd.bt_fast = (emax * emax * emax + du * du / 3.0 <= 1e-6) ? 1 : 0;
   }
   gd.nc_bt = (int)std::floor(2.0 * hmax_bt) + 1;

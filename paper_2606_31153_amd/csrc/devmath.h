@@ -25,4 +25,9 @@ __device__ inline typename Pair<T>::v2 load_pair(const T *p) {
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double fast_rcp(double x) { return 1.0 / x; }
 
+// reciprocal square root: hardware approximation (1 ulp) in float, correctly
+// rounded square root and division in double
+__device__ inline float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double fast_rsq(double x) { return 1.0 / sqrt(x); }
+
 }  // namespace gkb

@@ -224,91 +224,120 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // ---------------------------------------------------------------------------
 // ray-driven: B^T (transpose of the pixel-driven back projector)
 // Ray (v,k) collects every pixel whose detector coordinate is within one bin
-// of k, with the hat weight 1 - |u(p) - k|.  On each line the candidates lie
-// within h of the ray's crossing: NC consecutive pixels from ceil(c - h).
+// of k, with the hat weight 1 - |u(p) - k|.  On each line those pixels lie
+// within the ray's half-width h of its crossing c, so the window of
+// floor(2h) + 1 consecutive pixels from ceil(c - h) holds all of them (h
+// bounds the half-width on every line of the ray).  The window length is
+// taken as the wavefront's maximum, which makes the candidate loop uniform;
+// candidates outside the support get a negative weight, clamped to zero.
 // ---------------------------------------------------------------------------
+// Sum over lines lo..hi of one ray with n candidates per line: n = CNT, or
+// the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.
+template <typename T, bool FAN, int CNT, int MAXC>
+__device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, long long r,
+                                 T hr, int nrt) {
+  constexpr int NQ = CNT ? CNT : MAXC;
+  const int n = CNT ? CNT : nrt;
+  const int meta = rt.meta_bt[r];
+  const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
+  const bool rowdom = (meta >> 30) & 1;
+  const T base = rt.base[r], slope = rt.slope[r];
+  const int ld = rowdom ? g.ldR : g.ldT;
+  const T mid = rowdom ? T(0.5) * T(g.ny - 1) : T(0.5) * T(g.nx - 1);
+  unsigned off = (rowdom ? 0u : (unsigned)g.offT) + (unsigned)(lo * ld + g.pad);
+  T jf = T(lo) - mid;
+  // crossings farther than h from the image only meet zero weights; the
+  // clamp keeps every candidate inside the padded line
+  const T clo = -hr - T(0.5), chi = T((rowdom ? g.nx : g.ny) - 1) + hr + T(0.5);
+  T acc = T(0);
+  if (!FAN) {
+    const T inv_h = T(1) / hr;
+    for (int j = lo; j <= hi; ++j) {
+      const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
+      const T i0f = ceil(c - hr);
+      const T d0 = i0f - c;  // offset of the first candidate from the crossing
+      const T *p = pad + (off + (unsigned)(int)i0f);
+      T v[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q < n) v[q] = p[q];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (q < n) {
+          const T wt = fma(-fabs(d0 + T(q)), inv_h, T(1));
+          acc = fma(fmax(wt, T(0)), v[q], acc);
+        }
+      }
+      jf += T(1);
+      off += (unsigned)ld;
+    }
+  } else {
+    const T t0 = rt.t0[r], dt = rt.dt[r], dperp = rt.dperp[r], dpar = rt.dpar[r];
+    const T inv_dg = T(g.inv_du);
+    const bool series = sizeof(T) == 4 && g.bt_fast;
+    for (int j = lo; j <= hi; ++j) {
+      const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
+      const T along0 = fma(jf, dt, t0);
+      const T i0f = ceil(c - hr);
+      const T d0 = i0f - c;
+      const T *p = pad + (off + (unsigned)(int)i0f);
+      T v[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q < n) v[q] = p[q];
+      if (series) {
+        // |angle| / dg = kz |d| (1 - e + e^2) with e = kd d, written as
+        // |d| (kz + d (a1 + d a2)): one reciprocal per line
+        const T inv0 = fast_rcp(along0);
+        const T kd = dpar * inv0, kz = fabs(dperp) * inv0 * inv_dg;
+        const T a1 = -kz * kd, a2 = -a1 * kd;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (q < n) {
+            const T d = d0 + T(q);
+            const T gq = fma(fma(a2, d, a1), d, kz);
+            const T wt = fma(-fabs(d), gq, T(1));
+            acc = fma(fmax(wt, T(0)), v[q], acc);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (q < n) {
+            const T d = d0 + T(q);
+            // tangent of the angle between the ray and the pixel, seen from the source
+            const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
+            const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
+            acc = fma(fmax(wt, T(0)), v[q], acc);
+          }
+        }
+      }
+      jf += T(1);
+      off += (unsigned)ld;
+    }
+  }
+  return acc;
+}
+
 template <typename T, bool FAN, int NC>
 __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
                                      const Epi<T> &e, Blk b) {
   const long long r = (long long)b.id * kBlock + threadIdx.x;
   const bool valid = r < g.m;
+  const T hr = valid ? rt.h[r] : T(0);
+  // window length: the wavefront's largest floor(2h) + 1.  It is at most the
+  // slice's own candidate count (plus one where h rounds up in float), which
+  // its padding is sized for; a longer window than a ray needs only adds zero
+  // weights.  NC is the largest count of the launch (of all its slices).
+  const int cnt = min(wave_max(valid ? (int)floor(T(2) * hr) + 1 : 0), NC);
   T acc = T(0);
   if (valid) {
-    const int meta = rt.meta_bt[r];
-    const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
-    const bool rowdom = (meta >> 30) & 1;
-    const T base = rt.base[r], slope = rt.slope[r];
-    const int ld = rowdom ? g.ldR : g.ldT;
-    const T mid = rowdom ? T(0.5) * T(g.ny - 1) : T(0.5) * T(g.nx - 1);
-    unsigned off = (rowdom ? 0u : (unsigned)g.offT) + (unsigned)(lo * ld + g.pad);
-    T jf = T(lo) - mid;
-    // crossings farther than h from the image only meet zero weights; the
-    // clamp keeps every candidate inside the padded line
-    const T hr = rt.h[r];
-    const T clo = -hr - T(0.5), chi = T((rowdom ? g.nx : g.ny) - 1) + hr + T(0.5);
-    if (!FAN) {
-      const T h = hr;
-      const T inv_h = T(1) / h;
-      for (int j = lo; j <= hi; ++j) {
-        const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
-        const T i0f = ceil(c - h);
-        const int cnt = (int)(floor(c + h) - i0f) + 1;
-        const T *p = pad + (off + (unsigned)(int)i0f);
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          if (q < cnt) {
-            const T wt = T(1) - fabs(c - (i0f + T(q))) * inv_h;
-            const T v = p[q];
-            acc += (wt > T(0)) ? wt * v : T(0);
-          }
-        }
-        jf += T(1);
-        off += (unsigned)ld;
-      }
-    } else {
-      const T t0 = rt.t0[r], dt = rt.dt[r], dperp = rt.dperp[r], dpar = rt.dpar[r];
-      const T inv_dg = T(g.inv_du);
-      // candidate half-width on a line at distance `along` from the source
-      const T hfac = T(g.tan_dg) / (fabs(dperp) - T(g.tan_dg));
-      const bool series = sizeof(T) == 4 && g.bt_fast;
-      for (int j = lo; j <= hi; ++j) {
-        const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
-        const T along0 = fma(jf, dt, t0);
-        const T h = fmin(hfac * along0 * T(1.0001) + T(1e-4), hr);
-        const T i0f = ceil(c - h);
-        const int cnt = (int)(floor(c + h) - i0f) + 1;
-        const T *p = pad + (off + (unsigned)(int)i0f);
-        if (series) {
-          // |angle| / dg = kz |d| (1 - e + e^2), e = kd d: one reciprocal per line
-          const T inv0 = fast_rcp(along0);
-          const T kd = dpar * inv0, kz = fabs(dperp) * inv0 * inv_dg;
-#pragma unroll
-          for (int q = 0; q < NC; ++q) {
-            if (q < cnt) {
-              const T d = (i0f + T(q)) - c;
-              const T e = kd * d;
-              const T wt = T(1) - kz * fabs(d) * fma(e, e - T(1), T(1));
-              const T v = p[q];
-              acc += (wt > T(0)) ? wt * v : T(0);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < NC; ++q) {
-            if (q < cnt) {
-              const T d = (i0f + T(q)) - c;
-              // tangent of the angle between the ray and the pixel, seen from the source
-              const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
-              const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
-              const T v = p[q];
-              acc += (wt > T(0)) ? wt * v : T(0);
-            }
-          }
-        }
-        jf += T(1);
-        off += (unsigned)ld;
-      }
-    }
+    if (cnt == NC)
+      acc = back_adj_ray<T, FAN, NC, NC>(g, rt, pad, r, hr, cnt);
+    else if (cnt == NC - 1)
+      acc = back_adj_ray<T, FAN, NC - 1, NC>(g, rt, pad, r, hr, cnt);
+    else
+      acc = back_adj_ray<T, FAN, 0, NC>(g, rt, pad, r, hr, cnt);
   }
   epilogue(e, r, valid, acc, yo, b);
 }
@@ -422,6 +451,28 @@ __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const
 // |d_dom| bounded by that of the pixel's own ray plus the fan spread of the
 // candidates.
 // ---------------------------------------------------------------------------
+// Parallel-beam A^T: hat-weighted sum of n consecutive bins from `row`, the
+// first at distance d0 (in bins) from the pixel's detector coordinate;
+// n = CNT, or the uniform runtime count nrt (at most MAXC) when CNT == 0.
+template <typename T, int CNT, int MAXC>
+__device__ inline T at_par_bins(const T *__restrict__ row, T d0, T slope, int nrt) {
+  constexpr int NQ = CNT ? CNT : MAXC;
+  const int n = CNT ? CNT : nrt;
+  T yv[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (q < n) yv[q] = row[q];
+  T part = T(0);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < n) {
+      const T wt = fma(-fabs(d0 - T(q)), slope, T(1));
+      part = fma(fmax(wt, T(0)), yv[q], part);
+    }
+  }
+  return part;
+}
+
 template <typename T, bool FAN, int NC>
 __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                     const Epi<T> &e, Blk b) {
@@ -443,18 +494,15 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
         T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
         u = fmin(fmax(u, ulo), uhi);
         const T w = vt.p2[v], slope = vt.p3[v], h = vt.p4[v];
+        // the bins within h of u lie in the floor(2h) + 1 bins from ceil(u - h);
+        // h is the view's, so the count is uniform
+        const int cv = min((int)floor(T(2) * h) + 1, NC);
         const T k0f = ceil(u - h);
-        const int cnt = (int)(floor(u + h) - k0f) + 1;
+        const T d0 = u - k0f;  // offset of u from the first candidate
         const T *row = ypad + (roff + (unsigned)(int)k0f);
-        T part = T(0);
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-          if (q < cnt) {
-            const T wt = T(1) - fabs(u - (k0f + T(q))) * slope;
-            const T yv = row[q];
-            part += (wt > T(0)) ? wt * yv : T(0);
-          }
-        }
+        const T part = cv == NC       ? at_par_bins<T, NC, NC>(row, d0, slope, cv)
+                       : cv == NC - 1 ? at_par_bins<T, NC - 1, NC>(row, d0, slope, cv)
+                                      : at_par_bins<T, 0, NC>(row, d0, slope, cv);
         acc = fma(w, part, acc);
         roff += ldY;
       }
@@ -472,7 +520,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
         // |d_dom| of the pixel's ray: (p - S) = a c + b c_perp, c = -(cos b, sin b)
         const T wx = fma(bb, sb, -a * cb), wy = -fma(a, sb, bb * cb);
         const T r2 = fma(a, a, bb * bb);
-        const T rinv = rsqrt(r2);
+        const T rinv = fast_rsq(r2);
         const T ddm = fmin(fmax(fabs(wx), fabs(wy)) * rinv + spread, T(1));
         // candidates: |g_k - g_p| < asin(|d_dom| / |p - S|) <= z (1 + z^2)
         const T z = ddm * rinv;
@@ -485,16 +533,29 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
           // delta_k = |p - S| sin(g_p - g_k) with g_p - g_k = (up - k) dg; the sine to
           // third order, whose relative truncation error x^4/120 is below 1e-9 for
           // the candidate angles of a fan with D >= 2 N
-          const T Dp = r2 * rinv;
+          // with d = up - k: delta = d (c1 + c3 d^2), c1 = |p - S| dg, c3 = -c1 dg^2 / 6
           const T dg = T(g.du);
+          const T c1 = r2 * rinv * dg, c3 = c1 * dg * dg * T(-1.0 / 6.0);
+          const T d0 = up - k0f;
+          // the padded row holds the slice's own window of g.nc_at bins;
+          // NC may be larger in a launch over several slices
+          typename Pair<T>::v2 pw[NC];
+          if (g.nc_at == NC) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) pw[q] = yw[q];
+          } else {
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+              if (q < cnt) pw[q] = yw[q];
+          }
 #pragma unroll
           for (int q = 0; q < NC; ++q) {
             if (q < cnt) {
-              const auto pq = yw[q];
-              const T sa = (up - (k0f + T(q))) * dg;
-              const T delta = Dp * sa * fma(sa * sa, T(-1.0 / 6.0), T(1));
-              const T wt = T(1) - fabs(delta) * pq.y;
-              acc += (wt > T(0)) ? wt * pq.x : T(0);
+              const auto pq = pw[q];
+              const T d = d0 - T(q);
+              const T delta = d * fma(c3, d * d, c1);
+              const T wt = fma(-fabs(delta), pq.y, T(1));
+              acc = fma(fmax(wt, T(0)), pq.x, acc);
             }
           }
         } else {
@@ -505,8 +566,8 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
               const auto gq = cs[q];
               const auto pq = yw[q];
               const T delta = fma(bb, gq.x, -a * gq.y);
-              const T wt = T(1) - fabs(delta) * pq.y;
-              acc += (wt > T(0)) ? wt * pq.x : T(0);
+              const T wt = fma(-fabs(delta), pq.y, T(1));
+              acc = fma(fmax(wt, T(0)), pq.x, acc);
             }
           }
         }

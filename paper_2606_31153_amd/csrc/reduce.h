@@ -12,6 +12,14 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Maximum of an int over the 64 lanes of a wavefront, as a wave-uniform
+// (scalar) value.  Every lane of the wavefront must take part.
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 // Sum over a workgroup of NT threads; the result is valid in thread 0.
 // `lds` holds NT/64 doubles.  Fixed order: lane butterfly, then waves 0..NT/64-1.
 template <int NT>
