@@ -80,6 +80,8 @@ struct HostTables {
   std::vector<double> p0, p1, p2, p3, p4;
   // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
   std::vector<double> gcs;
+  // fan A^T: per (32x8 pixel tile, view) bound of the candidate half-width, [tile][view]
+  std::vector<double> htile;
   bool has_coldom = false;
   double min_along = 1e300;  // fan: smallest source distance of a B^T crossing
   // cone beam, per (view, column)
@@ -132,6 +134,53 @@ void line_range(double c_mid, double slope, double mid, int nlines, double cmin,
   if (lo > hi) {
     lo = 1;
     hi = 0;
+  }
+}
+
+// Fan-beam A^T: a pixel p gets a nonzero weight from the bins k with
+// |g_p - g_k| < asin(|d_dom,k| / |p - S|) (Joseph's weight as a function of the
+// fan angle); the kernel bounds |d_dom,k| by the pixel's own ray's plus the fan
+// spread of the candidates, and asin(z) by z (1 + z^2).  Per 32x8 tile of
+// pixel centres and per view, the largest such half-width (in bins) over the
+// tile follows from the tile's nearest point to the source (largest 1/|p - S|)
+// and the largest max(|cos|, |sin|) of the directions from the source to the
+// tile (1 if they cross an axis direction, else at a corner).  The kernel
+// takes a window of floor(2H) + 1 bins from ceil(u_p - H) for every pixel of
+// the tile.
+void fan_tile_halfwidths(const gkb_geometry *g, const std::vector<double> &ang, HostTables &t) {
+  const GeomDev &gd = t.gd;
+  const int nx = g->nx, ny = g->ny, nv = g->n_views;
+  const int tx_n = (nx + 31) / 32, ty_n = (ny + 7) / 8;
+  const double midx = 0.5 * (nx - 1), midy = 0.5 * (ny - 1);
+  const double quarter = 0.5 * M_PI;
+  t.htile.assign((size_t)tx_n * ty_n * nv, 0.0);
+  for (int v = 0; v < nv; ++v) {
+    const double Sx = g->src_dist * std::cos(ang[v]), Sy = g->src_dist * std::sin(ang[v]);
+    for (int ty = 0; ty < ty_n; ++ty)
+      for (int tx = 0; tx < tx_n; ++tx) {
+        // rectangle of the tile's pixel centres
+        const double x0 = tx * 32 - midx, x1 = std::min(tx * 32 + 31, nx - 1) - midx;
+        const double y0 = ty * 8 - midy, y1 = std::min(ty * 8 + 7, ny - 1) - midy;
+        const double dx = std::max({x0 - Sx, 0.0, Sx - x1}), dy = std::max({y0 - Sy, 0.0, Sy - y1});
+        const double rinv = 1.0 / std::sqrt(dx * dx + dy * dy);
+        // directions from the source to the corners, as angles about the
+        // direction to the tile's centre (the tile subtends less than pi)
+        const double cx = 0.5 * (x0 + x1) - Sx, cy = 0.5 * (y0 + y1) - Sy;
+        const double phic = std::atan2(cy, cx);
+        double lo = 0.0, hi = 0.0, ddm = 0.0;
+        const double xs[2] = {x0, x1}, ys[2] = {y0, y1};
+        for (double px : xs)
+          for (double py : ys) {
+            const double ex = px - Sx, ey = py - Sy;
+            const double dphi = std::atan2(cx * ey - cy * ex, cx * ex + cy * ey);
+            lo = std::min(lo, dphi);
+            hi = std::max(hi, dphi);
+            ddm = std::max(ddm, std::max(std::fabs(ex), std::fabs(ey)) / std::sqrt(ex * ex + ey * ey));
+          }
+        if (std::ceil((phic + lo) / quarter) <= (phic + hi) / quarter) ddm = 1.0;
+        const double z = std::min(ddm + gd.dd_spread, 1.0) * rinv;
+        t.htile[((size_t)ty * tx_n + tx) * nv + v] = gd.hmax_fan * z * (1.0 + z * z) + 1e-3;
+      }
   }
 }
 
@@ -302,6 +351,7 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     t.wpad.assign(gd.ypad_elems, 0.0);
     for (int v = 0; v < nv; ++v)
       for (int k = 0; k < nu; ++k) t.wpad[(long long)v * gd.ldY + gd.padY + k] = t.w[(long long)v * nu + k];
+    fan_tile_halfwidths(g, ang, t);
   }
 }
 
@@ -481,8 +531,9 @@ hipError_t upload_tables(const HostTables &h, DevTables &d) {
   const bool fan = h.gd.kind == GKB_FAN2D;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t rayT = al(sizeof(T) * m), rayI = al(sizeof(int) * m), viewT = al(sizeof(T) * nv),
-               binT = al(sizeof(T) * 2 * h.gd.ldY), wpT = al(sizeof(T) * (fan ? h.gd.ypad_elems : 1));
-  const size_t total = 8 * rayT + 2 * rayI + 5 * viewT + binT + wpT;
+               binT = al(sizeof(T) * 2 * h.gd.ldY), wpT = al(sizeof(T) * (fan ? h.gd.ypad_elems : 1)),
+               tileT = al(sizeof(T) * std::max<size_t>(h.htile.size(), 1));
+  const size_t total = 8 * rayT + 2 * rayI + 5 * viewT + binT + wpT + tileT;
   hipError_t e = d.buf.ensure(total);
   if (e != hipSuccess) return e;
   char *p = d.buf.as<char>();
@@ -521,6 +572,7 @@ hipError_t upload_tables(const HostTables &h, DevTables &d) {
   vt.p4 = put(h.p4, viewT);
   vt.gcos = put(h.gcs, binT);
   rt.wpad = put(h.wpad, wpT);
+  vt.htile = put(h.htile, tileT);
   if constexpr (sizeof(T) == 4) {
     d.rt32 = rt;
     d.vt32 = vt;
@@ -566,7 +618,7 @@ struct gkb_ctx {
   bool own_stream = false;
   std::map<std::string, std::unique_ptr<DevTables>> tables;
   // scratch for standalone projector calls and reductions
-  DevBuf xpad, ypad, partials, counters;
+  DevBuf xpad, ypad, partials;
   // solve workspace
   DevBuf Q, Y, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
   int *host_flag = nullptr;      // host-mapped
@@ -579,7 +631,7 @@ struct gkb_ctx {
   size_t bpin_slot = 0;
   hipEvent_t bpin_ev[2] = {nullptr, nullptr};
   // learned filter: activations, masks, filter output, training buffers
-  DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ncnt, ny;
+  DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ny;
   // tracing
   bool trace = false;
   std::map<std::string, TraceStat> stats;
@@ -772,10 +824,6 @@ gkb_status ensure_scratch(gkb_ctx *c, const GeomDev &g, size_t elem, long long n
   HIPC(c->xpad.ensure(elem * (size_t)g.pad_elems));
   HIPC(c->ypad.ensure(2 * elem * (size_t)g.ypad_elems));
   HIPC(c->partials.ensure(sizeof(double) * std::max<long long>(nblocks_times_cols, 1024)));
-  if (!c->counters.p) {
-    HIPC(c->counters.ensure(256 * sizeof(unsigned)));
-    HIPC(hipMemset(c->counters.p, 0, 256 * sizeof(unsigned)));
-  }
   return GKB_OK;
 }
 
@@ -987,10 +1035,6 @@ gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S,
   HIPC(c->npart.ensure(sizeof(float) * (size_t)net_wgrad_blocks() * kNetC * kNetC * kNetK));
   HIPC(c->nsums.ensure(sizeof(double) * 2 * (size_t)S));
   HIPC(c->nred.ensure(sizeof(double) * 2 * 1024));
-  if (!c->ncnt.p) {
-    HIPC(c->ncnt.ensure(64));
-    HIPC(hipMemset(c->ncnt.p, 0, 64));
-  }
   const long long nb = std::max<long long>(std::max(ray_blocks(gd), pixel_blocks(gd)), 1);
   stt = ensure_scratch(c, gd, sizeof(float), nb);
   if (stt != GKB_OK) return stt;
@@ -1033,7 +1077,7 @@ gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S,
     launch_pad_sino<float>(gd, col<const float>(out + si * mS), c->ypad.as<float>(), nullptr, st);
     launch_back<float>(gd, vt_of<float>(*d), c->ypad.as<float>(), c->nxh.as<float>(), pe, nullptr, st);
     launch_net_resid(c->nxh.as<float>(), x + si * n, c->nr.as<float>(), n, c->nred.as<double>(),
-                     c->ncnt.as<unsigned>(), c->nsums.as<double>() + 2 * si, st);
+                     c->nsums.as<double>() + 2 * si, st);
     launch_net_scale(c->nr.as<float>(), n, c->nsums.as<double>() + 2 * si, S, st);
     launch_pad_image<float>(gd, col<const float>(c->nr.as<float>()), c->xpad.as<float>(), d->has_coldom, nullptr,
                             st);
@@ -1089,7 +1133,6 @@ struct Solver {
   T *xpad = nullptr, *ypad = nullptr;
   Ctl ctl{};
   double *partials = nullptr;
-  unsigned *counters = nullptr;
   hipStream_t st;
   const int *stop = nullptr;
   const int *kp = nullptr;
@@ -1150,7 +1193,6 @@ struct Solver {
     ctl.ldG = (int)ldG;
     ctl.host_stop = c->host_flag_dev;
     partials = c->partials.as<double>();
-    counters = c->counters.as<unsigned>();
     stop = ctl.ip + CI_STOP;
     kp = ctl.ip + CI_K;
     return GKB_OK;
@@ -1161,7 +1203,6 @@ struct Solver {
     e.ctl = ctl;
     e.use_ctl = 1;
     e.partials = partials;
-    e.counter = counters;
     return e;
   }
 
@@ -1284,7 +1325,7 @@ struct Solver {
     reorth_and_normalize_impl(reorth);
     {
       TraceScope ts(c, "gram");
-      launch_gram<T>(ctl, Y, ldy, m, 0, partials, counters, st);
+      launch_gram<T>(ctl, Y, ldy, m, 0, partials, st);
     }
     {
       TraceScope ts(c, "small_solve");
@@ -1295,13 +1336,13 @@ struct Solver {
   void reorth_and_normalize_impl(bool reorth) {
     TraceScope ts(c, "reorth");
     if (reorth) {
-      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, counters, st);
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, counters, st);
-      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, counters, st);
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, counters, st);
+      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, st);
+      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
     } else {
       // no reorthogonalisation: only the norm alpha_{k+1} = ||w|| (no columns)
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, counters, st, 0);
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st, 0);
     }
     launch_normalize<T>(ctl, w, Q, ldq, dimq, st);
   }
@@ -1342,7 +1383,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
 
   // start-up (k = 0): Y_0 = b, G_00 = ||b||^2; s~_1 = rhs, t_1; q_1, alpha_1
   launch_copy<T>(b, S.Y, g.m, st);
-  launch_gram<T>(S.ctl, S.Y, S.ldy, g.m, 1, S.partials, S.counters, st);
+  launch_gram<T>(S.ctl, S.Y, S.ldy, g.m, 1, S.partials, st);
   if (mode == MODE_BA) {
     Epi<T> e = S.epi();
     e.norm_to_t = 1;
@@ -1354,10 +1395,10 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     }
   } else {
     launch_copy<T>(b, S.s, g.m, st);
-    launch_norm_to<T>(S.ctl, S.s, g.m, NORM_T1, S.partials, S.counters, st);
+    launch_norm_to<T>(S.ctl, S.s, g.m, NORM_T1, S.partials, st);
   }
   S.apply_Mt(true);
-  launch_norm_to<T>(S.ctl, S.w, S.dimq, NORM_ALPHA1, S.partials, S.counters, st);
+  launch_norm_to<T>(S.ctl, S.w, S.dimq, NORM_ALPHA1, S.partials, st);
   launch_normalize<T>(S.ctl, S.w, S.Q, S.ldq, S.dimq, st);
   HIPC(hipGetLastError());
   double h3[3];
@@ -1597,7 +1638,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
   // workspaces
   HIPC(c->bws.ensure(bytesT));
   HIPC(c->bwd.ensure(sizeof(double) * ndbl));
-  HIPC(c->bwi.ensure(sizeof(int) * (size_t)ns * (CI_COUNT + 16)));
+  HIPC(c->bwi.ensure(sizeof(int) * (size_t)ns * CI_COUNT));
   HIPC(c->bsd.ensure(sizeof(SliceDev<T>) * (size_t)ns));
   const size_t slot_ints = (size_t)ns + BF_COUNT * (size_t)(ns + 1);
   if (c->bmap.bytes < sizeof(int) * slot_ints) {
@@ -1619,9 +1660,6 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
   char *wsT = c->bws.as<char>();
   double *wsD = c->bwd.as<double>();
   int *wsI = c->bwi.as<int>();
-  unsigned *cnt0 = reinterpret_cast<unsigned *>(wsI + (size_t)ns * CI_COUNT);
-  // counters start at zero; each last-arriving workgroup resets its own
-  HIPC(hipMemsetAsync(cnt0, 0, sizeof(unsigned) * 16 * (size_t)ns, st));
 
   // slice descriptors and control headers
   std::vector<SliceDev<T>> hsd(ns);
@@ -1662,7 +1700,6 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     d.dimq = h.dimq;
     d.dims = h.dims;
     d.partials = wsD + h.opart;
-    d.counter = cnt0 + 16 * (size_t)s;
     d.has_coldom = h.d->has_coldom ? 1 : 0;
     d.reorth = o.reorth != 0;
     double *hd = hdp.data() + (size_t)s * CD_COUNT;

@@ -462,24 +462,28 @@ template <typename T>
 void launch_cone_fwd(const GeomDev &g, const ConeTab<T> &ct, const T *pad, Col<T> y, const Epi<T> &e,
                      const int *stop, hipStream_t s) {
   hipLaunchKernelGGL(k_cone_fwd<T>, dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, ct, pad, y, e, stop);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, ray_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T>
 void launch_cone_back_adj(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt, const T *pad, Col<T> y,
                           const Epi<T> &e, const int *stop, hipStream_t s) {
   hipLaunchKernelGGL(k_cone_back_adj<T>, dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, ct, vt, pad, y, e, stop);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, ray_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T>
 void launch_cone_back(const GeomDev &g, const ViewTab<T> &vt, const T *ypad, T *x, const Epi<T> &e,
                       const int *stop, hipStream_t s) {
   hipLaunchKernelGGL(k_cone_back<T>, dim3(cone_voxel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, cone_voxel_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T>
 void launch_cone_fwd_adj(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt, const T *wy, T *x,
                          const Epi<T> &e, const int *stop, hipStream_t s) {
   hipLaunchKernelGGL(k_cone_fwd_adj<T>, dim3(cone_voxel_blocks(g)), dim3(kBlock), 0, s, g, ct, vt, wy, x, e, stop);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, cone_voxel_blocks(g), NORM_T1, stop, s);
 }
 
 #define GKB_INST(T)                                                                                             \

@@ -27,20 +27,12 @@ __device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T ra
     outp[idx] = outT;
     if (e.out_raw.base) e.out_raw.get()[idx] = raw;
   }
+  // ||out||^2: one partial per workgroup; a finalising kernel launched after
+  // the projector sums them into t[k+1]
   if (e.norm_to_t) {
     const double v = valid ? (double)outT * (double)outT : 0.0;
     const double bs = block_sum<kBlock>(v, red);
-    const unsigned nb = b.n;
     if (threadIdx.x == 0) e.partials[b.id] = bs;
-    if (arrive_last(e.counter, nb)) {
-      double acc = 0.0;
-      for (unsigned b = threadIdx.x; b < nb; b += kBlock) acc += e.partials[b];
-      const double tot = block_sum<kBlock>(acc, red);
-      if (threadIdx.x == 0) {
-        e.ctl.t[k + 1] = sqrt(tot);
-        *e.counter = 0u;
-      }
-    }
   }
 }
 

@@ -85,8 +85,7 @@ struct Epi {
   int norm_to_t;       // 1: reduce ||out||^2 into t[k+1]
   Col<const T> prev;
   Col<T> out_raw;      // base == nullptr: not stored
-  double *partials;    // per-block partial sums
-  unsigned *counter;
+  double *partials;    // per-block partial sums of ||out||^2 (norm_to_t)
 };
 
 // Geometry tables kept in device memory (one set per geometry and dtype).
@@ -115,6 +114,7 @@ struct ViewTab {       // per view (pixel-driven kernels B, A^T)
   const T *p3;         // PAR: du/|d_dom| (A^T hat slope in bins)
   const T *p4;         // PAR: |d_dom|/du (A^T hat half-width in bins)
   const T *gcos;       // FAN: (cos(gamma_k), sin(gamma_k)) pairs, padded like a sinogram row [2 (n_det + 2 padY)]
+  const T *htile;      // FAN: A^T candidate half-width bound per (32x8 pixel tile, view), [tile][view]
 };
 
 struct GeomDev {
@@ -209,7 +209,6 @@ struct SliceDev {
   T *x;
   long long ldq, ldy, dimq, dims;
   double *partials;
-  unsigned *counter;
   int has_coldom;
   int reorth;
 };
@@ -307,19 +306,21 @@ int vec_blocks(long long dim);
 template <typename T>
 void launch_copy(const T *src, T *dst, long long n, hipStream_t s);
 template <typename T>
-void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *partials, unsigned *counter,
-                    hipStream_t s);
+void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *partials, hipStream_t s);
 template <typename T>
 void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
-                     unsigned *counter, hipStream_t s);
+                     hipStream_t s);
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
-                       unsigned *counter, hipStream_t s, int reorth = 1);
+                       hipStream_t s, int reorth = 1);
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s);
 template <typename T>
-void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials,
-                 unsigned *counter, hipStream_t s);
+void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials, hipStream_t s);
+// t[k+1] (NORM_T1) or alpha[k+1] (NORM_ALPHA1) = sqrt(sum of nb partials), after
+// the kernel that wrote them (a projector with norm_to_t, cgs_update, norm_to);
+// skipped when stop is set
+void launch_norm_finalize(Ctl ctl, const double *partials, int nb, int which, const int *stop, hipStream_t s);
 void launch_small_solve(Ctl ctl, hipStream_t s);
 template <typename T>
 void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, hipStream_t s);
@@ -353,8 +354,8 @@ void launch_net_adam(float *w, float *m, float *v, const float *g, int n, double
 void launch_net_prep(const float *W, const NetW &nw, hipStream_t st);
 // training loss of one sample: r = xhat - x; sums[0] = ||r||^2, sums[1] = ||x||^2;
 // then r *= 2 / (||x||^2 * batch)
-void launch_net_resid(const float *xhat, const float *x, float *r, long long n, double *partials, unsigned *counter,
-                      double *sums, hipStream_t st);
+void launch_net_resid(const float *xhat, const float *x, float *r, long long n, double *partials, double *sums,
+                      hipStream_t st);
 void launch_net_scale(float *r, long long n, const double *sums, int batch, hipStream_t st);
 
 // norm targets for launch_norm_to
@@ -377,6 +378,8 @@ template <typename T>
 void launch_b_copy(const BatchDev<T> &bd, const BatchLaunch &bl, int src_sel, int dst_sel, hipStream_t s);
 template <typename T>
 void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int fam, int which, hipStream_t s);
+template <typename T>
+void launch_b_norm_finalize(const BatchDev<T> &bd, const BatchLaunch &bl, int fam, int which, hipStream_t s);
 template <typename T>
 void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>

@@ -3,9 +3,10 @@
 // Precision split: vectors (Q, Y, s, w) are stored in T (float or double);
 // every inner product, norm and reorthogonalisation update is formed and
 // accumulated in double; alpha, t, the projected solve and the discrepancy
-// test are double.  All reductions are deterministic (fixed-order wave
-// butterflies, fixed-order sum over workgroups by the last workgroup to
-// arrive).
+// test are double.  All reductions are deterministic: fixed-order wave
+// butterflies, one partial per workgroup, and a fixed-order sum of the
+// partials by a one-workgroup finalising kernel launched after the producer
+// (no workgroup waits for or signals another).
 //
 // Reorthogonalisation (one-sided, on q only; Alg. "GKB" step 9 and its
 // AB/BA counterparts) is classical Gram-Schmidt applied twice:
@@ -154,13 +155,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *_
   reduce_cols_body(ctl, partials, nb, which, blockIdx.x, which == 0 ? k : k + 1);
 }
 
-// ---- w -= Q[:, 0..k-1] c (FP64 per element); last == 1: alpha[k+1] = ||w|| ----
+// ---- w -= Q[:, 0..k-1] c (FP64 per element); last == 1: partials of ||w||^2
+// (alpha[k+1] = ||w|| by the finalising kernel) ----
 template <typename T>
 __device__ inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q, long long ld, T *__restrict__ w,
-                                       long long dim, int last, double *partials, unsigned *counter, Blk b,
-                                       int ncols) {
+                                       long long dim, int last, double *partials, Blk b, int ncols) {
   __shared__ double lds[kBlock / 64];
-  const int k = ctl.ip[CI_K];
   const double *__restrict__ cc = ctl.c;
   const long long r = ((long long)b.id * kBlock + threadIdx.x) * RPT;
   double acc[RPT];
@@ -188,26 +188,37 @@ __device__ inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q, 
   if (last) {
     const double s = block_sum<kBlock>(nrm, lds);
     if (threadIdx.x == 0) partials[b.id] = s;
-    if (arrive_last(counter, b.n)) {
-      double a = 0.0;
-      for (unsigned i = threadIdx.x; i < b.n; i += kBlock) a += partials[i];
-      const double tot = block_sum<kBlock>(a, lds);
-      if (threadIdx.x == 0) {
-        ctl.alpha[k + 1] = sqrt(tot);
-        *counter = 0u;
-      }
-    }
   }
 }
 
-// reorth == 0: no columns, only alpha[k+1] = ||w|| (with last == 1)
+// reorth == 0: no columns, only the partials of ||w||^2 (with last == 1)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restrict__ Q, long long ld,
                                                        T *__restrict__ w, long long dim, int last,
-                                                       double *partials, unsigned *counter, int reorth) {
+                                                       double *partials, int reorth) {
   if (ctl.ip[CI_STOP]) return;
-  cgs_update_body(ctl, Q, ld, w, dim, last, partials, counter, Blk{blockIdx.x, gridDim.x},
-                  reorth ? ctl.ip[CI_K] : 0);
+  cgs_update_body(ctl, Q, ld, w, dim, last, partials, Blk{blockIdx.x, gridDim.x}, reorth ? ctl.ip[CI_K] : 0);
+}
+
+// ---- finalising kernel: t[k+1] (which == NORM_T1) or alpha[k+1]
+// (NORM_ALPHA1) = sqrt of the sum of nb partials ----
+__device__ inline void norm_finalize_body(const Ctl &ctl, const double *__restrict__ partials, unsigned nb,
+                                          int which) {
+  __shared__ double lds[kBlock / 64];
+  const double tot = partial_total<kBlock>(partials, nb, 1, lds);
+  if (threadIdx.x == 0) {
+    const int k = ctl.ip[CI_K];
+    if (which == NORM_T1)
+      ctl.t[k + 1] = sqrt(tot);
+    else
+      ctl.alpha[k + 1] = sqrt(tot);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_finalize(Ctl ctl, const double *__restrict__ partials, int nb,
+                                                          int which, const int *stop) {
+  if (stop && *stop) return;
+  norm_finalize_body(ctl, partials, (unsigned)nb, which);
 }
 
 // ---- Q[:, k] = w / alpha[k+1] ------------------------------------------------
@@ -384,10 +395,9 @@ __global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ a, T *__r
   copy_body(a, b, n, Blk{blockIdx.x, gridDim.x});
 }
 
-// ||v|| into t[k+1] (which == NORM_T1) or alpha[k+1] (NORM_ALPHA1)
+// partials of ||v||^2 (the finalising kernel writes ||v|| into t[k+1] or alpha[k+1])
 template <typename T>
-__device__ inline void norm_to_body(const Ctl &ctl, const T *__restrict__ v, long long dim, int which,
-                                    double *partials, unsigned *counter, Blk b) {
+__device__ inline void norm_to_body(const T *__restrict__ v, long long dim, double *partials, Blk b) {
   __shared__ double lds[kBlock / 64];
   const long long stride = (long long)b.n * kBlock;
   double acc = 0.0;
@@ -397,26 +407,13 @@ __device__ inline void norm_to_body(const Ctl &ctl, const T *__restrict__ v, lon
   }
   const double s = block_sum<kBlock>(acc, lds);
   if (threadIdx.x == 0) partials[b.id] = s;
-  if (arrive_last(counter, b.n)) {
-    double a = 0.0;
-    for (unsigned i = threadIdx.x; i < b.n; i += kBlock) a += partials[i];
-    const double tot = block_sum<kBlock>(a, lds);
-    if (threadIdx.x == 0) {
-      const int k = ctl.ip[CI_K];
-      if (which == NORM_T1)
-        ctl.t[k + 1] = sqrt(tot);
-      else
-        ctl.alpha[k + 1] = sqrt(tot);
-      *counter = 0u;
-    }
-  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_norm_to(Ctl ctl, const T *__restrict__ v, long long dim, int which,
-                                                    double *partials, unsigned *counter) {
+__global__ __launch_bounds__(kBlock) void k_norm_to(Ctl ctl, const T *__restrict__ v, long long dim,
+                                                    double *partials) {
   if (ctl.ip[CI_STOP]) return;
-  norm_to_body(ctl, v, dim, which, partials, counter, Blk{blockIdx.x, gridDim.x});
+  norm_to_body(v, dim, partials, Blk{blockIdx.x, gridDim.x});
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
@@ -437,7 +434,19 @@ __global__ __launch_bounds__(kBlock) void kb_norm_to(BatchDev<T> bd, int sel, in
   const SliceDev<T> &d = slice_of(bd, fam, blockIdx.x, b);
   if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
-  norm_to_body<T>(d.ctl, resolve(d, sel, k), fam == BF_VM ? d.g.m : d.dimq, which, d.partials, d.counter, b);
+  (void)which;
+  norm_to_body<T>(resolve(d, sel, k), fam == BF_VM ? d.g.m : d.dimq, d.partials, b);
+}
+
+// finalising kernel of a batched reduction: one workgroup per active slice
+// sums the slice's partials of family fam
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_norm_finalize(BatchDev<T> bd, int fam, int which) {
+  const int a = blockIdx.x;
+  const SliceDev<T> &d = bd.sd[bd.active[a]];
+  if (skip(bd, d)) return;
+  const int *pre = bd.pre + fam * (bd.na + 1);
+  norm_finalize_body(d.ctl, d.partials, (unsigned)(pre[a + 1] - pre[a]), which);
 }
 
 // gram == 0: Q^T w for reorthogonalisation (no columns when the slice does
@@ -472,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void kb_cgs_update(BatchDev<T> bd, int last
   const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
   if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
-  cgs_update_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, last, d.partials, d.counter, b, d.reorth ? k : 0);
+  cgs_update_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, last, d.partials, b, d.reorth ? k : 0);
 }
 
 template <typename T>
@@ -539,16 +548,18 @@ template <typename T>
 void launch_copy(const T *src, T *dst, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy<T>, dim3(vec_blocks(n)), dim3(kBlock), 0, s, src, dst, n);
 }
+void launch_norm_finalize(Ctl ctl, const double *partials, int nb, int which, const int *stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(kBlock), 0, s, ctl, partials, nb, which, stop);
+}
 template <typename T>
-void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *partials, unsigned *counter,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_norm_to<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, v, dim, which, partials,
-                     counter);
+void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *partials, hipStream_t s) {
+  const int nb = vec_blocks(dim);
+  hipLaunchKernelGGL(k_norm_to<T>, dim3(nb), dim3(kBlock), 0, s, ctl, v, dim, partials);
+  launch_norm_finalize(ctl, partials, nb, which, ctl.ip + CI_STOP, s);
 }
 template <typename T>
 void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
-                     unsigned *counter, hipStream_t s) {
-  (void)counter;
+                     hipStream_t s) {
   const int nb = vec_blocks(dim);
   const dim3 grid(nb, (ctl.K + CH) / CH);
   hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials, 0);
@@ -556,20 +567,18 @@ void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long di
 }
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
-                       unsigned *counter, hipStream_t s, int reorth) {
+                       hipStream_t s, int reorth) {
   const int nb = vec_blocks(dim);
-  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, counter,
-                     reorth);
+  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, reorth);
+  if (last) launch_norm_finalize(ctl, partials, nb, NORM_ALPHA1, ctl.ip + CI_STOP, s);
 }
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s) {
   hipLaunchKernelGGL(k_normalize<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim);
 }
 template <typename T>
-void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials, unsigned *counter,
-                 hipStream_t s) {
+void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials, hipStream_t s) {
   (void)init;
-  (void)counter;
   const int nb = vec_blocks(dim);
   const dim3 grid(nb, (ctl.K + 1 + CH) / CH);
   hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Y, ld, (const T *)nullptr, dim, partials, 1);
@@ -589,9 +598,14 @@ void launch_b_copy(const BatchDev<T> &bd, const BatchLaunch &bl, int src_sel, in
   if (bl.tot[BF_VM] > 0) hipLaunchKernelGGL(kb_copy<T>, dim3(bl.tot[BF_VM]), dim3(kBlock), 0, s, bd, src_sel, dst_sel);
 }
 template <typename T>
+void launch_b_norm_finalize(const BatchDev<T> &bd, const BatchLaunch &bl, int fam, int which, hipStream_t s) {
+  if (bl.na > 0) hipLaunchKernelGGL(kb_norm_finalize<T>, dim3(bl.na), dim3(kBlock), 0, s, bd, fam, which);
+}
+template <typename T>
 void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int fam, int which, hipStream_t s) {
-  if (bl.tot[fam] > 0)
-    hipLaunchKernelGGL(kb_norm_to<T>, dim3(bl.tot[fam]), dim3(kBlock), 0, s, bd, sel, fam, which);
+  if (bl.tot[fam] <= 0) return;
+  hipLaunchKernelGGL(kb_norm_to<T>, dim3(bl.tot[fam]), dim3(kBlock), 0, s, bd, sel, fam, which);
+  launch_b_norm_finalize(bd, bl, fam, which, s);
 }
 template <typename T>
 void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
@@ -601,7 +615,9 @@ void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t
 }
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s) {
-  if (bl.tot[BF_VQ] > 0) hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd, last);
+  if (bl.tot[BF_VQ] <= 0) return;
+  hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd, last);
+  if (last) launch_b_norm_finalize(bd, bl, BF_VQ, NORM_ALPHA1, s);
 }
 template <typename T>
 void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
@@ -632,16 +648,16 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
 
 #define GKB_INST(T)                                                                                         \
   template void launch_copy<T>(const T *, T *, long long, hipStream_t);                                    \
-  template void launch_norm_to<T>(Ctl, const T *, long long, int, double *, unsigned *, hipStream_t);      \
-  template void launch_cgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, unsigned *,  \
-                                   hipStream_t);                                                           \
-  template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, unsigned *, \
-                                     hipStream_t, int);                                                         \
+  template void launch_norm_to<T>(Ctl, const T *, long long, int, double *, hipStream_t);                  \
+  template void launch_cgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t); \
+  template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, hipStream_t, \
+                                     int);                                                                  \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t);               \
-  template void launch_gram<T>(Ctl, const T *, long long, long long, int, double *, unsigned *, hipStream_t); \
+  template void launch_gram<T>(Ctl, const T *, long long, long long, int, double *, hipStream_t);          \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
+  template void launch_b_norm_finalize<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t); \
   template void launch_b_cgs_dots<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                \
   template void launch_b_cgs_update<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);         \
   template void launch_b_normalize<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);               \

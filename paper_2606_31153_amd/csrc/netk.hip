@@ -391,10 +391,9 @@ __global__ __launch_bounds__(256) void k_net_prep(const float *__restrict__ W, N
   }
 }
 
-// r = xhat - x with the FP64 sums ||r||^2 and ||x||^2 (last workgroup finalises)
+// r = xhat - x with per-workgroup partials of the FP64 sums ||r||^2 and ||x||^2
 __global__ __launch_bounds__(256) void k_net_resid(const float *__restrict__ xhat, const float *__restrict__ x,
-                                                   float *__restrict__ r, long long n, double *partials,
-                                                   unsigned *counter, double *sums) {
+                                                   float *__restrict__ r, long long n, double *partials) {
   __shared__ double red[4];
   double rr = 0.0, xx = 0.0;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
@@ -409,19 +408,17 @@ __global__ __launch_bounds__(256) void k_net_resid(const float *__restrict__ xha
     partials[2 * blockIdx.x] = brr;
     partials[2 * blockIdx.x + 1] = bxx;
   }
-  if (arrive_last(counter, gridDim.x)) {
-    double a = 0.0, b = 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += 256) {
-      a += partials[2 * i];
-      b += partials[2 * i + 1];
-    }
-    const double ta = block_sum<256>(a, red);
-    const double tb = block_sum<256>(b, red);
-    if (threadIdx.x == 0) {
-      sums[0] = ta;
-      sums[1] = tb;
-      *counter = 0u;
-    }
+}
+
+// sums[0], sums[1] from the nb partial pairs of k_net_resid (fixed order)
+__global__ __launch_bounds__(256) void k_net_resid_finalize(const double *__restrict__ partials, int nb,
+                                                            double *sums) {
+  __shared__ double red[4];
+  const double ta = partial_total<256>(partials, (unsigned)nb, 2, red);
+  const double tb = partial_total<256>(partials + 1, (unsigned)nb, 2, red);
+  if (threadIdx.x == 0) {
+    sums[0] = ta;
+    sums[1] = tb;
   }
 }
 
@@ -435,10 +432,11 @@ __global__ __launch_bounds__(256) void k_net_scale(float *__restrict__ r, long l
 
 int net_segments(int L, int tile) { return (L + tile - 1) / tile; }
 
-void launch_net_resid(const float *xhat, const float *x, float *r, long long n, double *partials, unsigned *counter,
-                      double *sums, hipStream_t st) {
+void launch_net_resid(const float *xhat, const float *x, float *r, long long n, double *partials, double *sums,
+                      hipStream_t st) {
   const int nb = (int)std::min<long long>((n + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_net_resid, dim3(nb), dim3(256), 0, st, xhat, x, r, n, partials, counter, sums);
+  hipLaunchKernelGGL(k_net_resid, dim3(nb), dim3(256), 0, st, xhat, x, r, n, partials);
+  hipLaunchKernelGGL(k_net_resid_finalize, dim3(1), dim3(256), 0, st, (const double *)partials, nb, sums);
 }
 
 void launch_net_scale(float *r, long long n, const double *sums, int batch, hipStream_t st) {

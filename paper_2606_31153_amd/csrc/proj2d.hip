@@ -473,6 +473,31 @@ __device__ inline T at_par_bins(const T *__restrict__ row, T d0, T slope, int nr
   return part;
 }
 
+// Fan-beam A^T in float: sum over n bins of (w y)_k max(0, 1 - |delta_k| w_k)
+// with the pairs (w y, w) from yw, the first bin at distance d0 below the
+// pixel's coordinate and delta = d (c1 + c3 d^2) for d = u_p - k; n = CNT, or
+// the uniform runtime count nrt (at most MAXC) when CNT == 0.
+template <typename T, int CNT, int MAXC>
+__device__ inline T at_fan_bins(const typename Pair<T>::v2 *__restrict__ yw, T d0, T c1, T c3, int nrt) {
+  constexpr int NQ = CNT ? CNT : MAXC;
+  const int n = CNT ? CNT : nrt;
+  typename Pair<T>::v2 pw[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (q < n) pw[q] = yw[q];
+  T part = T(0);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < n) {
+      const T d = d0 - T(q);
+      const T delta = d * fma(c3, d * d, c1);
+      const T wt = fma(-fabs(delta), pw[q].y, T(1));
+      part = fma(fmax(wt, T(0)), pw[q].x, part);
+    }
+  }
+  return part;
+}
+
 template <typename T, bool FAN, int NC>
 __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                     const Epi<T> &e, Blk b) {
@@ -480,16 +505,16 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
   tile_pixel(g, b.id, i, j);
   const bool valid = i < g.nx && j < g.ny;
   T acc = T(0);
-  if (valid) {
-    const T px = T(i) - T(0.5) * T(g.nx - 1);
-    const T py = T(j) - T(0.5) * T(g.ny - 1);
-    const T off = T(g.off);
-    const unsigned ldY = (unsigned)g.ldY;
-    unsigned roff = (unsigned)g.padY;
-    // bins farther than the candidate half-width from the detector have zero
-    // weight; the clamp keeps every candidate inside the padded row
-    const T ulo = -T(g.uclamp_at), uhi = T(g.nu - 1) + T(g.uclamp_at);
-    if (!FAN) {
+  const T px = T(i) - T(0.5) * T(g.nx - 1);
+  const T py = T(j) - T(0.5) * T(g.ny - 1);
+  const T off = T(g.off);
+  const unsigned ldY = (unsigned)g.ldY;
+  unsigned roff = (unsigned)g.padY;
+  // bins farther than the candidate half-width from the detector have zero
+  // weight; the clamp keeps every candidate inside the padded row
+  const T ulo = -T(g.uclamp_at), uhi = T(g.nu - 1) + T(g.uclamp_at);
+  if (!FAN) {
+    if (valid) {
       for (int v = 0; v < g.nv; ++v) {
         T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
         u = fmin(fmax(u, ulo), uhi);
@@ -506,58 +531,46 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
         acc = fma(w, part, acc);
         roff += ldY;
       }
-    } else {
-      // ypad holds (w y, w) per padded bin, w = 1/|d_dom| of the ray (0 in the pads);
-      // vt.gcos holds (cos g_k, sin g_k) per padded bin
-      const T D = T(g.D), inv_dg = T(g.inv_du), hfac = T(g.hmax_fan), spread = T(g.dd_spread);
-      const bool fast = g.fast_atan != 0;
-      for (int v = 0; v < g.nv; ++v) {
+    }
+  } else {
+    // ypad holds (w y, w) per padded bin, w = 1/|d_dom| of the ray (0 in the
+    // pads); vt.gcos holds (cos g_k, sin g_k) per padded bin.  The candidate
+    // window of every pixel of the tile is floor(2H) + 1 bins from ceil(u_p - H),
+    // H the tile's half-width bound for the view, which a lane of the wavefront
+    // holds for 64 views at a time.  Every lane runs the loop (pixels outside
+    // the image too: the clamp keeps their reads inside the padded rows, and
+    // their sums are discarded).
+    const T D = T(g.D), inv_dg = T(g.inv_du);
+    const bool fast = g.fast_atan != 0;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ ht = vt.htile + (long long)b.id * g.nv;
+    for (int v0 = 0; v0 < g.nv; v0 += 64) {
+      const T hl = (v0 + lane < g.nv) ? ht[v0 + lane] : T(0);
+      const int vend = min(g.nv, v0 + 64);
+      for (int v = v0; v < vend; ++v) {
+        const T H = lane_value(hl, v - v0);
+        const int cnt = min((int)floor(T(2) * H) + 1, NC);
         const T cb = vt.p0[v], sb = vt.p1[v];
         const T a = D - fma(px, cb, py * sb);
         const T bb = fma(px, sb, -py * cb);
         T up = fma(fan_angle<T>(bb, a, fast), inv_dg, off);
         up = fmin(fmax(up, ulo), uhi);
-        // |d_dom| of the pixel's ray: (p - S) = a c + b c_perp, c = -(cos b, sin b)
-        const T wx = fma(bb, sb, -a * cb), wy = -fma(a, sb, bb * cb);
-        const T r2 = fma(a, a, bb * bb);
-        const T rinv = fast_rsq(r2);
-        const T ddm = fmin(fmax(fabs(wx), fabs(wy)) * rinv + spread, T(1));
-        // candidates: |g_k - g_p| < asin(|d_dom| / |p - S|) <= z (1 + z^2)
-        const T z = ddm * rinv;
-        const T h = hfac * z * fma(z, z, T(1)) + T(1e-3);
-        const T k0f = ceil(up - h);
-        const int cnt = (int)(floor(up + h) - k0f) + 1;
+        const T k0f = ceil(up - H);
         const unsigned k0 = (unsigned)((int)g.padY + (int)k0f);
         const typename Pair<T>::v2 *yw = reinterpret_cast<const typename Pair<T>::v2 *>(ypad) + (roff - g.padY + k0);
         if constexpr (sizeof(T) == 4) {
           // delta_k = |p - S| sin(g_p - g_k) with g_p - g_k = (up - k) dg; the sine to
           // third order, whose relative truncation error x^4/120 is below 1e-9 for
-          // the candidate angles of a fan with D >= 2 N
-          // with d = up - k: delta = d (c1 + c3 d^2), c1 = |p - S| dg, c3 = -c1 dg^2 / 6
+          // the candidate angles of a fan with D >= 2 N:
+          // delta = d (c1 + c3 d^2), c1 = |p - S| dg, c3 = -c1 dg^2 / 6, d = up - k
           const T dg = T(g.du);
-          const T c1 = r2 * rinv * dg, c3 = c1 * dg * dg * T(-1.0 / 6.0);
+          const T r2 = fma(a, a, bb * bb);
+          const T c1 = r2 * fast_rsq(r2) * dg, c3 = c1 * dg * dg * T(-1.0 / 6.0);
           const T d0 = up - k0f;
-          // the padded row holds the slice's own window of g.nc_at bins;
-          // NC may be larger in a launch over several slices
-          typename Pair<T>::v2 pw[NC];
-          if (g.nc_at == NC) {
-#pragma unroll
-            for (int q = 0; q < NC; ++q) pw[q] = yw[q];
-          } else {
-#pragma unroll
-            for (int q = 0; q < NC; ++q)
-              if (q < cnt) pw[q] = yw[q];
-          }
-#pragma unroll
-          for (int q = 0; q < NC; ++q) {
-            if (q < cnt) {
-              const auto pq = pw[q];
-              const T d = d0 - T(q);
-              const T delta = d * fma(c3, d * d, c1);
-              const T wt = fma(-fabs(delta), pq.y, T(1));
-              acc = fma(fmax(wt, T(0)), pq.x, acc);
-            }
-          }
+          acc += cnt == NC       ? at_fan_bins<T, NC, NC>(yw, d0, c1, c3, cnt)
+                 : cnt == NC - 1 ? at_fan_bins<T, NC - 1, NC>(yw, d0, c1, c3, cnt)
+                 : cnt == NC - 2 ? at_fan_bins<T, (NC > 2 ? NC - 2 : 0), NC>(yw, d0, c1, c3, cnt)
+                                 : at_fan_bins<T, 0, NC>(yw, d0, c1, c3, cnt);
         } else {
           const typename Pair<T>::v2 *cs = reinterpret_cast<const typename Pair<T>::v2 *>(vt.gcos) + k0;
 #pragma unroll
@@ -574,6 +587,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
         roff += ldY;
       }
     }
+    if (!valid) acc = T(0);
   }
   epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo, b);
 }
@@ -602,7 +616,6 @@ __device__ inline Epi<T> make_epi(const SliceDev<T> &d, const EpiCfg &ec, int k)
   e.prev = Col<const T>{resolve(d, ec.prev_buf, k), 0, 0, nullptr};
   e.out_raw = Col<T>{resolve(d, ec.out_raw_buf, k), 0, 0, nullptr};
   e.partials = d.partials;
-  e.counter = d.counter;
   return e;
 }
 
@@ -724,6 +737,7 @@ template <typename T>
 void launch_fwd(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e, const int *stop,
                 hipStream_t s) {
   hipLaunchKernelGGL(k_fwd<T>, dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, pad, y, e, stop);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, ray_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T, bool FAN>
@@ -748,6 +762,7 @@ void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T>
     back_adj_nc<T, true>(g, rt, pad, y, e, stop, s);
   else
     back_adj_nc<T, false>(g, rt, pad, y, e, stop, s);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, ray_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T>
@@ -757,6 +772,7 @@ void launch_back(const GeomDev &g, const ViewTab<T> &vt, const T *ypad, T *x, co
     hipLaunchKernelGGL((k_back<T, true>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
   else
     hipLaunchKernelGGL((k_back<T, false>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, pixel_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T, bool FAN>
@@ -781,6 +797,7 @@ void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt,
     fwd_adj_nc<T, true>(g, vt, rt, ypad, x, e, stop, s);
   else
     fwd_adj_nc<T, false>(g, vt, rt, ypad, x, e, stop, s);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, pixel_blocks(g), NORM_T1, stop, s);
 }
 
 // ---- batched launchers ----
@@ -800,8 +817,9 @@ void launch_b_pad_sino(const BatchDev<T> &bd, const BatchLaunch &bl, int in_sel,
 
 template <typename T>
 void launch_b_fwd(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
-  if (bl.tot[BF_RAY] > 0)
-    hipLaunchKernelGGL(kb_fwd<T>, dim3(bl.tot[BF_RAY]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  if (bl.tot[BF_RAY] <= 0) return;
+  hipLaunchKernelGGL(kb_fwd<T>, dim3(bl.tot[BF_RAY]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_RAY, NORM_T1, s);
 }
 
 template <typename T, bool FAN>
@@ -825,6 +843,7 @@ void launch_b_back_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel
     b_back_adj_nc<T, true>(bd, bl, out_sel, ec, s);
   else
     b_back_adj_nc<T, false>(bd, bl, out_sel, ec, s);
+  if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_RAY, NORM_T1, s);
 }
 
 template <typename T>
@@ -834,6 +853,7 @@ void launch_b_back(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, Ep
     hipLaunchKernelGGL((kb_back<T, true>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
   else
     hipLaunchKernelGGL((kb_back<T, false>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_PIX, NORM_T1, s);
 }
 
 template <typename T, bool FAN>
@@ -857,6 +877,7 @@ void launch_b_fwd_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel,
     b_fwd_adj_nc<T, true>(bd, bl, out_sel, ec, s);
   else
     b_fwd_adj_nc<T, false>(bd, bl, out_sel, ec, s);
+  if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_PIX, NORM_T1, s);
 }
 
 #define GKB_INST(T)                                                                                               \

@@ -49,19 +49,15 @@ __device__ inline double block_sum_all(double v, double *lds) {
   return r;
 }
 
-// Called by every thread after the block has published its partial results
-// (ordinary stores followed by this call).  Returns true in exactly one
-// block: the last one to arrive, which may then read every block's partials.
-// The last block must reset *counter to 0 before it exits.
-__device__ inline bool arrive_last(unsigned *counter, unsigned nblocks) {
-  __shared__ unsigned s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(counter, 1u) == nblocks - 1u) ? 1u : 0u;
-  __syncthreads();
-  const bool last = s_last != 0u;
-  if (last) __threadfence();
-  return last;
+// Sum of nb per-workgroup partial results p[i * stride] (i < nb), in a fixed
+// order; valid in thread 0.  Used by the finalising kernels that run after the
+// kernel that wrote the partials (the kernel boundary orders the two, so no
+// workgroup of the producing kernel has to wait for or signal another).
+template <int NT>
+__device__ inline double partial_total(const double *__restrict__ p, unsigned nb, unsigned stride, double *lds) {
+  double a = 0.0;
+  for (unsigned i = threadIdx.x; i < nb; i += NT) a += p[(size_t)i * stride];
+  return block_sum<NT>(a, lds);
 }
 
 }  // namespace gkb
