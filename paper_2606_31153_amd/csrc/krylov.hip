@@ -294,18 +294,20 @@ __device__ inline void small_solve_body(const Ctl &ctl) {
     dp[CD_PHIBAR] = -s * phibar;
   }
   __syncthreads();
+  // reciprocals of the diagonal, formed in parallel, so that the serial
+  // back substitution below multiplies instead of dividing
   for (int i = 1 + threadIdx.x; i <= k; i += kSolveThreads) {
-    s_rd[i] = ctl.Rd[i];
+    s_rd[i] = 1.0 / ctl.Rd[i];
     s_rth[i] = ctl.Rth[i];
     s_rphi[i] = ctl.Rphi[i];
   }
   __syncthreads();
   // back substitution R u = Rphi (serial, operands in LDS)
   if (threadIdx.x == 0) {
-    double un = s_rphi[k] / s_rd[k];
+    double un = s_rphi[k] * s_rd[k];
     s_u[k] = un;
     for (int i = k - 1; i >= 1; --i) {
-      un = (s_rphi[i] - s_rth[i + 1] * un) / s_rd[i];
+      un = (s_rphi[i] - s_rth[i + 1] * un) * s_rd[i];
       s_u[i] = un;
     }
     s_u[0] = 0.0;

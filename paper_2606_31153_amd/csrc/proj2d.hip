@@ -181,7 +181,27 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
     const T clo = T(-1.5), chi = T(rowdom ? g.nx : g.ny) + T(0.5);
     T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
     int j = lo;
-    // four lines per step: the eight taps are in flight together
+    // eight lines per step: the sixteen taps are in flight together
+    for (; j + 7 <= hi; j += 8) {
+      T c[8], fl[8];
+      typename Pair<T>::v2 p[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        c[q] = fmin(fmax(fma(jf + T(q), slope, base), clo), chi);
+        fl[q] = floor(c[q]);
+        p[q] = load_pair(pad + (off + (unsigned)(q * ld) + (unsigned)(int)fl[q]));
+      }
+      a0 += fma(c[0] - fl[0], p[0].y - p[0].x, p[0].x);
+      a1 += fma(c[1] - fl[1], p[1].y - p[1].x, p[1].x);
+      a2 += fma(c[2] - fl[2], p[2].y - p[2].x, p[2].x);
+      a3 += fma(c[3] - fl[3], p[3].y - p[3].x, p[3].x);
+      a0 += fma(c[4] - fl[4], p[4].y - p[4].x, p[4].x);
+      a1 += fma(c[5] - fl[5], p[5].y - p[5].x, p[5].x);
+      a2 += fma(c[6] - fl[6], p[6].y - p[6].x, p[6].x);
+      a3 += fma(c[7] - fl[7], p[7].y - p[7].x, p[7].x);
+      jf += T(8);
+      off += 8u * (unsigned)ld;
+    }
     for (; j + 3 <= hi; j += 4) {
       T c[4], fl[4];
       typename Pair<T>::v2 p[4];
@@ -232,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // candidates outside the support get a negative weight, clamped to zero.
 // ---------------------------------------------------------------------------
 // Sum over lines lo..hi of one ray with n candidates per line: n = CNT, or
-// the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.
+// the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.  Two
+// lines per step, the taps of both loaded before either is weighted.
 template <typename T, bool FAN, int CNT, int MAXC>
 __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, long long r,
                                  T hr, int nrt) {
@@ -249,18 +270,29 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
   // crossings farther than h from the image only meet zero weights; the
   // clamp keeps every candidate inside the padded line
   const T clo = -hr - T(0.5), chi = T((rowdom ? g.nx : g.ny) - 1) + hr + T(0.5);
-  T acc = T(0);
-  if (!FAN) {
-    const T inv_h = T(1) / hr;
-    for (int j = lo; j <= hi; ++j) {
-      const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
-      const T i0f = ceil(c - hr);
-      const T d0 = i0f - c;  // offset of the first candidate from the crossing
-      const T *p = pad + (off + (unsigned)(int)i0f);
-      T v[NQ];
+  T t0 = T(0), dt = T(0), dperp = T(0), dpar = T(0);
+  if (FAN) {
+    t0 = rt.t0[r];
+    dt = rt.dt[r];
+    dperp = rt.dperp[r];
+    dpar = rt.dpar[r];
+  }
+  const T inv_h = FAN ? T(0) : T(1) / hr;
+  const T inv_dg = T(g.inv_du);
+  const bool series = sizeof(T) == 4 && g.bt_fast;
+  // the line at jfl (padded-line offset offl): offset d0 of the window's
+  // first pixel from the crossing, and the window's taps
+  auto taps = [&](T jfl, unsigned offl, T &d0, T (&v)[NQ]) {
+    const T c = fmin(fmax(fma(jfl, slope, base), clo), chi);
+    const T i0f = ceil(c - hr);
+    d0 = i0f - c;
+    const T *p = pad + (offl + (unsigned)(int)i0f);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q < n) v[q] = p[q];
+    for (int q = 0; q < NQ; ++q)
+      if (q < n) v[q] = p[q];
+  };
+  auto weigh = [&](T jfl, T d0, const T (&v)[NQ], T &acc) {
+    if (!FAN) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q < n) {
@@ -268,23 +300,8 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
           acc = fma(fmax(wt, T(0)), v[q], acc);
         }
       }
-      jf += T(1);
-      off += (unsigned)ld;
-    }
-  } else {
-    const T t0 = rt.t0[r], dt = rt.dt[r], dperp = rt.dperp[r], dpar = rt.dpar[r];
-    const T inv_dg = T(g.inv_du);
-    const bool series = sizeof(T) == 4 && g.bt_fast;
-    for (int j = lo; j <= hi; ++j) {
-      const T c = fmin(fmax(fma(jf, slope, base), clo), chi);
-      const T along0 = fma(jf, dt, t0);
-      const T i0f = ceil(c - hr);
-      const T d0 = i0f - c;
-      const T *p = pad + (off + (unsigned)(int)i0f);
-      T v[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q < n) v[q] = p[q];
+    } else {
+      const T along0 = fma(jfl, dt, t0);
       if (series) {
         // |angle| / dg = kz |d| (1 - e + e^2) with e = kd d, written as
         // |d| (kz + d (a1 + d a2)): one reciprocal per line
@@ -312,9 +329,23 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
           }
         }
       }
-      jf += T(1);
-      off += (unsigned)ld;
     }
+  };
+  T acc = T(0);
+  int j = lo;
+  for (; j + 1 <= hi; j += 2) {
+    T d0a, d0b, va[NQ], vb[NQ];
+    taps(jf, off, d0a, va);
+    taps(jf + T(1), off + (unsigned)ld, d0b, vb);
+    weigh(jf, d0a, va, acc);
+    weigh(jf + T(1), d0b, vb, acc);
+    jf += T(2);
+    off += 2u * (unsigned)ld;
+  }
+  if (j <= hi) {
+    T d0a, va[NQ];
+    taps(jf, off, d0a, va);
+    weigh(jf, d0a, va, acc);
   }
   return acc;
 }
@@ -322,8 +353,13 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
 template <typename T, bool FAN, int NC>
 __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
                                      const Epi<T> &e, Blk b) {
-  const long long r = (long long)b.id * kBlock + threadIdx.x;
-  const bool valid = r < g.m;
+  // workgroup = 64 consecutive bins of 4 consecutive views (one view per
+  // wavefront): the four wavefronts of a workgroup cross nearly the same
+  // image lines at nearly the same places
+  const int tiles_u = (g.nu + 63) >> 6;
+  const int view = (int)(b.id / tiles_u) * 4 + (threadIdx.x >> 6), bin = (int)(b.id % tiles_u) * 64 + (threadIdx.x & 63);
+  const bool valid = view < g.nv && bin < g.nu;
+  const long long r = valid ? (long long)view * g.nu + bin : 0;
   const T hr = valid ? rt.h[r] : T(0);
   // window length: the wavefront's largest floor(2h) + 1.  It is at most the
   // slice's own candidate count (plus one where h rounds up in float), which
@@ -701,7 +737,13 @@ __global__ __launch_bounds__(kBlock) void kb_fwd_adj(BatchDev<T> bd, int out_sel
 int pixel_blocks(const GeomDev &g) {
   return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * (g.kind == 2 ? g.nz : 1);
 }
-int ray_blocks(const GeomDev &g) { return (int)((g.m + kBlock - 1) / kBlock); }
+// Grid of the ray-driven kernels: B^T takes workgroups of 64 bins x 4 views,
+// A the same count of workgroups over consecutive rays (256 per workgroup;
+// the grid covers at least ceil(m / 256), surplus workgroups have no valid ray).
+int ray_blocks(const GeomDev &g) {
+  if (g.kind == 2) return (int)((g.m + kBlock - 1) / kBlock);
+  return ((g.nu + 63) / 64) * ((g.nv + 3) / 4);
+}
 
 template <typename T>
 void launch_pad_image(const GeomDev &g, Col<const T> x, T *pad, bool cols, const int *stop, hipStream_t s) {
