@@ -421,7 +421,7 @@ def main():
     elapsed = time.perf_counter() - t0
     ctx.trace_enable(False)
     kernels = {}
-    for name in ("fwd", "back", "fwd_adj", "back_adj", "reorth", "gram", "small_solve"):
+    for name in ("fwd", "back", "fwd_adj", "back_adj", "reorth", "small_solve", "residual"):
         cnt, ms = ctx.trace_get(name)
         if cnt:
             kernels[name] = {"launches": cnt, "avg_ms": ms / cnt, "total_ms": ms}

@@ -328,6 +328,10 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     // atan(z) = z are exact to e^3 + dg^2 / 3 relative
     const double emax = (2.0 * hmax_bt + 1.0) / t.min_along;
     gd.bt_fast = (emax * emax * emax + du * du / 3.0 <= 1e-6) ? 1 : 0;
+    // A^T in float: delta_k = |p - S| sin(g_p - g_k) with |g_p - g_k| <= (h + 1) dg
+    // over the candidate window; sin(x) = x is exact to x^2 / 6 relative
+    const double xmax = (hmax_at + 1.0) * du;
+    gd.at_fast = (xmax * xmax / 6.0 <= 1e-6) ? 1 : 0;
   }
   gd.nc_bt = (int)std::floor(2.0 * hmax_bt) + 1;
   gd.nc_at = (int)std::floor(2.0 * hmax_at) + 1;
@@ -620,7 +624,7 @@ struct gkb_ctx {
   // scratch for standalone projector calls and reductions
   DevBuf xpad, ypad, partials;
   // solve workspace
-  DevBuf Q, Y, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
+  DevBuf Q, yk, rdbl, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
   int *host_flag = nullptr;      // host-mapped
   int *host_flag_dev = nullptr;  // its device address
   // batched solves: vectors, control blocks, slice descriptors, launch maps
@@ -1128,8 +1132,8 @@ struct Solver {
   int mode;
   int K;
   long long n, m, dimq, dims;
-  long long ldq, ldy;  // column strides of Q and Y (multiples of 4)
-  T *Q = nullptr, *Y = nullptr, *s = nullptr, *w = nullptr, *tn = nullptr, *tm = nullptr;
+  long long ldq;  // column stride of Q (a multiple of 4)
+  T *Q = nullptr, *yk = nullptr, *s = nullptr, *w = nullptr, *tn = nullptr, *tm = nullptr;
   T *xpad = nullptr, *ypad = nullptr;
   Ctl ctl{};
   double *partials = nullptr;
@@ -1146,20 +1150,19 @@ struct Solver {
     m = g.m;
     dimq = (mode == MODE_AB) ? m : n;
     ldq = (dimq + 3) / 4 * 4;
-    ldy = (m + 3) / 4 * 4;
     dims = (mode == MODE_BA) ? n : m;
     st = c->stream;
   }
 
   gkb_status alloc() {
-    const long long ldG = K + 2;
     HIPC(c->Q.ensure(sizeof(T) * (size_t)ldq * (K + 1)));
-    HIPC(c->Y.ensure(sizeof(T) * (size_t)ldy * (K + 1)));
+    HIPC(c->yk.ensure(sizeof(T) * (size_t)m));
+    HIPC(c->rdbl.ensure(sizeof(double) * 2 * (size_t)((m + 3) / 4 * 4)));
     HIPC(c->s.ensure(sizeof(T) * (size_t)dims));
     HIPC(c->w.ensure(sizeof(T) * (size_t)dimq));
     HIPC(c->tmp_n.ensure(sizeof(T) * (size_t)n));
     HIPC(c->tmp_m.ensure(sizeof(T) * (size_t)m));
-    const size_t nd = CD_COUNT + 9 * (size_t)(K + 2) + (size_t)ldG * ldG;
+    const size_t nd = CD_COUNT + 9 * (size_t)(K + 2);
     HIPC(c->ctl_d.ensure(sizeof(double) * nd));
     HIPC(c->ctl_i.ensure(sizeof(int) * CI_COUNT));
     const long long vb = std::max<long long>(
@@ -1172,7 +1175,7 @@ struct Solver {
       HIPC(hipHostGetDevicePointer((void **)&c->host_flag_dev, c->host_flag, 0));
     }
     Q = c->Q.as<T>();
-    Y = c->Y.as<T>();
+    yk = c->yk.as<T>();
     s = c->s.as<T>();
     w = c->w.as<T>();
     tn = c->tmp_n.as<T>();
@@ -1188,9 +1191,9 @@ struct Solver {
       *a = dp;
       dp += K + 2;
     }
-    ctl.G = dp;
+    ctl.aw = c->rdbl.as<double>();
+    ctl.r = ctl.aw + (m + 3) / 4 * 4;  // 32-byte aligned quads
     ctl.K = K;
-    ctl.ldG = (int)ldG;
     ctl.host_stop = c->host_flag_dev;
     partials = c->partials.as<double>();
     stop = ctl.ip + CI_STOP;
@@ -1206,9 +1209,8 @@ struct Solver {
     return e;
   }
 
-  // column i (0-based, shifted by the device counter k) of Q / Y
+  // column i (0-based, shifted by the device counter k) of Q
   Col<const T> qcol(int off) const { return colk<const T>(Q, ldq, off, kp); }
-  Col<T> ycol(int off) const { return colk<T>(Y, ldy, off, kp); }
 
   // ----- the four projectors with device-addressed operands -----
   bool cone() const { return g.kind == GKB_CONE3D; }
@@ -1266,19 +1268,19 @@ struct Solver {
     e.prev = col<const T>(s);
     e.norm_to_t = 1;
     if (mode == MODE_BA) {  // Y_k = A q_k ; s~ = B Y_k - ...  (B F Y_k with the filter)
-      A(qcol(-1), ycol(0), plain_epi<T>());
+      A(qcol(-1), col<T>(yk), plain_epi<T>());
       if (filtered()) {
-        filter(NET_F, colk<const T>(Y, ldy, 0, kp));
+        filter(NET_F, col<const T>(yk));
         B(col<const T>(c->nout.as<T>()), s, e);
       } else {
-        B(colk<const T>(Y, ldy, 0, kp), s, e);
+        B(col<const T>(yk), s, e);
       }
     } else if (mode == MODE_AB) {  // Y_k = A B q_k ; s~ = Y_k - ...
       B(qcol(-1), tn, plain_epi<T>());
-      e.out_raw = ycol(0);
+      e.out_raw = col<T>(yk);
       A(col<const T>(tn), col<T>(s), e);
     } else {  // matched: Y_k = A q_k ; s~ = Y_k - ...
-      e.out_raw = ycol(0);
+      e.out_raw = col<T>(yk);
       A(qcol(-1), col<T>(s), e);
     }
   }
@@ -1324,12 +1326,12 @@ struct Solver {
     apply_Mt(false);
     reorth_and_normalize_impl(reorth);
     {
-      TraceScope ts(c, "gram");
-      launch_gram<T>(ctl, Y, ldy, m, 0, partials, st);
-    }
-    {
       TraceScope ts(c, "small_solve");
       launch_small_solve(ctl, st);
+    }
+    {
+      TraceScope ts(c, "residual");
+      launch_resid<T>(ctl, yk, m, partials, st);
     }
   }
 
@@ -1381,9 +1383,8 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   HIPC(hipMemcpyAsync(S.ctl.dp, hdp, sizeof hdp, hipMemcpyHostToDevice, st));
   *c->host_flag = 0;
 
-  // start-up (k = 0): Y_0 = b, G_00 = ||b||^2; s~_1 = rhs, t_1; q_1, alpha_1
-  launch_copy<T>(b, S.Y, g.m, st);
-  launch_gram<T>(S.ctl, S.Y, S.ldy, g.m, 1, S.partials, st);
+  // start-up (k = 0): r_0 = -b, ||b||; s~_1 = rhs, t_1; q_1, alpha_1
+  launch_resid_init<T>(S.ctl, b, g.m, S.partials, st);
   if (mode == MODE_BA) {
     Epi<T> e = S.epi();
     e.norm_to_t = 1;
@@ -1404,11 +1405,11 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   double h3[3];
   HIPC(hipMemcpyAsync(&h3[0], S.ctl.t + 1, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPC(hipMemcpyAsync(&h3[1], S.ctl.alpha + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPC(hipMemcpyAsync(&h3[2], S.ctl.G, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(&h3[2], S.ctl.dp + CD_BNORM, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
-  const double t1 = h3[0], bb = h3[2];
+  const double t1 = h3[0], bnorm = h3[2];
   const double a1 = (t1 > 0.0) ? h3[1] : 0.0;  // M^T (s/t_1) is 0/0 when t_1 = 0
-  if (!std::isfinite(bb) || !std::isfinite(t1) || !std::isfinite(a1))
+  if (!std::isfinite(bnorm) || !std::isfinite(t1) || !std::isfinite(a1))
     return fail(GKB_ENONFINITE, "non-finite value in b (or in the start-up vectors)");
   gkb_solve_info inf{};
   inf.t1 = t1;
@@ -1419,7 +1420,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     HIPC(hipMemsetAsync(x, 0, sizeof(T) * (size_t)g.n, st));
     HIPC(hipStreamSynchronize(st));
     reason = GKB_STOP_BREAKDOWN;
-    inf.residual = std::sqrt(bb);
+    inf.residual = bnorm;
     inf.proj_residual = t1;
   } else {
     launch_set_int(S.ctl.ip + CI_K, 1, st);
@@ -1536,13 +1537,14 @@ inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct SliceHost {
   const DevTables *d;
-  long long n, m, dimq, dims, ldq, ldy;
+  long long n, m, dimq, dims, ldq;
   int K;
   int cnt[BF_COUNT];
   // byte offsets into the vector workspace
-  size_t oQ, oY, os, ow, otn, otm, oxp, oyp;
-  // element offsets into the double workspace (control arrays, partials)
-  size_t oarr, opart;
+  size_t oQ, oyk, os, ow, otn, otm, oxp, oyp;
+  // element offsets into the double workspace (control arrays, residual
+  // vectors Aw and r, partials)
+  size_t oarr, ores, opart;
 };
 
 // Launch map of the slices in `active` (slice ids): the active list followed
@@ -1603,7 +1605,6 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.dimq = mode == MODE_AB ? g.m : g.n;
     h.dims = mode == MODE_BA ? g.n : g.m;
     h.ldq = (h.dimq + 3) / 4 * 4;
-    h.ldy = (g.m + 3) / 4 * 4;
     bl.nc_bt = std::max(bl.nc_bt, g.nc_bt);
     bl.nc_at = std::max(bl.nc_at, g.nc_at);
     bl.kmax = std::max(bl.kmax, h.K);
@@ -1620,7 +1621,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       return o;
     };
     h.oQ = take((size_t)h.ldq * (h.K + 1));
-    h.oY = take((size_t)h.ldy * (h.K + 1));
+    h.oyk = take((size_t)g.m);
     h.os = take((size_t)h.dims);
     h.ow = take((size_t)h.dimq);
     h.otn = take((size_t)g.n);
@@ -1628,7 +1629,10 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.oxp = take((size_t)g.pad_elems);
     h.oyp = take(2 * (size_t)g.ypad_elems);
     h.oarr = ndbl;
-    ndbl += 9 * (size_t)(h.K + 2) + (size_t)(h.K + 2) * (h.K + 2);
+    ndbl += 9 * (size_t)(h.K + 2);
+    ndbl = (ndbl + 31) / 32 * 32;
+    h.ores = ndbl;
+    ndbl += 2 * (size_t)((g.m + 3) / 4 * 4);
     h.opart = ndbl;
     ndbl += (size_t)std::max<long long>(
         {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
@@ -1681,14 +1685,14 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       *a = dp;
       dp += h.K + 2;
     }
-    ctl.G = dp;
+    ctl.aw = wsD + h.ores;
+    ctl.r = ctl.aw + (h.m + 3) / 4 * 4;
     ctl.K = h.K;
-    ctl.ldG = h.K + 2;
     ctl.host_stop = c->bflags_dev + s;
     d.xpad = reinterpret_cast<T *>(wsT + h.oxp);
     d.ypad = reinterpret_cast<T *>(wsT + h.oyp);
     d.Q = reinterpret_cast<T *>(wsT + h.oQ);
-    d.Y = reinterpret_cast<T *>(wsT + h.oY);
+    d.yk = reinterpret_cast<T *>(wsT + h.oyk);
     d.s = reinterpret_cast<T *>(wsT + h.os);
     d.w = reinterpret_cast<T *>(wsT + h.ow);
     d.tn = reinterpret_cast<T *>(wsT + h.otn);
@@ -1696,7 +1700,6 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     d.b = static_cast<const T *>(bv[s]);
     d.x = static_cast<T *>(xv[s]);
     d.ldq = h.ldq;
-    d.ldy = h.ldy;
     d.dimq = h.dimq;
     d.dims = h.dims;
     d.partials = wsD + h.opart;
@@ -1756,9 +1759,8 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     }
   };
 
-  // start-up (k = 0 in every slice): Y_0 = b, G_00; s~_1 = rhs, t_1; q_1, alpha_1
-  launch_b_copy<T>(bd, bl, BS_B, BS_Y_CUR, st);
-  launch_b_gram<T>(bd, bl, st);
+  // start-up (k = 0 in every slice): r_0 = -b, ||b||; s~_1 = rhs, t_1; q_1, alpha_1
+  launch_b_resid_init<T>(bd, bl, st);
   if (mode == MODE_BA) {
     opB(BS_B, BS_S, EpiCfg{IN_ONE, PREV_NONE, BS_NONE, 1, BS_NONE});
   } else {
@@ -1776,9 +1778,9 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
   std::vector<gkb_solve_info> inf(ns);
   std::vector<int> loop;
   for (int s = 0; s < ns; ++s) {
-    const double t1 = rep[4 * s], bb = rep[4 * s + 2];
+    const double t1 = rep[4 * s], bnorm = rep[4 * s + 2];
     const double a1 = t1 > 0.0 ? rep[4 * s + 1] : 0.0;
-    if (!std::isfinite(bb) || !std::isfinite(t1) || !std::isfinite(a1))
+    if (!std::isfinite(bnorm) || !std::isfinite(t1) || !std::isfinite(a1))
       return fail(GKB_ENONFINITE, "non-finite value in b of slice " + std::to_string(s));
     inf[s] = gkb_solve_info{};
     inf[s].t1 = t1;
@@ -1788,7 +1790,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       hi[CI_STOP] = 1;
       hi[CI_REASON] = GKB_STOP_BREAKDOWN;
       inf[s].reason = GKB_STOP_BREAKDOWN;
-      inf[s].residual = std::sqrt(bb);
+      inf[s].residual = bnorm;
       inf[s].proj_residual = t1;
     } else {
       hi[CI_K] = 1;
@@ -1827,12 +1829,12 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
         launch_b_normalize<T>(bd, bl, st);
       }
       {
-        TraceScope ts(c, "gram");
-        launch_b_gram<T>(bd, bl, st);
-      }
-      {
         TraceScope ts(c, "small_solve");
         launch_b_small_solve<T>(bd, bl, st);
+      }
+      {
+        TraceScope ts(c, "residual");
+        launch_b_resid<T>(bd, bl, st);
       }
       HIPC(hipEventRecord(evs[k % L], st));
       if (k >= L) {

@@ -47,7 +47,7 @@ __device__ inline T *resolve(const SliceDev<T> &d, int sel, int k) {
     case BS_TN: return d.tn;
     case BS_TM: return d.tm;
     case BS_Q_PREV: return d.Q + (long long)(k - 1) * d.ldq;
-    case BS_Y_CUR: return d.Y + (long long)k * d.ldy;
+    case BS_Y_CUR: return d.yk;
     default: return nullptr;
   }
 }

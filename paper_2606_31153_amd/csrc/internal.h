@@ -33,6 +33,7 @@ enum CtlDbl : int {
   CD_PRES = 9,     // projected residual at k
   CD_USEDP = 10,
   CD_KMAX = 11,
+  CD_BNORM = 12,   // ||b||
   CD_COUNT = 16
 };
 
@@ -49,11 +50,11 @@ struct Ctl {
   double *Rd;     // diagonal of R
   double *Rth;    // superdiagonal of R (Rth[i] couples columns i-1, i)
   double *Rphi;   // rotated right-hand side
-  double *G;      // (K+2) x (K+2) Gram of [b, Y_1, ..., Y_K], row-major
   double *c;      // CGS coefficients [K+1]
+  double *aw;     // [m] A-image of the last column of W = Q R^{-1}
+  double *r;      // [m] r_k = A x_k - b
   int *host_stop; // host-mapped mirror of ip[CI_STOP] (may be null)
   int K;
-  int ldG;
 };
 
 // A vector selected by the device-side iteration counter:
@@ -129,7 +130,8 @@ struct GeomDev {
   double tan_dg;       // fan B^T: tan(bin pitch)
   double dd_spread;    // fan A^T: bound on the |d_dom| change across the candidate rays
   int fast_atan;       // fan, float: every pixel's fan angle has |tan| <= 0.5
-  int bt_fast;         // fan B^T, float: series forms of the candidate weights are exact to FP32
+  int bt_fast;         // fan B^T, float: series forms of the candidate weights (relative error <= 1e-6)
+  int at_fast;         // fan A^T, float: first-order sine of the candidate angles (relative error <= 1e-6)
   // padded image: row-major region (ny lines of ldR = nx + 2 pad), then the
   // column-major region at offT (nx lines of ldT = ny + 2 pad)
   int pad, ldR, ldT;
@@ -193,7 +195,7 @@ enum BufSel : int {
   BS_TN,      // n-vector temporary
   BS_TM,      // m-vector temporary
   BS_Q_PREV,  // Q[:, k-1] = q_k
-  BS_Y_CUR    // Y[:, k]
+  BS_Y_CUR    // the current A-image Y_k
 };
 
 // Everything one slice of a batch needs on the device.
@@ -204,10 +206,10 @@ struct SliceDev {
   ViewTab<T> vt;
   Ctl ctl;
   T *xpad, *ypad;
-  T *Q, *Y, *s, *w, *tn, *tm;
+  T *Q, *yk, *s, *w, *tn, *tm;
   const T *b;
   T *x;
-  long long ldq, ldy, dimq, dims;
+  long long ldq, dimq, dims;
   double *partials;
   int has_coldom;
   int reorth;
@@ -316,7 +318,9 @@ void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, i
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s);
 template <typename T>
-void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials, hipStream_t s);
+void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream_t s);
+template <typename T>
+void launch_resid_init(Ctl ctl, const T *b, long long m, double *partials, hipStream_t s);
 // t[k+1] (NORM_T1) or alpha[k+1] (NORM_ALPHA1) = sqrt(sum of nb partials), after
 // the kernel that wrote them (a projector with norm_to_t, cgs_update, norm_to);
 // skipped when stop is set
@@ -358,8 +362,9 @@ void launch_net_resid(const float *xhat, const float *x, float *r, long long n, 
                       hipStream_t st);
 void launch_net_scale(float *r, long long n, const double *sums, int batch, hipStream_t st);
 
-// norm targets for launch_norm_to
-enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1 };
+// targets of the finalising reductions: t[k+1], alpha[k+1], dp[CD_BNORM] =
+// ||b||, and rho[k] = ||r_k|| with the stopping decision of iteration k
+enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO = 3 };
 
 // ---- batched launchers: one launch covers every active slice ----
 template <typename T>
@@ -387,7 +392,9 @@ void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last,
 template <typename T>
 void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>
-void launch_b_gram(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+void launch_b_resid(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+template <typename T>
+void launch_b_resid_init(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>
 void launch_b_small_solve(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>

@@ -11,15 +11,19 @@
 // Reorthogonalisation (one-sided, on q only; Alg. "GKB" step 9 and its
 // AB/BA counterparts) is classical Gram-Schmidt applied twice:
 //   c1 = Q^T w;  w -= Q c1;  c2 = Q^T w;  w -= Q c2;  alpha = ||w||.
-// The discrepancy residual ||A x_k - b|| is obtained from the Gram matrix of
-// the stored A-images Y_i (BA, GKB: A q_i; AB: A B q_i) and b:
-//   ||Y u - b||^2 = u^T (Y^T Y) u - 2 u^T (Y^T b) + ||b||^2,
-// which equals ||A x_k - b||^2 because A x_k = sum_i u_i Y_i.
 // The projected problem min ||C_k u - t_1 e_1||^2 + lambda^2 ||u||^2
 // (eq. proj GKB) is solved by Givens rotations updated once per iteration
 // (the factorisation Paige and Saunders use for LSQR, with the damping rows
-// for lambda); this gives the same minimiser as the SVD route of the paper
-// in O(k) work per iteration.
+// for lambda): R_k u_k = phi_k with R_k upper bidiagonal, whose leading
+// parts (and phi's leading entries) do not change from one iteration to the
+// next.  This gives the same minimiser as the SVD route of the paper in O(k)
+// work per iteration.
+// The discrepancy residual ||A x_k - b|| (eq. DP) follows from the A-images
+// Y_i of the basis (BA, GKB: A q_i; AB: A B q_i): A x_k = Y_k u_k = W_k phi_k
+// with W_k = Y_k R_k^{-1}, so with the short recurrences (in double)
+//   Aw_k = (Y_k - Rth_k Aw_{k-1}) / Rd_k,   r_k = r_{k-1} + phi_k Aw_k,  r_0 = -b
+// r_k = A x_k - b is carried from one iteration to the next at O(m) cost and
+// rho_k = ||r_k||; only the current A-image is kept.
 
 #include <algorithm>
 
@@ -89,17 +93,15 @@ __device__ inline void store_quad(T *__restrict__ p, long long r, long long dim,
 }
 
 // ---- partial inner products: workgroup (x, y) covers rows [x*1024, x*1024+1024)
-// and columns [16 y, 16 y + 16) of V, against w.  gram == 0: columns 0..k-1 of
-// Q against w (reorthogonalisation); gram == 1: columns 0..k of Y against
-// Y_k (Gram row k).  Result: partials[x * ldp + column].
+// and columns [16 y, 16 y + 16) of Q (columns 0..ncol-1), against w.
+// Result: partials[x * ldp + column].
 template <typename T>
 __device__ inline void dots_body(const Ctl &ctl, const T *__restrict__ V, long long ld, const T *__restrict__ w,
-                                 long long dim, double *partials, int gram, unsigned bx, unsigned by, int ncol) {
-  const int k = ctl.ip[CI_K];
+                                 long long dim, double *partials, unsigned bx, unsigned by, int ncol) {
   const int c0 = by * CH;
   if (c0 >= ncol) return;
   __shared__ double lds[(kBlock / 64) * CH];
-  const T *__restrict__ wv = gram ? V + (long long)k * ld : w;
+  const T *__restrict__ wv = w;
   const long long r = ((long long)bx * kBlock + threadIdx.x) * RPT;
   double wq[RPT];
   load_quad(wv, r, dim, wq);
@@ -121,38 +123,27 @@ __device__ inline void dots_body(const Ctl &ctl, const T *__restrict__ V, long l
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dots(Ctl ctl, const T *__restrict__ V, long long ld,
-                                                 const T *__restrict__ w, long long dim, double *partials, int gram) {
+                                                 const T *__restrict__ w, long long dim, double *partials) {
   if (ctl.ip[CI_STOP]) return;
-  const int k = ctl.ip[CI_K];
-  dots_body(ctl, V, ld, w, dim, partials, gram, blockIdx.x, blockIdx.y, gram ? k + 1 : k);
+  dots_body(ctl, V, ld, w, dim, partials, blockIdx.x, blockIdx.y, ctl.ip[CI_K]);
 }
 
-// ---- column sums of the per-workgroup partials: one workgroup per column ----
-// which == 0: c[col] (col < k);  which == 1: Gram row k, G[k][col] = G[col][k] (col <= k)
-__device__ inline void reduce_cols_body(const Ctl &ctl, const double *__restrict__ partials, int nb, int which,
-                                        int col, int ncol) {
+// ---- column sums of the per-workgroup partials: c[col] (col < ncol), one
+// workgroup per column ----
+__device__ inline void reduce_cols_body(const Ctl &ctl, const double *__restrict__ partials, int nb, int col,
+                                        int ncol) {
   __shared__ double lds[kBlock / 64];
-  const int k = ctl.ip[CI_K];
   if (col >= ncol) return;
   const int ldp = ctl.K + 2;
   double acc = 0.0;
   for (int b = threadIdx.x; b < nb; b += kBlock) acc += partials[(long long)b * ldp + col];
   const double tot = block_sum<kBlock>(acc, lds);
-  if (threadIdx.x == 0) {
-    if (which == 0) {
-      ctl.c[col] = tot;
-    } else {
-      ctl.G[(long long)k * ctl.ldG + col] = tot;
-      ctl.G[(long long)col * ctl.ldG + k] = tot;
-    }
-  }
+  if (threadIdx.x == 0) ctl.c[col] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *__restrict__ partials, int nb,
-                                                        int which) {
+__global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *__restrict__ partials, int nb) {
   if (ctl.ip[CI_STOP]) return;
-  const int k = ctl.ip[CI_K];
-  reduce_cols_body(ctl, partials, nb, which, blockIdx.x, which == 0 ? k : k + 1);
+  reduce_cols_body(ctl, partials, nb, blockIdx.x, ctl.ip[CI_K]);
 }
 
 // ---- w -= Q[:, 0..k-1] c (FP64 per element); last == 1: partials of ||w||^2
@@ -202,16 +193,20 @@ __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restr
 
 // ---- finalising kernel: t[k+1] (which == NORM_T1) or alpha[k+1]
 // (NORM_ALPHA1) = sqrt of the sum of nb partials ----
+__device__ inline void stop_test(const Ctl &ctl, double rho);
+
 __device__ inline void norm_finalize_body(const Ctl &ctl, const double *__restrict__ partials, unsigned nb,
                                           int which) {
   __shared__ double lds[kBlock / 64];
   const double tot = partial_total<kBlock>(partials, nb, 1, lds);
   if (threadIdx.x == 0) {
     const int k = ctl.ip[CI_K];
-    if (which == NORM_T1)
-      ctl.t[k + 1] = sqrt(tot);
-    else
-      ctl.alpha[k + 1] = sqrt(tot);
+    switch (which) {
+      case NORM_T1: ctl.t[k + 1] = sqrt(tot); break;
+      case NORM_ALPHA1: ctl.alpha[k + 1] = sqrt(tot); break;
+      case NORM_BNORM: ctl.dp[CD_BNORM] = sqrt(tot); break;
+      default: stop_test(ctl, sqrt(tot)); break;  // NORM_RHO
+    }
   }
 }
 
@@ -323,43 +318,103 @@ __device__ inline void small_solve_body(const Ctl &ctl) {
     pr = fma(r, r, pr);
   }
   pr = block_sum<kSolveThreads>(pr, s_red);
-  // ||Y u - b||^2 = sum_j u_j (sum_i u_i G_ij) - 2 sum_j u_j G_0j + G_00 (i, j = 1..k)
-  double part = 0.0;
-  for (int j = 1 + threadIdx.x; j <= k; j += kSolveThreads) {
-    double sj = -2.0 * ctl.G[j];
-    for (int i = 1; i <= k; ++i) sj = fma(s_u[i], ctl.G[(long long)i * ctl.ldG + j], sj);
-    part = fma(s_u[j], sj, part);
-  }
-  part = block_sum<kSolveThreads>(part, s_red);
   if (threadIdx.x == 0) {
     dp[CD_PRES] = sqrt(pr);
     ctl.pres[k] = dp[CD_PRES];
-    const double rho2 = part + ctl.G[0];
-    const double rho = sqrt(fmax(rho2, 0.0));
-    ctl.rho[k] = rho;
-    // breakdown scale: max_i sqrt(alpha_i^2 + t_{i+1}^2)
-    const double ak = ctl.alpha[k], tk1 = ctl.t[k + 1];
-    const double sc = fmax(dp[CD_BSCALE], sqrt(ak * ak + tk1 * tk1));
-    dp[CD_BSCALE] = sc;
-    const double eta = dp[CD_ETAEPS] * sc;
-    int reason = 0;
-    if (dp[CD_USEDP] != 0.0 && rho <= dp[CD_TAUE])
-      reason = 1;  // GKB_STOP_DP
-    else if (!(tk1 > eta))
-      reason = 3;  // GKB_STOP_BREAKDOWN
-    else if (k >= ctl.K)
-      reason = dp[CD_USEDP] != 0.0 ? 4 : 2;  // DP_NOT_REACHED / KMAX
-    else if (!(ctl.alpha[k + 1] > eta))
-      reason = 3;
-    ctl.ip[CI_KSTOP] = k;
-    if (reason) {
-      ctl.ip[CI_REASON] = reason;
-      ctl.ip[CI_STOP] = 1;
-      if (ctl.host_stop) *(volatile int *)ctl.host_stop = 1;
-    } else {
-      ctl.ip[CI_K] = k + 1;
-    }
   }
+}
+
+// ---- the discrepancy residual rho_k = ||r_k|| (kept by the recurrences above)
+// and the stopping decision of iteration k (thread 0 of a finalising kernel) ----
+__device__ inline void stop_test(const Ctl &ctl, double rho) {
+  double *dp = ctl.dp;
+  const int k = ctl.ip[CI_K];
+  ctl.rho[k] = rho;
+  // breakdown scale: max_i sqrt(alpha_i^2 + t_{i+1}^2)
+  const double ak = ctl.alpha[k], tk1 = ctl.t[k + 1];
+  const double sc = fmax(dp[CD_BSCALE], sqrt(ak * ak + tk1 * tk1));
+  dp[CD_BSCALE] = sc;
+  const double eta = dp[CD_ETAEPS] * sc;
+  int reason = 0;
+  if (dp[CD_USEDP] != 0.0 && rho <= dp[CD_TAUE])
+    reason = 1;  // GKB_STOP_DP
+  else if (!(tk1 > eta))
+    reason = 3;  // GKB_STOP_BREAKDOWN
+  else if (k >= ctl.K)
+    reason = dp[CD_USEDP] != 0.0 ? 4 : 2;  // DP_NOT_REACHED / KMAX
+  else if (!(ctl.alpha[k + 1] > eta))
+    reason = 3;
+  ctl.ip[CI_KSTOP] = k;
+  if (reason) {
+    ctl.ip[CI_REASON] = reason;
+    ctl.ip[CI_STOP] = 1;
+    if (ctl.host_stop) *(volatile int *)ctl.host_stop = 1;
+  } else {
+    ctl.ip[CI_K] = k + 1;
+  }
+}
+
+// ---- residual recurrences: Aw = (Y_k - Rth_k Aw) / Rd_k, r += Rphi_k Aw
+// (Aw not read at k = 1), partials of ||r||^2 ----
+template <typename T>
+__device__ inline void resid_body(const Ctl &ctl, const T *__restrict__ yk, long long m, double *partials, Blk b) {
+  __shared__ double lds[kBlock / 64];
+  const int k = ctl.ip[CI_K];
+  const double th = k > 1 ? ctl.Rth[k] : 0.0, inv = 1.0 / ctl.Rd[k], ph = ctl.Rphi[k];
+  const long long r0 = ((long long)b.id * kBlock + threadIdx.x) * RPT;
+  double y[RPT], aw[RPT], rr[RPT];
+  load_quad(yk, r0, m, y);
+  load_quad(ctl.r, r0, m, rr);
+  if (k > 1) {
+    load_quad(ctl.aw, r0, m, aw);
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) aw[i] = fma(-th, aw[i], y[i]) * inv;
+  } else {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) aw[i] = y[i] * inv;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    rr[i] = fma(ph, aw[i], rr[i]);
+    acc = fma(rr[i], rr[i], acc);
+  }
+  if (r0 < m) {
+    store_quad(ctl.aw, r0, m, aw);
+    store_quad(ctl.r, r0, m, rr);
+  }
+  const double s = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) partials[b.id] = s;
+}
+
+// ---- start-up: r_0 = -b, partials of ||b||^2 ----
+template <typename T>
+__device__ inline void resid_init_body(const Ctl &ctl, const T *__restrict__ bv, long long m, double *partials, Blk b) {
+  __shared__ double lds[kBlock / 64];
+  const long long r0 = ((long long)b.id * kBlock + threadIdx.x) * RPT;
+  double y[RPT], rr[RPT];
+  load_quad(bv, r0, m, y);
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    rr[i] = -y[i];
+    acc = fma(y[i], y[i], acc);
+  }
+  if (r0 < m) store_quad(ctl.r, r0, m, rr);
+  const double s = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) partials[b.id] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_resid(Ctl ctl, const T *__restrict__ yk, long long m, double *partials) {
+  if (ctl.ip[CI_STOP]) return;
+  resid_body(ctl, yk, m, partials, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_resid_init(Ctl ctl, const T *__restrict__ bv, long long m,
+                                                       double *partials) {
+  resid_init_body(ctl, bv, m, partials, Blk{blockIdx.x, gridDim.x});
 }
 
 __global__ __launch_bounds__(kSolveThreads) void k_small_solve(Ctl ctl) {
@@ -451,30 +506,41 @@ __global__ __launch_bounds__(kBlock) void kb_norm_finalize(BatchDev<T> bd, int f
   norm_finalize_body(d.ctl, d.partials, (unsigned)(pre[a + 1] - pre[a]), which);
 }
 
-// gram == 0: Q^T w for reorthogonalisation (no columns when the slice does
-// not reorthogonalise); gram == 1: Gram row k of Y
+// Q^T w for reorthogonalisation (no columns when the slice does not
+// reorthogonalise)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void kb_dots(BatchDev<T> bd, int gram) {
+__global__ __launch_bounds__(kBlock) void kb_dots(BatchDev<T> bd) {
   Blk b;
-  const SliceDev<T> &d = slice_of(bd, gram ? BF_VM : BF_VQ, blockIdx.x, b);
+  const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
   if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
-  if (gram)
-    dots_body<T>(d.ctl, d.Y, d.ldy, nullptr, d.g.m, d.partials, 1, b.id, blockIdx.y, k + 1);
-  else
-    dots_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, d.partials, 0, b.id, blockIdx.y, d.reorth ? k : 0);
+  dots_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, d.partials, b.id, blockIdx.y, d.reorth ? k : 0);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void kb_reduce_cols(BatchDev<T> bd, int which) {
+__global__ __launch_bounds__(kBlock) void kb_reduce_cols(BatchDev<T> bd) {
   const int a = blockIdx.y;
   const SliceDev<T> &d = bd.sd[bd.active[a]];
   if (skip(bd, d)) return;
-  const int fam = which == 0 ? BF_VQ : BF_VM;
-  const int *pre = bd.pre + fam * (bd.na + 1);
+  const int *pre = bd.pre + BF_VQ * (bd.na + 1);
   const int k = d.ctl.ip[CI_K];
-  const int ncol = which == 0 ? (d.reorth ? k : 0) : k + 1;
-  reduce_cols_body(d.ctl, d.partials, pre[a + 1] - pre[a], which, blockIdx.x, ncol);
+  reduce_cols_body(d.ctl, d.partials, pre[a + 1] - pre[a], blockIdx.x, d.reorth ? k : 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_resid(BatchDev<T> bd) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_VM, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  resid_body<T>(d.ctl, d.yk, d.g.m, d.partials, b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_resid_init(BatchDev<T> bd) {
+  Blk b;
+  const SliceDev<T> &d = slice_of(bd, BF_VM, blockIdx.x, b);
+  if (skip(bd, d)) return;
+  resid_init_body<T>(d.ctl, d.b, d.g.m, d.partials, b);
 }
 
 template <typename T>
@@ -509,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void kb_solution(BatchDev<T> bd, int out_se
 }
 
 // Per-slice scalars for the host, 4 per slice.  phase 0: t_1, alpha_1,
-// ||b||^2; phase 1: k_stop, reason, rho[k_stop], pres[k_stop].
+// ||b||; phase 1: k_stop, reason, rho[k_stop], pres[k_stop].
 template <typename T>
 __global__ void kb_report(const SliceDev<T> *sd, int ns, int phase, double *out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -518,7 +584,7 @@ __global__ void kb_report(const SliceDev<T> *sd, int ns, int phase, double *out)
   if (phase == 0) {
     out[4 * s] = c.t[1];
     out[4 * s + 1] = c.alpha[1];
-    out[4 * s + 2] = c.G[0];
+    out[4 * s + 2] = c.dp[CD_BNORM];
     out[4 * s + 3] = 0.0;
   } else {
     const int ks = c.ip[CI_KSTOP];
@@ -564,8 +630,8 @@ void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long di
                      hipStream_t s) {
   const int nb = vec_blocks(dim);
   const dim3 grid(nb, (ctl.K + CH) / CH);
-  hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials, 0);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 1), dim3(kBlock), 0, s, ctl, (const double *)partials, nb, 0);
+  hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials);
+  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 1), dim3(kBlock), 0, s, ctl, (const double *)partials, nb);
 }
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
@@ -579,12 +645,16 @@ void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hi
   hipLaunchKernelGGL(k_normalize<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim);
 }
 template <typename T>
-void launch_gram(Ctl ctl, const T *Y, long long ld, long long dim, int init, double *partials, hipStream_t s) {
-  (void)init;
-  const int nb = vec_blocks(dim);
-  const dim3 grid(nb, (ctl.K + 1 + CH) / CH);
-  hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Y, ld, (const T *)nullptr, dim, partials, 1);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 2), dim3(kBlock), 0, s, ctl, (const double *)partials, nb, 1);
+void launch_resid_init(Ctl ctl, const T *b, long long m, double *partials, hipStream_t s) {
+  const int nb = vec_blocks(m);
+  hipLaunchKernelGGL(k_resid_init<T>, dim3(nb), dim3(kBlock), 0, s, ctl, b, m, partials);
+  launch_norm_finalize(ctl, partials, nb, NORM_BNORM, nullptr, s);
+}
+template <typename T>
+void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream_t s) {
+  const int nb = vec_blocks(m);
+  hipLaunchKernelGGL(k_resid<T>, dim3(nb), dim3(kBlock), 0, s, ctl, yk, m, partials);
+  launch_norm_finalize(ctl, partials, nb, NORM_RHO, ctl.ip + CI_STOP, s);
 }
 void launch_small_solve(Ctl ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl);
@@ -612,8 +682,8 @@ void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int
 template <typename T>
 void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
   if (bl.tot[BF_VQ] <= 0) return;
-  hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VQ], (bl.kmax + CH) / CH), dim3(kBlock), 0, s, bd, 0);
-  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 1, bl.na), dim3(kBlock), 0, s, bd, 0);
+  hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VQ], (bl.kmax + CH) / CH), dim3(kBlock), 0, s, bd);
+  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 1, bl.na), dim3(kBlock), 0, s, bd);
 }
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s) {
@@ -626,10 +696,16 @@ void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_
   if (bl.tot[BF_VQ] > 0) hipLaunchKernelGGL(kb_normalize<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd);
 }
 template <typename T>
-void launch_b_gram(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+void launch_b_resid(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
   if (bl.tot[BF_VM] <= 0) return;
-  hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VM], (bl.kmax + 1 + CH) / CH), dim3(kBlock), 0, s, bd, 1);
-  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 2, bl.na), dim3(kBlock), 0, s, bd, 1);
+  hipLaunchKernelGGL(kb_resid<T>, dim3(bl.tot[BF_VM]), dim3(kBlock), 0, s, bd);
+  launch_b_norm_finalize(bd, bl, BF_VM, NORM_RHO, s);
+}
+template <typename T>
+void launch_b_resid_init(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+  if (bl.tot[BF_VM] <= 0) return;
+  hipLaunchKernelGGL(kb_resid_init<T>, dim3(bl.tot[BF_VM]), dim3(kBlock), 0, s, bd);
+  launch_b_norm_finalize(bd, bl, BF_VM, NORM_BNORM, s);
 }
 template <typename T>
 void launch_b_small_solve(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
@@ -655,7 +731,8 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, hipStream_t, \
                                      int);                                                                  \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t);               \
-  template void launch_gram<T>(Ctl, const T *, long long, long long, int, double *, hipStream_t);          \
+  template void launch_resid<T>(Ctl, const T *, long long, double *, hipStream_t);                         \
+  template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
@@ -663,7 +740,8 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_b_cgs_dots<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                \
   template void launch_b_cgs_update<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);         \
   template void launch_b_normalize<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);               \
-  template void launch_b_gram<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                    \
+  template void launch_b_resid<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                   \
+  template void launch_b_resid_init<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);              \
   template void launch_b_small_solve<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);             \
   template void launch_b_solution<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);           \
   template void launch_b_set_k<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);              \

@@ -534,6 +534,27 @@ __device__ inline T at_fan_bins(const typename Pair<T>::v2 *__restrict__ yw, T d
   return part;
 }
 
+// As at_fan_bins with the first-order sine, delta = c1 d, and the offsets
+// scaled by c1: the first bin at distance dc1 = c1 d0.  Adds to acc.
+template <typename T, int CNT, int MAXC>
+__device__ inline T at_fan_bins_lin(const typename Pair<T>::v2 *__restrict__ yw, T dc1, T c1, int nrt, T acc) {
+  constexpr int NQ = CNT ? CNT : MAXC;
+  const int n = CNT ? CNT : nrt;
+  typename Pair<T>::v2 pw[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (q < n) pw[q] = yw[q];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < n) {
+      const T delta = q == 0 ? dc1 : fma(T(-q), c1, dc1);
+      const T wt = fma(-fabs(delta), pw[q].y, T(1));
+      acc = fma(fmax(wt, T(0)), pw[q].x, acc);
+    }
+  }
+  return acc;
+}
+
 template <typename T, bool FAN, int NC>
 __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                     const Epi<T> &e, Blk b) {
@@ -601,12 +622,22 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
           // delta = d (c1 + c3 d^2), c1 = |p - S| dg, c3 = -c1 dg^2 / 6, d = up - k
           const T dg = T(g.du);
           const T r2 = fma(a, a, bb * bb);
-          const T c1 = r2 * fast_rsq(r2) * dg, c3 = c1 * dg * dg * T(-1.0 / 6.0);
+          const T c1 = r2 * fast_rsq(r2) * dg;
           const T d0 = up - k0f;
-          acc += cnt == NC       ? at_fan_bins<T, NC, NC>(yw, d0, c1, c3, cnt)
-                 : cnt == NC - 1 ? at_fan_bins<T, NC - 1, NC>(yw, d0, c1, c3, cnt)
-                 : cnt == NC - 2 ? at_fan_bins<T, (NC > 2 ? NC - 2 : 0), NC>(yw, d0, c1, c3, cnt)
-                                 : at_fan_bins<T, 0, NC>(yw, d0, c1, c3, cnt);
+          if (g.at_fast) {
+            // sin(x) = x over the window (relative error within 1e-6)
+            const T dc1 = d0 * c1;
+            acc = cnt == NC       ? at_fan_bins_lin<T, NC, NC>(yw, dc1, c1, cnt, acc)
+                  : cnt == NC - 1 ? at_fan_bins_lin<T, NC - 1, NC>(yw, dc1, c1, cnt, acc)
+                  : cnt == NC - 2 ? at_fan_bins_lin<T, (NC > 2 ? NC - 2 : 0), NC>(yw, dc1, c1, cnt, acc)
+                                  : at_fan_bins_lin<T, 0, NC>(yw, dc1, c1, cnt, acc);
+          } else {
+            const T c3 = c1 * dg * dg * T(-1.0 / 6.0);
+            acc += cnt == NC       ? at_fan_bins<T, NC, NC>(yw, d0, c1, c3, cnt)
+                   : cnt == NC - 1 ? at_fan_bins<T, NC - 1, NC>(yw, d0, c1, c3, cnt)
+                   : cnt == NC - 2 ? at_fan_bins<T, (NC > 2 ? NC - 2 : 0), NC>(yw, d0, c1, c3, cnt)
+                                   : at_fan_bins<T, 0, NC>(yw, d0, c1, c3, cnt);
+          }
         } else {
           const typename Pair<T>::v2 *cs = reinterpret_cast<const typename Pair<T>::v2 *>(vt.gcos) + k0;
 #pragma unroll
