@@ -209,8 +209,14 @@ gkb_status gkb_net_train_step(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g,
 
 /* Kernel timing.  While enabled, every launch of the named kernels is
  * bracketed by HIP events on the context's stream; gkb_trace_get returns the
- * launch count and summed device milliseconds since the last reset. */
+ * launch count and summed device milliseconds since the last reset.  Each
+ * event pair costs the stream a few microseconds between launches.
+ * gkb_trace_only restricts the recording to one kernel name (NULL or "":
+ * every kernel again).  Names: "fwd" (A), "back" (B), "fwd_adj" (A^T),
+ * "back_adj" (B^T), "reorth", "small_solve", "residual", "filter",
+ * "filter_t". */
 gkb_status gkb_trace_enable(gkb_ctx *ctx, int on);
+gkb_status gkb_trace_only(gkb_ctx *ctx, const char *kernel);
 gkb_status gkb_trace_reset(gkb_ctx *ctx);
 gkb_status gkb_trace_get(gkb_ctx *ctx, const char *kernel, int *count, double *total_ms);
 

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "GKB_OK", -1: "GKB_EINVAL", -2: "GKB_ENOMEM", -3: "GKB_EDEVIC
                 -5: "GKB_EUNSUPPORTED"}
 EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gkb_forward", "gkb_back",
             "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve",
-            "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
+            "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_only", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
             "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step")
 NET_PARAMS = 19008
@@ -106,6 +106,7 @@ def lib() -> ctypes.CDLL:
         L.gkb_net_train_step.argtypes = [vp, vp, G, cp, vp, vp, cp, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double)]
         L.gkb_trace_enable.argtypes = [vp, cp]
+        L.gkb_trace_only.argtypes = [vp, ctypes.c_char_p]
         L.gkb_trace_reset.argtypes = [vp]
         L.gkb_trace_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(cp), ctypes.POINTER(ctypes.c_double)]
         _lib = L
@@ -184,6 +185,10 @@ class Context:
     # ---- tracing ----
     def trace_enable(self, on: bool = True):
         _check(lib().gkb_trace_enable(self.handle, 1 if on else 0))
+
+    def trace_only(self, kernel: Optional[str]):
+        """Record only `kernel` while tracing (None: every kernel)."""
+        _check(lib().gkb_trace_only(self.handle, kernel.encode() if kernel else None))
 
     def trace_reset(self):
         _check(lib().gkb_trace_reset(self.handle))

@@ -638,6 +638,7 @@ struct gkb_ctx {
   DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ny;
   // tracing
   bool trace = false;
+  std::string trace_only;  // non-empty: record only this kernel name
   std::map<std::string, TraceStat> stats;
   std::vector<hipEvent_t> event_pool;
 
@@ -674,7 +675,7 @@ struct TraceScope {
   const char *name;
   hipEvent_t a = nullptr;
   TraceScope(gkb_ctx *ctx, const char *n) : c(ctx), name(n) {
-    if (c->trace) {
+    if (c->trace && (c->trace_only.empty() || c->trace_only == n)) {
       a = c->get_event();
       (void)hipEventRecord(a, c->stream);
     }
@@ -1167,7 +1168,8 @@ struct Solver {
     HIPC(c->ctl_i.ensure(sizeof(int) * CI_COUNT));
     const long long vb = std::max<long long>(
         {(long long)vec_blocks(dimq), (long long)vec_blocks(m), (long long)vec_blocks(dims)});
-    const long long pb = std::max<long long>({(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2)});
+    const long long pb = std::max<long long>(
+        {(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2), (long long)upd_blocks(dimq)});
     gkb_status stt = ensure_scratch(c, g, sizeof(T), pb);
     if (stt != GKB_OK) return stt;
     if (!c->host_flag) {
@@ -1611,6 +1613,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.cnt[BF_RAY] = ray_blocks(g);
     h.cnt[BF_PIX] = pixel_blocks(g);
     h.cnt[BF_VQ] = vec_blocks(h.dimq);
+    h.cnt[BF_VQU] = upd_blocks(h.dimq);
     h.cnt[BF_VM] = vec_blocks(g.m);
     h.cnt[BF_PADR] = (int)std::min<long long>(((long long)g.ny * g.ldR + 255) / 256, 2048);
     h.cnt[BF_PADC] = d->has_coldom ? ((g.ldT + 31) / 32) * ((g.nx + 31) / 32) : 0;
@@ -1636,6 +1639,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.opart = ndbl;
     ndbl += (size_t)std::max<long long>(
         {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
+         (long long)h.cnt[BF_VQU],
          (long long)h.cnt[BF_VM] * (h.K + 2), 1024LL});
     ndbl = (ndbl + 31) / 32 * 32;
   }
@@ -2184,6 +2188,11 @@ gkb_status gkb_net_train_step(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, i
 gkb_status gkb_trace_enable(gkb_ctx *c, int on) {
   if (!c) return fail(GKB_EINVAL, "context is NULL");
   c->trace = on != 0;
+  return GKB_OK;
+}
+gkb_status gkb_trace_only(gkb_ctx *c, const char *kernel) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  c->trace_only = kernel ? kernel : "";
   return GKB_OK;
 }
 gkb_status gkb_trace_reset(gkb_ctx *c) {

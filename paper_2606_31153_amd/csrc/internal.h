@@ -226,6 +226,7 @@ enum BlockFam : int {
   BF_PADR,     // row-major image padding
   BF_PADC,     // column-major image padding (32x32 tiles)
   BF_PADS,     // sinogram padding
+  BF_VQU,      // CGS update over Q's dimension (upd_blocks)
   BF_COUNT
 };
 
@@ -305,6 +306,7 @@ int cone_voxel_blocks(const GeomDev &g);
 
 // ---- Krylov vector kernels (krylov.hip) ----
 int vec_blocks(long long dim);
+int upd_blocks(long long dim);  // workgroups of the CGS update
 template <typename T>
 void launch_copy(const T *src, T *dst, long long n, hipStream_t s);
 template <typename T>

@@ -146,11 +146,80 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *_
   reduce_cols_body(ctl, partials, nb, blockIdx.x, ctl.ip[CI_K]);
 }
 
-// ---- w -= Q[:, 0..k-1] c (FP64 per element); last == 1: partials of ||w||^2
-// (alpha[k+1] = ||w|| by the finalising kernel) ----
+// Wavefronts that share the rows of a CGS update workgroup (and split its
+// columns): 4 for vectors of up to 2^19 entries, whose workgroups would
+// otherwise be too few to keep HBM busy, else 1.
+__host__ __device__ inline int upd_split(long long dim) { return dim <= (1LL << 19) ? 4 : 1; }
+
+// ---- w -= Q[:, 0..ncols-1] c (FP64 per element); last == 1: partials of
+// ||w||^2 (alpha[k+1] = ||w|| by the finalising kernel).  The four wavefronts
+// of a workgroup form groups of `split` that share 256 rows (4 per lane); the
+// members of a group sum a share of the columns each, added in LDS in a fixed
+// order. ----
 template <typename T>
-__device__ inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q, long long ld, T *__restrict__ w,
-                                       long long dim, int last, double *partials, Blk b, int ncols) {
+__device__ __attribute__((always_inline)) inline void cgs_update_split(const Ctl &ctl, const T *__restrict__ Q,
+                                                                      long long ld, T *__restrict__ w, long long dim,
+                                                                      int last, double *partials, Blk b, int ncols) {
+  constexpr int NW = kBlock / 64;
+  __shared__ double part[NW - 1][64 * RPT];
+  __shared__ double lds[NW];
+  const double *__restrict__ cc = ctl.c;
+  const int split = upd_split(dim), groups = NW / split;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int grp = wid / split, mem = wid - grp * split;
+  const long long r = (((long long)b.id * groups + grp) * 64 + lane) * RPT;
+  const int per = (ncols + split - 1) / split;
+  const int j0 = mem * per, j1 = min(ncols, j0 + per);
+  // the leading member starts from w, the others from 0
+  double acc[RPT] = {0.0, 0.0, 0.0, 0.0};
+  if (mem == 0) load_quad(w, r, dim, acc);
+  for (int c0 = j0; c0 < j1; c0 += CH) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if (c0 + j < j1) {
+        double q[RPT];
+        load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
+        const double cj = cc[c0 + j];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) acc[i] = fma(-cj, q[i], acc[i]);
+      }
+    }
+  }
+  if (split > 1) {
+    const int slot = grp * (split - 1) + mem - 1;  // LDS slot of a non-leading member
+    if (mem > 0) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) part[slot][lane * RPT + i] = acc[i];
+    }
+    __syncthreads();
+    if (mem == 0) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        for (int v = 1; v < split; ++v) acc[i] += part[grp * (split - 1) + v - 1][lane * RPT + i];
+    }
+  }
+  double nrm = 0.0;
+  if (mem == 0) {
+    T out[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      out[i] = (T)acc[i];
+      nrm = fma((double)out[i], (double)out[i], nrm);
+    }
+    if (r < dim) store_quad(w, r, dim, out);
+  }
+  if (last) {
+    const double s = block_sum<kBlock>(nrm, lds);
+    if (threadIdx.x == 0) partials[b.id] = s;
+  }
+}
+
+// ---- w -= Q[:, 0..ncols-1] c (FP64 per element), each lane 4 rows and
+// every column; last == 1: partials of ||w||^2 ----
+template <typename T>
+__device__ __attribute__((always_inline)) inline void cgs_update_rows(const Ctl &ctl, const T *__restrict__ Q,
+                                                                      long long ld, T *__restrict__ w, long long dim,
+                                                                      int last, double *partials, Blk b, int ncols) {
   __shared__ double lds[kBlock / 64];
   const double *__restrict__ cc = ctl.c;
   const long long r = ((long long)b.id * kBlock + threadIdx.x) * RPT;
@@ -180,6 +249,16 @@ __device__ inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q, 
     const double s = block_sum<kBlock>(nrm, lds);
     if (threadIdx.x == 0) partials[b.id] = s;
   }
+}
+
+template <typename T>
+__device__ __attribute__((always_inline)) inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q,
+                                                                      long long ld, T *__restrict__ w, long long dim,
+                                                                      int last, double *partials, Blk b, int ncols) {
+  if (upd_split(dim) > 1)
+    cgs_update_split(ctl, Q, ld, w, dim, last, partials, b, ncols);
+  else
+    cgs_update_rows(ctl, Q, ld, w, dim, last, partials, b, ncols);
 }
 
 // reorth == 0: no columns, only the partials of ||w||^2 (with last == 1)
@@ -546,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void kb_resid_init(BatchDev<T> bd) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void kb_cgs_update(BatchDev<T> bd, int last) {
   Blk b;
-  const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
+  const SliceDev<T> &d = slice_of(bd, BF_VQU, blockIdx.x, b);
   if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
   cgs_update_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, last, d.partials, b, d.reorth ? k : 0);
@@ -611,6 +690,10 @@ int vec_blocks(long long dim) {
   long long b = (dim + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
   return (int)std::max<long long>(b, 1);
 }
+int upd_blocks(long long dim) {
+  const long long rows = 64LL * RPT * (kBlock / 64 / upd_split(dim));
+  return (int)std::max<long long>((dim + rows - 1) / rows, 1);
+}
 
 template <typename T>
 void launch_copy(const T *src, T *dst, long long n, hipStream_t s) {
@@ -636,7 +719,7 @@ void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long di
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        hipStream_t s, int reorth) {
-  const int nb = vec_blocks(dim);
+  const int nb = upd_blocks(dim);
   hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, reorth);
   if (last) launch_norm_finalize(ctl, partials, nb, NORM_ALPHA1, ctl.ip + CI_STOP, s);
 }
@@ -687,9 +770,9 @@ void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t
 }
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s) {
-  if (bl.tot[BF_VQ] <= 0) return;
-  hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQ]), dim3(kBlock), 0, s, bd, last);
-  if (last) launch_b_norm_finalize(bd, bl, BF_VQ, NORM_ALPHA1, s);
+  if (bl.tot[BF_VQU] <= 0) return;
+  hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQU]), dim3(kBlock), 0, s, bd, last);
+  if (last) launch_b_norm_finalize(bd, bl, BF_VQU, NORM_ALPHA1, s);
 }
 template <typename T>
 void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
