@@ -80,7 +80,7 @@ struct HostTables {
   std::vector<double> p0, p1, p2, p3, p4;
   // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
   std::vector<double> gcs;
-  // fan A^T: per (32x8 pixel tile, view) bound of the candidate half-width, [tile][view]
+  // fan A^T: per (32x4 pixel tile, view) bound of the candidate half-width, [tile][view]
   std::vector<double> htile;
   bool has_coldom = false;
   double min_along = 1e300;  // fan: smallest source distance of a B^T crossing
@@ -140,7 +140,7 @@ void line_range(double c_mid, double slope, double mid, int nlines, double cmin,
 // Fan-beam A^T: a pixel p gets a nonzero weight from the bins k with
 // |g_p - g_k| < asin(|d_dom,k| / |p - S|) (Joseph's weight as a function of the
 // fan angle); the kernel bounds |d_dom,k| by the pixel's own ray's plus the fan
-// spread of the candidates, and asin(z) by z (1 + z^2).  Per 32x8 tile of
+// spread of the candidates, and asin(z) by z (1 + z^2).  Per 32x4 tile of
 // pixel centres and per view, the largest such half-width (in bins) over the
 // tile follows from the tile's nearest point to the source (largest 1/|p - S|)
 // and the largest max(|cos|, |sin|) of the directions from the source to the
@@ -150,7 +150,7 @@ void line_range(double c_mid, double slope, double mid, int nlines, double cmin,
 void fan_tile_halfwidths(const gkb_geometry *g, const std::vector<double> &ang, HostTables &t) {
   const GeomDev &gd = t.gd;
   const int nx = g->nx, ny = g->ny, nv = g->n_views;
-  const int tx_n = (nx + 31) / 32, ty_n = (ny + 7) / 8;
+  const int tx_n = (nx + kPixTileX - 1) / kPixTileX, ty_n = (ny + kPixTileY - 1) / kPixTileY;
   const double midx = 0.5 * (nx - 1), midy = 0.5 * (ny - 1);
   const double quarter = 0.5 * M_PI;
   t.htile.assign((size_t)tx_n * ty_n * nv, 0.0);
@@ -159,8 +159,8 @@ void fan_tile_halfwidths(const gkb_geometry *g, const std::vector<double> &ang, 
     for (int ty = 0; ty < ty_n; ++ty)
       for (int tx = 0; tx < tx_n; ++tx) {
         // rectangle of the tile's pixel centres
-        const double x0 = tx * 32 - midx, x1 = std::min(tx * 32 + 31, nx - 1) - midx;
-        const double y0 = ty * 8 - midy, y1 = std::min(ty * 8 + 7, ny - 1) - midy;
+        const double x0 = tx * kPixTileX - midx, x1 = std::min(tx * kPixTileX + kPixTileX - 1, nx - 1) - midx;
+        const double y0 = ty * kPixTileY - midy, y1 = std::min(ty * kPixTileY + kPixTileY - 1, ny - 1) - midy;
         const double dx = std::max({x0 - Sx, 0.0, Sx - x1}), dy = std::max({y0 - Sy, 0.0, Sy - y1});
         const double rinv = 1.0 / std::sqrt(dx * dx + dy * dy);
         // directions from the source to the corners, as angles about the

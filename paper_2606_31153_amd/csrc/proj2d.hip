@@ -14,9 +14,10 @@
 //    column-stepping rays both read along one padded line, every tap is in
 //    bounds without a test, and the two taps of a crossing are one 8-byte
 //    load addressed by a 32-bit offset from a uniform base.
-//  * pixel-driven kernels (B, A^T): one thread per pixel, 32x8 pixel tiles
-//    per 256-thread workgroup, loop over views; per-view constants are
-//    uniform across the workgroup (scalar loads).  They read a zero-padded
+//  * pixel-driven kernels (B, A^T): a 256-thread workgroup per 32x4 pixel
+//    tile, two threads per pixel (even and odd views, summed through LDS),
+//    each looping over its views; per-view constants are uniform across a
+//    wavefront (scalar loads).  They read a zero-padded
 //    copy of the sinogram; the detector coordinate is clamped into the padded
 //    range (taps outside the detector read zeros).
 //  * gathers only: every output element is written by one thread, the sum
@@ -388,18 +389,36 @@ __global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, co
 // ---------------------------------------------------------------------------
 // pixel-driven: B (back projection by linear interpolation on the detector)
 // ---------------------------------------------------------------------------
-__device__ inline void tile_pixel(const GeomDev &g, unsigned blk, int &i, int &j) {
-  const int tiles_x = (g.nx + 31) >> 5;
+// Pixel of this thread in tile blk, and the thread's view group.
+__device__ inline int tile_pixel(const GeomDev &g, unsigned blk, int &i, int &j) {
+  const int tiles_x = (g.nx + kPixTileX - 1) / kPixTileX;
   const int tx = (int)blk % tiles_x, ty = (int)blk / tiles_x;
-  i = tx * 32 + (threadIdx.x & 31);
-  j = ty * 8 + (threadIdx.x >> 5);
+  constexpr int tpix = kPixTileX * kPixTileY;
+  i = tx * kPixTileX + (int)(threadIdx.x % kPixTileX);
+  j = ty * kPixTileY + (int)((threadIdx.x % tpix) / kPixTileX);
+  return (int)(threadIdx.x / tpix);
+}
+
+// Sum of the view groups' partial sums of a pixel, in group order, returned
+// to group 0 (other groups get 0).  Every thread of the workgroup calls it.
+template <typename T>
+__device__ inline T gather_view_groups(T acc) {
+  constexpr int tpix = kPixTileX * kPixTileY;
+  __shared__ T xch[(kViewGroups - 1) * tpix];
+  const int grp = (int)(threadIdx.x / tpix), pix = (int)(threadIdx.x % tpix);
+  if (grp > 0) xch[(grp - 1) * tpix + pix] = acc;
+  __syncthreads();
+  if (grp > 0) return T(0);
+#pragma unroll
+  for (int q = 1; q < kViewGroups; ++q) acc += xch[(q - 1) * tpix + pix];
+  return acc;
 }
 
 template <typename T, bool FAN>
 __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                  const Epi<T> &e, Blk b) {
   int i, j;
-  tile_pixel(g, b.id, i, j);
+  const int grp = tile_pixel(g, b.id, i, j);
   const bool valid = i < g.nx && j < g.ny;
   T acc = T(0);
   if (valid) {
@@ -407,52 +426,54 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
     const T py = T(j) - T(0.5) * T(g.ny - 1);
     const T off = T(g.off);
     const T ulo = T(-2), uhi = T(g.nu + 1);
+    // this group's views: grp, grp + VS, ...
+    constexpr int VS = kViewGroups;
     const unsigned ldY = (unsigned)g.ldY;
-    unsigned roff = (unsigned)g.padY;
+    unsigned roff = (unsigned)g.padY + (unsigned)grp * ldY;
     if (!FAN) {
       T a[4] = {T(0), T(0), T(0), T(0)};
-      int v = 0;
-      for (; v + 3 < g.nv; v += 4) {
+      int v = grp;
+      for (; v + 3 * VS < g.nv; v += 4 * VS) {
         T u[4], fl[4];
         typename Pair<T>::v2 p[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          u[q] = fmin(fmax(fma(px, vt.p0[v + q], fma(py, vt.p1[v + q], off)), ulo), uhi);
+          u[q] = fmin(fmax(fma(px, vt.p0[v + q * VS], fma(py, vt.p1[v + q * VS], off)), ulo), uhi);
           fl[q] = floor(u[q]);
-          p[q] = load_pair(ypad + (roff + (unsigned)q * ldY + (unsigned)(int)fl[q]));
+          p[q] = load_pair(ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)fl[q]));
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[q] += fma(u[q] - fl[q], p[q].y - p[q].x, p[q].x);
-        roff += 4u * ldY;
+        roff += (unsigned)(4 * VS) * ldY;
       }
-      for (; v < g.nv; ++v) {
+      for (; v < g.nv; v += VS) {
         const T u0 = fmin(fmax(fma(px, vt.p0[v], fma(py, vt.p1[v], off)), ulo), uhi);
         const T f0l = floor(u0);
         const auto p0 = load_pair(ypad + (roff + (unsigned)(int)f0l));
         a[0] += fma(u0 - f0l, p0.y - p0.x, p0.x);
-        roff += ldY;
+        roff += (unsigned)VS * ldY;
       }
       acc = (a[0] + a[1]) + (a[2] + a[3]);
     } else {
       const T D = T(g.D), inv_dg = T(g.inv_du);
       const bool fast = g.fast_atan != 0;
       T a0 = T(0), a1 = T(0);
-      int v = 0;
-      for (; v + 1 < g.nv; v += 2) {
+      int v = grp;
+      for (; v + VS < g.nv; v += 2 * VS) {
         T u[2], fl[2];
         typename Pair<T>::v2 p[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const T cb = vt.p0[v + q], sb = vt.p1[v + q];
+          const T cb = vt.p0[v + q * VS], sb = vt.p1[v + q * VS];
           const T a = D - fma(px, cb, py * sb);
           const T bb = fma(px, sb, -py * cb);
           u[q] = fmin(fmax(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo), uhi);
           fl[q] = floor(u[q]);
-          p[q] = load_pair(ypad + (roff + (unsigned)q * ldY + (unsigned)(int)fl[q]));
+          p[q] = load_pair(ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)fl[q]));
         }
         a0 += fma(u[0] - fl[0], p[0].y - p[0].x, p[0].x);
         a1 += fma(u[1] - fl[1], p[1].y - p[1].x, p[1].x);
-        roff += 2u * ldY;
+        roff += (unsigned)(2 * VS) * ldY;
       }
       if (v < g.nv) {
         const T cb = vt.p0[v], sb = vt.p1[v];
@@ -466,7 +487,9 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
       acc = a0 + a1;
     }
   }
-  epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo, b);
+  acc = gather_view_groups(acc);
+  const bool own = valid && grp == 0;
+  epilogue(e, own ? (long long)j * g.nx + i : 0, own, acc, xo, b);
 }
 
 template <typename T, bool FAN>
@@ -559,20 +582,22 @@ template <typename T, bool FAN, int NC>
 __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                     const Epi<T> &e, Blk b) {
   int i, j;
-  tile_pixel(g, b.id, i, j);
+  const int grp = tile_pixel(g, b.id, i, j);
   const bool valid = i < g.nx && j < g.ny;
   T acc = T(0);
   const T px = T(i) - T(0.5) * T(g.nx - 1);
   const T py = T(j) - T(0.5) * T(g.ny - 1);
   const T off = T(g.off);
+  // this group's views: grp, grp + VS, ...
+  constexpr int VS = kViewGroups;
   const unsigned ldY = (unsigned)g.ldY;
-  unsigned roff = (unsigned)g.padY;
+  unsigned roff = (unsigned)g.padY + (unsigned)grp * ldY;
   // bins farther than the candidate half-width from the detector have zero
   // weight; the clamp keeps every candidate inside the padded row
   const T ulo = -T(g.uclamp_at), uhi = T(g.nu - 1) + T(g.uclamp_at);
   if (!FAN) {
     if (valid) {
-      for (int v = 0; v < g.nv; ++v) {
+      for (int v = grp; v < g.nv; v += VS) {
         T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
         u = fmin(fmax(u, ulo), uhi);
         const T w = vt.p2[v], slope = vt.p3[v], h = vt.p4[v];
@@ -586,7 +611,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
                        : cv == NC - 1 ? at_par_bins<T, NC - 1, NC>(row, d0, slope, cv)
                                       : at_par_bins<T, 0, NC>(row, d0, slope, cv);
         acc = fma(w, part, acc);
-        roff += ldY;
+        roff += (unsigned)VS * ldY;
       }
     }
   } else {
@@ -594,18 +619,20 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
     // pads); vt.gcos holds (cos g_k, sin g_k) per padded bin.  The candidate
     // window of every pixel of the tile is floor(2H) + 1 bins from ceil(u_p - H),
     // H the tile's half-width bound for the view, which a lane of the wavefront
-    // holds for 64 views at a time.  Every lane runs the loop (pixels outside
-    // the image too: the clamp keeps their reads inside the padded rows, and
-    // their sums are discarded).
+    // holds for 64 of the group's views at a time.  Every lane runs the loop
+    // (pixels outside the image too: the clamp keeps their reads inside the
+    // padded rows, and their sums are discarded).
     const T D = T(g.D), inv_dg = T(g.inv_du);
     const bool fast = g.fast_atan != 0;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ ht = vt.htile + (long long)b.id * g.nv;
-    for (int v0 = 0; v0 < g.nv; v0 += 64) {
-      const T hl = (v0 + lane < g.nv) ? ht[v0 + lane] : T(0);
-      const int vend = min(g.nv, v0 + 64);
-      for (int v = v0; v < vend; ++v) {
-        const T H = lane_value(hl, v - v0);
+    const int nvg = (g.nv - grp + VS - 1) / VS;  // views of this group
+    for (int t0 = 0; t0 < nvg; t0 += 64) {
+      const T hl = (t0 + lane < nvg) ? ht[grp + VS * (t0 + lane)] : T(0);
+      const int tend = min(nvg, t0 + 64);
+      for (int t = t0; t < tend; ++t) {
+        const int v = grp + VS * t;
+        const T H = lane_value(hl, t - t0);
         const int cnt = min((int)floor(T(2) * H) + 1, NC);
         const T cb = vt.p0[v], sb = vt.p1[v];
         const T a = D - fma(px, cb, py * sb);
@@ -651,12 +678,14 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
             }
           }
         }
-        roff += ldY;
+        roff += (unsigned)VS * ldY;
       }
     }
     if (!valid) acc = T(0);
   }
-  epilogue(e, valid ? (long long)j * g.nx + i : 0, valid, acc, xo, b);
+  acc = gather_view_groups(acc);
+  const bool own = valid && grp == 0;
+  epilogue(e, own ? (long long)j * g.nx + i : 0, own, acc, xo, b);
 }
 
 template <typename T, bool FAN, int NC>
@@ -766,7 +795,8 @@ __global__ __launch_bounds__(kBlock) void kb_fwd_adj(BatchDev<T> bd, int out_sel
 }  // namespace
 
 int pixel_blocks(const GeomDev &g) {
-  return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * (g.kind == 2 ? g.nz : 1);
+  if (g.kind == 2) return ((g.nx + 31) / 32) * ((g.ny + 7) / 8) * g.nz;
+  return ((g.nx + kPixTileX - 1) / kPixTileX) * ((g.ny + kPixTileY - 1) / kPixTileY);
 }
 // Grid of the ray-driven kernels: B^T takes workgroups of 64 bins x 4 views,
 // A the same count of workgroups over consecutive rays (256 per workgroup;
