@@ -80,7 +80,7 @@ struct HostTables {
   std::vector<double> p0, p1, p2, p3, p4;
   // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
   std::vector<double> gcs;
-  // fan A^T: per (32x4 pixel tile, view) bound of the candidate half-width, [tile][view]
+  // fan A^T: per (32x2 pixel tile, view) bound of the candidate half-width, [tile][view]
   std::vector<double> htile;
   bool has_coldom = false;
   double min_along = 1e300;  // fan: smallest source distance of a B^T crossing
@@ -140,7 +140,7 @@ void line_range(double c_mid, double slope, double mid, int nlines, double cmin,
 // Fan-beam A^T: a pixel p gets a nonzero weight from the bins k with
 // |g_p - g_k| < asin(|d_dom,k| / |p - S|) (Joseph's weight as a function of the
 // fan angle); the kernel bounds |d_dom,k| by the pixel's own ray's plus the fan
-// spread of the candidates, and asin(z) by z (1 + z^2).  Per 32x4 tile of
+// spread of the candidates, and asin(z) by z (1 + z^2).  Per 32x2 tile of
 // pixel centres and per view, the largest such half-width (in bins) over the
 // tile follows from the tile's nearest point to the source (largest 1/|p - S|)
 // and the largest max(|cos|, |sin|) of the directions from the source to the

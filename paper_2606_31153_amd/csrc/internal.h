@@ -12,7 +12,7 @@ constexpr int kBlock = 256;
 // Pixel-driven 2D kernels: a workgroup covers a kPixTileX x kPixTileY pixel
 // tile with kViewGroups groups of threads, group g taking the views
 // g, g + kViewGroups, ...; the groups' sums meet in LDS.
-constexpr int kPixTileX = 32, kPixTileY = 4, kViewGroups = 2;
+constexpr int kPixTileX = 32, kPixTileY = 2, kViewGroups = 4;
 static_assert(kPixTileX * kPixTileY * kViewGroups == kBlock, "pixel tile must fill the workgroup");
 
 // Integer fields of the device control block.
@@ -120,7 +120,7 @@ struct ViewTab {       // per view (pixel-driven kernels B, A^T)
   const T *p3;         // PAR: du/|d_dom| (A^T hat slope in bins)
   const T *p4;         // PAR: |d_dom|/du (A^T hat half-width in bins)
   const T *gcos;       // FAN: (cos(gamma_k), sin(gamma_k)) pairs, padded like a sinogram row [2 (n_det + 2 padY)]
-  const T *htile;      // FAN: A^T candidate half-width bound per (32x4 pixel tile, view), [tile][view]
+  const T *htile;      // FAN: A^T candidate half-width bound per (32x2 pixel tile, view), [tile][view]
 };
 
 struct GeomDev {
@@ -225,7 +225,7 @@ struct SliceDev {
 // is the launch's total.
 enum BlockFam : int {
   BF_RAY = 0,  // ray-driven projectors: ceil(m / 256)
-  BF_PIX,      // pixel-driven projectors: 32x4 tiles (2D), 32x8 (cone)
+  BF_PIX,      // pixel-driven projectors: 32x2 tiles (2D), 32x8 (cone)
   BF_VQ,       // vector kernels over Q's dimension
   BF_VM,       // vector kernels over m
   BF_PADR,     // row-major image padding

@@ -14,10 +14,10 @@
 //    column-stepping rays both read along one padded line, every tap is in
 //    bounds without a test, and the two taps of a crossing are one 8-byte
 //    load addressed by a 32-bit offset from a uniform base.
-//  * pixel-driven kernels (B, A^T): a 256-thread workgroup per 32x4 pixel
-//    tile, two threads per pixel (even and odd views, summed through LDS),
-//    each looping over its views; per-view constants are uniform across a
-//    wavefront (scalar loads).  They read a zero-padded
+//  * pixel-driven kernels (B, A^T): a 256-thread workgroup per 32x2 pixel
+//    tile, four threads per pixel (views of one residue mod 4 each, summed
+//    through LDS), each looping over its views; per-view constants are
+//    uniform across a wavefront (scalar loads).  They read a zero-padded
 //    copy of the sinogram; the detector coordinate is clamped into the padded
 //    range (taps outside the detector read zeros).
 //  * gathers only: every output element is written by one thread, the sum
