@@ -30,6 +30,14 @@ __device__ inline double fast_rcp(double x) { return 1.0 / x; }
 __device__ inline float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double fast_rsq(double x) { return 1.0 / sqrt(x); }
 
+// max(w, 0) for a weight w <= 1 (every hat weight 1 - |x| s with s >= 0):
+// written as a clamp to [0, 1], which the compiler folds into the clamp bit
+// of the instruction that forms w
+template <typename T>
+__device__ inline T hat_clamp(T w) {
+  return fmin(fmax(w, T(0)), T(1));
+}
+
 // value of v in lane l of the wavefront (l uniform)
 __device__ inline float lane_value(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));

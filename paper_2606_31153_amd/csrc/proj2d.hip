@@ -298,7 +298,7 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
       for (int q = 0; q < NQ; ++q) {
         if (q < n) {
           const T wt = fma(-fabs(d0 + T(q)), inv_h, T(1));
-          acc = fma(fmax(wt, T(0)), v[q], acc);
+          acc = fma(hat_clamp(wt), v[q], acc);
         }
       }
     } else {
@@ -315,7 +315,7 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
             const T d = d0 + T(q);
             const T gq = fma(fma(a2, d, a1), d, kz);
             const T wt = fma(-fabs(d), gq, T(1));
-            acc = fma(fmax(wt, T(0)), v[q], acc);
+            acc = fma(hat_clamp(wt), v[q], acc);
           }
         }
       } else {
@@ -326,7 +326,7 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
             // tangent of the angle between the ray and the pixel, seen from the source
             const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
             const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
-            acc = fma(fmax(wt, T(0)), v[q], acc);
+            acc = fma(hat_clamp(wt), v[q], acc);
           }
         }
       }
@@ -526,7 +526,7 @@ __device__ inline T at_par_bins(const T *__restrict__ row, T d0, T slope, int nr
   for (int q = 0; q < NQ; ++q) {
     if (q < n) {
       const T wt = fma(-fabs(d0 - T(q)), slope, T(1));
-      part = fma(fmax(wt, T(0)), yv[q], part);
+      part = fma(hat_clamp(wt), yv[q], part);
     }
   }
   return part;
@@ -551,7 +551,7 @@ __device__ inline T at_fan_bins(const typename Pair<T>::v2 *__restrict__ yw, T d
       const T d = d0 - T(q);
       const T delta = d * fma(c3, d * d, c1);
       const T wt = fma(-fabs(delta), pw[q].y, T(1));
-      part = fma(fmax(wt, T(0)), pw[q].x, part);
+      part = fma(hat_clamp(wt), pw[q].x, part);
     }
   }
   return part;
@@ -572,7 +572,7 @@ __device__ inline T at_fan_bins_lin(const typename Pair<T>::v2 *__restrict__ yw,
     if (q < n) {
       const T delta = q == 0 ? dc1 : fma(T(-q), c1, dc1);
       const T wt = fma(-fabs(delta), pw[q].y, T(1));
-      acc = fma(fmax(wt, T(0)), pw[q].x, acc);
+      acc = fma(hat_clamp(wt), pw[q].x, acc);
     }
   }
   return acc;
@@ -674,7 +674,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
               const auto pq = yw[q];
               const T delta = fma(bb, gq.x, -a * gq.y);
               const T wt = fma(-fabs(delta), pq.y, T(1));
-              acc = fma(fmax(wt, T(0)), pq.x, acc);
+              acc = fma(hat_clamp(wt), pq.x, acc);
             }
           }
         }
