@@ -204,8 +204,8 @@ __device__ inline void cone_fwd_body(const GeomDev &g, const ConeTab<T> &ct, con
       T s[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const T p1 = fmin(fmax(fma(tf + T(u), slope1, base1), c1lo), c1hi);
-        const T p2 = fmin(fmax(fma(tf + T(u), slope2, base2), c2lo), c2hi);
+        const T p1 = clampv(fma(tf + T(u), slope1, base1), c1lo, c1hi);
+        const T p2 = clampv(fma(tf + T(u), slope2, base2), c2lo, c2hi);
         const T f1 = floor(p1), f2 = floor(p2);
         const unsigned o = poff + (unsigned)u * plane + (unsigned)((int)f2 * ld + (int)f1);
         const auto pa = load_pair(vol + o);
@@ -220,8 +220,8 @@ __device__ inline void cone_fwd_body(const GeomDev &g, const ConeTab<T> &ct, con
       poff += 2u * plane;
     }
     if (t <= hi) {
-      const T p1 = fmin(fmax(fma(tf, slope1, base1), c1lo), c1hi);
-      const T p2 = fmin(fmax(fma(tf, slope2, base2), c2lo), c2hi);
+      const T p1 = clampv(fma(tf, slope1, base1), c1lo, c1hi);
+      const T p2 = clampv(fma(tf, slope2, base2), c2lo, c2hi);
       const T f1 = floor(p1), f2 = floor(p2);
       const unsigned o = poff + (unsigned)((int)f2 * ld + (int)f1);
       const auto pa = load_pair(vol + o);
@@ -330,8 +330,8 @@ __device__ inline void cone_back_body(const GeomDev &g, const ViewTab<T> &vt, co
         T unum, depth;
         cone_project(x, y, vt.p0[v + q], vt.p1[v + q], D, unum, depth);
         const T inv = fast_rcp(depth);
-        const T u = fmin(fmax(fma(unum, Su * inv, offu), ulo), uhi);
-        const T w = fmin(fmax(fma(z, Sw * inv, offw), wlo), whi);
+        const T u = clampv(fma(unum, Su * inv, offu), ulo, uhi);
+        const T w = clampv(fma(z, Sw * inv, offw), wlo, whi);
         const T fu = floor(u), fw = floor(w);
         const unsigned o = voff + (unsigned)q * (unsigned)g.sliceY + (unsigned)((int)fw * ld + (int)fu);
         const auto pa = load_pair(ypad + o);
@@ -348,8 +348,8 @@ __device__ inline void cone_back_body(const GeomDev &g, const ViewTab<T> &vt, co
       T unum, depth;
       cone_project(x, y, vt.p0[v], vt.p1[v], D, unum, depth);
       const T inv = fast_rcp(depth);
-      const T u = fmin(fmax(fma(unum, Su * inv, offu), ulo), uhi);
-      const T w = fmin(fmax(fma(z, Sw * inv, offw), wlo), whi);
+      const T u = clampv(fma(unum, Su * inv, offu), ulo, uhi);
+      const T w = clampv(fma(z, Sw * inv, offw), wlo, whi);
       const T fu = floor(u), fw = floor(w);
       const unsigned o = voff + (unsigned)((int)fw * ld + (int)fu);
       const auto pa = load_pair(ypad + o);

@@ -38,6 +38,10 @@ __device__ inline T hat_clamp(T w) {
   return fmin(fmax(w, T(0)), T(1));
 }
 
+// min(max(x, lo), hi) for lo <= hi and finite x: one median-of-three in float
+__device__ inline float clampv(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ inline double clampv(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+
 // value of v in lane l of the wavefront (l uniform)
 __device__ inline float lane_value(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));

@@ -188,7 +188,7 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
       typename Pair<T>::v2 p[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        c[q] = fmin(fmax(fma(jf + T(q), slope, base), clo), chi);
+        c[q] = clampv(fma(jf + T(q), slope, base), clo, chi);
         fl[q] = floor(c[q]);
         p[q] = load_pair(pad + (off + (unsigned)(q * ld) + (unsigned)(int)fl[q]));
       }
@@ -208,7 +208,7 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
       typename Pair<T>::v2 p[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        c[q] = fmin(fmax(fma(jf + T(q), slope, base), clo), chi);
+        c[q] = clampv(fma(jf + T(q), slope, base), clo, chi);
         fl[q] = floor(c[q]);
         p[q] = load_pair(pad + (off + (unsigned)(q * ld) + (unsigned)(int)fl[q]));
       }
@@ -220,7 +220,7 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
       off += 4u * (unsigned)ld;
     }
     for (; j <= hi; ++j) {
-      const T c0 = fmin(fmax(fma(jf, slope, base), clo), chi);
+      const T c0 = clampv(fma(jf, slope, base), clo, chi);
       const T f0l = floor(c0);
       const auto p0 = load_pair(pad + (off + (unsigned)(int)f0l));
       a0 += fma(c0 - f0l, p0.y - p0.x, p0.x);
@@ -280,11 +280,12 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
   }
   const T inv_h = FAN ? T(0) : T(1) / hr;
   const T inv_dg = T(g.inv_du);
+  const T kzr = fabs(dperp) * inv_dg;
   const bool series = sizeof(T) == 4 && g.bt_fast;
   // the line at jfl (padded-line offset offl): offset d0 of the window's
   // first pixel from the crossing, and the window's taps
   auto taps = [&](T jfl, unsigned offl, T &d0, T (&v)[NQ]) {
-    const T c = fmin(fmax(fma(jfl, slope, base), clo), chi);
+    const T c = clampv(fma(jfl, slope, base), clo, chi);
     const T i0f = ceil(c - hr);
     d0 = i0f - c;
     const T *p = pad + (offl + (unsigned)(int)i0f);
@@ -297,7 +298,7 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q < n) {
-          const T wt = fma(-fabs(d0 + T(q)), inv_h, T(1));
+          const T wt = fma(-fabs(q == 0 ? d0 : d0 + T(q)), inv_h, T(1));
           acc = fma(hat_clamp(wt), v[q], acc);
         }
       }
@@ -307,12 +308,12 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
         // |angle| / dg = kz |d| (1 - e + e^2) with e = kd d, written as
         // |d| (kz + d (a1 + d a2)): one reciprocal per line
         const T inv0 = fast_rcp(along0);
-        const T kd = dpar * inv0, kz = fabs(dperp) * inv0 * inv_dg;
+        const T kd = dpar * inv0, kz = kzr * inv0;
         const T a1 = -kz * kd, a2 = -a1 * kd;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (q < n) {
-            const T d = d0 + T(q);
+            const T d = q == 0 ? d0 : d0 + T(q);
             const T gq = fma(fma(a2, d, a1), d, kz);
             const T wt = fma(-fabs(d), gq, T(1));
             acc = fma(hat_clamp(wt), v[q], acc);
@@ -322,7 +323,7 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           if (q < n) {
-            const T d = d0 + T(q);
+            const T d = q == 0 ? d0 : d0 + T(q);
             // tangent of the angle between the ray and the pixel, seen from the source
             const T z = dperp * d * fast_rcp(fma(dpar, d, along0));
             const T wt = T(1) - fabs(small_atan(z)) * inv_dg;
@@ -438,7 +439,7 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
         typename Pair<T>::v2 p[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          u[q] = fmin(fmax(fma(px, vt.p0[v + q * VS], fma(py, vt.p1[v + q * VS], off)), ulo), uhi);
+          u[q] = clampv(fma(px, vt.p0[v + q * VS], fma(py, vt.p1[v + q * VS], off)), ulo, uhi);
           fl[q] = floor(u[q]);
           p[q] = load_pair(ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)fl[q]));
         }
@@ -447,7 +448,7 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
         roff += (unsigned)(4 * VS) * ldY;
       }
       for (; v < g.nv; v += VS) {
-        const T u0 = fmin(fmax(fma(px, vt.p0[v], fma(py, vt.p1[v], off)), ulo), uhi);
+        const T u0 = clampv(fma(px, vt.p0[v], fma(py, vt.p1[v], off)), ulo, uhi);
         const T f0l = floor(u0);
         const auto p0 = load_pair(ypad + (roff + (unsigned)(int)f0l));
         a[0] += fma(u0 - f0l, p0.y - p0.x, p0.x);
@@ -467,7 +468,7 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
           const T cb = vt.p0[v + q * VS], sb = vt.p1[v + q * VS];
           const T a = D - fma(px, cb, py * sb);
           const T bb = fma(px, sb, -py * cb);
-          u[q] = fmin(fmax(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo), uhi);
+          u[q] = clampv(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo, uhi);
           fl[q] = floor(u[q]);
           p[q] = load_pair(ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)fl[q]));
         }
@@ -479,7 +480,7 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
         const T cb = vt.p0[v], sb = vt.p1[v];
         const T a = D - fma(px, cb, py * sb);
         const T bb = fma(px, sb, -py * cb);
-        const T u = fmin(fmax(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo), uhi);
+        const T u = clampv(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo, uhi);
         const T fl = floor(u);
         const auto p = load_pair(ypad + (roff + (unsigned)(int)fl));
         a0 += fma(u - fl, p.y - p.x, p.x);
@@ -599,7 +600,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
     if (valid) {
       for (int v = grp; v < g.nv; v += VS) {
         T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
-        u = fmin(fmax(u, ulo), uhi);
+        u = clampv(u, ulo, uhi);
         const T w = vt.p2[v], slope = vt.p3[v], h = vt.p4[v];
         // the bins within h of u lie in the floor(2h) + 1 bins from ceil(u - h);
         // h is the view's, so the count is uniform
@@ -638,7 +639,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
         const T a = D - fma(px, cb, py * sb);
         const T bb = fma(px, sb, -py * cb);
         T up = fma(fan_angle<T>(bb, a, fast), inv_dg, off);
-        up = fmin(fmax(up, ulo), uhi);
+        up = clampv(up, ulo, uhi);
         const T k0f = ceil(up - H);
         const unsigned k0 = (unsigned)((int)g.padY + (int)k0f);
         const typename Pair<T>::v2 *yw = reinterpret_cast<const typename Pair<T>::v2 *>(ypad) + (roff - g.padY + k0);
