@@ -458,16 +458,23 @@ static void cone_joseph(const or_geom *g, const double *x, double *y, int adjoin
   }
 }
 
-static void cone_pixel_coords(const or_geom *g, int v, double xi, double yj, double zl, double *u, double *w) {
-  const double b = g->ang[v];
-  const double Sx = g->D * cos(b), Sy = g->D * sin(b);
-  const double cx = -cos(b), cy = -sin(b);
-  const double ex = -sin(b), ey = cos(b);
+/* detector coordinates (u, w) of the point (xi, yj, zl) in the view with
+   source angle b, given cos b and sin b */
+static void cone_pixel_coords_cs(const or_geom *g, double cb, double sb, double xi, double yj, double zl, double *u,
+                                 double *w) {
+  const double Sx = g->D * cb, Sy = g->D * sb;
+  const double cx = -cb, cy = -sb;
+  const double ex = -sb, ey = cb;
   const double px = xi - Sx, py = yj - Sy, pz = zl;
   const double depth = px * cx + py * cy; /* distance along the central ray */
   const double mag = g->SDD / depth;
   *u = (px * ex + py * ey) * mag / g->du + (g->nu - 1) / 2.0;
   *w = pz * mag / g->dw + (g->nw - 1) / 2.0;
+}
+
+static void cone_pixel_coords(const or_geom *g, int v, double xi, double yj, double zl, double *u, double *w) {
+  const double b = g->ang[v];
+  cone_pixel_coords_cs(g, cos(b), sin(b), xi, yj, zl, u, w);
 }
 
 /* (B y) at voxel (i, j, l): the sum over views of the bilinear interpolation
@@ -554,6 +561,39 @@ int or_cone_back_sampled(const or_geom *g, const double *y, const long long *ids
     const long long id = ids[s];
     const int i = (int)(id % g->nx), j = (int)((id / g->nx) % g->ny), l = (int)(id / ((long long)g->nx * g->ny));
     out[s] = cone_back_voxel(g, y, i, j, l);
+  }
+  return 0;
+}
+
+/* (B^T x) at the listed detector pixels (index (v * nw + r) * nu + k): the
+   transpose of cone_pixel read one output at a time, i.e. the sum over every
+   voxel of the bilinear weight with which the voxel's projection in view v
+   reaches pixel (k, r), times the voxel's value. */
+int or_cone_back_adjoint_sampled(const or_geom *g, const double *x, const long long *ids, long long count,
+                                 double *out) {
+  if (g->kind != OR_CONE3D) return -1;
+  const long long m = g_m(g);
+  for (long long s = 0; s < count; ++s)
+    if (ids[s] < 0 || ids[s] >= m) return -1;
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  for (long long s = 0; s < count; ++s) {
+    const long long id = ids[s];
+    const int k = (int)(id % g->nu), r = (int)((id / g->nu) % g->nw), v = (int)(id / ((long long)g->nu * g->nw));
+    const double cb = cos(g->ang[v]), sb = sin(g->ang[v]);
+    double acc = 0.0;
+#pragma omp parallel for collapse(2) reduction(+ : acc) schedule(static)
+    for (int l = 0; l < nz; ++l)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          double u, w;
+          cone_pixel_coords_cs(g, cb, sb, i - (nx - 1) / 2.0, j - (ny - 1) / 2.0, l - (nz - 1) / 2.0, &u, &w);
+          const double fu = floor(u), fw = floor(w);
+          const int e1 = k - (int)fu, e2 = r - (int)fw;
+          if (e1 < 0 || e1 > 1 || e2 < 0 || e2 > 1) continue;
+          const double a = u - fu, c = w - fw;
+          acc += (e1 ? a : 1.0 - a) * (e2 ? c : 1.0 - c) * x[((size_t)l * ny + j) * nx + i];
+        }
+    out[s] = acc;
   }
   return 0;
 }

@@ -463,6 +463,7 @@ void build_cone_tables(const gkb_geometry *g, HostTables &t) {
   gd.nc_bt = 2;
   gd.nc_at = 2;
   gd.P3 = 2;
+  gd.dmax3 = D + std::hypot(midx + gd.P3 + 1.0, midy + gd.P3 + 1.0);
   gd.ldX = ny + 2 * gd.P3;
   gd.ldV = nx + 2 * gd.P3;
   gd.planeX = (long long)(nz + 2 * gd.P3) * gd.ldX;

@@ -244,55 +244,187 @@ __global__ __launch_bounds__(kBlock) void k_cone_fwd(GeomDev g, ConeTab<T> ct, c
 }
 
 // ---------------------------------------------------------------------------
-// B^T: transpose of the voxel-driven back projector, one thread per ray
+// B^T: transpose of the voxel-driven back projector, one thread per ray.
+// Ray (v, r, k) collects every voxel whose detector coordinates (u, w) are
+// within one pixel of (k, r), with the weight (1 - |u - k|)(1 - |w - r|).
+// On each dominant plane those voxels lie within the ray's in-plane
+// half-width h1 of its crossing, and in the rows whose projected row
+// coordinate can reach r at the depths of those columns.
 // ---------------------------------------------------------------------------
+constexpr int kConeBtRows = 6;  // most rows of the uniform window
+
+// Generic form: the exact candidate columns and rows of every plane, with
+// data-dependent loops.  Used where the uniform windows would be too large.
+template <typename T>
+__device__ inline T cone_bt_ray_generic(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt,
+                                        const T *__restrict__ pad, const RayIdx &q) {
+  const int meta = ct.meta_bt[q.vk];
+  const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
+  const bool ydom = (meta >> 30) & 1;
+  const T base1 = ct.base1[q.vk], slope1 = ct.slope1[q.vk], h1 = ct.h1[q.vk];
+  const T cb = vt.p0[q.v], sb = vt.p1[q.v], D = T(g.D);
+  const T midx = T(0.5) * T(g.nx - 1), midy = T(0.5) * T(g.ny - 1), midz = T(0.5) * T(g.nz - 1);
+  const T mid = ydom ? midy : midx, mid1 = ydom ? midx : midy;
+  const int n1 = ydom ? g.nx : g.ny;
+  const int ld = ydom ? g.ldV : g.ldX;
+  const long long plane = ydom ? g.planeY : g.planeX;
+  const T *__restrict__ vol = pad + (ydom ? g.offYD : 0LL) + (g.P3 * ld + g.P3);
+  const T Su = T(g.Su), Sw = T(g.Sw), offu = T(g.off), offw = T(g.offw);
+  const T kf = T(q.k), rf = T(q.r);
+  const T inv_sw = T(1) / Sw;
+  const T eps = T(1e-3);
+  T acc = T(0);
+  for (int t = lo; t <= hi; ++t) {
+    const T tf = T(t) - mid;
+    const T c1 = fma(tf, slope1, base1);
+    const int j0 = max((int)ceil(c1 - h1), 0), j1 = min((int)floor(c1 + h1), n1 - 1);
+    const T *__restrict__ pl = vol + (long long)t * plane;
+    for (int jj = j0; jj <= j1; ++jj) {
+      const T o = T(jj) - mid1;
+      T unum, depth;
+      cone_project(ydom ? o : tf, ydom ? tf : o, cb, sb, D, unum, depth);
+      const T inv = fast_rcp(depth);
+      const T u = fma(unum, Su * inv, offu);
+      const T wu = T(1) - fabs(u - kf);
+      if (wu > T(0)) {
+        const T mw = Sw * inv;
+        // heights whose row coordinate z mw + offw is within one row of r
+        const T zh = depth * inv_sw, zc = (rf - offw) * zh + midz;
+        const int l0 = max((int)ceil(zc - zh - eps), 0), l1 = min((int)floor(zc + zh + eps), g.nz - 1);
+        for (int l = l0; l <= l1; ++l) {
+          const T ww = T(1) - fabs(fma(T(l) - midz, mw, offw) - rf);
+          if (ww > T(0)) acc = fma(wu * ww, pl[(long long)l * ld + jj], acc);
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+// Windowed form: on every plane NJ consecutive columns from ceil(c1 - h1)
+// and nl consecutive rows (NJ and nl uniform over the wavefront), every
+// weight a clamped hat, no data-dependent branches.  The first row is the
+// lowest that the projected row coordinate can bring within one row of r at
+// the window's depths: the row interval of a column at depth d is
+// midz + (rho -+ 1) d / Sw (rho = r - offw), linear in d, and the depth is
+// linear along the window, so its extremes sit at the window's ends.  Both
+// window starts are clamped into the padded volume; since each window is at
+// least as long as the set of voxels with nonzero weight, the clamp keeps
+// every such voxel of the volume inside it.  Planes where the ray's height
+// is farther than the window's reach from the volume are skipped.
+template <typename T, int NJ>
+__device__ inline T cone_bt_ray_win(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt,
+                                    const T *__restrict__ pad, const RayIdx &q, int nl) {
+  const int meta = ct.meta_bt[q.vk];
+  int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
+  const bool ydom = (meta >> 30) & 1;
+  const T base1 = ct.base1[q.vk], slope1 = ct.slope1[q.vk], h1 = ct.h1[q.vk];
+  const T cb = vt.p0[q.v], sb = vt.p1[q.v], D = T(g.D);
+  const T midx = T(0.5) * T(g.nx - 1), midy = T(0.5) * T(g.ny - 1), midz = T(0.5) * T(g.nz - 1);
+  const T mid = ydom ? midy : midx, mid1 = ydom ? midx : midy;
+  const int n1 = ydom ? g.nx : g.ny;
+  const int ld = ydom ? g.ldV : g.ldX;
+  const long long plane = ydom ? g.planeY : g.planeX;
+  const T *__restrict__ vol = pad + (ydom ? g.offYD : 0LL) + (g.P3 * ld + g.P3);
+  const T Su = T(g.Su), Sw = T(g.Sw), inv_sw = T(1) / Sw;
+  const T rho = T(q.r) - T(g.offw);
+  const T eps = T(1e-3);
+  // depth D - (x cos + y sin) and Su (y cos - x sin) of the voxel at in-plane
+  // offset o on the plane at offset tf: affine in o and in tf
+  const T ddo = ydom ? -cb : -sb, duo = (ydom ? -sb : cb) * Su;
+  const T dtt = ydom ? -sb : -cb, utt = (ydom ? cb : -sb) * Su;
+  {
+    // height of the ray at plane offset tf: base2 + slope2 tf; a voxel of the
+    // window is within zm rows of it
+    const T vv = rho * T(g.dw);
+    const T base2 = fma(vv, ct.lmid[q.vk], midz), slope2 = vv * ct.lslope[q.vk];
+    const T zm = fma(T(g.dmax3), inv_sw, fabs(rho) * inv_sw * (h1 + T(1))) + T(1);
+    if (slope2 != T(0)) {
+      T ta = (T(-1) - zm - base2) / slope2, tb = (T(g.nz) + zm - base2) / slope2;
+      if (ta > tb) {
+        const T tt = ta;
+        ta = tb;
+        tb = tt;
+      }
+      lo = max(lo, (int)fmin(fmax(ceil(ta + mid) - T(1), T(-1)), T(32767)));
+      hi = min(hi, (int)fmin(fmax(floor(tb + mid) + T(1), T(-1)), T(32767)));
+    } else if (!(base2 > T(-1) - zm && base2 < T(g.nz) + zm)) {
+      hi = lo - 1;
+    }
+  }
+  // lowest row reachable: midz + rm d at the window end that minimises it
+  const T rm = (rho - T(1)) * inv_sw;
+  const bool last_end = (rm >= T(0)) != (ddo >= T(0));
+  const T cmin = (last_end ? rm * (T(NJ - 1) * ddo) : T(0)) + (midz - eps);
+  const T cu = T(g.off) - T(q.k), cw = T(g.offw) - T(q.r);
+  const T jlo = T(-g.P3), jhi = T(n1 - 1 + g.P3 - (NJ - 1));
+  const T llo = T(-g.P3), lhi = T(g.nz - 1 + g.P3 - (nl - 1));
+  T acc = T(0);
+  for (int t = lo; t <= hi; ++t) {
+    const T tf = T(t) - mid;
+    const T j0f = clampv(ceil(fma(tf, slope1, base1) - h1), jlo, jhi);
+    const T o0 = j0f - mid1;
+    const T dep0 = fma(o0, ddo, fma(tf, dtt, D));
+    const T uns0 = fma(o0, duo, tf * utt);
+    const T l0f = clampv(ceil(fma(rm, dep0, cmin)), llo, lhi);
+    const T z0 = l0f - midz;
+    const T *__restrict__ pl = vol + (long long)t * plane + ((int)l0f * ld + (int)j0f);
+    T v[kConeBtRows][NJ];
+#pragma unroll
+    for (int p = 0; p < kConeBtRows; ++p)
+      if (p < nl) {
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) v[p][c] = pl[p * ld + c];
+      }
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+      const T dep = c == 0 ? dep0 : fma(T(c), ddo, dep0);
+      const T uns = c == 0 ? uns0 : fma(T(c), duo, uns0);
+      const T inv = fast_rcp(dep);
+      const T wu = hat_clamp(T(1) - fabs(fma(uns, inv, cu)));
+      const T mw = Sw * inv;
+      const T b0 = fma(z0, mw, cw);
+      T col = T(0);
+#pragma unroll
+      for (int p = 0; p < kConeBtRows; ++p)
+        if (p < nl) {
+          const T wr = p == 0 ? b0 : fma(T(p), mw, b0);
+          col = fma(hat_clamp(T(1) - fabs(wr)), v[p][c], col);
+        }
+      acc = fma(wu, col, acc);
+    }
+  }
+  return acc;
+}
+
 template <typename T>
 __device__ inline void cone_back_adj_body(const GeomDev &g, const ConeTab<T> &ct, const ViewTab<T> &vt,
                                           const T *__restrict__ pad, T *yo, const Epi<T> &e, Blk b) {
   const long long rr = (long long)b.id * kBlock + threadIdx.x;
   const bool valid = rr < g.m;
+  const RayIdx q = ray_index(g, valid ? rr : 0);
+  // uniform window sizes: columns floor(2 h1) + 1 (at least 2); rows from the
+  // largest row interval over the window's depth range
+  const T h1 = ct.h1[q.vk];
+  const int nj = max(wave_max(valid ? (int)floor(T(2) * h1) + 1 : 0), 2);
+  const bool ydom = (ct.meta_bt[q.vk] >> 30) & 1;
+  const T ddo = fabs(ydom ? vt.p0[q.v] : vt.p1[q.v]);
+  const T rho = fabs(T(q.r) - T(g.offw));
+  const int nl_ray = (int)floor(fma(T(2), T(g.dmax3), rho * ddo * T(nj - 1)) / T(g.Sw) + T(2e-3)) + 1;
+  const int nl = wave_max(valid ? nl_ray : 0);
   T acc = T(0);
   if (valid) {
-    const RayIdx q = ray_index(g, rr);
-    const int meta = ct.meta_bt[q.vk];
-    const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
-    const bool ydom = (meta >> 30) & 1;
-    const T base1 = ct.base1[q.vk], slope1 = ct.slope1[q.vk], h1 = ct.h1[q.vk];
-    const T cb = vt.p0[q.v], sb = vt.p1[q.v], D = T(g.D);
-    const T midx = T(0.5) * T(g.nx - 1), midy = T(0.5) * T(g.ny - 1), midz = T(0.5) * T(g.nz - 1);
-    const T mid = ydom ? midy : midx, mid1 = ydom ? midx : midy;
-    const int n1 = ydom ? g.nx : g.ny;
-    const int ld = ydom ? g.ldV : g.ldX;
-    const long long plane = ydom ? g.planeY : g.planeX;
-    const T *__restrict__ vol = pad + (ydom ? g.offYD : 0LL) + (g.P3 * ld + g.P3);
-    const T Su = T(g.Su), Sw = T(g.Sw), offu = T(g.off), offw = T(g.offw);
-    const T kf = T(q.k), rf = T(q.r);
-    const T inv_sw = T(1) / Sw;
-    const T eps = T(1e-3);
-    for (int t = lo; t <= hi; ++t) {
-      const T tf = T(t) - mid;
-      const T c1 = fma(tf, slope1, base1);
-      const int j0 = max((int)ceil(c1 - h1), 0), j1 = min((int)floor(c1 + h1), n1 - 1);
-      const T *__restrict__ pl = vol + (long long)t * plane;
-      for (int jj = j0; jj <= j1; ++jj) {
-        const T o = T(jj) - mid1;
-        T unum, depth;
-        cone_project(ydom ? o : tf, ydom ? tf : o, cb, sb, D, unum, depth);
-        const T inv = fast_rcp(depth);
-        const T u = fma(unum, Su * inv, offu);
-        const T wu = T(1) - fabs(u - kf);
-        if (wu > T(0)) {
-          const T mw = Sw * inv;
-          // heights whose row coordinate z mw + offw is within one row of r
-          const T zh = depth * inv_sw, zc = (rf - offw) * zh + midz;
-          const int l0 = max((int)ceil(zc - zh - eps), 0), l1 = min((int)floor(zc + zh + eps), g.nz - 1);
-          for (int l = l0; l <= l1; ++l) {
-            const T ww = T(1) - fabs(fma(T(l) - midz, mw, offw) - rf);
-            if (ww > T(0)) acc = fma(wu * ww, pl[(long long)l * ld + jj], acc);
-          }
-        }
-      }
-    }
+    const bool fits = nl <= kConeBtRows && nl <= g.nz + 2 * g.P3 && nj <= min(g.nx, g.ny) + 2 * g.P3;
+    if (fits && nj == 2)
+      acc = cone_bt_ray_win<T, 2>(g, ct, vt, pad, q, nl);
+    else if (fits && nj == 3)
+      acc = cone_bt_ray_win<T, 3>(g, ct, vt, pad, q, nl);
+    else if (fits && nj == 4)
+      acc = cone_bt_ray_win<T, 4>(g, ct, vt, pad, q, nl);
+    else if (fits && nj == 5)
+      acc = cone_bt_ray_win<T, 5>(g, ct, vt, pad, q, nl);
+    else
+      acc = cone_bt_ray_generic(g, ct, vt, pad, q);
   }
   epilogue(e, rr, valid, acc, yo, b);
 }

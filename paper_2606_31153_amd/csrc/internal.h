@@ -155,6 +155,7 @@ struct GeomDev {
   double offw;         // (nw-1)/2
   double Su, Sw;       // SDD/du, SDD/dw
   double hk_fac;       // A^T: candidate columns within hk_fac/depth of the voxel's detector coordinate
+  double dmax3;        // B^T: bound on the depth D - (x cos + y sin) of every padded voxel
   // padded volume: x-dominant copy [i][l+P][j+P] (planes of (nz+2P) x ldX),
   // then at offYD the y-dominant copy [j][l+P][i+P] (planes of (nz+2P) x ldV)
   int P3, ldX, ldV;

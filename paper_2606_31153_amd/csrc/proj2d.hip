@@ -285,7 +285,7 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
   // the line at jfl (padded-line offset offl): offset d0 of the window's
   // first pixel from the crossing, and the window's taps
   auto taps = [&](T jfl, unsigned offl, T &d0, T (&v)[NQ]) {
-    const T c = clampv(fma(jfl, slope, base), clo, chi);
+    const T c = clampv(T(fma(jfl, slope, base)), clo, chi);
     const T i0f = ceil(c - hr);
     d0 = i0f - c;
     const T *p = pad + (offl + (unsigned)(int)i0f);

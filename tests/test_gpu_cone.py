@@ -54,6 +54,11 @@ GEOMS = {
                    angles=np.deg2rad([0.0, 17.0, 44.3, 91.0, 180.0, 233.0, 301.7])),
     "flat": cone(24, 24, 1, 10, 40, 3, 1.0, 1.0, 40.0, 80.0),
     "tall": cone(12, 12, 30, 9, 20, 40, 1.5, 1.5, 24.0, 50.0),
+    # fine detector: two-column B^T windows
+    "fine": cone(18, 15, 10, 11, 60, 40, 0.55, 0.6, 28.0, 50.0),
+    # coarse detector: B^T windows beyond the uniform-window limits (the
+    # per-voxel candidate loops)
+    "coarse": cone(16, 14, 12, 9, 9, 8, 5.0, 6.0, 30.0, 60.0),
 }
 
 OPS = {"A": ("gkb_forward", "A", "n"), "B": ("gkb_back", "B", "m"),
@@ -187,6 +192,27 @@ def test_cone_full_size_512(ctx):
     lhs = torch.dot(Btx.double(), yd.double()).item()
     rhs = torch.dot(xd.double(), By.double()).item()
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    note("cone 512: B^T at sampled pixels against the oracle")
+    # random pixels, and pixels of large row or column offset that still see
+    # the volume (the rows' windows reach farthest in height there)
+    pick = np.random.default_rng(9)
+    nv, nw, nu = g.n_views, g.n_det_v, g.n_det_u
+
+    def offset(n, lo, hi, count):
+        e = pick.integers(lo, hi + 1, count)
+        return np.where(pick.random(count) < 0.5, n // 2 - e, n // 2 - 1 + e)
+
+    vv = pick.integers(0, nv, 48)
+    rr = np.concatenate([pick.integers(0, nw, 16), offset(nw, 150, 250, 16), pick.integers(nw // 4, 3 * nw // 4, 16)])
+    kk = np.concatenate([pick.integers(0, nu, 16), pick.integers(nu // 4, 3 * nu // 4, 16),
+                         offset(nu, nu // 2 - 140, nu // 2 - 40, 16)])
+    ids = (vv.astype(np.int64) * nw + rr) * nu + kk
+    ref = oracle.Operator(g).Bt_at(x.astype(np.float64), ids)
+    got = Btx[torch.from_numpy(ids).to(DEV)].double().cpu().numpy()
+    note("cone 512: B^T sampled rel %.3e, max abs %.3e of %.3e" % (rel(got, ref), np.max(np.abs(got - ref)),
+                                                                   np.max(np.abs(ref))))
+    assert rel(got, ref) <= 1e-5
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
 SOLVE_GEOMS = [cone(14, 13, 9, 23, 25, 17, 1.3, 1.2, 26.0, 50.0),

@@ -228,6 +228,20 @@ def test_cone_dense_and_adjoint():
     assert np.max(np.abs(B - Bd)) <= 1e-13 * np.max(np.abs(B))
 
 
+def test_cone_sampled_back_adjoint_is_the_transpose():
+    # every pixel of B^T evaluated one at a time equals the transposed dense
+    # matrix of B built independently, and satisfies <B^T x, y> = <x, B y>
+    g = TINY_CONE
+    op = oracle.Operator(g)
+    r = np.random.default_rng(5)
+    x = r.standard_normal(g.n)
+    y = r.standard_normal(g.m)
+    Bd = dense.dense_B(g)
+    bt = op.Bt_at(x, np.arange(g.m))
+    assert np.max(np.abs(bt - Bd.T @ x)) <= 1e-13 * np.max(np.abs(Bd.T @ x))
+    assert abs(bt @ y - x @ op.B(y).reshape(-1)) <= 1e-12 * np.linalg.norm(bt) * np.linalg.norm(y)
+
+
 def test_cone_constant_volume_central_ray():
     # the central ray of every view runs along the x-y plane through the centre;
     # for a constant volume its Joseph sum is the number of crossed planes / |d_dom|
@@ -258,6 +272,10 @@ def test_cone_sampled_outputs_equal_the_full_operators():
     vox = r.choice(g.n, 40, replace=False)
     assert np.array_equal(op.A_at(x, rays), op.A(x).reshape(-1)[rays])
     assert np.array_equal(op.B_at(y, vox), op.B(y).reshape(-1)[vox])
+    # B^T at sampled pixels gathers what the scatter loop adds up: equal to
+    # rounding (another summation order)
+    bt = op.Bt(x).reshape(-1)
+    assert np.max(np.abs(op.Bt_at(x, rays) - bt[rays])) <= 1e-12 * np.max(np.abs(bt))
     with pytest.raises(ValueError):
         op.A_at(x, [g.m])
     with pytest.raises(ValueError):
