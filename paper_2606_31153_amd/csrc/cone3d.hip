@@ -251,7 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_cone_fwd(GeomDev g, ConeTab<T> ct, c
 // half-width h1 of its crossing, and in the rows whose projected row
 // coordinate can reach r at the depths of those columns.
 // ---------------------------------------------------------------------------
-constexpr int kConeBtRows = 6;  // most rows of the uniform window
+constexpr int kConeBtRows = 4;    // most rows of the uniform window
+constexpr int kConeBtPlanes = 4;  // planes whose loads are in flight together
 
 // Generic form: the exact candidate columns and rows of every plane, with
 // data-dependent loops.  Used where the uniform windows would be too large.
@@ -359,40 +360,60 @@ __device__ inline T cone_bt_ray_win(const GeomDev &g, const ConeTab<T> &ct, cons
   const T cu = T(g.off) - T(q.k), cw = T(g.offw) - T(q.r);
   const T jlo = T(-g.P3), jhi = T(n1 - 1 + g.P3 - (NJ - 1));
   const T llo = T(-g.P3), lhi = T(g.nz - 1 + g.P3 - (nl - 1));
-  T acc = T(0);
-  for (int t = lo; t <= hi; ++t) {
+  // plane t's window: the depth and Su * unum of its first column, the
+  // height offset of its first row, and its values
+  auto window = [&](int t, T &dep0, T &uns0, T &z0, T (&v)[kConeBtRows][NJ]) {
     const T tf = T(t) - mid;
-    const T j0f = clampv(ceil(fma(tf, slope1, base1) - h1), jlo, jhi);
+    const T j0f = clampv(T(ceil(T(fma(tf, slope1, base1)) - h1)), jlo, jhi);
     const T o0 = j0f - mid1;
-    const T dep0 = fma(o0, ddo, fma(tf, dtt, D));
-    const T uns0 = fma(o0, duo, tf * utt);
-    const T l0f = clampv(ceil(fma(rm, dep0, cmin)), llo, lhi);
-    const T z0 = l0f - midz;
+    dep0 = T(fma(o0, ddo, T(fma(tf, dtt, D))));
+    uns0 = T(fma(o0, duo, tf * utt));
+    const T l0f = clampv(T(ceil(T(fma(rm, dep0, cmin)))), llo, lhi);
+    z0 = l0f - midz;
     const T *__restrict__ pl = vol + (long long)t * plane + ((int)l0f * ld + (int)j0f);
-    T v[kConeBtRows][NJ];
 #pragma unroll
     for (int p = 0; p < kConeBtRows; ++p)
       if (p < nl) {
 #pragma unroll
         for (int c = 0; c < NJ; ++c) v[p][c] = pl[p * ld + c];
       }
+  };
+  auto weigh = [&](T dep0, T uns0, T z0, const T (&v)[kConeBtRows][NJ], T &acc) {
 #pragma unroll
     for (int c = 0; c < NJ; ++c) {
-      const T dep = c == 0 ? dep0 : fma(T(c), ddo, dep0);
-      const T uns = c == 0 ? uns0 : fma(T(c), duo, uns0);
+      const T dep = c == 0 ? dep0 : T(fma(T(c), ddo, dep0));
+      const T uns = c == 0 ? uns0 : T(fma(T(c), duo, uns0));
       const T inv = fast_rcp(dep);
-      const T wu = hat_clamp(T(1) - fabs(fma(uns, inv, cu)));
+      const T wu = hat_clamp(T(T(1) - fabs(T(fma(uns, inv, cu)))));
       const T mw = Sw * inv;
-      const T b0 = fma(z0, mw, cw);
+      const T b0 = T(fma(z0, mw, cw));
       T col = T(0);
 #pragma unroll
       for (int p = 0; p < kConeBtRows; ++p)
         if (p < nl) {
-          const T wr = p == 0 ? b0 : fma(T(p), mw, b0);
-          col = fma(hat_clamp(T(1) - fabs(wr)), v[p][c], col);
+          const T wr = p == 0 ? b0 : T(fma(T(p), mw, b0));
+          col = T(fma(hat_clamp(T(T(1) - fabs(wr))), v[p][c], col));
         }
-      acc = fma(wu, col, acc);
+      acc = T(fma(wu, col, acc));
     }
+  };
+  // kConeBtPlanes planes per step: the loads of all of them are issued
+  // before any is weighed
+  T acc = T(0);
+  int t = lo;
+  for (; t + kConeBtPlanes - 1 <= hi; t += kConeBtPlanes) {
+    T d[kConeBtPlanes], u[kConeBtPlanes], z[kConeBtPlanes];
+    T v[kConeBtPlanes][kConeBtRows][NJ];
+#pragma unroll
+    for (int i = 0; i < kConeBtPlanes; ++i) window(t + i, d[i], u[i], z[i], v[i]);
+#pragma unroll
+    for (int i = 0; i < kConeBtPlanes; ++i) weigh(d[i], u[i], z[i], v[i], acc);
+  }
+  for (; t <= hi; ++t) {
+    T da, ua, za;
+    T va[kConeBtRows][NJ];
+    window(t, da, ua, za, va);
+    weigh(da, ua, za, va, acc);
   }
   return acc;
 }
