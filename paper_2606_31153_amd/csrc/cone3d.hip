@@ -160,6 +160,8 @@ __global__ __launch_bounds__(256) void k_cone_weight(Col<const T> yc, ConeTab<T>
 // ---------------------------------------------------------------------------
 // A: Joseph forward, one thread per ray
 // ---------------------------------------------------------------------------
+constexpr int kConeFwdPlanes = 8;  // planes whose tap loads are in flight together
+
 template <typename T>
 __device__ inline void cone_fwd_body(const GeomDev &g, const ConeTab<T> &ct, const T *__restrict__ pad, T *yo,
                                      const Epi<T> &e, Blk b) {
@@ -197,29 +199,35 @@ __device__ inline void cone_fwd_body(const GeomDev &g, const ConeTab<T> &ct, con
     const T c1lo = T(-1.5), c1hi = T(n1) + T(0.5), c2lo = T(-1.5), c2hi = T(g.nz) + T(0.5);
     unsigned poff = (unsigned)max(lo, 0) * plane + (unsigned)(g.P3 * ld + g.P3);
     T tf = T(lo) - mid;
-    T a0 = T(0), a1 = T(0);
-    int t = lo;
-    // two planes per step: four pair loads in flight
-    for (; t + 1 <= hi; t += 2) {
-      T s[2];
+    T a[kConeFwdPlanes];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < kConeFwdPlanes; ++u) a[u] = T(0);
+    int t = lo;
+    // kConeFwdPlanes planes per step: the pair loads of all of them are
+    // issued before any is interpolated
+    for (; t + kConeFwdPlanes - 1 <= hi; t += kConeFwdPlanes) {
+      typename Pair<T>::v2 pa[kConeFwdPlanes], pb[kConeFwdPlanes];
+      T fr[kConeFwdPlanes], fz[kConeFwdPlanes];
+#pragma unroll
+      for (int u = 0; u < kConeFwdPlanes; ++u) {
         const T p1 = clampv(fma(tf + T(u), slope1, base1), c1lo, c1hi);
         const T p2 = clampv(fma(tf + T(u), slope2, base2), c2lo, c2hi);
         const T f1 = floor(p1), f2 = floor(p2);
         const unsigned o = poff + (unsigned)u * plane + (unsigned)((int)f2 * ld + (int)f1);
-        const auto pa = load_pair(vol + o);
-        const auto pb = load_pair(vol + o + ld);
-        const T fr = p1 - f1;
-        const T va = fma(fr, pa.y - pa.x, pa.x), vb = fma(fr, pb.y - pb.x, pb.x);
-        s[u] = fma(p2 - f2, vb - va, va);
+        pa[u] = load_pair(vol + o);
+        pb[u] = load_pair(vol + o + ld);
+        fr[u] = p1 - f1;
+        fz[u] = p2 - f2;
       }
-      a0 += s[0];
-      a1 += s[1];
-      tf += T(2);
-      poff += 2u * plane;
+#pragma unroll
+      for (int u = 0; u < kConeFwdPlanes; ++u) {
+        const T va = fma(fr[u], pa[u].y - pa[u].x, pa[u].x), vb = fma(fr[u], pb[u].y - pb[u].x, pb[u].x);
+        a[u] += fma(fz[u], vb - va, va);
+      }
+      tf += T(kConeFwdPlanes);
+      poff += (unsigned)kConeFwdPlanes * plane;
     }
-    if (t <= hi) {
+    for (; t <= hi; ++t) {
       const T p1 = clampv(fma(tf, slope1, base1), c1lo, c1hi);
       const T p2 = clampv(fma(tf, slope2, base2), c2lo, c2hi);
       const T f1 = floor(p1), f2 = floor(p2);
@@ -228,10 +236,14 @@ __device__ inline void cone_fwd_body(const GeomDev &g, const ConeTab<T> &ct, con
       const auto pb = load_pair(vol + o + ld);
       const T fr = p1 - f1;
       const T va = fma(fr, pa.y - pa.x, pa.x), vb = fma(fr, pb.y - pb.x, pb.x);
-      a0 += fma(p2 - f2, vb - va, va);
+      a[0] += fma(p2 - f2, vb - va, va);
+      tf += T(1);
+      poff += plane;
     }
+#pragma unroll
+    for (int u = 1; u < kConeFwdPlanes; ++u) a[0] += a[u];
     const T w = sqrt(fma(vv, vv, ct.dxy2[q.vk])) * fabs(lsl);
-    acc = (a0 + a1) * w;
+    acc = a[0] * w;
   }
   epilogue(e, rr, valid, acc, yo, b);
 }
