@@ -48,7 +48,7 @@ OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each
 # scaled by the plain-copy calibration), profiles/fan512_gkb_hbm_traffic.txt.
 # An entry must be removed when its kernel changes.
-MEASURED_TRAFFIC = {"fwd": (13317.2 * 1.9960 + 4328.8) * 1024.0, "back_adj": (19310.4 * 1.9960 + 2880.0) * 1024.0}
+MEASURED_TRAFFIC = {}
 
 
 def joseph_crossings(geom) -> int:

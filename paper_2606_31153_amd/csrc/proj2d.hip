@@ -253,8 +253,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // candidates outside the support get a negative weight, clamped to zero.
 // ---------------------------------------------------------------------------
 // Sum over lines lo..hi of one ray with n candidates per line: n = CNT, or
-// the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.  Two
-// lines per step, the taps of both loaded before either is weighted.
+// the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.
+// kBtLines lines per step, the taps of all of them loaded before any is
+// weighted.
+constexpr int kBtLines = 2;
 template <typename T, bool FAN, int CNT, int MAXC>
 __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, long long r,
                                  T hr, int nrt) {
@@ -335,19 +337,21 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
   };
   T acc = T(0);
   int j = lo;
-  for (; j + 1 <= hi; j += 2) {
-    T d0a, d0b, va[NQ], vb[NQ];
-    taps(jf, off, d0a, va);
-    taps(jf + T(1), off + (unsigned)ld, d0b, vb);
-    weigh(jf, d0a, va, acc);
-    weigh(jf + T(1), d0b, vb, acc);
-    jf += T(2);
-    off += 2u * (unsigned)ld;
+  for (; j + kBtLines - 1 <= hi; j += kBtLines) {
+    T d0[kBtLines], v[kBtLines][NQ];
+#pragma unroll
+    for (int i = 0; i < kBtLines; ++i) taps(jf + T(i), off + (unsigned)(i * ld), d0[i], v[i]);
+#pragma unroll
+    for (int i = 0; i < kBtLines; ++i) weigh(jf + T(i), d0[i], v[i], acc);
+    jf += T(kBtLines);
+    off += (unsigned)(kBtLines * ld);
   }
-  if (j <= hi) {
+  for (; j <= hi; ++j) {
     T d0a, va[NQ];
     taps(jf, off, d0a, va);
     weigh(jf, d0a, va, acc);
+    jf += T(1);
+    off += (unsigned)ld;
   }
   return acc;
 }
