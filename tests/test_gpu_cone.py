@@ -59,6 +59,8 @@ GEOMS = {
     # coarse detector: B^T windows beyond the uniform-window limits (the
     # per-voxel candidate loops)
     "coarse": cone(16, 14, 12, 9, 9, 8, 5.0, 6.0, 30.0, 60.0),
+    # the full-size proportions at 32^3
+    "cube32": synth.cone3d(32, 40, 64, 48),
 }
 
 OPS = {"A": ("gkb_forward", "A", "n"), "B": ("gkb_back", "B", "m"),
