@@ -75,6 +75,7 @@ struct HostTables {
   // per ray
   std::vector<double> base, slope, w, h, t0, dt, dperp, dpar;
   std::vector<int> meta, meta_bt;
+  std::vector<int> order_fwd, order_bt;  // workgroup dispatch orders of A and B^T
   std::vector<double> wpad;  // fan: 1/|d_dom| in padded sinogram layout
   // per view
   std::vector<double> p0, p1, p2, p3, p4;
@@ -186,6 +187,8 @@ void fan_tile_halfwidths(const gkb_geometry *g, const std::vector<double> &ang, 
 
 // Ray geometry in pixel index coordinates (crossing at the middle line and
 // its slope per line), filled for every ray of a 2D geometry.
+void ray_dispatch_orders(HostTables &t, int nu, int nv);
+
 void build_tables(const gkb_geometry *g, HostTables &t) {
   const int nx = g->nx, ny = g->ny, nv = g->n_views, nu = g->n_det_u;
   const long long m = (long long)nv * nu;
@@ -357,6 +360,41 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
       for (int k = 0; k < nu; ++k) t.wpad[(long long)v * gd.ldY + gd.padY + k] = t.w[(long long)v * nu + k];
     fan_tile_halfwidths(g, ang, t);
   }
+  ray_dispatch_orders(t, nu, nv);
+}
+
+// Dispatch orders of the ray-driven 2D kernels.  A workgroup lasts as long
+// as its longest ray (its wavefronts loop until their last lane is done and
+// meet at the closing reduction), and a launch holds more workgroups than the
+// GPU runs at once, so the workgroups are issued longest first (the
+// longest-processing-time rule): the tail of the launch is then made of short
+// ones.  A: workgroup w holds rays 256 w .. 256 w + 255; B^T: workgroup w
+// holds bins 64 (w mod T) .. + 63 of views 4 (w div T) .. + 3, T = ceil(nu / 64).
+// Ties keep their index order.
+void ray_dispatch_orders(HostTables &t, int nu, int nv) {
+  const long long m = (long long)nu * nv;
+  const int tiles_u = (nu + 63) / 64, nblk = tiles_u * ((nv + 3) / 4);
+  auto lines = [](int meta) { return std::max(0, ((meta >> 15) & 0x7fff) - (meta & 0x7fff) + 1); };
+  std::vector<int> key(nblk);
+  auto order_by = [&](std::vector<int> &order) {
+    order.resize(nblk);
+    for (int w = 0; w < nblk; ++w) order[w] = w;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] > key[b]; });
+  };
+  for (int w = 0; w < nblk; ++w) {
+    int k = 0;
+    for (long long r = (long long)w * 256; r < std::min(m, (long long)w * 256 + 256); ++r) k = std::max(k, lines(t.meta[r]));
+    key[w] = k;
+  }
+  order_by(t.order_fwd);
+  for (int w = 0; w < nblk; ++w) {
+    const int v0 = (w / tiles_u) * 4, b0 = (w % tiles_u) * 64;
+    int k = 0;
+    for (int v = v0; v < std::min(nv, v0 + 4); ++v)
+      for (int b = b0; b < std::min(nu, b0 + 64); ++b) k = std::max(k, lines(t.meta_bt[(long long)v * nu + b]));
+    key[w] = k;
+  }
+  order_by(t.order_bt);
 }
 
 // Cone beam: per (view, column) the ray's dominant axis and its crossings
@@ -538,7 +576,7 @@ hipError_t upload_tables(const HostTables &h, DevTables &d) {
   const size_t rayT = al(sizeof(T) * m), rayI = al(sizeof(int) * m), viewT = al(sizeof(T) * nv),
                binT = al(sizeof(T) * 2 * h.gd.ldY), wpT = al(sizeof(T) * (fan ? h.gd.ypad_elems : 1)),
                tileT = al(sizeof(T) * std::max<size_t>(h.htile.size(), 1));
-  const size_t total = 8 * rayT + 2 * rayI + 5 * viewT + binT + wpT + tileT;
+  const size_t total = 8 * rayT + 4 * rayI + 5 * viewT + binT + wpT + tileT;
   hipError_t e = d.buf.ensure(total);
   if (e != hipSuccess) return e;
   char *p = d.buf.as<char>();
@@ -570,6 +608,8 @@ hipError_t upload_tables(const HostTables &h, DevTables &d) {
   rt.dpar = put(h.dpar, rayT);
   rt.meta = put_i(h.meta);
   rt.meta_bt = put_i(h.meta_bt);
+  rt.order_fwd = put_i(h.order_fwd);
+  rt.order_bt = put_i(h.order_bt);
   vt.p0 = put(h.p0, viewT);
   vt.p1 = put(h.p1, viewT);
   vt.p2 = put(h.p2, viewT);

@@ -110,6 +110,11 @@ struct RayTab {        // per ray, m entries: ray-driven kernels (A, B^T)
   const T *dpar;       // along-ray distance change per unit offset along the line
   // fan-beam A^T: 1/|d_dom| per ray in padded sinogram layout (zeros in the pads)
   const T *wpad;
+  // dispatch order of the workgroups of A and B^T: workgroup b of a launch
+  // takes tile order[b]; tiles with the longest rays come first, so that the
+  // last workgroups to start are short ones
+  const int *order_fwd;
+  const int *order_bt;
 };
 
 template <typename T>

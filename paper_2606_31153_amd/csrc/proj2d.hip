@@ -165,7 +165,8 @@ __global__ __launch_bounds__(256) void k_pad_sino_w(Col<const T> yc, const T *__
 template <typename T>
 __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
                                 const Epi<T> &e, Blk b) {
-  const long long r = (long long)b.id * kBlock + threadIdx.x;
+  const unsigned wg = rt.order_fwd ? (unsigned)rt.order_fwd[b.id] : b.id;
+  const long long r = (long long)wg * kBlock + threadIdx.x;
   const bool valid = r < g.m;
   T acc = T(0);
   if (valid) {
@@ -363,7 +364,8 @@ __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, cons
   // wavefront): the four wavefronts of a workgroup cross nearly the same
   // image lines at nearly the same places
   const int tiles_u = (g.nu + 63) >> 6;
-  const int view = (int)(b.id / tiles_u) * 4 + (threadIdx.x >> 6), bin = (int)(b.id % tiles_u) * 64 + (threadIdx.x & 63);
+  const unsigned wg = rt.order_bt ? (unsigned)rt.order_bt[b.id] : b.id;
+  const int view = (int)(wg / tiles_u) * 4 + (threadIdx.x >> 6), bin = (int)(wg % tiles_u) * 64 + (threadIdx.x & 63);
   const bool valid = view < g.nv && bin < g.nu;
   const long long r = valid ? (long long)view * g.nu + bin : 0;
   const T hr = valid ? rt.h[r] : T(0);
