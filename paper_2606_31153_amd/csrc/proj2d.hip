@@ -396,14 +396,18 @@ __global__ __launch_bounds__(kBlock) void k_back_adj(GeomDev g, RayTab<T> rt, co
 // ---------------------------------------------------------------------------
 // pixel-driven: B (back projection by linear interpolation on the detector)
 // ---------------------------------------------------------------------------
-// Pixel of this thread in tile blk, and the thread's view group.
+// Pixel of this thread in tile blk, and the thread's view group.  A group is
+// a whole number of wavefronts, so the group index, and with it every view
+// index, is uniform across a wavefront: it is returned as such, which keeps
+// the per-view constants in scalar loads.
 __device__ inline int tile_pixel(const GeomDev &g, unsigned blk, int &i, int &j) {
   const int tiles_x = (g.nx + kPixTileX - 1) / kPixTileX;
   const int tx = (int)blk % tiles_x, ty = (int)blk / tiles_x;
   constexpr int tpix = kPixTileX * kPixTileY;
+  static_assert(tpix % 64 == 0, "a view group must be whole wavefronts");
   i = tx * kPixTileX + (int)(threadIdx.x % kPixTileX);
   j = ty * kPixTileY + (int)((threadIdx.x % tpix) / kPixTileX);
-  return (int)(threadIdx.x / tpix);
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / tpix));
 }
 
 // Sum of the view groups' partial sums of a pixel, in group order, returned
