@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.
 // kBtLines lines per step, the taps of all of them loaded before any is
 // weighted.
-constexpr int kBtLines = 2;
+constexpr int kBtLines = 6;
 template <typename T, bool FAN, int CNT, int MAXC>
 __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, long long r,
                                  T hr, int nrt) {
