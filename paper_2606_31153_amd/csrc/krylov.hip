@@ -35,7 +35,7 @@ namespace gkb {
 
 namespace {
 
-constexpr int CH = 16;  // columns per workgroup in the multi-dot kernels
+constexpr int CH = 4;   // columns per workgroup in the multi-dot kernels
 constexpr int RPT = 4;  // rows per thread (one 4-wide vector load)
 constexpr int ROWS_PER_BLOCK = kBlock * RPT;
 
@@ -93,7 +93,7 @@ __device__ inline void store_quad(T *__restrict__ p, long long r, long long dim,
 }
 
 // ---- partial inner products: workgroup (x, y) covers rows [x*1024, x*1024+1024)
-// and columns [16 y, 16 y + 16) of Q (columns 0..ncol-1), against w.
+// and columns [CH y, CH y + CH) of Q (columns 0..ncol-1), against w.
 // Result: partials[x * ldp + column].
 template <typename T>
 __device__ inline void dots_body(const Ctl &ctl, const T *__restrict__ V, long long ld, const T *__restrict__ w,
