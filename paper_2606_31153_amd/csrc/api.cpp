@@ -664,6 +664,7 @@ struct gkb_ctx {
   std::map<std::string, std::unique_ptr<DevTables>> tables;
   // scratch for standalone projector calls and reductions
   DevBuf xpad, ypad, partials;
+  DevBuf ywpad;  // fan-beam A^T input as (w y, w) pairs, apart from ypad so that neither layout overwrites the other's pads
   // solve workspace
   DevBuf Q, yk, rdbl, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
   int *host_flag = nullptr;      // host-mapped
@@ -869,6 +870,7 @@ Epi<T> plain_epi() {
 gkb_status ensure_scratch(gkb_ctx *c, const GeomDev &g, size_t elem, long long nblocks_times_cols) {
   HIPC(c->xpad.ensure(elem * (size_t)g.pad_elems));
   HIPC(c->ypad.ensure(2 * elem * (size_t)g.ypad_elems));
+  if (g.kind == GKB_FAN2D) HIPC(c->ywpad.ensure(2 * elem * (size_t)g.ypad_elems));
   HIPC(c->partials.ensure(sizeof(double) * std::max<long long>(nblocks_times_cols, 1024)));
   return GKB_OK;
 }
@@ -1176,7 +1178,13 @@ struct Solver {
   long long n, m, dimq, dims;
   long long ldq;  // column stride of Q (a multiple of 4)
   T *Q = nullptr, *yk = nullptr, *s = nullptr, *w = nullptr, *tn = nullptr, *tm = nullptr;
-  T *xpad = nullptr, *ypad = nullptr;
+  T *xpad = nullptr, *ypad = nullptr, *ywpad = nullptr;
+  // Padded inputs written by the producers.  A kernel that makes a vector the
+  // next projector reads also writes its padded copy (PadOut), and the tags
+  // name the vector whose copy each padded buffer holds, so the consumer
+  // skips its padding kernel.  2D solves without the learned filter only.
+  enum Tag : int { TAG_NONE = 0, TAG_Q, TAG_YK, TAG_S, TAG_TM, TAG_BQ, TAG_ATS };
+  int tag_x = TAG_NONE, tag_y = TAG_NONE, tag_yw = TAG_NONE;
   Ctl ctl{};
   double *partials = nullptr;
   hipStream_t st;
@@ -1225,6 +1233,7 @@ struct Solver {
     tm = c->tmp_m.as<T>();
     xpad = c->xpad.as<T>();
     ypad = c->ypad.as<T>();
+    ywpad = (g.kind == GKB_FAN2D) ? c->ywpad.as<T>() : ypad;
     double *dp = c->ctl_d.as<double>();
     ctl.ip = c->ctl_i.as<int>();
     ctl.dp = dp;
@@ -1257,52 +1266,94 @@ struct Solver {
 
   // ----- the four projectors with device-addressed operands -----
   bool cone() const { return g.kind == GKB_CONE3D; }
-  void A(Col<const T> in, Col<T> out, const Epi<T> &e) {
+  bool fusing() const { return !cone() && !filtered(); }
+  // padded copies in the layouts A / B^T (image), B (sinogram) and A^T read
+  PadOut<T> pad_image_out() const {
+    PadOut<T> p{};
+    p.dst = xpad;
+    p.kind = PADK_IMAGE;
+    p.n1 = g.nx;
+    p.lead = g.ldR;
+    p.off0 = g.pad;
+    p.ldT = g.ldT;
+    p.offT = d.has_coldom ? g.offT : -1;
+    return p;
+  }
+  PadOut<T> pad_sino_out() const {
+    PadOut<T> p{};
+    p.dst = ypad;
+    p.kind = PADK_SINO;
+    p.n1 = g.nu;
+    p.lead = g.ldY;
+    p.off0 = g.padY;
+    return p;
+  }
+  PadOut<T> pad_adj_out() const {
+    if (g.kind != GKB_FAN2D) return pad_sino_out();
+    PadOut<T> p = pad_sino_out();
+    p.dst = ywpad;
+    p.kind = PADK_SINO_W;
+    p.w = rt_of<T>(d).w;
+    return p;
+  }
+  // the four projectors; `tag` names the input (TAG_NONE: unknown), and the
+  // padding kernel is skipped when the padded buffer already holds it
+  void A(Col<const T> in, Col<T> out, const Epi<T> &e, int tag = TAG_NONE) {
     if (cone()) {
       launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stop, st);
       TraceScope ts(c, "fwd");
       launch_cone_fwd<T>(g, ct_of<T>(d), xpad, out, e, stop, st);
       return;
     }
-    launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
+    if (tag == TAG_NONE || tag_x != tag) launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
+    tag_x = tag;
     TraceScope ts(c, "fwd");
     launch_fwd<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
   }
-  void Bt(Col<const T> in, Col<T> out, const Epi<T> &e) {
+  void Bt(Col<const T> in, Col<T> out, const Epi<T> &e, int tag = TAG_NONE) {
     if (cone()) {
       launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stop, st);
       TraceScope ts(c, "back_adj");
       launch_cone_back_adj<T>(g, ct_of<T>(d), vt_of<T>(d), xpad, out, e, stop, st);
       return;
     }
-    launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
+    if (tag == TAG_NONE || tag_x != tag) launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
+    tag_x = tag;
     TraceScope ts(c, "back_adj");
     launch_back_adj<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
   }
   // stp: the stop flag the launches test (nullptr: run unconditionally)
-  void B(Col<const T> in, T *out, const Epi<T> &e, const int *stp) {
+  void B(Col<const T> in, T *out, const Epi<T> &e, const int *stp, int tag = TAG_NONE) {
     if (cone()) {
       launch_cone_pad_sino<T>(g, in, ypad, stp, st);
       TraceScope ts(c, "back");
       launch_cone_back<T>(g, vt_of<T>(d), ypad, out, e, stp, st);
       return;
     }
-    launch_pad_sino<T>(g, in, ypad, stp, st);
+    if (tag == TAG_NONE || tag_y != tag) launch_pad_sino<T>(g, in, ypad, stp, st);
+    tag_y = tag;
     TraceScope ts(c, "back");
     launch_back<T>(g, vt_of<T>(d), ypad, out, e, stp, st);
   }
-  void B(Col<const T> in, T *out, const Epi<T> &e) { B(in, out, e, stop); }
-  void At(Col<const T> in, T *out, const Epi<T> &e) {
+  void B(Col<const T> in, T *out, const Epi<T> &e, int tag = TAG_NONE) { B(in, out, e, stop, tag); }
+  void At(Col<const T> in, T *out, const Epi<T> &e, int tag = TAG_NONE) {
     if (cone()) {
       launch_cone_weight_sino<T>(g, ct_of<T>(d), in, ypad, stop, st);
       TraceScope ts(c, "fwd_adj");
       launch_cone_fwd_adj<T>(g, ct_of<T>(d), vt_of<T>(d), ypad, out, e, stop, st);
       return;
     }
-    launch_pad_sino_adj<T>(g, rt_of<T>(d), in, ypad, stop, st);
+    int &tg = (g.kind == GKB_FAN2D) ? tag_yw : tag_y;
+    if (tag == TAG_NONE || tg != tag) launch_pad_sino_adj<T>(g, rt_of<T>(d), in, ywpad, stop, st);
+    tg = tag;
     TraceScope ts(c, "fwd_adj");
-    launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), ypad, out, e, stop, st);
+    launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), ywpad, out, e, stop, st);
   }
+  // after a launch whose epilogue wrote the padded copy of the vector `tag`
+  void wrote_image(int tag) { tag_x = tag; }
+  void wrote_sino(int tag) { tag_y = tag; }
+  void wrote_adj(int tag) { (g.kind == GKB_FAN2D ? tag_yw : tag_y) = tag; }
+  void forget_pads() { tag_x = tag_y = tag_yw = TAG_NONE; }
 
   // s~ <- M q_k - alpha_k/t_k s~ (s stored unnormalised, s_k = s~/t_k); t_{k+1}; Y_k
   void apply_M() {
@@ -1310,21 +1361,33 @@ struct Solver {
     e.prev_sel = PREV_NEG_ALPHA_OVER_T;
     e.prev = col<const T>(s);
     e.norm_to_t = 1;
+    const bool fu = fusing();
+    Epi<T> pe = plain_epi<T>();
     if (mode == MODE_BA) {  // Y_k = A q_k ; s~ = B Y_k - ...  (B F Y_k with the filter)
-      A(qcol(-1), col<T>(yk), plain_epi<T>());
+      if (fu) pe.pout = pad_sino_out();
+      A(qcol(-1), col<T>(yk), pe, TAG_Q);
+      if (fu) wrote_sino(TAG_YK);
       if (filtered()) {
         filter(NET_F, col<const T>(yk));
         B(col<const T>(c->nout.as<T>()), s, e);
       } else {
-        B(col<const T>(yk), s, e);
+        if (fu) e.pout = pad_image_out();
+        B(col<const T>(yk), s, e, TAG_YK);
+        if (fu) wrote_image(TAG_S);
       }
     } else if (mode == MODE_AB) {  // Y_k = A B q_k ; s~ = Y_k - ...
-      B(qcol(-1), tn, plain_epi<T>());
+      if (fu) pe.pout = pad_image_out();
+      B(qcol(-1), tn, pe, TAG_Q);
+      if (fu) wrote_image(TAG_BQ);
       e.out_raw = col<T>(yk);
-      A(col<const T>(tn), col<T>(s), e);
+      if (fu) e.pout = pad_adj_out();
+      A(col<const T>(tn), col<T>(s), e, TAG_BQ);
+      if (fu) wrote_adj(TAG_S);
     } else {  // matched: Y_k = A q_k ; s~ = Y_k - ...
       e.out_raw = col<T>(yk);
-      A(qcol(-1), col<T>(s), e);
+      if (fu) e.pout = pad_adj_out();
+      A(qcol(-1), col<T>(s), e, TAG_Q);
+      if (fu) wrote_adj(TAG_S);
     }
   }
 
@@ -1346,21 +1409,26 @@ struct Solver {
       e1.prev_sel = PREV_NEG_TNEXT;
       e1.prev = qcol(-1);
     }
+    const bool fu = fusing();
     if (mode == MODE_BA) {  // A^T (B^T s)  (A^T F^T B^T s with the filter)
-      Bt(col<const T>(s), col<T>(tm), e0);
+      if (fu) e0.pout = pad_adj_out();
+      Bt(col<const T>(s), col<T>(tm), e0, TAG_S);
+      if (fu) wrote_adj(TAG_TM);
       if (filtered()) {
         filter(NET_FT, col<const T>(tm));
         At(col<const T>(c->nout.as<T>()), w, e1);
       } else {
-        At(col<const T>(tm), w, e1);
+        At(col<const T>(tm), w, e1, TAG_TM);
       }
     } else if (mode == MODE_AB) {  // B^T (A^T s)
-      At(col<const T>(s), tn, e0);
-      Bt(col<const T>(tn), col<T>(w), e1);
+      if (fu) e0.pout = pad_image_out();
+      At(col<const T>(s), tn, e0, TAG_S);
+      if (fu) wrote_image(TAG_ATS);
+      Bt(col<const T>(tn), col<T>(w), e1, TAG_ATS);
     } else {  // A^T s
       Epi<T> e = e1;
       e.in_sel = IN_INV_TNEXT;
-      At(col<const T>(s), w, e);
+      At(col<const T>(s), w, e, TAG_S);
     }
   }
 
@@ -1389,7 +1457,21 @@ struct Solver {
       // no reorthogonalisation: only the norm alpha_{k+1} = ||w|| (no columns)
       launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st, 0);
     }
-    launch_normalize<T>(ctl, w, Q, ldq, dimq, st);
+    normalize();
+  }
+
+  // q_{k+1} = w / alpha_{k+1}, with the padded copy the next iteration's first
+  // projector reads (A: image; AB's B: sinogram)
+  void normalize() {
+    if (!fusing()) {
+      launch_normalize<T>(ctl, w, Q, ldq, dimq, st);
+      return;
+    }
+    launch_normalize<T>(ctl, w, Q, ldq, dimq, st, mode == MODE_AB ? pad_sino_out() : pad_image_out());
+    if (mode == MODE_AB)
+      wrote_sino(TAG_Q);
+    else
+      wrote_image(TAG_Q);
   }
 };
 
@@ -1426,6 +1508,14 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   HIPC(hipMemcpyAsync(S.ctl.dp, hdp, sizeof hdp, hipMemcpyHostToDevice, st));
   *c->host_flag = 0;
 
+  // the padded buffers the producers write into keep zero pads from here on
+  if (S.fusing()) {
+    HIPC(hipMemsetAsync(S.xpad, 0, sizeof(T) * (size_t)g.pad_elems, st));
+    HIPC(hipMemsetAsync(S.ypad, 0, sizeof(T) * (size_t)g.ypad_elems, st));
+    if (g.kind == GKB_FAN2D) HIPC(hipMemsetAsync(S.ywpad, 0, 2 * sizeof(T) * (size_t)g.ypad_elems, st));
+  }
+  S.forget_pads();
+
   // start-up (k = 0): r_0 = -b, ||b||; s~_1 = rhs, t_1; q_1, alpha_1
   launch_resid_init<T>(S.ctl, b, g.m, S.partials, st);
   if (mode == MODE_BA) {
@@ -1443,7 +1533,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   }
   S.apply_Mt(true);
   launch_norm_to<T>(S.ctl, S.w, S.dimq, NORM_ALPHA1, S.partials, st);
-  launch_normalize<T>(S.ctl, S.w, S.Q, S.ldq, S.dimq, st);
+  S.normalize();
   HIPC(hipGetLastError());
   double h3[3];
   HIPC(hipMemcpyAsync(&h3[0], S.ctl.t + 1, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1482,6 +1572,8 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
       }
     }
     HIPC(hipGetLastError());
+    // launches queued after the stop did not run: no padded copy is known
+    S.forget_pads();
     // solution x = Q_k u_k (BA, matched) or B (Q_k u_k) (AB)
     if (mode == MODE_AB) {
       launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, S.tm, st);

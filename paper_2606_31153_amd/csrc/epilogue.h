@@ -6,6 +6,25 @@
 
 namespace gkb {
 
+// Element idx of a vector into its padded copy (see PadOut).
+template <typename T>
+__device__ inline void pad_store(const PadOut<T> &p, long long idx, T v) {
+  const int a = (int)(idx / p.n1), b = (int)(idx - (long long)a * p.n1);
+  if (p.kind == PADK_IMAGE) {  // a = row j, b = column i
+    p.dst[(long long)a * p.lead + p.off0 + b] = v;
+    if (p.offT >= 0) p.dst[p.offT + (long long)b * p.ldT + p.off0 + a] = v;
+  } else {  // a = view, b = bin
+    const long long q = (long long)a * p.lead + p.off0 + b;
+    if (p.kind == PADK_SINO) {
+      p.dst[q] = v;
+    } else {
+      const T w = p.w[idx];
+      p.dst[2 * q] = w * v;
+      p.dst[2 * q + 1] = w;
+    }
+  }
+}
+
 // Epilogue shared by all projector kernels.  Every thread of the block calls
 // it (the norm reduction needs the whole block).
 template <typename T>
@@ -26,6 +45,7 @@ __device__ inline void epilogue(const Epi<T> &e, long long idx, bool valid, T ra
   if (valid) {
     outp[idx] = outT;
     if (e.out_raw.base) e.out_raw.get()[idx] = raw;
+    if (e.pout.dst) pad_store(e.pout, idx, outT);
   }
   // ||out||^2: one partial per workgroup; a finalising kernel launched after
   // the projector sums them into t[k+1]

@@ -82,6 +82,26 @@ struct Col {
 enum EpiIn : int { IN_ONE = 0, IN_INV_TNEXT = 1 };
 enum EpiPrev : int { PREV_NONE = 0, PREV_NEG_ALPHA_OVER_T = 1, PREV_NEG_TNEXT = 2 };
 
+// A padded copy of a kernel's output, in the layout the next projector reads,
+// written besides the output itself.  Only interior positions are written:
+// the pads keep the zeros they were given when the solve started.
+enum PadKind : int {
+  PADK_IMAGE = 0,   // image [ny][nx]: row-major region (and the column-major one at offT >= 0)
+  PADK_SINO = 1,    // sinogram [nv][nu]: rows of lead = nu + 2 off0
+  PADK_SINO_W = 2   // sinogram as (w y, w) pairs (fan-beam A^T), w per ray
+};
+template <typename T>
+struct PadOut {
+  T *dst;              // nullptr: no padded copy
+  int kind;            // PadKind
+  int n1;              // image: nx; sinogram: nu
+  int lead;            // image: ldR; sinogram: ldY
+  int off0;            // image: pad; sinogram: padY
+  int ldT;             // image: column-major line length
+  long long offT;      // image: column-major region (-1: none)
+  const T *w;          // PADK_SINO_W: per-ray weights
+};
+
 template <typename T>
 struct Epi {
   Ctl ctl;             // valid when use_ctl
@@ -92,6 +112,7 @@ struct Epi {
   Col<const T> prev;
   Col<T> out_raw;      // base == nullptr: not stored
   double *partials;    // per-block partial sums of ||out||^2 (norm_to_t)
+  PadOut<T> pout;      // padded copy of the output (pout.dst == nullptr: none)
 };
 
 // Geometry tables kept in device memory (one set per geometry and dtype).
@@ -329,7 +350,8 @@ template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        hipStream_t s, int reorth = 1);
 template <typename T>
-void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s);
+void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s,
+                      PadOut<T> pout = PadOut<T>{});
 template <typename T>
 void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream_t s);
 template <typename T>

@@ -28,6 +28,7 @@
 #include <algorithm>
 
 #include "batch.h"
+#include "epilogue.h"
 #include "internal.h"
 #include "reduce.h"
 
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_norm_finalize(Ctl ctl, const double 
 // ---- Q[:, k] = w / alpha[k+1] ------------------------------------------------
 template <typename T>
 __device__ inline void normalize_body(const Ctl &ctl, const T *__restrict__ w, T *__restrict__ Q, long long ld,
-                                      long long dim, unsigned blk) {
+                                      long long dim, unsigned blk, const PadOut<T> &pout) {
   const int k = ctl.ip[CI_K];
   const double inv = 1.0 / ctl.alpha[k + 1];
   T *q = Q + (long long)k * ld;
@@ -310,13 +311,19 @@ __device__ inline void normalize_body(const Ctl &ctl, const T *__restrict__ w, T
 #pragma unroll
   for (int i = 0; i < RPT; ++i) out[i] = (T)(v[i] * inv);
   store_quad(q, r, dim, out);
+  if (pout.dst) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (r + i < dim) pad_store(pout, r + i, out[i]);
+  }
 }
 
+// q_{k+1} = w / alpha_{k+1}, and optionally its padded copy for the next projector
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restrict__ w, T *__restrict__ Q,
-                                                      long long ld, long long dim) {
+                                                      long long ld, long long dim, PadOut<T> pout) {
   if (ctl.ip[CI_STOP]) return;
-  normalize_body(ctl, w, Q, ld, dim, blockIdx.x);
+  normalize_body(ctl, w, Q, ld, dim, blockIdx.x, pout);
 }
 
 // ---- projected solve, discrepancy test, advance --------------------------------
@@ -636,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void kb_normalize(BatchDev<T> bd) {
   Blk b;
   const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
   if (skip(bd, d)) return;
-  normalize_body<T>(d.ctl, d.w, d.Q, d.ldq, d.dimq, b.id);
+  normalize_body<T>(d.ctl, d.w, d.Q, d.ldq, d.dimq, b.id, PadOut<T>{});
 }
 
 template <typename T>
@@ -724,8 +731,8 @@ void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, i
   if (last) launch_norm_finalize(ctl, partials, nb, NORM_ALPHA1, ctl.ip + CI_STOP, s);
 }
 template <typename T>
-void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim);
+void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s, PadOut<T> pout) {
+  hipLaunchKernelGGL(k_normalize<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim, pout);
 }
 template <typename T>
 void launch_resid_init(Ctl ctl, const T *b, long long m, double *partials, hipStream_t s) {
@@ -813,7 +820,7 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_cgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t); \
   template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, hipStream_t, \
                                      int);                                                                  \
-  template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t);               \
+  template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t, PadOut<T>);               \
   template void launch_resid<T>(Ctl, const T *, long long, double *, hipStream_t);                         \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \

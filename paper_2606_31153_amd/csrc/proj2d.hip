@@ -714,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, co
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ inline Epi<T> make_epi(const SliceDev<T> &d, const EpiCfg &ec, int k) {
-  Epi<T> e;
+  Epi<T> e{};
   e.ctl = d.ctl;
   e.use_ctl = 1;
   e.in_sel = ec.in_sel;
