@@ -335,6 +335,10 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     // over the candidate window; sin(x) = x is exact to x^2 / 6 relative
     const double xmax = (hmax_at + 1.0) * du;
     gd.at_fast = (xmax * xmax / 6.0 <= 1e-6) ? 1 : 0;
+    // A: adjacent rays are D dg apart at the centre; below 0.9 pixels the 64
+    // rays of a wavefront usually cross a line within 64 pixels (the kernel
+    // checks every line)
+    gd.fwd_seg = (g->src_dist * du <= 0.9) ? 1 : 0;
   }
   gd.nc_bt = (int)std::floor(2.0 * hmax_bt) + 1;
   gd.nc_at = (int)std::floor(2.0 * hmax_at) + 1;
@@ -342,7 +346,8 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   gd.ldR = nx + 2 * gd.pad;
   gd.ldT = ny + 2 * gd.pad;
   gd.offT = (long long)ny * gd.ldR;
-  gd.pad_elems = gd.offT + (long long)nx * gd.ldT;
+  // 64 elements of slack: A's segment loads read up to 62 past the end of a padded line
+  gd.pad_elems = gd.offT + (long long)nx * gd.ldT + 64;
   gd.uclamp_at = hmax_at + 1.0;
   gd.padY = std::max(4, gd.nc_at + (int)std::ceil(2.0 * hmax_at) + 3);
   gd.ldY = nu + 2 * gd.padY;

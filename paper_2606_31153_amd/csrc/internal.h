@@ -163,6 +163,7 @@ struct GeomDev {
   int fast_atan;       // fan, float: every pixel's fan angle has |tan| <= 0.5
   int bt_fast;         // fan B^T, float: series forms of the candidate weights (relative error <= 1e-6)
   int at_fast;         // fan A^T, float: first-order sine of the candidate angles (relative error <= 1e-6)
+  int fwd_seg;         // A, float: adjacent rays cross a line less than a pixel apart (segment loads)
   // padded image: row-major region (ny lines of ldR = nx + 2 pad), then the
   // column-major region at offT (nx lines of ldT = ny + 2 pad)
   int pad, ldR, ldT;

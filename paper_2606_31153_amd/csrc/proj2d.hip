@@ -162,6 +162,73 @@ __global__ __launch_bounds__(256) void k_pad_sino_w(Col<const T> yc, const T *__
 // ---------------------------------------------------------------------------
 // ray-driven: A (Joseph forward)
 // ---------------------------------------------------------------------------
+// One line's taps of every lane from a segment of the line: each lane loads
+// one element of the 64 from s0 (the wavefront's smallest left tap, from its
+// first and last lanes, whose crossings bound the others') and the lanes
+// exchange them, so the texture path sees one contiguous load instead of 64
+// scattered pairs.  Where some lane's pair is not inside the segment (the
+// rays spread over more than 63 pixels, or are not ordered) the pair is
+// gathered instead; the test is uniform over the wavefront.
+__device__ inline float seg_lerp(const float *__restrict__ line, float c, int lane) {
+  const float f = floorf(c);
+  const int fi = (int)f;
+  const int s0 = min(__builtin_amdgcn_readlane(fi, 0), __builtin_amdgcn_readlane(fi, 63));
+  const int dl = fi - s0;
+  const float v = line[s0 + lane];
+  float t0, t1;
+  if (__ballot((unsigned)dl > 62u) == 0) {
+    t0 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(dl * 4, __builtin_bit_cast(int, v)));
+    t1 = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(dl * 4 + 4, __builtin_bit_cast(int, v)));
+  } else {
+    const auto p = load_pair(line + fi);
+    t0 = p.x;
+    t1 = p.y;
+  }
+  return fmaf(c - f, t1 - t0, t0);
+}
+
+// A for a wavefront of 64 valid rays that all step along the same axis: one
+// loop over the lines any of them crosses (a ray's crossings outside its own
+// range fall into the zero padding and add nothing), eight lines per step.
+__device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, const float *__restrict__ pad,
+                                    long long r) {
+  const int meta = rt.meta[r];
+  const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
+  const bool rowdom = (meta >> 30) & 1;
+  // lines any lane crosses; none when every ray misses the image
+  const int wlo = wave_min(lo <= hi ? lo : (1 << 20)), whi = wave_max(lo <= hi ? hi : -1);
+  if (wlo > whi) return 0.f;
+  const float base = rt.base[r], slope = rt.slope[r];
+  const int ld = rowdom ? g.ldR : g.ldT;
+  const float mid = rowdom ? 0.5f * float(g.ny - 1) : 0.5f * float(g.nx - 1);
+  const float *__restrict__ line0 = pad + (rowdom ? 0LL : g.offT) + g.pad;
+  const float clo = -1.5f, chi = float(rowdom ? g.nx : g.ny) + 0.5f;
+  const int lane = threadIdx.x & 63;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int j = wlo;
+  for (; j <= whi - 7; j += 8) {
+    float s[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float c = clampv(fmaf(float(j + q) - mid, slope, base), clo, chi);
+      s[q] = seg_lerp(line0 + (long long)(j + q) * ld, c, lane);
+    }
+    a0 += s[0];
+    a1 += s[1];
+    a2 += s[2];
+    a3 += s[3];
+    a0 += s[4];
+    a1 += s[5];
+    a2 += s[6];
+    a3 += s[7];
+  }
+  for (; j <= whi; ++j) {
+    const float c = clampv(fmaf(float(j) - mid, slope, base), clo, chi);
+    a0 += seg_lerp(line0 + (long long)j * ld, c, lane);
+  }
+  return ((a0 + a1) + (a2 + a3)) * rt.w[r];
+}
+
 template <typename T>
 __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
                                 const Epi<T> &e, Blk b) {
@@ -169,7 +236,16 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
   const long long r = (long long)wg * kBlock + threadIdx.x;
   const bool valid = r < g.m;
   T acc = T(0);
-  if (valid) {
+  bool seg = false;
+  if constexpr (sizeof(T) == 4) {
+    if (g.fwd_seg) {
+      // every lane a ray, all stepping along the same axis
+      const bool rd = valid && ((rt.meta[r] >> 30) & 1);
+      seg = __ballot(!valid) == 0 && (__ballot(rd) == 0 || __ballot(!rd) == 0);
+    }
+    if (seg) acc = fwd_ray_seg(g, rt, pad, r);
+  }
+  if (valid && !seg) {
     const int meta = rt.meta[r];
     const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
     const bool rowdom = (meta >> 30) & 1;

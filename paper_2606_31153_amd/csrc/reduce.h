@@ -20,6 +20,14 @@ __device__ inline int wave_max(int v) {
   return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Minimum of an int over the 64 lanes of a wavefront, wave-uniform.  Every
+// lane of the wavefront must take part.
+__device__ inline int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 // Sum over a workgroup of NT threads; the result is valid in thread 0.
 // `lds` holds NT/64 doubles.  Fixed order: lane butterfly, then waves 0..NT/64-1.
 template <int NT>
