@@ -37,6 +37,7 @@ namespace gkb {
 namespace {
 
 constexpr int CH = 4;   // columns per workgroup in the multi-dot kernels
+constexpr int UCH = 16; // columns per unrolled step of the update loops
 constexpr int RPT = 4;  // rows per thread (one 4-wide vector load)
 constexpr int ROWS_PER_BLOCK = kBlock * RPT;
 
@@ -174,9 +175,9 @@ __device__ __attribute__((always_inline)) inline void cgs_update_split(const Ctl
   // the leading member starts from w, the others from 0
   double acc[RPT] = {0.0, 0.0, 0.0, 0.0};
   if (mem == 0) load_quad(w, r, dim, acc);
-  for (int c0 = j0; c0 < j1; c0 += CH) {
+  for (int c0 = j0; c0 < j1; c0 += UCH) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
+    for (int j = 0; j < UCH; ++j) {
       if (c0 + j < j1) {
         double q[RPT];
         load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
@@ -226,9 +227,9 @@ __device__ __attribute__((always_inline)) inline void cgs_update_rows(const Ctl 
   const long long r = ((long long)b.id * kBlock + threadIdx.x) * RPT;
   double acc[RPT];
   load_quad(w, r, dim, acc);
-  for (int c0 = 0; c0 < ncols; c0 += CH) {
+  for (int c0 = 0; c0 < ncols; c0 += UCH) {
 #pragma unroll
-    for (int j = 0; j < CH; ++j) {
+    for (int j = 0; j < UCH; ++j) {
       if (c0 + j < ncols) {
         double q[RPT];
         load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
