@@ -9,7 +9,8 @@ namespace gkb {
 // Element idx of a vector into its padded copy (see PadOut).
 template <typename T>
 __device__ inline void pad_store(const PadOut<T> &p, long long idx, T v) {
-  const int a = (int)(idx / p.n1), b = (int)(idx - (long long)a * p.n1);
+  // 2D vectors have fewer than 2^31 elements
+  const unsigned a = (unsigned)idx / (unsigned)p.n1, b = (unsigned)idx - a * (unsigned)p.n1;
   if (p.kind == PADK_IMAGE) {  // a = row j, b = column i
     p.dst[(long long)a * p.lead + p.off0 + b] = v;
     if (p.offT >= 0) p.dst[p.offT + (long long)b * p.ldT + p.off0 + a] = v;
