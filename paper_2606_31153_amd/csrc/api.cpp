@@ -1223,7 +1223,8 @@ struct Solver {
     const long long vb = std::max<long long>(
         {(long long)vec_blocks(dimq), (long long)vec_blocks(m), (long long)vec_blocks(dims)});
     const long long pb = std::max<long long>(
-        {(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2), (long long)upd_blocks(dimq)});
+        {(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2), (long long)upd_blocks(dimq),
+         (long long)mid_blocks(dimq) * (K + 2)});
     gkb_status stt = ensure_scratch(c, g, sizeof(T), pb);
     if (stt != GKB_OK) return stt;
     if (!c->host_flag) {
@@ -1437,10 +1438,10 @@ struct Solver {
     }
   }
 
-  void iteration(bool reorth) {
+  void iteration(bool reorth, int k) {
     apply_M();
     apply_Mt(false);
-    reorth_and_normalize_impl(reorth);
+    reorth_and_normalize_impl(reorth, k);
     {
       TraceScope ts(c, "small_solve");
       launch_small_solve(ctl, st);
@@ -1451,12 +1452,17 @@ struct Solver {
     }
   }
 
-  void reorth_and_normalize_impl(bool reorth) {
+  // k: the iteration (the columns q_1..q_k of Q)
+  void reorth_and_normalize_impl(bool reorth, int k) {
     TraceScope ts(c, "reorth");
     if (reorth) {
       launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, st);
-      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+      if (K <= mid_max_k(sizeof(T))) {
+        launch_cgs_mid<T>(ctl, Q, ldq, w, dimq, partials, k, st);
+      } else {
+        launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, st);
+        launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+      }
       launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
     } else {
       // no reorthogonalisation: only the norm alpha_{k+1} = ||w|| (no columns)
@@ -1568,7 +1574,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     const bool reorth = o->reorth != 0;
     int launched = 0;
     for (int k = 1; k <= o->k_max; ++k) {
-      S.iteration(reorth);
+      S.iteration(reorth, k);
       HIPC(hipEventRecord(evs[k % L], st));
       ++launched;
       if (k >= L) {
@@ -1728,6 +1734,8 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
   bl.nc_bt = 2;
   bl.nc_at = 2;
   bl.kmax = 1;
+  bl.mid_kmax = -1;
+  bl.any_plain = 0;
   size_t bytesT = 0, ndbl = (size_t)ns * CD_COUNT;
   for (int s = 0; s < ns; ++s) {
     DevTables *d = nullptr;
@@ -1752,6 +1760,12 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.cnt[BF_PIX] = pixel_blocks(g);
     h.cnt[BF_VQ] = vec_blocks(h.dimq);
     h.cnt[BF_VQU] = upd_blocks(h.dimq);
+    const bool mid = h.K <= mid_max_k(sizeof(T));
+    h.cnt[BF_VQM] = mid ? mid_blocks(h.dimq) : 0;
+    if (mid)
+      bl.mid_kmax = std::max(bl.mid_kmax, h.K);
+    else
+      bl.any_plain = 1;
     h.cnt[BF_VM] = vec_blocks(g.m);
     h.cnt[BF_PADR] = (int)std::min<long long>(((long long)g.ny * g.ldR + 255) / 256, 2048);
     h.cnt[BF_PADC] = d->has_coldom ? ((g.ldT + 31) / 32) * ((g.nx + 31) / 32) : 0;
@@ -1777,7 +1791,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.opart = ndbl;
     ndbl += (size_t)std::max<long long>(
         {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
-         (long long)h.cnt[BF_VQU],
+         (long long)h.cnt[BF_VQU], (long long)h.cnt[BF_VQM] * (h.K + 2),
          (long long)h.cnt[BF_VM] * (h.K + 2), 1024LL});
     ndbl = (ndbl + 31) / 32 * 32;
   }
@@ -1965,8 +1979,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       {
         TraceScope ts(c, "reorth");
         launch_b_cgs_dots<T>(bd, bl, st);
-        launch_b_cgs_update<T>(bd, bl, 0, st);
-        launch_b_cgs_dots<T>(bd, bl, st);
+        launch_b_cgs_second<T>(bd, bl, k, st);
         launch_b_cgs_update<T>(bd, bl, 1, st);
         launch_b_normalize<T>(bd, bl, st);
       }

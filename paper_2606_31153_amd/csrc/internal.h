@@ -260,6 +260,7 @@ enum BlockFam : int {
   BF_PADC,     // column-major image padding (32x32 tiles)
   BF_PADS,     // sinogram padding
   BF_VQU,      // CGS update over Q's dimension (upd_blocks)
+  BF_VQM,      // fused CGS2 middle over Q's dimension (mid_blocks; slices with k_max <= mid_max_k)
   BF_COUNT
 };
 
@@ -277,6 +278,8 @@ struct BatchLaunch {
   int na;
   int tot[BF_COUNT];
   int kmax;      // largest k_max over the slices
+  int mid_kmax;  // largest k_max over the slices that take the fused CGS2 middle (-1: none)
+  int any_plain; // some slice's k_max exceeds mid_max_k (separate update and inner products)
   int fan;       // all slices fan beam (else all parallel beam)
   int nc_bt, nc_at;
 };
@@ -340,6 +343,19 @@ int cone_voxel_blocks(const GeomDev &g);
 // ---- Krylov vector kernels (krylov.hip) ----
 int vec_blocks(long long dim);
 int upd_blocks(long long dim);  // workgroups of the CGS update
+// Fused middle of CGS2 (w -= Q c, then the inner products of the new w with
+// the same columns, from one read of Q): a workgroup takes kMidSub sub-blocks
+// of 64 rows and holds a sub-block's columns in LDS (kMidLd entries each,
+// within kMidLdsBytes).  Solves whose k_max exceeds mid_max_k use the separate
+// update and inner-product kernels.
+constexpr int kMidSub = 8, kMidLd = 65, kMidLdsBytes = 58 * 1024;  // + 4.5 KB static LDS
+__host__ __device__ constexpr int mid_max_k(int elem) {
+  return (kMidLdsBytes / (kMidLd * elem) < kBlock ? kMidLdsBytes / (kMidLd * elem) : kBlock) - 1;
+}
+int mid_blocks(long long dim);
+template <typename T>
+void launch_cgs_mid(Ctl ctl, const T *Q, long long ld, T *w, long long dim, double *partials, int k,
+                    hipStream_t s);  // k: the iteration (columns 0..k-1)
 template <typename T>
 void launch_copy(const T *src, T *dst, long long n, hipStream_t s);
 template <typename T>
@@ -425,6 +441,10 @@ template <typename T>
 void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s);
+// second CGS2 round up to its coefficients: the fused middle for slices with
+// k_max <= mid_max_k, update + inner products for the others
+template <typename T>
+void launch_b_cgs_second(const BatchDev<T> &bd, const BatchLaunch &bl, int k, hipStream_t s);
 template <typename T>
 void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>

@@ -139,6 +139,20 @@ def test_batch_without_reorthogonalisation(ctx):
 
 
 @pytest.mark.parametrize("method", [gk.GKB_METHOD_BA, gk.GKB_METHOD_AB])
+def test_batch_mixes_fused_and_separate_cgs(ctx, method):
+    # FP64 slices with k_max 113 (second CGS round as one fused pass over Q)
+    # and 114 (separate update and inner-product kernels) in one batch
+    geoms, bs, opts = build(MIX[:3], 730)
+    opts = [dict(o, k_max=k) for o, k in zip(opts, (113, 114, 20))]
+    note("batch fused/separate CGS %s" % method)
+    rb, xb = run_batch(ctx, method, geoms, bs, opts, torch.float64)
+    for s in range(3):
+        rs, xs = run_single(ctx, method, geoms[s], bs[s], opts[s], torch.float64)
+        assert_same(rb[s], xb[s], rs, xs)
+    assert rb[2].k_stop == 20
+
+
+@pytest.mark.parametrize("method", [gk.GKB_METHOD_BA, gk.GKB_METHOD_AB])
 def test_batch_matches_oracle_fp64(ctx, method):
     mix = [MIX[0], MIX[1], MIX[3]]
     geoms, bs, opts = build(mix, 720)
