@@ -70,7 +70,8 @@ typedef enum {
   GKB_STOP_KMAX = 2,            /* k_max iterations, DP off */
   GKB_STOP_BREAKDOWN = 3,       /* t_{k+1} or alpha_{k+1} vanished: invariant subspace, x exact there */
   GKB_STOP_DP_NOT_REACHED = 4,  /* DP on but not met by k_max; x = x_{k_max} */
-  GKB_STOP_FALLBACK = 5         /* learned preconditioner rejected; plain BA-GKB result returned */
+  GKB_STOP_FALLBACK = 5,        /* learned preconditioner rejected; plain BA-GKB result returned */
+  GKB_STOP_RNS = 6              /* residual norm stagnation (eq. RNS): x = x_k at the first such k */
 } gkb_stop_reason;
 
 typedef enum { GKB_PAR2D = 0, GKB_FAN2D = 1, GKB_CONE3D = 2 } gkb_geom_kind;
@@ -100,6 +101,10 @@ typedef struct {
   double *residual_history; /* optional HOST [k_max]: ||A x_k - b||, k = 1..k_stop */
   double *alpha_history;    /* optional HOST [k_max+1]: alpha_1.. */
   double *t_history;        /* optional HOST [k_max+1]: t_1.. */
+  double rns_eps;           /* > 0: also stop at the first k >= 2 with
+                             * | ||A x_{k-1} - b|| - ||A x_k - b|| | < rns_eps ||A x_{k-1} - b||
+                             * (residual norm stagnation, eq. RNS, Sec. 5) and return x_k;
+                             * 0 = off.  Tested after the discrepancy principle. */
 } gkb_solve_opts;
 
 typedef struct {

@@ -28,7 +28,7 @@ _lib = None
 KIND = {0: 0, 1: 1, 2: 2}
 OR_DENSE = 9
 MODE_AB, MODE_BA, MODE_GKB = 0, 1, 2
-STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED = 1, 2, 3, 4
+STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED, STOP_RNS = 1, 2, 3, 4, 6
 
 
 def build(force: bool = True) -> str:
@@ -53,7 +53,8 @@ class _Geom(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int), ("lam", ctypes.c_double), ("use_dp", ctypes.c_int),
-                ("tau", ctypes.c_double), ("noise_norm", ctypes.c_double), ("reorth", ctypes.c_int)]
+                ("tau", ctypes.c_double), ("noise_norm", ctypes.c_double), ("reorth", ctypes.c_int),
+                ("rns_eps", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -190,11 +191,14 @@ class GKBResult:
 
 
 def gkb(op: Operator, mode: int, b, k_max: int, lam: float = 0.0, use_dp: bool = False, tau: float = 1.0,
-        noise_norm: float = 0.0, reorth: int = 1, want_bases: bool = False) -> GKBResult:
-    """AB-GKB (mode 0), BA-GKB (mode 1) or matched GKB (mode 2)."""
+        noise_norm: float = 0.0, reorth: int = 1, want_bases: bool = False, rns_eps: float = 0.0) -> GKBResult:
+    """AB-GKB (mode 0), BA-GKB (mode 1) or matched GKB (mode 2).  Stops by the
+    discrepancy principle (use_dp), residual norm stagnation (rns_eps > 0,
+    eq. RNS: the first k >= 2 whose residual changed by less than rns_eps
+    relative to the previous one; x_k is returned), breakdown or k_max."""
     b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
     assert b.size == op.m
-    o = _Opts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, reorth)
+    o = _Opts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, reorth, rns_eps)
     info = _Info()
     x = np.zeros(op.n)
     rho = np.zeros(k_max)

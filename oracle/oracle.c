@@ -769,6 +769,7 @@ void or_proj_solve(int k, const double *alpha, const double *t, double lam, doub
 #define OR_STOP_KMAX 2
 #define OR_STOP_BREAKDOWN 3
 #define OR_STOP_DP_NOT_REACHED 4
+#define OR_STOP_RNS 6
 
 typedef struct {
   int k_max;
@@ -777,6 +778,7 @@ typedef struct {
   double tau;
   double noise_norm;
   int reorth; /* 0 none, 1 CGS2 (two classical passes), 2 MGS (one modified pass) */
+  double rns_eps; /* > 0: residual norm stagnation test, eq. (RNS); 0 = off */
 } or_opts;
 
 typedef struct {
@@ -824,6 +826,7 @@ int or_gkb(const or_geom *g, int mode, const double *b, const or_opts *o, double
   const long long m = g_m(g), n = g_n(g);
   if (o->k_max < 1) return -1;
   if (o->use_dp && !(o->tau > 0.0)) return -1;
+  if (!(o->rns_eps >= 0.0)) return -1;
   const long long dims = (mode == OR_MODE_AB) ? m : (mode == OR_MODE_BA ? n : m); /* s vectors */
   const long long dimq = (mode == OR_MODE_AB) ? m : n;                            /* q vectors */
   const int K = o->k_max;
@@ -909,6 +912,13 @@ int or_gkb(const or_geom *g, int mode, const double *b, const or_opts *o, double
     /* (iii) discrepancy principle */
     if (o->use_dp && rho[k - 1] <= o->tau * o->noise_norm) {
       info->reason = OR_STOP_DP;
+      goto done;
+    }
+    /* (iii') residual norm stagnation, eq. (RNS): the change of ||A x - b||
+     * from x_{k-1} to x_k, relative to ||A x_{k-1} - b||, is below eps;
+     * x_k is returned */
+    if (o->rns_eps > 0.0 && k >= 2 && fabs(rho[k - 2] - rho[k - 1]) < o->rns_eps * rho[k - 2]) {
+      info->reason = OR_STOP_RNS;
       goto done;
     }
     /* breakdown threshold: 100 eps max_i ||(alpha_i, t_{i+1})|| */

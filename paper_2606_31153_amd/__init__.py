@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgkb.so")
 
 GKB_OK, GKB_EINVAL, GKB_ENOMEM, GKB_EDEVICE, GKB_ENONFINITE, GKB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-STOP_NONE, STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED, STOP_FALLBACK = 0, 1, 2, 3, 4, 5
+STOP_NONE, STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED, STOP_FALLBACK, STOP_RNS = 0, 1, 2, 3, 4, 5, 6
 GKB_PAR2D, GKB_FAN2D, GKB_CONE3D = 0, 1, 2
 GKB_F32, GKB_F64 = 0, 1
 GKB_METHOD_AB, GKB_METHOD_BA = 0, 1
@@ -59,7 +59,7 @@ class SolveOpts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("noise_norm", ctypes.c_double), ("reorth", ctypes.c_int),
                 ("precond", ctypes.c_void_p), ("residual_history", ctypes.POINTER(ctypes.c_double)),
                 ("alpha_history", ctypes.POINTER(ctypes.c_double)),
-                ("t_history", ctypes.POINTER(ctypes.c_double))]
+                ("t_history", ctypes.POINTER(ctypes.c_double)), ("rns_eps", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -244,7 +244,8 @@ class SolveResult:
 
 
 def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, use_dp: bool = False,
-           tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True, precond=None) -> SolveResult:
+           tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True, precond=None,
+           rns_eps: float = 0.0) -> SolveResult:
     g, keep = make_geometry(geom)
     code = _dtype_code(b)
     if x.dtype != b.dtype:
@@ -255,7 +256,7 @@ def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, us
     P = ctypes.POINTER(ctypes.c_double)
     o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0,
                   None if precond is None else precond.handle,
-                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P))
+                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P), rns_eps)
     info = SolveInfo()
     _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(b, geom.m), ctypes.byref(o),
                                 _dev_ptr(x, geom.n), ctypes.byref(info)))
@@ -281,14 +282,14 @@ def gkb_gkb_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
 
 
 def _opts(k_max: int, lam: float = 0.0, use_dp: bool = False, tau: float = 1.0, noise_norm: float = 0.0,
-          reorth: bool = True):
+          reorth: bool = True, rns_eps: float = 0.0):
     """(SolveOpts, history arrays) for one problem."""
     rho = np.zeros(max(k_max, 1))
     alpha = np.zeros(k_max + 1)
     t = np.zeros(k_max + 1)
     P = ctypes.POINTER(ctypes.c_double)
     o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0, None,
-                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P))
+                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P), rns_eps)
     return o, (rho, alpha, t)
 
 
@@ -296,7 +297,7 @@ def gkb_batch_solve(ctx: Context, method: int, geoms, bs, xs, opts) -> list:
     """Batched solve of independent slices (AB-GKB or BA-GKB per ``method``):
     ``geoms``, ``bs``, ``xs`` are per-slice geometries and device tensors;
     ``opts`` is a list of per-slice keyword dicts (k_max, lam, use_dp, tau,
-    noise_norm, reorth).  Returns one SolveResult per slice."""
+    noise_norm, reorth, rns_eps).  Returns one SolveResult per slice."""
     ns = len(geoms)
     if not (len(bs) == len(xs) == len(opts) == ns):
         raise ValueError("geoms, bs, xs and opts must have one entry per slice")

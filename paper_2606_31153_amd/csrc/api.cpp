@@ -1515,6 +1515,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   hdp[CD_ETAEPS] = 100.0 * (sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16) * 2.0;
   hdp[CD_USEDP] = o->use_dp ? 1.0 : 0.0;
   hdp[CD_KMAX] = o->k_max;
+  hdp[CD_RNS] = o->rns_eps;
   HIPC(hipMemcpyAsync(S.ctl.ip, hip_, sizeof hip_, hipMemcpyHostToDevice, st));
   HIPC(hipMemcpyAsync(S.ctl.dp, hdp, sizeof hdp, hipMemcpyHostToDevice, st));
   *c->host_flag = 0;
@@ -1632,6 +1633,7 @@ gkb_status validate_opts(const gkb_solve_opts *o) {
     return fail(GKB_EINVAL, "tau must be > 0 when the discrepancy principle is on");
   if (o->use_dp && (!(o->noise_norm >= 0.0) || !std::isfinite(o->noise_norm)))
     return fail(GKB_EINVAL, "noise_norm must be finite and >= 0");
+  if (!(o->rns_eps >= 0.0) || !std::isfinite(o->rns_eps)) return fail(GKB_EINVAL, "rns_eps must be finite and >= 0");
   return GKB_OK;
 }
 
@@ -1867,6 +1869,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     hd[CD_ETAEPS] = 100.0 * (sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16) * 2.0;
     hd[CD_USEDP] = o.use_dp ? 1.0 : 0.0;
     hd[CD_KMAX] = o.k_max;
+    hd[CD_RNS] = o.rns_eps;
     c->bflags[s] = 0;
   }
   HIPC(hipMemcpyAsync(c->bsd.p, hsd.data(), sizeof(SliceDev<T>) * ns, hipMemcpyHostToDevice, st));

@@ -39,6 +39,7 @@ enum CtlDbl : int {
   CD_USEDP = 10,
   CD_KMAX = 11,
   CD_BNORM = 12,   // ||b||
+  CD_RNS = 13,     // residual norm stagnation tolerance (0 = off)
   CD_COUNT = 16
 };
 

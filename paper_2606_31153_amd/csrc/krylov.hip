@@ -574,6 +574,8 @@ __device__ inline void stop_test(const Ctl &ctl, double rho) {
   int reason = 0;
   if (dp[CD_USEDP] != 0.0 && rho <= dp[CD_TAUE])
     reason = 1;  // GKB_STOP_DP
+  else if (dp[CD_RNS] > 0.0 && k >= 2 && fabs(ctl.rho[k - 1] - rho) < dp[CD_RNS] * ctl.rho[k - 1])
+    reason = 6;  // GKB_STOP_RNS (eq. RNS): the relative change of the residual norm fell below the tolerance
   else if (!(tk1 > eta))
     reason = 3;  // GKB_STOP_BREAKDOWN
   else if (k >= ctl.K)

@@ -139,6 +139,22 @@ def test_batch_without_reorthogonalisation(ctx):
 
 
 @pytest.mark.parametrize("method", [gk.GKB_METHOD_BA, gk.GKB_METHOD_AB])
+def test_batch_with_stagnation_stops(ctx, method):
+    # per-slice residual norm stagnation tolerances (eq. RNS), one slice
+    # without, one with the discrepancy principle as well
+    geoms, bs, opts = build(MIX[:4], 740)
+    for o, eps in zip(opts, (0.05, 0.0, 0.01, 0.002)):
+        o["rns_eps"] = eps
+        o["k_max"] = 40
+    note("batch rns %s" % method)
+    rb, xb = run_batch(ctx, method, geoms, bs, opts, torch.float64)
+    for s in range(4):
+        rs, xs = run_single(ctx, method, geoms[s], bs[s], opts[s], torch.float64)
+        assert_same(rb[s], xb[s], rs, xs)
+    assert any(r.reason == gk.STOP_RNS for r in rb)
+
+
+@pytest.mark.parametrize("method", [gk.GKB_METHOD_BA, gk.GKB_METHOD_AB])
 def test_batch_mixes_fused_and_separate_cgs(ctx, method):
     # FP64 slices with k_max 113 (second CGS round as one fused pass over Q)
     # and 114 (separate update and inner-product kernels) in one batch

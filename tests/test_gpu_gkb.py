@@ -136,6 +136,48 @@ def test_fp64_fixed_30_iterations(ctx, mode):
     assert np.allclose(res.rho, ref.rho, rtol=1e-8)
 
 
+def rns_eps_with_margin(rho, k_min=4):
+    """A stagnation tolerance whose first crossing (eq. RNS) falls at some k
+    >= k_min with a factor of at least 1.1 to spare on both sides (FP32
+    rounding moves these ratios by about 1e-4 relative), so that rounding
+    cannot move the stop; returns (eps, k)."""
+    ratio = np.abs(np.diff(rho)) / rho[:-1]  # ratio[j] belongs to k = j + 2
+    for j in range(k_min - 2, ratio.size):
+        lo = ratio[j]
+        hi = ratio[:j].min() if j > 0 else np.inf
+        if hi > 1.21 * lo:
+            return float(np.sqrt(lo * min(hi, 4 * lo))), j + 2
+    raise AssertionError("no well-separated stagnation point")
+
+
+# Residual norm stagnation (eq. RNS) against the oracle: same stopping
+# iteration and reason, x to the FP64 / FP32 bars.
+@pytest.mark.parametrize("mode", ["ab", "ba"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_rns_stop_matches_oracle(ctx, mode, dtype):
+    geom = synth.par2d(64, 89, 91)
+    op, xt, b, en = problem(geom, 1004, 0.01)
+    if dtype == torch.float32:
+        b = np.float32(b).astype(np.float64)
+    plain = oracle.gkb(op, MODES[mode][0], b, 40)
+    eps, k_exp = rns_eps_with_margin(plain.rho, k_min=12)
+    ref = oracle.gkb(op, MODES[mode][0], b, 40, rns_eps=eps)
+    assert (ref.k_stop, ref.reason) == (k_exp, oracle.STOP_RNS)
+    note("rns %s %s eps=%.3g k=%d" % (mode, dtype, eps, k_exp))
+    res, x = gpu_solve(ctx, geom, mode, b, dtype, 40, rns_eps=eps)
+    assert (res.k_stop, res.reason) == (k_exp, gk.STOP_RNS)
+    assert rel(x, ref.x.reshape(-1)) <= (1e-10 if dtype == torch.float64 else 1e-4)
+    assert np.allclose(res.rho, ref.rho, rtol=1e-9 if dtype == torch.float64 else 1e-3)
+
+
+def test_rns_invalid_tolerance_rejected(ctx):
+    geom = synth.par2d(16, 10)
+    b = np.ones(geom.m)
+    for bad in (-1e-3, float("nan"), float("inf")):
+        with pytest.raises(RuntimeError):
+            gpu_solve(ctx, geom, "ba", b, torch.float32, 5, rns_eps=bad)
+
+
 # The second reorthogonalisation round runs as one fused pass over Q while
 # k_max + 1 columns of a 64-row block fit that kernel's LDS budget (k_max up
 # to 113 in FP64, 227 in FP32), else as separate update and inner-product

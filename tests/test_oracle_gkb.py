@@ -214,6 +214,57 @@ def test_dp_residual_is_literal():
         assert r.residual == pytest.approx(np.linalg.norm(op.A(r.x).reshape(-1) - b), rel=1e-12)
 
 
+# ---- residual norm stagnation, eq. (RNS): stop at the first k >= 2 with
+# | rho_{k-1} - rho_k | < eps rho_{k-1}, returning x_k
+def rns_problem():
+    g = synth.par2d(32, 40)
+    op = oracle.Operator(g)
+    b_true = op.A(synth.ellipse_phantom(32, 11)).reshape(-1)
+    b, en = synth.add_noise(b_true, synth.noise_direction(b_true.size, 11), 0.02)
+    return op, b, en
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+def test_rns_stop_index_and_iterate(mode):
+    op, b, en = rns_problem()
+    plain = oracle.gkb(op, mode, b, 40)
+    ratio = np.abs(np.diff(plain.rho)) / plain.rho[:-1]  # ratio[j] belongs to k = j + 2
+    for eps in (0.3, 0.05, 0.01, 1e-3):
+        r = oracle.gkb(op, mode, b, 40, rns_eps=eps)
+        hit = np.nonzero(ratio < eps)[0]
+        if hit.size:
+            assert r.reason == oracle.STOP_RNS and r.k_stop == hit[0] + 2
+        else:
+            assert r.reason == oracle.STOP_KMAX and r.k_stop == 40
+        # the same iterates up to the stop, and the returned x is x_{k_stop}
+        assert np.array_equal(r.rho, plain.rho[:r.k_stop])
+        ref = oracle.gkb(op, mode, b, r.k_stop)
+        assert np.array_equal(r.x, ref.x)
+
+
+def test_rns_invariants():
+    op, b, en = rns_problem()
+    for mode in (oracle.MODE_AB, oracle.MODE_BA):
+        # eps = 0 is off
+        r0 = oracle.gkb(op, mode, b, 25, rns_eps=0.0)
+        assert r0.reason == oracle.STOP_KMAX and r0.k_stop == 25
+        # larger tolerances stop no later
+        ks = [oracle.gkb(op, mode, b, 40, rns_eps=e).k_stop for e in (1e-4, 1e-3, 1e-2, 1e-1, 0.5)]
+        assert all(k1 >= k2 for k1, k2 in zip(ks, ks[1:]))
+    # AB-GKB minimises ||A B z - b|| over nested Krylov spaces, so its residual
+    # never grows and stays positive here: every relative change is below 1,
+    # and eps = 1 stops at the first iteration where the test applies
+    r = oracle.gkb(op, oracle.MODE_AB, b, 40, rns_eps=1.0)
+    assert (r.k_stop, r.reason) == (2, oracle.STOP_RNS)
+    # the discrepancy principle is tested first
+    dp = oracle.gkb(op, oracle.MODE_AB, b, 40, use_dp=True, tau=1.0, noise_norm=en)
+    assert dp.reason == oracle.STOP_DP
+    both = oracle.gkb(op, oracle.MODE_AB, b, 40, use_dp=True, tau=1.0, noise_norm=en, rns_eps=1e-9)
+    assert (both.k_stop, both.reason) == (dp.k_stop, oracle.STOP_DP)
+    with pytest.raises(ValueError):
+        oracle.gkb(op, oracle.MODE_AB, b, 5, rns_eps=-1.0)
+
+
 # ---- G11: breakdown on an invariant subspace
 def test_g11_breakdown():
     d = np.array([2.0, 3.0, 5.0, 7.0])
