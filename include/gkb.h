@@ -105,6 +105,13 @@ typedef struct {
                              * | ||A x_{k-1} - b|| - ||A x_k - b|| | < rns_eps ||A x_{k-1} - b||
                              * (residual norm stagnation, eq. RNS, Sec. 5) and return x_k;
                              * 0 = off.  Tested after the discrepancy principle. */
+  const void *x_true;       /* optional DEVICE [n] (dtype of the solve): the exact image.  With
+                             * rre_history it turns on RRE(x_k) = ||x_k - x_true|| / ||x_true||
+                             * (eq. RE, Sec. 5) after every iteration: x_k is assembled as the
+                             * returned solution is (an extra GEMV over Q, and for AB a B call,
+                             * per iteration).  Single-slice solves only: gkb_batch_solve returns
+                             * GKB_EUNSUPPORTED.  x_true = 0 gives non-finite values. */
+  double *rre_history;      /* optional HOST [k_max]: RRE(x_k), k = 1..k_stop (needs x_true) */
 } gkb_solve_opts;
 
 typedef struct {

@@ -54,7 +54,7 @@ class _Geom(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int), ("lam", ctypes.c_double), ("use_dp", ctypes.c_int),
                 ("tau", ctypes.c_double), ("noise_norm", ctypes.c_double), ("reorth", ctypes.c_int),
-                ("rns_eps", ctypes.c_double)]
+                ("rns_eps", ctypes.c_double), ("xtrue", ctypes.c_void_p), ("rre", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
@@ -188,17 +188,25 @@ class GKBResult:
     Q: Optional[np.ndarray] = None
     S: Optional[np.ndarray] = None
     u: Optional[np.ndarray] = None
+    rre: Optional[np.ndarray] = None
 
 
 def gkb(op: Operator, mode: int, b, k_max: int, lam: float = 0.0, use_dp: bool = False, tau: float = 1.0,
-        noise_norm: float = 0.0, reorth: int = 1, want_bases: bool = False, rns_eps: float = 0.0) -> GKBResult:
+        noise_norm: float = 0.0, reorth: int = 1, want_bases: bool = False, rns_eps: float = 0.0,
+        x_true=None) -> GKBResult:
     """AB-GKB (mode 0), BA-GKB (mode 1) or matched GKB (mode 2).  Stops by the
     discrepancy principle (use_dp), residual norm stagnation (rns_eps > 0,
     eq. RNS: the first k >= 2 whose residual changed by less than rns_eps
-    relative to the previous one; x_k is returned), breakdown or k_max."""
+    relative to the previous one; x_k is returned), breakdown or k_max.
+    With x_true, ``rre`` holds RRE(x_k) = ||x_k - x_true|| / ||x_true|| (eq. RE)
+    for k = 1..k_stop."""
     b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
     assert b.size == op.m
-    o = _Opts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, reorth, rns_eps)
+    xt = None if x_true is None else np.ascontiguousarray(np.asarray(x_true, dtype=np.float64).reshape(-1))
+    assert xt is None or xt.size == op.n
+    rre = np.zeros(k_max)
+    o = _Opts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, reorth, rns_eps,
+              None if xt is None else xt.ctypes.data, None if xt is None else rre.ctypes.data)
     info = _Info()
     x = np.zeros(op.n)
     rho = np.zeros(k_max)
@@ -217,7 +225,7 @@ def gkb(op: Operator, mode: int, b, k_max: int, lam: float = 0.0, use_dp: bool =
     k = info.k_stop
     return GKBResult(x=x.reshape(op.image_shape), k_stop=k, reason=info.reason, residual=info.residual,
                      proj_residual=info.proj_residual, t1=info.t1, alpha1=info.alpha1, rho=rho[:k], pres=pres[:k],
-                     alpha=alpha, t=t, Q=Q, S=S, u=u[:k])
+                     alpha=alpha, t=t, Q=Q, S=S, u=u[:k], rre=None if xt is None else rre[:k])
 
 
 def proj_solve(alpha, t, k: int, lam: float = 0.0):

@@ -779,6 +779,8 @@ typedef struct {
   double noise_norm;
   int reorth; /* 0 none, 1 CGS2 (two classical passes), 2 MGS (one modified pass) */
   double rns_eps; /* > 0: residual norm stagnation test, eq. (RNS); 0 = off */
+  const double *xtrue; /* optional [n] exact image: with rre, RRE(x_k) of eq. (RE) per iteration */
+  double *rre;         /* optional [k_max]: ||x_k - xtrue|| / ||xtrue||, k = 1..k_stop */
 } or_opts;
 
 typedef struct {
@@ -904,6 +906,15 @@ int or_gkb(const or_geom *g, int mode, const double *b, const or_opts *o, double
     for (long long i = 0; i < m; ++i) ax[i] -= b[i];
     rho[k - 1] = nrm2(ax, m);
     memcpy(x, xk, sizeof(double) * (size_t)n);
+    if (o->xtrue && o->rre) { /* eq. (RE) on the iterate x_k */
+      double e2 = 0.0, t2 = 0.0;
+      for (long long i = 0; i < n; ++i) {
+        const double d = xk[i] - o->xtrue[i];
+        e2 += d * d;
+        t2 += o->xtrue[i] * o->xtrue[i];
+      }
+      o->rre[k - 1] = sqrt(e2) / sqrt(t2);
+    }
     info->k_stop = k;
     info->residual = rho[k - 1];
     info->proj_residual = pr;

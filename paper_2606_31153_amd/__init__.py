@@ -59,7 +59,8 @@ class SolveOpts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("noise_norm", ctypes.c_double), ("reorth", ctypes.c_int),
                 ("precond", ctypes.c_void_p), ("residual_history", ctypes.POINTER(ctypes.c_double)),
                 ("alpha_history", ctypes.POINTER(ctypes.c_double)),
-                ("t_history", ctypes.POINTER(ctypes.c_double)), ("rns_eps", ctypes.c_double)]
+                ("t_history", ctypes.POINTER(ctypes.c_double)), ("rns_eps", ctypes.c_double),
+                ("x_true", ctypes.c_void_p), ("rre_history", ctypes.POINTER(ctypes.c_double))]
 
 
 class SolveInfo(ctypes.Structure):
@@ -241,11 +242,12 @@ class SolveResult:
     rho: np.ndarray
     alpha: np.ndarray
     t: np.ndarray
+    rre: Optional[np.ndarray] = None  # RRE(x_k), k = 1..k_stop, when x_true was given
 
 
 def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, use_dp: bool = False,
            tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True, precond=None,
-           rns_eps: float = 0.0) -> SolveResult:
+           rns_eps: float = 0.0, x_true=None) -> SolveResult:
     g, keep = make_geometry(geom)
     code = _dtype_code(b)
     if x.dtype != b.dtype:
@@ -254,16 +256,23 @@ def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, us
     alpha = np.zeros(k_max + 1)
     t = np.zeros(k_max + 1)
     P = ctypes.POINTER(ctypes.c_double)
+    rre = None
+    if x_true is not None:
+        if x_true.dtype != b.dtype:
+            raise TypeError("x_true and b dtypes differ")
+        rre = np.zeros(max(k_max, 1))
     o = SolveOpts(k_max, lam, 1 if use_dp else 0, tau, noise_norm, 1 if reorth else 0,
                   None if precond is None else precond.handle,
-                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P), rns_eps)
+                  rho.ctypes.data_as(P), alpha.ctypes.data_as(P), t.ctypes.data_as(P), rns_eps,
+                  None if x_true is None else _dev_ptr(x_true, geom.n).value,
+                  None if rre is None else rre.ctypes.data_as(P))
     info = SolveInfo()
     _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(b, geom.m), ctypes.byref(o),
                                 _dev_ptr(x, geom.n), ctypes.byref(info)))
     k = info.k_stop
     return SolveResult(k_stop=k, reason=info.reason, residual=info.residual, proj_residual=info.proj_residual,
                        t1=info.t1, alpha1=info.alpha1, seconds=info.seconds, rho=rho[:k], alpha=alpha[:k + 1],
-                       t=t[:k + 1])
+                       t=t[:k + 1], rre=None if rre is None else rre[:k])
 
 
 def gkb_ab_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:

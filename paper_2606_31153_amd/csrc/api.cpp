@@ -1217,7 +1217,7 @@ struct Solver {
     HIPC(c->w.ensure(sizeof(T) * (size_t)dimq));
     HIPC(c->tmp_n.ensure(sizeof(T) * (size_t)n));
     HIPC(c->tmp_m.ensure(sizeof(T) * (size_t)m));
-    const size_t nd = CD_COUNT + 9 * (size_t)(K + 2);
+    const size_t nd = CD_COUNT + 10 * (size_t)(K + 2);
     HIPC(c->ctl_d.ensure(sizeof(double) * nd));
     HIPC(c->ctl_i.ensure(sizeof(int) * CI_COUNT));
     const long long vb = std::max<long long>(
@@ -1244,7 +1244,7 @@ struct Solver {
     ctl.ip = c->ctl_i.as<int>();
     ctl.dp = dp;
     dp += CD_COUNT;
-    double **arrs[] = {&ctl.alpha, &ctl.t, &ctl.rho, &ctl.pres, &ctl.u, &ctl.Rd, &ctl.Rth, &ctl.Rphi, &ctl.c};
+    double **arrs[] = {&ctl.alpha, &ctl.t, &ctl.rho, &ctl.pres, &ctl.u, &ctl.Rd, &ctl.Rth, &ctl.Rphi, &ctl.c, &ctl.rre};
     for (double **a : arrs) {
       *a = dp;
       dp += K + 2;
@@ -1471,6 +1471,21 @@ struct Solver {
     normalize();
   }
 
+  // RRE(x_k) = ||x_k - x_true|| / ||x_true|| (eq. RE) after iteration k: x_k
+  // is assembled from Q and u_k as the returned solution is (AB: B Q_k u_k).
+  // The kernels are not gated by the stop flag, so the stopping iterate's
+  // error is recorded; iterations queued after a stop recompute the same
+  // value.  The B call pads its own input, so later consumers re-pad.
+  void rre_step(const T *x_true) {
+    if (mode == MODE_AB) {
+      launch_solution<T>(ctl, Q, ldq, dimq, tm, st);
+      B(col<const T>(tm), tn, plain_epi<T>(), nullptr);
+    } else {
+      launch_solution<T>(ctl, Q, ldq, dimq, tn, st);
+    }
+    launch_rre<T>(ctl, tn, x_true, n, partials, st);
+  }
+
   // q_{k+1} = w / alpha_{k+1}, with the padded copy the next iteration's first
   // projector reads (A: image; AB's B: sinogram)
   void normalize() {
@@ -1573,9 +1588,12 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     std::vector<hipEvent_t> evs(L, nullptr);
     for (auto &e : evs) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const bool reorth = o->reorth != 0;
+    const T *x_true = (o->x_true && o->rre_history) ? static_cast<const T *>(o->x_true) : nullptr;
+    if (x_true) launch_norm_to<T>(S.ctl, x_true, g.n, NORM_XTRUE, S.partials, st);
     int launched = 0;
     for (int k = 1; k <= o->k_max; ++k) {
       S.iteration(reorth, k);
+      if (x_true) S.rre_step(x_true);
       HIPC(hipEventRecord(evs[k % L], st));
       ++launched;
       if (k >= L) {
@@ -1607,6 +1625,11 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     inf.proj_residual = pres[k_stop];
     if (o->residual_history)
       for (int k = 1; k <= k_stop; ++k) o->residual_history[k - 1] = rho[k];
+    if (x_true) {
+      std::vector<double> rre(o->k_max + 2);
+      HIPC(hipMemcpy(rre.data(), S.ctl.rre, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+      for (int k = 1; k <= k_stop; ++k) o->rre_history[k - 1] = rre[k];
+    }
     (void)launched;
   }
   if (o->alpha_history || o->t_history) {
@@ -1634,6 +1657,8 @@ gkb_status validate_opts(const gkb_solve_opts *o) {
   if (o->use_dp && (!(o->noise_norm >= 0.0) || !std::isfinite(o->noise_norm)))
     return fail(GKB_EINVAL, "noise_norm must be finite and >= 0");
   if (!(o->rns_eps >= 0.0) || !std::isfinite(o->rns_eps)) return fail(GKB_EINVAL, "rns_eps must be finite and >= 0");
+  if ((o->x_true == nullptr) != (o->rre_history == nullptr))
+    return fail(GKB_EINVAL, "x_true and rre_history are given together");
   return GKB_OK;
 }
 
@@ -1843,6 +1868,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       *a = dp;
       dp += h.K + 2;
     }
+    ctl.rre = nullptr;  // no reconstruction-error histories in batched solves
     ctl.aw = wsD + h.ores;
     ctl.r = ctl.aw + (h.m + 3) / 4 * 4;
     ctl.K = h.K;
@@ -2075,6 +2101,8 @@ gkb_status batch_entry(gkb_ctx *c, int method, int ns, const gkb_geometry *geoms
     if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
     if (geoms[s].kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "batched solves take 2D slices");
     if (opts[s].precond) return fail(GKB_EUNSUPPORTED, "batched solves run without the learned filter");
+    if (opts[s].x_true || opts[s].rre_history)
+      return fail(GKB_EUNSUPPORTED, "batched solves record no reconstruction-error history");
     st = validate_opts(&opts[s]);
     if (st != GKB_OK) return fail(st, "slice " + std::to_string(s) + ": " + g_err);
     if (!b[s] || !x[s]) return fail(GKB_EINVAL, "slice " + std::to_string(s) + ": data pointer is NULL");

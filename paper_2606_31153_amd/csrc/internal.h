@@ -40,6 +40,7 @@ enum CtlDbl : int {
   CD_KMAX = 11,
   CD_BNORM = 12,   // ||b||
   CD_RNS = 13,     // residual norm stagnation tolerance (0 = off)
+  CD_XTNORM = 14,  // ||x_true|| for the relative reconstruction error
   CD_COUNT = 16
 };
 
@@ -57,6 +58,7 @@ struct Ctl {
   double *Rth;    // superdiagonal of R (Rth[i] couples columns i-1, i)
   double *Rphi;   // rotated right-hand side
   double *c;      // CGS coefficients [K+1]
+  double *rre;    // [K+2] RRE(x_k) at rre[k] (single-slice solves with x_true; else null)
   double *aw;     // [m] A-image of the last column of W = Q R^{-1}
   double *r;      // [m] r_k = A x_k - b
   int *host_stop; // host-mapped mirror of ip[CI_STOP] (may be null)
@@ -372,6 +374,9 @@ void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hi
                       PadOut<T> pout = PadOut<T>{});
 template <typename T>
 void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream_t s);
+// rre[k_stop] = ||x - x_true|| / dp[CD_XTNORM] (eq. RE); runs after a stop too
+template <typename T>
+void launch_rre(Ctl ctl, const T *x, const T *x_true, long long n, double *partials, hipStream_t s);
 template <typename T>
 void launch_resid_init(Ctl ctl, const T *b, long long m, double *partials, hipStream_t s);
 // t[k+1] (NORM_T1) or alpha[k+1] (NORM_ALPHA1) = sqrt(sum of nb partials), after
@@ -417,7 +422,7 @@ void launch_net_scale(float *r, long long n, const double *sums, int batch, hipS
 
 // targets of the finalising reductions: t[k+1], alpha[k+1], dp[CD_BNORM] =
 // ||b||, and rho[k] = ||r_k|| with the stopping decision of iteration k
-enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO = 3 };
+enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO = 3, NORM_XTRUE = 4, NORM_RRE = 5 };
 
 // ---- batched launchers: one launch covers every active slice ----
 template <typename T>

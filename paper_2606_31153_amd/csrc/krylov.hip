@@ -435,6 +435,8 @@ __device__ inline void norm_finalize_body(const Ctl &ctl, const double *__restri
       case NORM_T1: ctl.t[k + 1] = sqrt(tot); break;
       case NORM_ALPHA1: ctl.alpha[k + 1] = sqrt(tot); break;
       case NORM_BNORM: ctl.dp[CD_BNORM] = sqrt(tot); break;
+      case NORM_XTRUE: ctl.dp[CD_XTNORM] = sqrt(tot); break;
+      case NORM_RRE: ctl.rre[ctl.ip[CI_KSTOP]] = sqrt(tot) / ctl.dp[CD_XTNORM]; break;
       default: stop_test(ctl, sqrt(tot)); break;  // NORM_RHO
     }
   }
@@ -711,6 +713,21 @@ __global__ __launch_bounds__(kBlock) void k_norm_to(Ctl ctl, const T *__restrict
   norm_to_body(v, dim, partials, Blk{blockIdx.x, gridDim.x});
 }
 
+// partials of ||a - b||^2 (the reconstruction error of x_k against x_true)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diff_norm(const T *__restrict__ a, const T *__restrict__ b,
+                                                      long long dim, double *partials) {
+  __shared__ double lds[kBlock / 64];
+  const long long stride = (long long)gridDim.x * kBlock;
+  double acc = 0.0;
+  for (long long r = (long long)blockIdx.x * kBlock + threadIdx.x; r < dim; r += stride) {
+    const double d = (double)a[r] - (double)b[r];
+    acc = fma(d, d, acc);
+  }
+  const double s = block_sum<kBlock>(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
 // ---- batched launches (see proj2d.hip): one grid over every active slice ----
@@ -936,6 +953,12 @@ void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream
   hipLaunchKernelGGL(k_resid<T>, dim3(nb), dim3(kBlock), 0, s, ctl, yk, m, partials);
   launch_norm_finalize(ctl, partials, nb, NORM_RHO, ctl.ip + CI_STOP, s);
 }
+template <typename T>
+void launch_rre(Ctl ctl, const T *x, const T *x_true, long long n, double *partials, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_diff_norm<T>, dim3(nb), dim3(kBlock), 0, s, x, x_true, n, partials);
+  launch_norm_finalize(ctl, partials, nb, NORM_RRE, nullptr, s);
+}
 void launch_small_solve(Ctl ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl);
 }
@@ -1034,6 +1057,7 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_cgs_mid<T>(Ctl, const T *, long long, T *, long long, double *, int, hipStream_t);   \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t, PadOut<T>);               \
   template void launch_resid<T>(Ctl, const T *, long long, double *, hipStream_t);                         \
+  template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \

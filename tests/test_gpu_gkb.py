@@ -170,6 +170,27 @@ def test_rns_stop_matches_oracle(ctx, mode, dtype):
     assert np.allclose(res.rho, ref.rho, rtol=1e-9 if dtype == torch.float64 else 1e-3)
 
 
+# RRE(x_k) per iteration (eq. RE) against the oracle's history; recording it
+# leaves the solve itself bit for bit unchanged.
+@pytest.mark.parametrize("mode", ["ab", "ba", "gkb"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_rre_history_matches_oracle(ctx, mode, dtype):
+    geom = synth.par2d(64, 89, 91)
+    op, xt, b, en = problem(geom, 1005, 0.01)
+    xt = xt.reshape(-1)
+    if dtype == torch.float32:
+        b = np.float32(b).astype(np.float64)
+        xt = np.float32(xt).astype(np.float64)
+    ref = oracle.gkb(op, MODES[mode][0], b, 25, x_true=xt)
+    note("rre %s %s" % (mode, dtype))
+    xtd = torch.tensor(xt, dtype=dtype, device=torch.device("cuda:0"))
+    res, x = gpu_solve(ctx, geom, mode, b, dtype, 25, x_true=xtd)
+    plain, x0 = gpu_solve(ctx, geom, mode, b, dtype, 25)
+    assert res.k_stop == ref.k_stop == 25
+    assert np.allclose(res.rre, ref.rre, rtol=1e-9 if dtype == torch.float64 else 1e-4, atol=0)
+    assert np.array_equal(x, x0) and np.array_equal(res.rho, plain.rho)
+
+
 def test_rns_invalid_tolerance_rejected(ctx):
     geom = synth.par2d(16, 10)
     b = np.ones(geom.m)

@@ -265,6 +265,30 @@ def test_rns_invariants():
         oracle.gkb(op, oracle.MODE_AB, b, 5, rns_eps=-1.0)
 
 
+# ---- relative reconstruction error, eq. (RE), per iteration
+@pytest.mark.parametrize("mode", [oracle.MODE_AB, oracle.MODE_BA])
+def test_rre_history_is_the_error_of_each_iterate(mode):
+    op, b, en = rns_problem()
+    xt = synth.ellipse_phantom(32, 11).reshape(-1)
+    r = oracle.gkb(op, mode, b, 12, x_true=xt)
+    assert r.rre.shape == (12,)
+    for k in (1, 2, 5, 12):
+        xk = oracle.gkb(op, mode, b, k).x.reshape(-1)
+        assert r.rre[k - 1] == pytest.approx(np.linalg.norm(xk - xt) / np.linalg.norm(xt), rel=1e-12)
+    # switching the history on changes nothing else
+    r0 = oracle.gkb(op, mode, b, 12)
+    assert np.array_equal(r0.x, r.x) and np.array_equal(r0.rho, r.rho)
+
+
+def test_rre_vanishes_on_a_consistent_full_rank_problem():
+    # B A nonsingular and b = A x_true: the full Krylov space holds x_true
+    g, A, B, _ = tiny_pair(n=4, views=9)
+    xt = np.random.default_rng(3).standard_normal(A.shape[1])
+    b = A @ xt
+    r = oracle.gkb(oracle.Operator(A=A, B=B), oracle.MODE_BA, b, A.shape[1], x_true=xt)
+    assert r.rre[-1] <= 1e-8 and r.rre[0] > 1e-3
+
+
 # ---- G11: breakdown on an invariant subspace
 def test_g11_breakdown():
     d = np.array([2.0, 3.0, 5.0, 7.0])
