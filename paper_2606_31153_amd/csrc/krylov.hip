@@ -332,7 +332,7 @@ __device__ __attribute__((always_inline)) inline void cgs_mid_body(const Ctl &ct
   };
   __syncthreads();  // csh
   if (ncols <= NW * U) {
-    T qn[U], wn;
+    T qn[U] = {}, wn = T(0);
     auto issue = [&](int sb) {
       const long long r = row(sb);
       const long long rc = r < dim ? r : 0LL;

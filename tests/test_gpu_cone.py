@@ -264,6 +264,33 @@ def test_cone_gkb_fp32_split(ctx, mode):
     assert rel(xd.double().cpu().numpy(), ref.x.reshape(-1)) <= 1e-4
 
 
+@pytest.mark.parametrize("mode", ["ab", "ba"])
+def test_cone_rns_stop_and_rre_history(ctx, mode):
+    # the stagnation stop (eq. RNS) and the per-iteration reconstruction
+    # error (eq. RE) through the cone projectors (AB assembles x_k with the
+    # cone B), FP64 against the oracle
+    g = SOLVE_GEOMS[0]
+    op, b, en = cone_problem(g, 820, 0.01)
+    xt = smooth_input(g, "A", 820).reshape(-1)
+    omode = oracle.MODE_AB if mode == "ab" else oracle.MODE_BA
+    plain = oracle.gkb(op, omode, b, 25)
+    ratio = np.abs(np.diff(plain.rho)) / plain.rho[:-1]
+    j = next(j for j in range(4, ratio.size) if ratio[:j].min() > 1.21 * ratio[j])
+    eps = float(np.sqrt(ratio[j] * min(ratio[:j].min(), 4 * ratio[j])))
+    ref = oracle.gkb(op, omode, b, 25, rns_eps=eps, x_true=xt)
+    assert (ref.k_stop, ref.reason) == (j + 2, oracle.STOP_RNS)
+    note("cone rns/rre %s eps=%.3g k=%d" % (mode, eps, j + 2))
+    bd = torch.tensor(b, dtype=torch.float64, device=DEV)
+    xd = torch.full((g.n,), float("nan"), dtype=torch.float64, device=DEV)
+    xtd = torch.tensor(xt, dtype=torch.float64, device=DEV)
+    fn = gk.gkb_ab_solve if mode == "ab" else gk.gkb_ba_solve
+    res = fn(ctx, g, bd, xd, 25, rns_eps=eps, x_true=xtd)
+    torch.cuda.synchronize()
+    assert (res.k_stop, res.reason) == (ref.k_stop, gk.STOP_RNS)
+    assert rel(xd.cpu().numpy(), ref.x.reshape(-1)) <= 1e-10
+    assert np.allclose(res.rre, ref.rre, rtol=1e-9, atol=0)
+
+
 def test_cone_invalid(ctx):
     # a detector so tall that rays near its top would step along z
     g = cone(8, 8, 8, 4, 12, 200, 1.0, 1.0, 20.0, 30.0)
