@@ -305,7 +305,7 @@ __device__ __attribute__((always_inline)) inline void cgs_mid_body(const Ctl &ct
   // when the columns are few), each over 64 / tpc rows of a sub-block
   const int tpc = ncols <= NW * U ? kBlock / (NW * U) : 1;
   const int jd = threadIdx.x / tpc, part_id = threadIdx.x % tpc, nr = MID_ROWS / tpc;
-  // rows of sub-block sb: clamped (in range) addresses; rows past dim read as 0
+  // this lane's row in sub-block sb; a row past dim loads from row 0 and counts as 0
   auto row = [&](int sb) { return ((long long)blk * MID_SUB + sb) * MID_ROWS + lane; };
   // add the four shares and w, store the new rows of w, then the inner products
   double dacc = 0.0;
