@@ -187,7 +187,7 @@ void fan_tile_halfwidths(const gkb_geometry *g, const std::vector<double> &ang, 
 
 // Ray geometry in pixel index coordinates (crossing at the middle line and
 // its slope per line), filled for every ray of a 2D geometry.
-void ray_dispatch_orders(HostTables &t, int nu, int nv);
+void ray_dispatch_orders(HostTables &t, int nu, int nv, bool fan);
 
 void build_tables(const gkb_geometry *g, HostTables &t) {
   const int nx = g->nx, ny = g->ny, nv = g->n_views, nu = g->n_det_u;
@@ -365,7 +365,7 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
       for (int k = 0; k < nu; ++k) t.wpad[(long long)v * gd.ldY + gd.padY + k] = t.w[(long long)v * nu + k];
     fan_tile_halfwidths(g, ang, t);
   }
-  ray_dispatch_orders(t, nu, nv);
+  ray_dispatch_orders(t, nu, nv, fan);
 }
 
 // Dispatch orders of the ray-driven 2D kernels.  A workgroup lasts as long
@@ -373,29 +373,35 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
 // meet at the closing reduction), and a launch holds more workgroups than the
 // GPU runs at once, so the workgroups are issued longest first (the
 // longest-processing-time rule): the tail of the launch is then made of short
-// ones.  A: workgroup w holds rays 256 w .. 256 w + 255; B^T: workgroup w
-// holds bins 64 (w mod T) .. + 63 of views 4 (w div T) .. + 3, T = ceil(nu / 64).
-// Ties keep their index order.
-void ray_dispatch_orders(HostTables &t, int nu, int nv) {
+// ones.  A: workgroup w holds rays 256 w .. 256 w + 255 (ceil(nu / 64) *
+// ceil(nv / 4) workgroups); B^T: workgroup w holds bins 64 (w mod T) .. + 63
+// of V views from V (w div T), T = ceil(nu / 64): V = 4 (parallel beam) or
+// V = 2 with each ray in two halves (fan beam; the key, the longest ray,
+// orders them as the longest half would).  Ties keep their index order.
+void ray_dispatch_orders(HostTables &t, int nu, int nv, bool fan) {
   const long long m = (long long)nu * nv;
-  const int tiles_u = (nu + 63) / 64, nblk = tiles_u * ((nv + 3) / 4);
+  const int tiles_u = (nu + 63) / 64;
   auto lines = [](int meta) { return std::max(0, ((meta >> 15) & 0x7fff) - (meta & 0x7fff) + 1); };
-  std::vector<int> key(nblk);
+  std::vector<int> key;
   auto order_by = [&](std::vector<int> &order) {
+    const int nblk = (int)key.size();
     order.resize(nblk);
     for (int w = 0; w < nblk; ++w) order[w] = w;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key[a] > key[b]; });
   };
-  for (int w = 0; w < nblk; ++w) {
+  key.assign(tiles_u * ((nv + 3) / 4), 0);
+  for (int w = 0; w < (int)key.size(); ++w) {
     int k = 0;
     for (long long r = (long long)w * 256; r < std::min(m, (long long)w * 256 + 256); ++r) k = std::max(k, lines(t.meta[r]));
     key[w] = k;
   }
   order_by(t.order_fwd);
-  for (int w = 0; w < nblk; ++w) {
-    const int v0 = (w / tiles_u) * 4, b0 = (w % tiles_u) * 64;
+  const int vpw = fan ? 2 : 4;
+  key.assign(tiles_u * ((nv + vpw - 1) / vpw), 0);
+  for (int w = 0; w < (int)key.size(); ++w) {
+    const int v0 = (w / tiles_u) * vpw, b0 = (w % tiles_u) * 64;
     int k = 0;
-    for (int v = v0; v < std::min(nv, v0 + 4); ++v)
+    for (int v = v0; v < std::min(nv, v0 + vpw); ++v)
       for (int b = b0; b < std::min(nu, b0 + 64); ++b) k = std::max(k, lines(t.meta_bt[(long long)v * nu + b]));
     key[w] = k;
   }
@@ -886,7 +892,7 @@ enum Op { OP_A = 0, OP_B = 1, OP_AT = 2, OP_BT = 3 };
 template <typename T>
 gkb_status apply_op(gkb_ctx *c, const DevTables &d, int op, const void *in, void *out) {
   const GeomDev &g = d.gd;
-  const long long nb = std::max<long long>(std::max(ray_blocks(g), pixel_blocks(g)), 1);
+  const long long nb = std::max<long long>({(long long)ray_blocks(g), (long long)bt_blocks(g), (long long)pixel_blocks(g), 1LL});
   gkb_status st = ensure_scratch(c, g, sizeof(T), nb);
   if (st != GKB_OK) return st;
   Epi<T> e = plain_epi<T>();
@@ -1088,7 +1094,7 @@ gkb_status net_grad_impl(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, int S,
   HIPC(c->npart.ensure(sizeof(float) * (size_t)net_wgrad_blocks() * kNetC * kNetC * kNetK));
   HIPC(c->nsums.ensure(sizeof(double) * 2 * (size_t)S));
   HIPC(c->nred.ensure(sizeof(double) * 2 * 1024));
-  const long long nb = std::max<long long>(std::max(ray_blocks(gd), pixel_blocks(gd)), 1);
+  const long long nb = std::max<long long>({(long long)ray_blocks(gd), (long long)bt_blocks(gd), (long long)pixel_blocks(gd), 1LL});
   stt = ensure_scratch(c, gd, sizeof(float), nb);
   if (stt != GKB_OK) return stt;
   float *a1 = c->na0.as<float>(), *a2 = c->na1.as<float>(), *a3 = c->na2.as<float>();
@@ -1223,7 +1229,8 @@ struct Solver {
     const long long vb = std::max<long long>(
         {(long long)vec_blocks(dimq), (long long)vec_blocks(m), (long long)vec_blocks(dims)});
     const long long pb = std::max<long long>(
-        {(long long)ray_blocks(g), (long long)pixel_blocks(g), vb * (K + 2), (long long)upd_blocks(dimq),
+        {(long long)ray_blocks(g), (long long)bt_blocks(g), (long long)pixel_blocks(g), vb * (K + 2),
+         (long long)upd_blocks(dimq),
          (long long)mid_blocks(dimq) * (K + 2)});
     gkb_status stt = ensure_scratch(c, g, sizeof(T), pb);
     if (stt != GKB_OK) return stt;
@@ -1784,6 +1791,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     bl.nc_at = std::max(bl.nc_at, g.nc_at);
     bl.kmax = std::max(bl.kmax, h.K);
     h.cnt[BF_RAY] = ray_blocks(g);
+    h.cnt[BF_RAYBT] = bt_blocks(g);
     h.cnt[BF_PIX] = pixel_blocks(g);
     h.cnt[BF_VQ] = vec_blocks(h.dimq);
     h.cnt[BF_VQU] = upd_blocks(h.dimq);
@@ -1817,7 +1825,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     ndbl += 2 * (size_t)((g.m + 3) / 4 * 4);
     h.opart = ndbl;
     ndbl += (size_t)std::max<long long>(
-        {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
+        {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_RAYBT], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
          (long long)h.cnt[BF_VQU], (long long)h.cnt[BF_VQM] * (h.K + 2),
          (long long)h.cnt[BF_VM] * (h.K + 2), 1024LL});
     ndbl = (ndbl + 31) / 32 * 32;

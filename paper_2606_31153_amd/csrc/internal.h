@@ -264,6 +264,7 @@ enum BlockFam : int {
   BF_PADS,     // sinogram padding
   BF_VQU,      // CGS update over Q's dimension (upd_blocks)
   BF_VQM,      // fused CGS2 middle over Q's dimension (mid_blocks; slices with k_max <= mid_max_k)
+  BF_RAYBT,    // B^T: bt_blocks
   BF_COUNT
 };
 
@@ -319,6 +320,7 @@ void launch_fwd_adj(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt,
                     const Epi<T> &e, const int *stop, hipStream_t s);
 int pixel_blocks(const GeomDev &g);
 int ray_blocks(const GeomDev &g);
+int bt_blocks(const GeomDev &g);  // workgroups of B^T (fan: 64 bins x 2 views x 2 halves of the rays)
 
 // ---- cone-beam launchers (cone3d.hip) ----
 template <typename T>

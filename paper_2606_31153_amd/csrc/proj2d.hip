@@ -329,18 +329,27 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // taken as the wavefront's maximum, which makes the candidate loop uniform;
 // candidates outside the support get a negative weight, clamped to zero.
 // ---------------------------------------------------------------------------
-// Sum over lines lo..hi of one ray with n candidates per line: n = CNT, or
-// the wave-uniform runtime count `nrt` (at most MAXC) when CNT == 0.
+// Sum over the lines lo..hi of one ray (half < 0), or over half of them
+// (half 0: the first floor(len / 2), half 1: the rest), with n candidates per
+// line: n = CNT, or the wave-uniform runtime count `nrt` (at most MAXC) when
+// CNT == 0.
 // kBtLines lines per step, the taps of all of them loaded before any is
 // weighted.
 constexpr int kBtLines = 6;
 template <typename T, bool FAN, int CNT, int MAXC>
 __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, long long r,
-                                 T hr, int nrt) {
+                                 T hr, int nrt, int half) {
   constexpr int NQ = CNT ? CNT : MAXC;
   const int n = CNT ? CNT : nrt;
   const int meta = rt.meta_bt[r];
-  const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
+  int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
+  if (half >= 0) {
+    const int mdl = lo + max(hi - lo + 1, 0) / 2;
+    if (half == 0)
+      hi = mdl - 1;
+    else
+      lo = mdl;
+  }
   const bool rowdom = (meta >> 30) & 1;
   const T base = rt.base[r], slope = rt.slope[r];
   const int ld = rowdom ? g.ldR : g.ldT;
@@ -436,12 +445,18 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
 template <typename T, bool FAN, int NC>
 __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
                                      const Epi<T> &e, Blk b) {
-  // workgroup = 64 consecutive bins of 4 consecutive views (one view per
-  // wavefront): the four wavefronts of a workgroup cross nearly the same
-  // image lines at nearly the same places
+  // workgroup = 64 consecutive bins of consecutive views, one view per
+  // wavefront, so that its wavefronts cross nearly the same image lines.
+  // Parallel beam: 4 views of whole rays.  Fan beam: 2 views, each ray split
+  // into two halves of its line range (wavefront 2 v + h takes half h of view
+  // v's rays): fan rays differ much in length, a workgroup lasts as long as
+  // its longest ray, and halving them shortens the launch's tail.
+  constexpr int VPW = FAN ? 2 : 4;
   const int tiles_u = (g.nu + 63) >> 6;
   const unsigned wg = rt.order_bt ? (unsigned)rt.order_bt[b.id] : b.id;
-  const int view = (int)(wg / tiles_u) * 4 + (threadIdx.x >> 6), bin = (int)(wg % tiles_u) * 64 + (threadIdx.x & 63);
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int half = FAN ? (wave & 1) : -1, lane = threadIdx.x & 63;
+  const int view = (int)(wg / tiles_u) * VPW + (FAN ? wave >> 1 : wave), bin = (int)(wg % tiles_u) * 64 + lane;
   const bool valid = view < g.nv && bin < g.nu;
   const long long r = valid ? (long long)view * g.nu + bin : 0;
   const T hr = valid ? rt.h[r] : T(0);
@@ -453,13 +468,22 @@ __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, cons
   T acc = T(0);
   if (valid) {
     if (cnt == NC)
-      acc = back_adj_ray<T, FAN, NC, NC>(g, rt, pad, r, hr, cnt);
+      acc = back_adj_ray<T, FAN, NC, NC>(g, rt, pad, r, hr, cnt, half);
     else if (cnt == NC - 1)
-      acc = back_adj_ray<T, FAN, NC - 1, NC>(g, rt, pad, r, hr, cnt);
+      acc = back_adj_ray<T, FAN, NC - 1, NC>(g, rt, pad, r, hr, cnt, half);
     else
-      acc = back_adj_ray<T, FAN, 0, NC>(g, rt, pad, r, hr, cnt);
+      acc = back_adj_ray<T, FAN, 0, NC>(g, rt, pad, r, hr, cnt, half);
   }
-  epilogue(e, r, valid, acc, yo, b);
+  bool own = valid;
+  if constexpr (FAN) {
+    // the halves meet in LDS: first half + second half, in the first half's wavefront
+    __shared__ T second[2][64];
+    if (half == 1) second[wave >> 1][lane] = acc;
+    __syncthreads();
+    if (half == 0) acc += second[wave >> 1][lane];
+    own = valid && half == 0;
+  }
+  epilogue(e, own ? r : 0, own, acc, yo, b);
 }
 
 template <typename T, bool FAN, int NC>
@@ -849,7 +873,7 @@ __global__ __launch_bounds__(kBlock) void kb_fwd(BatchDev<T> bd, int out_sel, Ep
 template <typename T, bool FAN, int NC>
 __global__ __launch_bounds__(kBlock) void kb_back_adj(BatchDev<T> bd, int out_sel, EpiCfg ec) {
   Blk b;
-  const SliceDev<T> &d = slice_of(bd, BF_RAY, blockIdx.x, b);
+  const SliceDev<T> &d = slice_of(bd, BF_RAYBT, blockIdx.x, b);
   if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
   const GeomDev g = d.g;
@@ -892,6 +916,10 @@ int ray_blocks(const GeomDev &g) {
   if (g.kind == 2) return (int)((g.m + kBlock - 1) / kBlock);
   return ((g.nu + 63) / 64) * ((g.nv + 3) / 4);
 }
+int bt_blocks(const GeomDev &g) {
+  if (g.kind != 1) return ray_blocks(g);  // parallel beam: 4 views of whole rays; cone: its own layout
+  return ((g.nu + 63) / 64) * ((g.nv + 1) / 2);
+}
 
 template <typename T>
 void launch_pad_image(const GeomDev &g, Col<const T> x, T *pad, bool cols, const int *stop, hipStream_t s) {
@@ -933,7 +961,7 @@ void launch_fwd(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, c
 template <typename T, bool FAN>
 static void back_adj_nc(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e,
                         const int *stop, hipStream_t s) {
-  const dim3 grid(ray_blocks(g)), blk(kBlock);
+  const dim3 grid(bt_blocks(g)), blk(kBlock);
   switch (g.nc_bt) {
     case 2: hipLaunchKernelGGL((k_back_adj<T, FAN, 2>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
     case 3: hipLaunchKernelGGL((k_back_adj<T, FAN, 3>), grid, blk, 0, s, g, rt, pad, y, e, stop); break;
@@ -952,7 +980,7 @@ void launch_back_adj(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T>
     back_adj_nc<T, true>(g, rt, pad, y, e, stop, s);
   else
     back_adj_nc<T, false>(g, rt, pad, y, e, stop, s);
-  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, ray_blocks(g), NORM_T1, stop, s);
+  if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, bt_blocks(g), NORM_T1, stop, s);
 }
 
 template <typename T>
@@ -1014,7 +1042,7 @@ void launch_b_fwd(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, Epi
 
 template <typename T, bool FAN>
 static void b_back_adj_nc(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
-  const dim3 grid(bl.tot[BF_RAY]), blk(kBlock);
+  const dim3 grid(bl.tot[BF_RAYBT]), blk(kBlock);
   switch (bl.nc_bt) {
     case 2: hipLaunchKernelGGL((kb_back_adj<T, FAN, 2>), grid, blk, 0, s, bd, out_sel, ec); break;
     case 3: hipLaunchKernelGGL((kb_back_adj<T, FAN, 3>), grid, blk, 0, s, bd, out_sel, ec); break;
@@ -1028,12 +1056,12 @@ static void b_back_adj_nc(const BatchDev<T> &bd, const BatchLaunch &bl, int out_
 
 template <typename T>
 void launch_b_back_adj(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
-  if (bl.tot[BF_RAY] <= 0) return;
+  if (bl.tot[BF_RAYBT] <= 0) return;
   if (bl.fan)
     b_back_adj_nc<T, true>(bd, bl, out_sel, ec, s);
   else
     b_back_adj_nc<T, false>(bd, bl, out_sel, ec, s);
-  if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_RAY, NORM_T1, s);
+  if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_RAYBT, NORM_T1, s);
 }
 
 template <typename T>
