@@ -48,8 +48,8 @@ OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each
 # scaled by the plain-copy calibration), profiles/fan512_gkb_hbm_traffic.txt.
 # An entry must be removed when its kernel changes.
-MEASURED_TRAFFIC = {"fwd": (14860.4 * 1.9965 + 8750.7) * 1024.0, "back": (8322.0 * 1.9965 + 2952.3) * 1024.0,
-                    "fwd_adj": (22178.5 * 1.9965 + 2062.7) * 1024.0, "back_adj": (21602.3 * 1.9965 + 5932.8) * 1024.0}
+MEASURED_TRAFFIC = {"fwd": (14860.3 * 1.9910 + 8750.9) * 1024.0, "back": (8316.0 * 1.9910 + 2952.5) * 1024.0,
+                    "fwd_adj": (22176.4 * 1.9910 + 2062.7) * 1024.0, "back_adj": (21653.9 * 1.9910 + 5939.8) * 1024.0}
 
 
 def joseph_crossings(geom) -> int:
