@@ -1689,8 +1689,12 @@ gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void 
     // non-finite value
     gkb_solve_info li{};
     st = solve_impl<float>(c, g, dtype, b, o, x, &li, mode);
+    // with the discrepancy principle on, the learned solution is kept only if
+    // it meets the discrepancy level, whatever stopped the iteration (a
+    // residual-stagnation stop above the level falls back as well)
+    const bool dp_missed = o->use_dp && !(li.residual <= o->tau * o->noise_norm);
     const bool bad = st == GKB_ENONFINITE ||
-                     (st == GKB_OK && (li.reason == GKB_STOP_DP_NOT_REACHED || !(li.t1 > 0.0) ||
+                     (st == GKB_OK && (li.reason == GKB_STOP_DP_NOT_REACHED || dp_missed || !(li.t1 > 0.0) ||
                                        (li.reason == GKB_STOP_BREAKDOWN && li.k_stop < 3)));
     if (!bad) {
       if (st == GKB_OK && info) *info = li;

@@ -208,6 +208,31 @@ def test_zero_filter_falls_back_to_plain(ctx):
     net.close()
 
 
+def test_learned_stop_above_the_discrepancy_level_falls_back(ctx):
+    # With the discrepancy principle on, a learned attempt that the residual
+    # stagnation rule ends above tau ||e|| must not be returned: the plain
+    # BA-GKB result comes back with reason FALLBACK.  tau = 0.5 lies below the
+    # smallest residual this overdetermined problem can reach (about
+    # sqrt((m - n) / m) ||e||), and rns_eps = 0.9 ends the attempt at k = 2.
+    geom = synth.par2d(32, 40)
+    net = gk.Net(ctx, seed=5)  # He-initialised random network
+    op = oracle.Operator(geom)
+    x = synth.rasterize_ellipses(synth.ellipse_params(961), geom.nx, geom.ny)
+    b, en = synth.add_noise(op.A(x).reshape(-1), synth.noise_direction(geom.m, 961), 0.02)
+    bd = dev32(b)
+    x1 = torch.zeros(geom.n, dtype=torch.float32, device=DEV)
+    x2 = torch.zeros(geom.n, dtype=torch.float32, device=DEV)
+    note("learned RNS stop above the DP level")
+    kw = dict(use_dp=True, tau=0.5, noise_norm=en, rns_eps=0.9)
+    r1 = gk.gkb_ba_solve(ctx, geom, bd, x1, 30, **kw)
+    r2 = gk.gkb_ba_solve(ctx, geom, bd, x2, 30, precond=net, **kw)
+    torch.cuda.synchronize()
+    assert r1.residual > 0.5 * en
+    assert r2.reason == gk.STOP_FALLBACK and r2.k_stop == r1.k_stop
+    assert torch.equal(x1, x2)
+    net.close()
+
+
 def test_weights_roundtrip_and_errors(ctx, tmp_path):
     net = gk.Net(ctx, seed=3)
     w = net.get_weights()
