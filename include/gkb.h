@@ -140,6 +140,23 @@ gkb_status gkb_back(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *
 gkb_status gkb_forward_adjoint(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *y, void *x);  /* x = A^T y */
 gkb_status gkb_back_adjoint(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *x, void *y);     /* y = B^T x */
 
+/* x = B y without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same kernels and result as gkb_back, for GKB_PAR2D and
+ * GKB_FAN2D (GKB_CONE3D: GKB_EUNSUPPORTED).  y (m elements) and x (n elements)
+ * are DEVICE pointers owned by the caller; asynchronous on the context's
+ * stream.  The scratch (the per-view constants and the zero-padded sinogram,
+ * n_views * (n_det_u + 2 * pad) elements with pad >= 4) lives in a fixed
+ * 32 MiB device array that the library holds on every GPU it runs on until
+ * the process ends; a geometry needing more returns GKB_EINVAL before any
+ * launch.  Every call on one GPU shares that array and overwrites it (the
+ * padding step writes every element it reads, so nothing carries over from
+ * one call to the next): calls that overlap on one GPU, from any context or
+ * stream, race.  The first call for a geometry builds its tables on the host
+ * (host memory only); later calls copy the view constants (2 * n_views
+ * values) into the array and launch two kernels. */
+gkb_status gkb_back_noalloc(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *y, void *x);
+
 /* AB-GKB (Alg. "AB-GKB"): GKB on M = AB from b; x = B Q_k u_k.
  * BA-GKB (Alg. "BA-GKB"): GKB on M = BA from B b; x = Q_k u_k.
  * Matched GKB (Alg. "GKB"): M = A, M^T = A^T; x = Q_k u_k (equivalent to LSQR).

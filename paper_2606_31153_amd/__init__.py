@@ -35,7 +35,7 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve",
             "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_only", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
-            "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step")
+            "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc")
 NET_PARAMS = 19008
 GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
@@ -87,7 +87,7 @@ def lib() -> ctypes.CDLL:
         L.gkb_destroy.restype = None
         L.gkb_set_stream.argtypes = [vp, vp]
         L.gkb_last_error.restype = ctypes.c_char_p
-        for name in ("gkb_forward", "gkb_back", "gkb_forward_adjoint", "gkb_back_adjoint"):
+        for name in ("gkb_forward", "gkb_back", "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_back_noalloc"):
             getattr(L, name).argtypes = [vp, G, cp, vp, vp]
         for name in ("gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve"):
             getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
@@ -218,6 +218,12 @@ def gkb_forward(ctx: Context, geom, x, y):
 def gkb_back(ctx: Context, geom, y, x):
     """x = B y (pixel-driven back projector)."""
     return _proj("gkb_back", ctx, geom, y, x, geom.m, geom.n)
+
+
+def gkb_back_noalloc(ctx: Context, geom, y, x):
+    """x = B y with no device allocation (scratch in the library's fixed
+    device array; overlapping calls on one GPU race)."""
+    return _proj("gkb_back_noalloc", ctx, geom, y, x, geom.m, geom.n)
 
 
 def gkb_forward_adjoint(ctx: Context, geom, y, x):

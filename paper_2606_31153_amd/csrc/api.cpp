@@ -20,6 +20,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -37,6 +38,8 @@ gkb_status fail(gkb_status st, const std::string &msg) {
   g_err = msg;
   return st;
 }
+
+inline size_t al256_bytes(size_t b) { return (b + 255) & ~size_t(255); }
 
 #define HIPC(expr)                                                                          \
   do {                                                                                      \
@@ -673,6 +676,14 @@ struct gkb_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::map<std::string, std::unique_ptr<DevTables>> tables;
+  // host-side geometry of gkb_back_noalloc: layout scalars and the view
+  // constants staged as they are copied into the device scratch array
+  struct NoallocGeom {
+    GeomDev gd{};
+    size_t off_p1 = 0, off_y = 0;          // byte offsets of p1 and the padded sinogram
+    std::vector<unsigned char> staged;     // [p0 | p1] in the dtype, off_y bytes
+  };
+  std::map<std::string, std::unique_ptr<NoallocGeom>> noalloc_geoms;
   // scratch for standalone projector calls and reductions
   DevBuf xpad, ypad, partials;
   DevBuf ywpad;  // fan-beam A^T input as (w y, w) pairs, apart from ypad so that neither layout overwrites the other's pads
@@ -969,6 +980,101 @@ gkb_status projector_call(gkb_ctx *c, const gkb_geometry *g, int dtype, const vo
   if (st != GKB_OK) return st;
   HIPC(hipSetDevice(c->device));
   return dtype == GKB_F32 ? apply_op<float>(c, *d, op, in, out) : apply_op<double>(c, *d, op, in, out);
+}
+
+// ----- allocation-free back projection -----
+// gkb_back_noalloc runs the same padding and B kernels as gkb_back, with their
+// scratch (the per-view constants and the padded sinogram) in the file-scope
+// device array `scratch` instead of context buffers, so that the call
+// allocates no device memory.  Every GPU the library runs on holds one copy of
+// the array until the process ends; host code reaches it only through the
+// per-device address resolved in gkb_create.  Calls that overlap on one GPU
+// (from any context or stream) share the array and race.
+constexpr size_t kNoallocBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+// The calling thread's current device must be `device`.
+gkb_status resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(GKB_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return GKB_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(GKB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return GKB_OK;
+}
+
+template <typename T>
+gkb_status back_noalloc_impl(gkb_ctx *c, const gkb_geometry *g, int dtype, const T *y, T *x) {
+  const std::string key = geom_key(g, dtype);
+  auto it = c->noalloc_geoms.find(key);
+  if (it == c->noalloc_geoms.end()) {
+    HostTables h;
+    build_tables(g, h);
+    if (h.gd.nc_bt > 8 || h.gd.nc_at > 8)
+      return fail(GKB_EUNSUPPORTED, "detector pitch too fine relative to the pixel pitch (more than 8 "
+                                    "interpolation candidates per line)");
+    if (h.gd.ypad_elems >= (1LL << 31)) return fail(GKB_EUNSUPPORTED, "sinogram too large for 32-bit offsets");
+    auto na = std::make_unique<gkb_ctx::NoallocGeom>();
+    na->gd = h.gd;
+    const size_t vb = al256_bytes(sizeof(T) * (size_t)h.gd.nv);
+    na->off_p1 = vb;
+    na->off_y = 2 * vb;
+    na->staged.assign(na->off_y, 0);
+    T *p0 = reinterpret_cast<T *>(na->staged.data());
+    T *p1 = reinterpret_cast<T *>(na->staged.data() + na->off_p1);
+    for (int v = 0; v < h.gd.nv; ++v) {
+      p0[v] = (T)h.p0[v];
+      p1[v] = (T)h.p1[v];
+    }
+    it = c->noalloc_geoms.emplace(key, std::move(na)).first;
+  }
+  const gkb_ctx::NoallocGeom &na = *it->second;
+  const GeomDev &gd = na.gd;
+  const size_t need = na.off_y + sizeof(T) * (size_t)gd.ypad_elems;
+  if (need > kNoallocBytes)
+    return fail(GKB_EINVAL, "gkb_back_noalloc: the geometry needs " + std::to_string(need) +
+                                " bytes of scratch, more than the fixed " + std::to_string(kNoallocBytes) +
+                                " (views x (detector bins + padding) too large)");
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    base = g_scratch_ptr[c->device];
+  }
+  if (!base) return fail(GKB_EDEVICE, "gkb_back_noalloc: scratch address not resolved for this device");
+  unsigned char *sb = static_cast<unsigned char *>(base);
+  HIPC(hipMemcpyAsync(sb, na.staged.data(), na.off_y, hipMemcpyHostToDevice, c->stream));
+  ViewTab<T> vt{};
+  vt.p0 = reinterpret_cast<const T *>(sb);
+  vt.p1 = reinterpret_cast<const T *>(sb + na.off_p1);
+  T *ypad = reinterpret_cast<T *>(sb + na.off_y);
+  // every element of the padded sinogram is written here (the pads as zeros)
+  launch_pad_sino<T>(gd, col<const T>(y), ypad, nullptr, c->stream);
+  launch_back<T>(gd, vt, ypad, x, plain_epi<T>(), nullptr, c->stream);
+  HIPC(hipGetLastError());
+  return GKB_OK;
+}
+
+gkb_status back_noalloc(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y, void *x) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!y || !x) return fail(GKB_EINVAL, "data pointer is NULL");
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  if (g->kind == GKB_CONE3D) return fail(GKB_EUNSUPPORTED, "gkb_back_noalloc: 2D geometries only");
+  HIPC(hipSetDevice(c->device));
+  return dtype == GKB_F32
+             ? back_noalloc_impl<float>(c, g, dtype, static_cast<const float *>(y), static_cast<float *>(x))
+             : back_noalloc_impl<double>(c, g, dtype, static_cast<const double *>(y), static_cast<double *>(x));
 }
 
 // --------------------------------------------------------------------------
@@ -2139,6 +2245,8 @@ gkb_status gkb_create(gkb_ctx **ctx, int device, void *hip_stream) {
   HIPC(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(GKB_EINVAL, "device index out of range");
   HIPC(hipSetDevice(device));
+  gkb_status sst = resolve_scratch(device);
+  if (sst != GKB_OK) return sst;
   auto *c = new gkb_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the default stream
@@ -2182,6 +2290,9 @@ gkb_status gkb_back(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y,
 }
 gkb_status gkb_forward_adjoint(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y, void *x) {
   return projector_call(c, g, dtype, y, x, OP_AT);
+}
+gkb_status gkb_back_noalloc(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y, void *x) {
+  return back_noalloc(c, g, dtype, y, x);
 }
 gkb_status gkb_back_adjoint(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *x, void *y) {
   return projector_call(c, g, dtype, x, y, OP_BT);
