@@ -236,6 +236,37 @@ gkb_status gkb_net_grad(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g, int b
 gkb_status gkb_net_train_step(gkb_ctx *ctx, gkb_net *net, const gkb_geometry *g, int batch, const void *b,
                               const void *x, int objective, double lr, double *loss);
 
+/* Host-side check of a geometry against the projector kernels' address
+ * arithmetic; needs no GPU and touches no device memory.  Every stride-th
+ * wavefront (2D ray-driven kernels, cone B^T), ray (cone A), pixel or voxel
+ * of the launches that gkb_forward, gkb_back, gkb_forward_adjoint and
+ * gkb_back_adjoint make for (g, dtype) is replayed on the host in the
+ * kernels' arithmetic, and stats[0..3] (A, B, A^T, B^T) count:
+ *   units          rays, pixels or voxels replayed;
+ *   reads          element reads;
+ *   out_of_bounds  reads outside their zero-padded line (2D) or the padded
+ *                  volume or sinogram (cone): must be 0;
+ *   uncovered      interpolation candidates (their weights found in double
+ *                  from the operator's definition, the linear or bilinear
+ *                  weights of Sec. 1's A and B) that lie outside the window
+ *                  or line range the kernel reads, with a weight above the
+ *                  rounding bound of the kernel's coordinates (GKB_F32:
+ *                  8 L 2^-24, L = max(nx, ny, nz, n_det_u, n_det_v) + 16, as a
+ *                  float coordinate moves a window edge by a few units in its
+ *                  last place; GKB_F64: 1e-9): must be 0;
+ *   max_uncovered_weight  the largest such weight (any size).
+ * *orders_ok (may be NULL) is 1 when the dispatch orders of the 2D ray-driven
+ * kernels are permutations of their launches' workgroups (1 for cone beam).
+ * Windows of the pixel-driven fan-beam kernels, which depend on approximated
+ * fan angles, are checked with the detector coordinate moved 1e-3 bins both
+ * ways.  Errors: GKB_EINVAL (bad geometry, stride < 1, stats NULL) and the
+ * geometries the projectors reject with GKB_EUNSUPPORTED. */
+typedef struct {
+  long long units, reads, out_of_bounds, uncovered;
+  double max_uncovered_weight;
+} gkb_check_stats;
+gkb_status gkb_check_geometry(const gkb_geometry *g, int dtype, int stride, gkb_check_stats *stats, int *orders_ok);
+
 /* Kernel timing.  While enabled, every launch of the named kernels is
  * bracketed by HIP events on the context's stream; gkb_trace_get returns the
  * launch count and summed device milliseconds since the last reset.  Each

@@ -35,7 +35,8 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve",
             "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_only", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
-            "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc")
+            "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc",
+            "gkb_check_geometry")
 NET_PARAMS = 19008
 GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
@@ -61,6 +62,11 @@ class SolveOpts(ctypes.Structure):
                 ("alpha_history", ctypes.POINTER(ctypes.c_double)),
                 ("t_history", ctypes.POINTER(ctypes.c_double)), ("rns_eps", ctypes.c_double),
                 ("x_true", ctypes.c_void_p), ("rre_history", ctypes.POINTER(ctypes.c_double))]
+
+
+class CheckStats(ctypes.Structure):
+    _fields_ = [("units", ctypes.c_longlong), ("reads", ctypes.c_longlong), ("out_of_bounds", ctypes.c_longlong),
+                ("uncovered", ctypes.c_longlong), ("max_uncovered_weight", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -106,6 +112,7 @@ def lib() -> ctypes.CDLL:
         L.gkb_net_grad.argtypes = [vp, vp, G, cp, vp, vp, cp, ctypes.POINTER(ctypes.c_double), FP]
         L.gkb_net_train_step.argtypes = [vp, vp, G, cp, vp, vp, cp, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double)]
+        L.gkb_check_geometry.argtypes = [G, cp, cp, ctypes.POINTER(CheckStats), ctypes.POINTER(cp)]
         L.gkb_trace_enable.argtypes = [vp, cp]
         L.gkb_trace_only.argtypes = [vp, ctypes.c_char_p]
         L.gkb_trace_reset.argtypes = [vp]
@@ -234,6 +241,16 @@ def gkb_forward_adjoint(ctx: Context, geom, y, x):
 def gkb_back_adjoint(ctx: Context, geom, x, y):
     """y = B^T x (exact transpose of B)."""
     return _proj("gkb_back_adjoint", ctx, geom, x, y, geom.n, geom.m)
+
+
+def gkb_check_geometry(geom, dtype_code: int = GKB_F32, stride: int = 1):
+    """Host replay of the projector kernels' address arithmetic for ``geom``
+    (no GPU): ({"A"|"B"|"At"|"Bt": CheckStats}, orders_ok)."""
+    g, keep = make_geometry(geom)
+    st = (CheckStats * 4)()
+    ok = ctypes.c_int()
+    _check(lib().gkb_check_geometry(ctypes.byref(g), dtype_code, stride, st, ctypes.byref(ok)))
+    return dict(zip(("A", "B", "At", "Bt"), st)), bool(ok.value)
 
 
 @dataclass

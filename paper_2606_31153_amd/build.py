@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgkb.so")
-SOURCES = ["csrc/proj2d.hip", "csrc/cone3d.hip", "csrc/krylov.hip", "csrc/netk.hip", "csrc/api.cpp"]
+SOURCES = ["csrc/proj2d.hip", "csrc/cone3d.hip", "csrc/krylov.hip", "csrc/netk.hip", "csrc/api.cpp", "csrc/selfcheck.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

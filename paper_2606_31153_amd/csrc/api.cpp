@@ -27,6 +27,7 @@
 
 #include "../../include/gkb.h"
 #include "internal.h"
+#include "tables.h"
 
 using namespace gkb;
 
@@ -74,40 +75,10 @@ struct DevBuf {
 // --------------------------------------------------------------------------
 // geometry tables
 // --------------------------------------------------------------------------
-struct HostTables {
-  // per ray
-  std::vector<double> base, slope, w, h, t0, dt, dperp, dpar;
-  std::vector<int> meta, meta_bt;
-  std::vector<int> order_fwd, order_bt;  // workgroup dispatch orders of A and B^T
-  std::vector<double> wpad;  // fan: 1/|d_dom| in padded sinogram layout
-  // per view
-  std::vector<double> p0, p1, p2, p3, p4;
-  // per bin (fan): (cos, sin) of the fan angle, padded like a sinogram row
-  std::vector<double> gcs;
-  // fan A^T: per (32x2 pixel tile, view) bound of the candidate half-width, [tile][view]
-  std::vector<double> htile;
-  bool has_coldom = false;
-  double min_along = 1e300;  // fan: smallest source distance of a B^T crossing
-  // cone beam, per (view, column)
-  std::vector<double> cbase1, cslope1, clmid, clslope, cdxy2, ch1, cpk;
-  std::vector<int> cmeta, cmeta_bt;
-  bool has_xdom = false, has_ydom = false;
-  double min_ddom = 0.0;
-  GeomDev gd{};
-};
 
-struct DevTables {
-  DevBuf buf;
-  RayTab<float> rt32{};
-  ViewTab<float> vt32{};
-  RayTab<double> rt64{};
-  ViewTab<double> vt64{};
-  ConeTab<float> ct32{};
-  ConeTab<double> ct64{};
-  bool has_coldom = false;
-  bool has_xdom = false, has_ydom = false;
-  GeomDev gd{};
-};
+}  // namespace
+
+namespace gkb {
 
 std::vector<double> view_angles(const gkb_geometry *g) {
   std::vector<double> a(g->n_views);
@@ -529,6 +500,23 @@ void build_cone_tables(const gkb_geometry *g, HostTables &t) {
   gd.pad_elems = gd.vol_pad_elems;
   gd.ypad_elems = std::max(gd.sino_pad_elems, gd.m);
 }
+
+}  // namespace gkb
+
+namespace {
+
+struct DevTables {
+  DevBuf buf;
+  RayTab<float> rt32{};
+  ViewTab<float> vt32{};
+  RayTab<double> rt64{};
+  ViewTab<double> vt64{};
+  ConeTab<float> ct32{};
+  ConeTab<double> ct64{};
+  bool has_coldom = false;
+  bool has_xdom = false, has_ydom = false;
+  GeomDev gd{};
+};
 
 template <typename T>
 hipError_t upload_cone_tables(const HostTables &h, DevTables &d) {
@@ -2293,6 +2281,36 @@ gkb_status gkb_forward_adjoint(gkb_ctx *c, const gkb_geometry *g, int dtype, con
 }
 gkb_status gkb_back_noalloc(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *y, void *x) {
   return back_noalloc(c, g, dtype, y, x);
+}
+
+gkb_status gkb_check_geometry(const gkb_geometry *g, int dtype, int stride, gkb_check_stats *stats, int *orders_ok) {
+  if (!stats) return fail(GKB_EINVAL, "stats is NULL");
+  if (stride < 1) return fail(GKB_EINVAL, "stride must be >= 1");
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  HostTables h;
+  CheckStat cs[4] = {};
+  int ok = 1;
+  if (g->kind == GKB_CONE3D) {
+    build_cone_tables(g, h);
+    if (!(h.min_ddom > 0.5 * (g->n_det_v - 1) * g->det_pitch_v))
+      return fail(GKB_EUNSUPPORTED, "cone beam: some ray would step along z");
+    check_tables_cone(g, h, dtype == GKB_F32, stride, cs);
+  } else {
+    build_tables(g, h);
+    if (h.gd.nc_bt > 8 || h.gd.nc_at > 8)
+      return fail(GKB_EUNSUPPORTED, "more than 8 interpolation candidates per line");
+    ok = check_tables_2d(g, h, dtype == GKB_F32, stride, cs) ? 1 : 0;
+  }
+  for (int i = 0; i < 4; ++i) {
+    stats[i].units = cs[i].units;
+    stats[i].reads = cs[i].reads;
+    stats[i].out_of_bounds = cs[i].out_of_bounds;
+    stats[i].uncovered = cs[i].uncovered;
+    stats[i].max_uncovered_weight = cs[i].max_uncovered_weight;
+  }
+  if (orders_ok) *orders_ok = ok;
+  return GKB_OK;
 }
 gkb_status gkb_back_adjoint(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *x, void *y) {
   return projector_call(c, g, dtype, x, y, OP_BT);
