@@ -81,7 +81,8 @@ def lib():
         L.or_proj_solve.restype = None
         L.or_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
         L.or_jacobi_svd.restype = ctypes.c_int
-        for name in ("or_cone_forward_sampled", "or_cone_back_sampled", "or_cone_back_adjoint_sampled"):
+        for name in ("or_cone_forward_sampled", "or_cone_back_sampled", "or_cone_back_adjoint_sampled",
+                     "or_cone_forward_adjoint_sampled"):
             f = getattr(L, name)
             f.argtypes = [G, P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_longlong, P]
             f.restype = ctypes.c_int
@@ -157,6 +158,10 @@ class Operator:
     def B_at(self, y, voxel_ids):
         """(B y) at the listed voxels (cone beam only)."""
         return self._sampled("or_cone_back_sampled", y, voxel_ids, self.m)
+
+    def At_at(self, y, voxel_ids):
+        """(A^T y) at the listed voxels (cone beam only)."""
+        return self._sampled("or_cone_forward_adjoint_sampled", y, voxel_ids, self.m)
 
     def Bt_at(self, x, ray_ids):
         """(B^T x) at the listed detector pixels (cone beam only)."""

@@ -375,15 +375,18 @@ static void vox_add(const or_geom *g, double *x, int i, int j, int l, double val
   x[((size_t)l * g->ny + j) * g->nx + i] += val;
 }
 
-static void cone_ray(const or_geom *g, int v, int row, int k, const double *x, double *xo, double yval,
-                     double *out) {
+/* source S, unit direction d and dominant axis of the ray of detector pixel
+   (k, row) in view v */
+static int cone_ray_setup(const or_geom *g, int v, int row, int k, double S[3], double d[3]) {
   const double b = g->ang[v];
-  const double S[3] = {g->D * cos(b), g->D * sin(b), 0.0};
+  S[0] = g->D * cos(b);
+  S[1] = g->D * sin(b);
+  S[2] = 0.0;
   const double cdir[3] = {-cos(b), -sin(b), 0.0};
   const double eu[3] = {-sin(b), cos(b), 0.0};
   const double uu = (k - (g->nu - 1) / 2.0) * g->du;
   const double vv = (row - (g->nw - 1) / 2.0) * g->dw;
-  double P[3], d[3];
+  double P[3];
   for (int a = 0; a < 3; ++a) P[a] = S[a] + g->SDD * cdir[a] + uu * eu[a] + (a == 2 ? vv : 0.0);
   double len = 0.0;
   for (int a = 0; a < 3; ++a) {
@@ -392,10 +395,16 @@ static void cone_ray(const or_geom *g, int v, int row, int k, const double *x, d
   }
   len = sqrt(len);
   for (int a = 0; a < 3; ++a) d[a] /= len;
-  /* dominant axis */
   int ax = 0;
   if (fabs(d[1]) > fabs(d[ax])) ax = 1;
   if (fabs(d[2]) > fabs(d[ax])) ax = 2;
+  return ax;
+}
+
+static void cone_ray(const or_geom *g, int v, int row, int k, const double *x, double *xo, double yval,
+                     double *out) {
+  double S[3], d[3];
+  const int ax = cone_ray_setup(g, v, row, k, S, d);
   const int dims[3] = {g->nx, g->ny, g->nz};
   const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
   const double w = 1.0 / fabs(d[ax]);
@@ -561,6 +570,44 @@ int or_cone_back_sampled(const or_geom *g, const double *y, const long long *ids
     const long long id = ids[s];
     const int i = (int)(id % g->nx), j = (int)((id / g->nx) % g->ny), l = (int)(id / ((long long)g->nx * g->ny));
     out[s] = cone_back_voxel(g, y, i, j, l);
+  }
+  return 0;
+}
+
+/* (A^T y) at the listed voxels (index (l * ny + j) * nx + i): the transpose
+   of cone_joseph read one output at a time.  Every ray of every view is set
+   up as in cone_ray; on the voxel plane along the ray's dominant axis that
+   holds the voxel, the ray's bilinear weight on the voxel (nonzero when its
+   crossing lies within one voxel in both in-plane coordinates), times
+   1/|d_dom| and the ray's value, is summed. */
+int or_cone_forward_adjoint_sampled(const or_geom *g, const double *y, const long long *ids, long long count,
+                                    double *out) {
+  if (g->kind != OR_CONE3D) return -1;
+  const long long n = g_n(g);
+  for (long long s = 0; s < count; ++s)
+    if (ids[s] < 0 || ids[s] >= n) return -1;
+  const int nx = g->nx, ny = g->ny, nz = g->nz, nu = g->nu, nw = g->nw, nv = g->nv;
+  const int dims[3] = {nx, ny, nz};
+  for (long long s = 0; s < count; ++s) {
+    const long long id = ids[s];
+    const int p[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((long long)nx * ny))};
+    double acc = 0.0;
+#pragma omp parallel for collapse(2) reduction(+ : acc) schedule(static)
+    for (int v = 0; v < nv; ++v)
+      for (int r = 0; r < nw; ++r)
+        for (int k = 0; k < nu; ++k) {
+          double S[3], d[3];
+          const int ax = cone_ray_setup(g, v, r, k, S, d);
+          const int a1 = (ax + 1) % 3, a2 = (ax + 2) % 3;
+          const double pa = p[ax] - (dims[ax] - 1) / 2.0;
+          const double lam = (pa - S[ax]) / d[ax];
+          const double p1 = S[a1] + lam * d[a1] + (dims[a1] - 1) / 2.0;
+          const double p2 = S[a2] + lam * d[a2] + (dims[a2] - 1) / 2.0;
+          const double w1 = 1.0 - fabs(p1 - p[a1]), w2 = 1.0 - fabs(p2 - p[a2]);
+          if (w1 <= 0.0 || w2 <= 0.0) continue;
+          acc += w1 * w2 / fabs(d[ax]) * y[((size_t)v * nw + r) * nu + k];
+        }
+    out[s] = acc;
   }
   return 0;
 }

@@ -151,8 +151,9 @@ def test_cone_unmatched_pair():
 
 
 def test_cone_full_size_512(ctx):
-    """512^3 volume, 720 views, 1024 x 768 detector: A and B at sampled
-    outputs against the oracle, A^T and B^T through the adjoint identities."""
+    """512^3 volume, 720 views, 1024 x 768 detector: A, B, A^T and B^T at
+    sampled outputs against the oracle, A^T and B^T also through the adjoint
+    identities."""
     g = synth.cone3d(512, 720, 1024, 768)
     note("cone 512: inputs")
     rx = synth.rng(5000, synth.PURPOSE_PHANTOM)
@@ -186,6 +187,20 @@ def test_cone_full_size_512(ctx):
     lhs = torch.dot(Ax.double(), yd.double()).item()
     rhs = torch.dot(xd.double(), Aty.double()).item()
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    # element by element at six random voxels and six on the faces, edges and
+    # corners of the volume (where the candidate windows meet the padding),
+    # against the oracle's A^T read one voxel at a time (every ray's weight)
+    n1 = g.nx - 1
+    edge = [(0, 0, 0), (n1, n1, n1), (0, n1 // 2, 7), (n1, 3, n1 // 2), (n1 // 3, 0, n1), (5, n1, 0)]
+    vid = [(l * g.ny + j) * g.nx + i for i, j, l in edge] + list(pick.choice(g.n, 6, replace=False))
+    vid = np.asarray(vid, dtype=np.int64)
+    note("cone 512: A^T at %d sampled voxels against the oracle" % vid.size)
+    ref = oracle.Operator(g).At_at(y.astype(np.float64), vid)
+    got = Aty[torch.from_numpy(vid).to(DEV)].double().cpu().numpy()
+    note("cone 512: A^T sampled rel %.3e, max abs %.3e of %.3e" % (rel(got, ref), np.max(np.abs(got - ref)),
+                                                                   np.max(np.abs(ref))))
+    assert rel(got, ref) <= 1e-5
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
     del Aty
     note("cone 512: B^T")
     Btx = torch.empty(g.m, dtype=torch.float32, device=DEV)

@@ -242,6 +242,23 @@ def test_cone_sampled_back_adjoint_is_the_transpose():
     assert abs(bt @ y - x @ op.B(y).reshape(-1)) <= 1e-12 * np.linalg.norm(bt) * np.linalg.norm(y)
 
 
+def test_cone_sampled_forward_adjoint_is_the_transpose():
+    # every voxel of A^T evaluated one at a time (each ray's weight on that
+    # voxel, over all rays) equals the transposed dense matrix of A built
+    # independently, the scatter-form A^T, and <A^T y, x> = <y, A x>
+    g = TINY_CONE
+    op = oracle.Operator(g)
+    r = np.random.default_rng(6)
+    x = r.standard_normal(g.n)
+    y = r.standard_normal(g.m)
+    Ad = dense.dense_A_cone(g)
+    at = op.At_at(y, np.arange(g.n))
+    ref = Ad.T @ y
+    assert np.max(np.abs(at - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert np.max(np.abs(at - op.At(y).reshape(-1))) <= 1e-13 * np.max(np.abs(ref))
+    assert abs(at @ x - y @ op.A(x).reshape(-1)) <= 1e-12 * np.linalg.norm(at) * np.linalg.norm(x)
+
+
 def test_cone_constant_volume_central_ray():
     # the central ray of every view runs along the x-y plane through the centre;
     # for a constant volume its Joseph sum is the number of crossed planes / |d_dom|
@@ -276,6 +293,8 @@ def test_cone_sampled_outputs_equal_the_full_operators():
     # rounding (another summation order)
     bt = op.Bt(x).reshape(-1)
     assert np.max(np.abs(op.Bt_at(x, rays) - bt[rays])) <= 1e-12 * np.max(np.abs(bt))
+    at = op.At(y).reshape(-1)
+    assert np.max(np.abs(op.At_at(y, vox) - at[vox])) <= 1e-12 * np.max(np.abs(at))
     with pytest.raises(ValueError):
         op.A_at(x, [g.m])
     with pytest.raises(ValueError):
