@@ -77,6 +77,8 @@ def lib():
         L.or_gkb.argtypes = [G, ctypes.c_int, P, ctypes.POINTER(_Opts), P, P, P, P, P, P, P, P,
                              ctypes.POINTER(_Info)]
         L.or_gkb.restype = ctypes.c_int
+        L.or_gmres.argtypes = [G, ctypes.c_int, P, ctypes.POINTER(_Opts), P, P, P, P, P, ctypes.POINTER(_Info)]
+        L.or_gmres.restype = ctypes.c_int
         L.or_proj_solve.argtypes = [ctypes.c_int, P, P, ctypes.c_double, P, P, P]
         L.or_proj_solve.restype = None
         L.or_jacobi_svd.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P]
@@ -231,6 +233,53 @@ def gkb(op: Operator, mode: int, b, k_max: int, lam: float = 0.0, use_dp: bool =
     return GKBResult(x=x.reshape(op.image_shape), k_stop=k, reason=info.reason, residual=info.residual,
                      proj_residual=info.proj_residual, t1=info.t1, alpha1=info.alpha1, rho=rho[:k], pres=pres[:k],
                      alpha=alpha, t=t, Q=Q, S=S, u=u[:k], rre=None if xt is None else rre[:k])
+
+
+@dataclass
+class GMRESResult:
+    x: np.ndarray
+    k_stop: int
+    reason: int
+    residual: float
+    proj_residual: float
+    beta: float                      # ||r_0||
+    rho: np.ndarray                  # ||A x_k - b||, k = 1..k_stop
+    pres: np.ndarray                 # ||H_k u_k - beta e_1||
+    H: Optional[np.ndarray] = None   # (k_stop + 1) x k_stop Hessenberg
+    Q: Optional[np.ndarray] = None   # (k_stop + 1) x dimq Arnoldi basis (rows)
+    rre: Optional[np.ndarray] = None
+
+
+def gmres(op: Operator, mode: int, b, k_max: int, use_dp: bool = False, tau: float = 1.0,
+          noise_norm: float = 0.0, rns_eps: float = 0.0, want_bases: bool = False, x_true=None) -> GMRESResult:
+    """AB-GMRES (mode 0) or BA-GMRES (mode 1) from x_0 = 0 (Algs. "AB-GMRES",
+    "BA-GMRES"; Arnoldi with modified Gram-Schmidt, eq. (proj) by the SVD of
+    H_k).  Stops by the discrepancy principle, residual norm stagnation,
+    breakdown or k_max, on the literal ||A x_k - b||."""
+    if mode not in (MODE_AB, MODE_BA):
+        raise ValueError("GMRES modes are MODE_AB and MODE_BA")
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+    assert b.size == op.m
+    xt = None if x_true is None else np.ascontiguousarray(np.asarray(x_true, dtype=np.float64).reshape(-1))
+    rre = np.zeros(k_max)
+    o = _Opts(k_max, 0.0, 1 if use_dp else 0, tau, noise_norm, 1, rns_eps,
+              None if xt is None else xt.ctypes.data, None if xt is None else rre.ctypes.data)
+    info = _Info()
+    x = np.zeros(op.n)
+    rho = np.zeros(k_max)
+    pres = np.zeros(k_max)
+    dimq = op.m if mode == MODE_AB else op.n
+    H = np.zeros((k_max + 1, k_max)) if want_bases else None
+    Q = np.zeros((k_max + 1, dimq)) if want_bases else None
+    rc = lib().or_gmres(ctypes.byref(op.g), mode, _ptr(b), ctypes.byref(o), _ptr(x), _ptr(rho), _ptr(pres),
+                        _ptr(H), _ptr(Q), ctypes.byref(info))
+    if rc != 0:
+        raise ValueError("oracle gmres: invalid arguments")
+    k = info.k_stop
+    return GMRESResult(x=x.reshape(op.image_shape), k_stop=k, reason=info.reason, residual=info.residual,
+                       proj_residual=info.proj_residual, beta=info.t1, rho=rho[:k], pres=pres[:k],
+                       H=None if H is None else H[:k + 1, :k], Q=None if Q is None else Q[:k + 1],
+                       rre=None if xt is None else rre[:k])
 
 
 def proj_solve(alpha, t, k: int, lam: float = 0.0):

@@ -33,6 +33,10 @@
  *  - Discrepancy principle (eq. DP): stop at the first k with
  *    ||A x_k - b|| <= tau ||e||, the residual evaluated literally with a
  *    fresh application of A to x_k.
+ *  - The comparison methods AB-GMRES and BA-GMRES (Sec. 2.1, Algs.
+ *    "AB-GMRES" and "BA-GMRES"): Arnoldi with modified Gram-Schmidt on
+ *    M = AB or BA, the Hessenberg projected problem (eq. proj) solved with
+ *    its SVD, the same stopping rules.
  *
  * Compiled with -ffp-contract=off so that every product is rounded as
  * written.
@@ -1030,6 +1034,178 @@ done:
   free(u);
   free(c1);
   free(qu);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* AB-GMRES and BA-GMRES (the paper's comparison methods, Sec. 2.1)          */
+/* ---------------------------------------------------------------------- */
+/*
+ * AB-GMRES (Alg. "AB-GMRES") and BA-GMRES (Alg. "BA-GMRES") from x_0 = 0.
+ * Arnoldi (eq. (Arn iter)) on M = AB with q in R^m and r_0 = b (AB), or on
+ * M = BA with q in R^n and r_0 = B b (BA): q_1 = r_0 / ||r_0||; at step k,
+ * w = M q_k is orthogonalised against q_1..q_k by one modified Gram-Schmidt
+ * pass as printed (h_{i,k} = q_i^T w, w -= h_{i,k} q_i), h_{k+1,k} = ||w||,
+ * q_{k+1} = w / h_{k+1,k}.  The projected problem (eq. proj)
+ *   u_k = argmin ||H_k u - ||r_0|| e_1||
+ * with the (k+1) x k upper Hessenberg H_k is solved through its SVD (Jacobi;
+ * singular values <= (k+1) eps s_max dropped).  x_k = B Q_k u_k (AB) or
+ * Q_k u_k (BA).  The stopping rules act on the data residual ||A x_k - b||
+ * (eqs. DP and RNS), evaluated literally with a fresh application of A;
+ * breakdown when h_{k+1,k} <= 100 eps max_i ||H_k(:, i)|| (the Krylov space is
+ * invariant and x_k its least-squares solution).  No Tikhonov term
+ * (lambda must be 0).
+ * Outputs: x (n) at k_stop; rho[k_max]; pres[k_max] = ||H_k u_k - ||r_0|| e_1||;
+ * optional Hout ((k_max+1) x k_max row-major, h_{i,j} at [(i-1) k_max + j-1]);
+ * optional Qout (dimq x (k_max+1), column i contiguous); info->t1 = ||r_0||,
+ * info->alpha1 = h_{2,1}.  Returns 0, or -1 on invalid arguments.
+ */
+int or_gmres(const or_geom *g, int mode, const double *b, const or_opts *o, double *x, double *rho, double *pres,
+             double *Hout, double *Qout, or_info *info) {
+  const long long m = g_m(g), n = g_n(g);
+  if (o->k_max < 1 || o->lambda != 0.0) return -1;
+  if (mode != OR_MODE_AB && mode != OR_MODE_BA) return -1;
+  if (o->use_dp && !(o->tau > 0.0)) return -1;
+  if (!(o->rns_eps >= 0.0)) return -1;
+  const long long dimq = (mode == OR_MODE_AB) ? m : n;
+  const int K = o->k_max;
+  double *Q = (double *)calloc((size_t)dimq * (K + 1), sizeof(double));
+  double *H = (double *)calloc((size_t)(K + 1) * K, sizeof(double));
+  double *w = (double *)calloc((size_t)dimq, sizeof(double));
+  double *tmp = (double *)calloc((size_t)(m > n ? m : n), sizeof(double));
+  double *qu = (double *)calloc((size_t)dimq, sizeof(double));
+  double *xk = (double *)calloc((size_t)n, sizeof(double));
+  double *ax = (double *)calloc((size_t)m, sizeof(double));
+  double *u = (double *)calloc((size_t)K, sizeof(double));
+  double *W = (double *)calloc((size_t)(K + 1) * K, sizeof(double));
+  double *V = (double *)calloc((size_t)K * K, sizeof(double));
+  double *sig = (double *)calloc((size_t)K, sizeof(double));
+  double scale = 0.0;
+  for (int i = 0; i < K; ++i) {
+    rho[i] = 0.0;
+    pres[i] = 0.0;
+  }
+  info->k_stop = 0;
+  info->reason = 0;
+  info->residual = 0.0;
+  info->proj_residual = 0.0;
+  info->alpha1 = 0.0;
+  memset(x, 0, sizeof(double) * (size_t)n);
+
+  /* r_0 = b (AB) or B b (BA) */
+  if (mode == OR_MODE_BA)
+    or_back(g, b, w);
+  else
+    memcpy(w, b, sizeof(double) * (size_t)dimq);
+  const double beta = nrm2(w, dimq);
+  info->t1 = beta;
+  if (!(beta > 0.0)) {
+    info->reason = OR_STOP_BREAKDOWN;
+    info->residual = nrm2(b, m);
+    goto done;
+  }
+  for (long long i = 0; i < dimq; ++i) Q[i] = w[i] / beta;
+
+  for (int k = 1; k <= K; ++k) {
+    const double *qk = Q + (size_t)(k - 1) * dimq;
+    /* w = M q_k, orthogonalised against q_1..q_k (modified Gram-Schmidt) */
+    apply_M(g, mode, qk, w, tmp);
+    for (int i = 1; i <= k; ++i) {
+      const double *qi = Q + (size_t)(i - 1) * dimq;
+      const double h = dot(qi, w, dimq);
+      H[(size_t)(i - 1) * K + (k - 1)] = h;
+      for (long long r = 0; r < dimq; ++r) w[r] -= h * qi[r];
+    }
+    const double hk1 = nrm2(w, dimq);
+    H[(size_t)k * K + (k - 1)] = hk1;
+    if (k == 1) info->alpha1 = hk1;
+    if (hk1 > 0.0) { /* q_{k+1}, used by the next step (and the Arnoldi relation) */
+      double *qn = Q + (size_t)k * dimq;
+      for (long long i = 0; i < dimq; ++i) qn[i] = w[i] / hk1;
+    }
+    {
+      double cn = 0.0;
+      for (int i = 0; i <= k; ++i) cn += H[(size_t)i * K + (k - 1)] * H[(size_t)i * K + (k - 1)];
+      if (sqrt(cn) > scale) scale = sqrt(cn);
+    }
+    /* projected problem through the SVD of H_k: u = sum_i (beta U[0][i] / s_i) V[:, i] */
+    for (int r = 0; r <= k; ++r)
+      for (int c = 0; c < k; ++c) W[(size_t)r * k + c] = H[(size_t)r * K + c];
+    or_jacobi_svd(k + 1, k, W, sig, V);
+    double smax = 0.0;
+    for (int i = 0; i < k; ++i) smax = fmax(smax, sig[i]);
+    for (int i = 0; i < k; ++i) u[i] = 0.0;
+    for (int i = 0; i < k; ++i) {
+      if (!(sig[i] > (k + 1) * DBL_EPSILON * smax)) continue;
+      const double coef = beta * W[i] / sig[i]; /* W[0][i] = U[0][i] */
+      for (int r = 0; r < k; ++r) u[r] += coef * V[(size_t)r * k + i];
+    }
+    {
+      double s2 = 0.0;
+      for (int r = 0; r <= k; ++r) {
+        double hu = r == 0 ? -beta : 0.0;
+        for (int c = 0; c < k; ++c) hu += H[(size_t)r * K + c] * u[c];
+        s2 += hu * hu;
+      }
+      pres[k - 1] = sqrt(s2);
+    }
+    /* x_k = (B) Q_k u_k and the literal residual ||A x_k - b|| */
+    for (long long i = 0; i < dimq; ++i) {
+      double acc = 0.0;
+      for (int c = 0; c < k; ++c) acc += Q[(size_t)c * dimq + i] * u[c];
+      qu[i] = acc;
+    }
+    if (mode == OR_MODE_AB)
+      or_back(g, qu, xk);
+    else
+      memcpy(xk, qu, sizeof(double) * (size_t)n);
+    or_forward(g, xk, ax);
+    for (long long i = 0; i < m; ++i) ax[i] -= b[i];
+    rho[k - 1] = nrm2(ax, m);
+    memcpy(x, xk, sizeof(double) * (size_t)n);
+    if (o->xtrue && o->rre) {
+      double e2 = 0.0, t2 = 0.0;
+      for (long long i = 0; i < n; ++i) {
+        const double d = xk[i] - o->xtrue[i];
+        e2 += d * d;
+        t2 += o->xtrue[i] * o->xtrue[i];
+      }
+      o->rre[k - 1] = sqrt(e2) / sqrt(t2);
+    }
+    info->k_stop = k;
+    info->residual = rho[k - 1];
+    info->proj_residual = pres[k - 1];
+    if (o->use_dp && rho[k - 1] <= o->tau * o->noise_norm) {
+      info->reason = OR_STOP_DP;
+      goto done;
+    }
+    if (o->rns_eps > 0.0 && k >= 2 && fabs(rho[k - 2] - rho[k - 1]) < o->rns_eps * rho[k - 2]) {
+      info->reason = OR_STOP_RNS;
+      goto done;
+    }
+    if (!(hk1 > 100.0 * DBL_EPSILON * scale)) {
+      info->reason = OR_STOP_BREAKDOWN;
+      goto done;
+    }
+    if (k == K) {
+      info->reason = o->use_dp ? OR_STOP_DP_NOT_REACHED : OR_STOP_KMAX;
+      goto done;
+    }
+  }
+done:
+  if (Hout) memcpy(Hout, H, sizeof(double) * (size_t)(K + 1) * K);
+  if (Qout) memcpy(Qout, Q, sizeof(double) * (size_t)dimq * (K + 1));
+  free(Q);
+  free(H);
+  free(w);
+  free(tmp);
+  free(qu);
+  free(xk);
+  free(ax);
+  free(u);
+  free(W);
+  free(V);
+  free(sig);
   return 0;
 }
 
