@@ -170,6 +170,34 @@ gkb_status gkb_ba_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const vo
 gkb_status gkb_gkb_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
                          void *x, gkb_solve_info *info);
 
+/* The paper's comparison methods (Sec. 2.1), from x_0 = 0 on the same
+ * projectors:
+ *   AB-GMRES (Alg. "AB-GMRES"): GMRES on A B y = b with B as right
+ *     preconditioner; Arnoldi basis in R^m from r_0 = b; x_k = B Q_k u_k.
+ *   BA-GMRES (Alg. "BA-GMRES"): GMRES on B A x = B b with B as left
+ *     preconditioner; Arnoldi basis in R^n from r_0 = B b; x_k = Q_k u_k.
+ * u_k = argmin ||H_k u - ||r_0|| e_1|| (eq. proj) with the (k+1) x k upper
+ * Hessenberg H_k of the Arnoldi relation M Q_k = Q_{k+1} H_k (eq. Arn iter).
+ * The Arnoldi vectors are orthogonalised by two classical Gram-Schmidt passes
+ * (the coefficients of both passes form H_k's column; the paper prints one
+ * modified pass, equal up to rounding), and u_k comes from a Givens QR of
+ * H_k updated once per iteration (the paper uses the SVD).  The stopping
+ * rules are those of the GKB solves on ||A x_k - b|| (eqs. DP and RNS), which
+ * is evaluated as ||Y_k u_k - b|| from the stored A-images Y (AB: A B q_i;
+ * BA: A q_i: m x k_max extra values of the vector type); breakdown when
+ * h_{k+1,k} vanishes (x_k is then the least-squares solution on an invariant
+ * Krylov space).
+ * Options as for the GKB solves, except: lambda must be 0 and precond NULL
+ * (GKB_EUNSUPPORTED otherwise); k_max <= 1024 (GKB_EINVAL); reorth is
+ * ignored (the Arnoldi basis is always orthogonalised).  Histories:
+ * residual_history as for GKB; alpha_history[0] = ||r_0||, alpha_history[k] =
+ * h_{k+1,k}; t_history is zeroed.  info->t1 = ||r_0||, info->alpha1 = h_{2,1},
+ * info->proj_residual = ||H_k u_k - ||r_0|| e_1||. */
+gkb_status gkb_ab_gmres_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b,
+                              const gkb_solve_opts *o, void *x, gkb_solve_info *info);
+gkb_status gkb_ba_gmres_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b,
+                              const gkb_solve_opts *o, void *x, gkb_solve_info *info);
+
 /* Batched multi-slice solve: n_slices independent problems, each with its own
  * geometry, b, options (k_max, lambda, tau, noise_norm, reorth, histories)
  * and discrepancy stop, solved by AB-GKB (method GKB_METHOD_AB) or BA-GKB

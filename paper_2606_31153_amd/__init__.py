@@ -36,7 +36,7 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_only", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
             "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc",
-            "gkb_check_geometry")
+            "gkb_check_geometry", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve")
 NET_PARAMS = 19008
 GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
@@ -95,7 +95,7 @@ def lib() -> ctypes.CDLL:
         L.gkb_last_error.restype = ctypes.c_char_p
         for name in ("gkb_forward", "gkb_back", "gkb_forward_adjoint", "gkb_back_adjoint", "gkb_back_noalloc"):
             getattr(L, name).argtypes = [vp, G, cp, vp, vp]
-        for name in ("gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve"):
+        for name in ("gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve"):
             getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
         L.gkb_batch_solve.argtypes = [vp, cp, cp, G, cp, ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                                       ctypes.POINTER(vp), ctypes.POINTER(SolveInfo)]
@@ -311,6 +311,17 @@ def gkb_ba_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
 def gkb_gkb_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
     """Matched GKB (B := A^T), equivalent to LSQR."""
     return _solve("gkb_gkb_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def gkb_ab_gmres_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """AB-GMRES (B as right preconditioner): x = B Q_k u_k.  ``alpha`` holds
+    ||r_0|| then h_{k+1,k}; ``t`` is zero."""
+    return _solve("gkb_ab_gmres_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def gkb_ba_gmres_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """BA-GMRES (B as left preconditioner): x = Q_k u_k."""
+    return _solve("gkb_ba_gmres_solve", ctx, geom, b, x, k_max, **kw)
 
 
 def _opts(k_max: int, lam: float = 0.0, use_dp: bool = False, tau: float = 1.0, noise_norm: float = 0.0,

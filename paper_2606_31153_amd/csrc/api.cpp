@@ -677,6 +677,7 @@ struct gkb_ctx {
   DevBuf ywpad;  // fan-beam A^T input as (w y, w) pairs, apart from ypad so that neither layout overwrites the other's pads
   // solve workspace
   DevBuf Q, yk, rdbl, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
+  DevBuf gm_y, gm_h;  // GMRES: the A-images Y and the Hessenberg columns
   int *host_flag = nullptr;      // host-mapped
   int *host_flag_dev = nullptr;  // its device address
   // batched solves: vectors, control blocks, slice descriptors, launch maps
@@ -1600,6 +1601,73 @@ struct Solver {
     else
       wrote_image(TAG_Q);
   }
+
+  // ----- AB-/BA-GMRES (Algs. "AB-GMRES", "BA-GMRES") on the same buffers -----
+  // Q holds the Arnoldi basis (dimension m for AB, n for BA), w the vector
+  // being orthogonalised, Y the A-images of the basis (AB: A B q_i, the raw
+  // product before orthogonalisation; BA: A q_i), ldy a multiple of 4.
+  T *Y = nullptr;
+  long long ldy = 0;
+
+  gkb_status gm_alloc() {
+    ldy = (m + 3) / 4 * 4;
+    HIPC(c->gm_y.ensure(sizeof(T) * (size_t)ldy * K));
+    ctl.ldh = K + 2;
+    HIPC(c->gm_h.ensure(sizeof(double) * (size_t)ctl.ldh * (K + 2)));
+    Y = c->gm_y.as<T>();
+    ctl.hm = c->gm_h.as<double>();
+    return GKB_OK;
+  }
+
+  // w = M q_k and the A-image Y[:, k-1]
+  void gm_apply_M() {
+    const bool fu = fusing();
+    Col<T> ycol = colk<T>(Y, ldy, -1, kp);
+    Epi<T> pe = plain_epi<T>();
+    if (mode == MODE_AB) {  // w = A (B q_k); Y_k = w before orthogonalisation
+      if (fu) pe.pout = pad_image_out();
+      B(qcol(-1), tn, pe, TAG_Q);
+      if (fu) wrote_image(TAG_BQ);
+      Epi<T> e = plain_epi<T>();
+      e.out_raw = ycol;
+      A(col<const T>(tn), col<T>(w), e, TAG_BQ);
+    } else {  // Y_k = A q_k ; w = B Y_k
+      if (fu) pe.pout = pad_sino_out();
+      A(qcol(-1), ycol, pe, TAG_Q);
+      if (fu) wrote_sino(TAG_YK);
+      B(colk<const T>(Y, ldy, -1, kp), w, plain_epi<T>(), TAG_YK);
+    }
+  }
+
+  // Arnoldi step: CGS2 of w against q_1..q_k, the two rounds' coefficients
+  // summed into column k of H; h_{k+1,k} = ||w|| into alpha[k+1]; q_{k+1}
+  void gm_orthogonalise(int k) {
+    TraceScope ts(c, "reorth");
+    launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+    launch_gm_hcol(ctl, 1, st);
+    if (K <= mid_max_k(sizeof(T))) {
+      launch_cgs_mid<T>(ctl, Q, ldq, w, dimq, partials, k, st);
+    } else {
+      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, st);
+      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+    }
+    launch_gm_hcol(ctl, 0, st);
+    launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
+    normalize();
+  }
+
+  void gm_iteration(int k, const T *b) {
+    gm_apply_M();
+    gm_orthogonalise(k);
+    {
+      TraceScope ts(c, "small_solve");
+      launch_gm_solve(ctl, st);
+    }
+    {
+      TraceScope ts(c, "residual");
+      launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st);
+    }
+  }
 };
 
 template <typename T>
@@ -1750,6 +1818,126 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   return GKB_OK;
 }
 
+// AB-GMRES / BA-GMRES from x_0 = 0: the Arnoldi iteration on M = AB or BA
+// with the stopping rules of the GKB solves on rho_k = ||A x_k - b||.
+template <typename T>
+gkb_status gm_solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const void *bv, const gkb_solve_opts *o,
+                         void *xv, gkb_solve_info *info, int mode) {
+  auto t_start = std::chrono::steady_clock::now();
+  DevTables *d = nullptr;
+  gkb_status stt = get_tables(c, geom, dtype, &d);
+  if (stt != GKB_OK) return stt;
+  Solver<T> S(c, *d, mode, o->k_max);
+  stt = S.alloc();
+  if (stt != GKB_OK) return stt;
+  stt = S.gm_alloc();
+  if (stt != GKB_OK) return stt;
+  const T *b = static_cast<const T *>(bv);
+  T *x = static_cast<T *>(xv);
+  hipStream_t st = c->stream;
+  const GeomDev &g = d->gd;
+
+  int hip_[CI_COUNT] = {0};
+  double hdp[CD_COUNT] = {0};
+  hdp[CD_TAUE] = o->use_dp ? o->tau * o->noise_norm : 0.0;
+  hdp[CD_ETAEPS] = 100.0 * (sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16) * 2.0;
+  hdp[CD_USEDP] = o->use_dp ? 1.0 : 0.0;
+  hdp[CD_KMAX] = o->k_max;
+  hdp[CD_RNS] = o->rns_eps;
+  HIPC(hipMemcpyAsync(S.ctl.ip, hip_, sizeof hip_, hipMemcpyHostToDevice, st));
+  HIPC(hipMemcpyAsync(S.ctl.dp, hdp, sizeof hdp, hipMemcpyHostToDevice, st));
+  *c->host_flag = 0;
+  if (S.fusing()) {
+    HIPC(hipMemsetAsync(S.xpad, 0, sizeof(T) * (size_t)g.pad_elems, st));
+    HIPC(hipMemsetAsync(S.ypad, 0, sizeof(T) * (size_t)g.ypad_elems, st));
+    if (g.kind == GKB_FAN2D) HIPC(hipMemsetAsync(S.ywpad, 0, 2 * sizeof(T) * (size_t)g.ypad_elems, st));
+  }
+  S.forget_pads();
+
+  // start-up (k = 0): ||b||; r_0 = b (AB) or B b (BA); alpha[1] = ||r_0||; q_1
+  launch_resid_init<T>(S.ctl, b, g.m, S.partials, st);
+  if (mode == MODE_BA)
+    S.B(col<const T>(b), S.w, plain_epi<T>());
+  else
+    launch_copy<T>(b, S.w, g.m, st);
+  launch_norm_to<T>(S.ctl, S.w, S.dimq, NORM_ALPHA1, S.partials, st);
+  S.normalize();
+  HIPC(hipGetLastError());
+  double h2[2];
+  HIPC(hipMemcpyAsync(&h2[0], S.ctl.alpha + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(&h2[1], S.ctl.dp + CD_BNORM, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  const double beta = h2[0], bnorm = h2[1];
+  if (!std::isfinite(bnorm) || !std::isfinite(beta))
+    return fail(GKB_ENONFINITE, "non-finite value in b (or in the start-up vector)");
+  gkb_solve_info inf{};
+  inf.t1 = beta;
+  int k_stop = 0, reason = 0;
+  std::vector<double> al(o->k_max + 2, 0.0);
+  if (!(beta > 0.0)) {
+    HIPC(hipMemsetAsync(x, 0, sizeof(T) * (size_t)g.n, st));
+    HIPC(hipStreamSynchronize(st));
+    reason = GKB_STOP_BREAKDOWN;
+    inf.residual = bnorm;
+  } else {
+    launch_set_int(S.ctl.ip + CI_K, 1, st);
+    const int L = 4;
+    std::vector<hipEvent_t> evs(L, nullptr);
+    for (auto &e : evs) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const T *x_true = (o->x_true && o->rre_history) ? static_cast<const T *>(o->x_true) : nullptr;
+    if (x_true) launch_norm_to<T>(S.ctl, x_true, g.n, NORM_XTRUE, S.partials, st);
+    for (int k = 1; k <= o->k_max; ++k) {
+      S.gm_iteration(k, b);
+      if (x_true) S.rre_step(x_true);
+      HIPC(hipEventRecord(evs[k % L], st));
+      if (k >= L) {
+        HIPC(hipEventSynchronize(evs[(k - L + 1) % L]));
+        if (*(volatile int *)c->host_flag) break;
+      }
+    }
+    HIPC(hipGetLastError());
+    S.forget_pads();
+    if (mode == MODE_AB) {
+      launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, S.tm, st);
+      S.B(col<const T>(S.tm), x, plain_epi<T>(), nullptr);
+    } else {
+      launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, x, st);
+    }
+    HIPC(hipGetLastError());
+    int hi[CI_COUNT];
+    HIPC(hipMemcpyAsync(hi, S.ctl.ip, sizeof hi, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    for (auto &e : evs) (void)hipEventDestroy(e);
+    k_stop = hi[CI_KSTOP];
+    reason = hi[CI_REASON];
+    std::vector<double> rho(o->k_max + 2), pres(o->k_max + 2);
+    HIPC(hipMemcpy(rho.data(), S.ctl.rho, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(pres.data(), S.ctl.pres, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    HIPC(hipMemcpy(al.data(), S.ctl.alpha, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+    inf.residual = rho[k_stop];
+    inf.proj_residual = pres[k_stop];
+    inf.alpha1 = al[2];
+    if (o->residual_history)
+      for (int k = 1; k <= k_stop; ++k) o->residual_history[k - 1] = rho[k];
+    if (x_true) {
+      std::vector<double> rre(o->k_max + 2);
+      HIPC(hipMemcpy(rre.data(), S.ctl.rre, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+      for (int k = 1; k <= k_stop; ++k) o->rre_history[k - 1] = rre[k];
+    }
+  }
+  al[1] = beta;
+  // alpha_history: ||r_0||, then h_{k+1,k} for k = 1..k_stop; t_history: zeros
+  for (int k = 1; k <= o->k_max + 1; ++k) {
+    if (o->alpha_history) o->alpha_history[k - 1] = (k <= k_stop + 1) ? al[k] : 0.0;
+    if (o->t_history) o->t_history[k - 1] = 0.0;
+  }
+  inf.k_stop = k_stop;
+  inf.reason = reason;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (info) *info = inf;
+  return GKB_OK;
+}
+
 gkb_status validate_opts(const gkb_solve_opts *o) {
   if (o->k_max < 1 || o->k_max > 4096) return fail(GKB_EINVAL, "k_max must be in [1, 4096]");
   if (!(o->lambda >= 0.0) || !std::isfinite(o->lambda)) return fail(GKB_EINVAL, "lambda must be finite and >= 0");
@@ -1761,6 +1949,23 @@ gkb_status validate_opts(const gkb_solve_opts *o) {
   if ((o->x_true == nullptr) != (o->rre_history == nullptr))
     return fail(GKB_EINVAL, "x_true and rre_history are given together");
   return GKB_OK;
+}
+
+gkb_status gm_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o, void *x,
+                    gkb_solve_info *info, int mode) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!o) return fail(GKB_EINVAL, "options are NULL");
+  if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  st = validate_opts(o);
+  if (st != GKB_OK) return st;
+  if (o->k_max > kGmMaxK) return fail(GKB_EINVAL, "GMRES: k_max must be <= 1024");
+  if (o->lambda != 0.0) return fail(GKB_EUNSUPPORTED, "GMRES has no Tikhonov term (lambda must be 0)");
+  if (o->precond) return fail(GKB_EUNSUPPORTED, "the learned filter is for BA-GKB only");
+  HIPC(hipSetDevice(c->device));
+  return dtype == GKB_F32 ? gm_solve_impl<float>(c, g, dtype, b, o, x, info, mode)
+                          : gm_solve_impl<double>(c, g, dtype, b, o, x, info, mode);
 }
 
 gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
@@ -2327,6 +2532,14 @@ gkb_status gkb_ba_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void
 gkb_status gkb_gkb_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
                          void *x, gkb_solve_info *info) {
   return solve_entry(c, g, dtype, b, o, x, info, MODE_GKB);
+}
+gkb_status gkb_ab_gmres_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                              void *x, gkb_solve_info *info) {
+  return gm_entry(c, g, dtype, b, o, x, info, MODE_AB);
+}
+gkb_status gkb_ba_gmres_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                              void *x, gkb_solve_info *info) {
+  return gm_entry(c, g, dtype, b, o, x, info, MODE_BA);
 }
 
 gkb_status gkb_batch_solve(gkb_ctx *c, int method, int n_slices, const gkb_geometry *geoms, int dtype,

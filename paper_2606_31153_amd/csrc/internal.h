@@ -63,6 +63,11 @@ struct Ctl {
   double *r;      // [m] r_k = A x_k - b
   int *host_stop; // host-mapped mirror of ip[CI_STOP] (may be null)
   int K;
+  // GMRES: Hessenberg / triangular columns, column j (1-based) at hm + j * ldh
+  // (rows 0..j); the Givens rotations in Rd (cosines) and Rth (sines), the
+  // rotated right-hand side in Rphi[1..k+1].  Null for GKB.
+  double *hm;
+  long long ldh;
 };
 
 // A vector selected by the device-side iteration counter:
@@ -424,7 +429,21 @@ void launch_net_scale(float *r, long long n, const double *sums, int batch, hipS
 
 // targets of the finalising reductions: t[k+1], alpha[k+1], dp[CD_BNORM] =
 // ||b||, and rho[k] = ||r_k|| with the stopping decision of iteration k
-enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO = 3, NORM_XTRUE = 4, NORM_RRE = 5 };
+enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO = 3, NORM_XTRUE = 4, NORM_RRE = 5,
+                        NORM_GMRHO = 6 };
+
+// ---- GMRES (Algs. "AB-GMRES", "BA-GMRES") on the same vectors and reductions ----
+constexpr int kGmMaxK = 1024;  // k_max limit of the GMRES solves
+// Hessenberg column k, rows 0..k-1, from the CGS coefficients ctl.c (first
+// round: set; second round: added)
+void launch_gm_hcol(Ctl ctl, int first, hipStream_t s);
+// Givens QR update of H_k with column k (h_{k+1,k} = alpha[k+1]), u_k by back
+// substitution, projected residual into pres[k]
+void launch_gm_solve(Ctl ctl, hipStream_t s);
+// rho_k = ||Y_k u_k - b|| (Y: the A-images, ld a multiple of 4) and the
+// stopping decision of iteration k
+template <typename T>
+void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s);
 
 // ---- batched launchers: one launch covers every active slice ----
 template <typename T>

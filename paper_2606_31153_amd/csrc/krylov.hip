@@ -424,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restr
 // ---- finalising kernel: t[k+1] (which == NORM_T1) or alpha[k+1]
 // (NORM_ALPHA1) = sqrt of the sum of nb partials ----
 __device__ inline void stop_test(const Ctl &ctl, double rho);
+__device__ inline void gm_stop_test(const Ctl &ctl, double rho);
 
 __device__ inline void norm_finalize_body(const Ctl &ctl, const double *__restrict__ partials, unsigned nb,
                                           int which) {
@@ -437,6 +438,7 @@ __device__ inline void norm_finalize_body(const Ctl &ctl, const double *__restri
       case NORM_BNORM: ctl.dp[CD_BNORM] = sqrt(tot); break;
       case NORM_XTRUE: ctl.dp[CD_XTNORM] = sqrt(tot); break;
       case NORM_RRE: ctl.rre[ctl.ip[CI_KSTOP]] = sqrt(tot) / ctl.dp[CD_XTNORM]; break;
+      case NORM_GMRHO: gm_stop_test(ctl, sqrt(tot)); break;
       default: stop_test(ctl, sqrt(tot)); break;  // NORM_RHO
     }
   }
@@ -584,6 +586,147 @@ __device__ inline void stop_test(const Ctl &ctl, double rho) {
     reason = dp[CD_USEDP] != 0.0 ? 4 : 2;  // DP_NOT_REACHED / KMAX
   else if (!(ctl.alpha[k + 1] > eta))
     reason = 3;
+  ctl.ip[CI_KSTOP] = k;
+  if (reason) {
+    ctl.ip[CI_REASON] = reason;
+    ctl.ip[CI_STOP] = 1;
+    if (ctl.host_stop) *(volatile int *)ctl.host_stop = 1;
+  } else {
+    ctl.ip[CI_K] = k + 1;
+  }
+}
+
+// ---- GMRES (Algs. "AB-GMRES" and "BA-GMRES") -----------------------------------
+// Arnoldi (eq. (Arn iter)) uses the CGS2 kernels above: the two rounds'
+// coefficients add up to the Hessenberg column, h_{k+1,k} = ||w|| is
+// alpha[k+1] and q_{k+1} = w / alpha[k+1] (alpha[1] = ||r_0||).  The
+// projected problem (eq. proj) min ||H_k u - ||r_0|| e_1|| is solved by
+// Givens rotations updated once per iteration (the usual GMRES
+// factorisation; the oracle takes the SVD of H_k): column k gets the k - 1
+// earlier rotations and a new one that annihilates h_{k+1,k}, the rotated
+// right-hand side g gains one entry, and u_k solves the k x k triangular
+// system R u = g.  |g_{k+1}| is the projected residual.
+
+__global__ __launch_bounds__(kBlock) void k_gm_hcol(Ctl ctl, int first) {
+  if (ctl.ip[CI_STOP]) return;
+  const int k = ctl.ip[CI_K];
+  double *col = ctl.hm + (long long)k * ctl.ldh;
+  for (int i = threadIdx.x; i < k; i += kBlock) col[i] = first ? ctl.c[i] : col[i] + ctl.c[i];
+}
+
+// One wavefront.  The serial rotation steps run in lane 0 on a copy of the
+// column in LDS; the back substitution goes column by column with the rows
+// spread over the lanes.
+__global__ __launch_bounds__(64) void k_gm_solve(Ctl ctl) {
+  if (ctl.ip[CI_STOP]) return;
+  __shared__ double s_col[kGmMaxK + 2];
+  __shared__ double s_g[kGmMaxK + 2];
+  const int k = ctl.ip[CI_K];
+  const int lane = threadIdx.x;
+  double *col = ctl.hm + (long long)k * ctl.ldh;
+  const double hk1 = ctl.alpha[k + 1];
+  double ss = 0.0;
+  for (int i = lane; i < k; i += 64) {
+    const double v = col[i];
+    s_col[i] = v;
+    ss = fma(v, v, ss);
+  }
+  ss = wave_sum(ss);
+  // g_1..g_{k-1} are final; lane 0 forms g_k and g_{k+1}
+  for (int i = lane + 1; i < k; i += 64) s_g[i] = ctl.Rphi[i];
+  __syncthreads();
+  if (lane == 0) {
+    double *dp = ctl.dp;
+    // breakdown scale: the largest Hessenberg column norm so far
+    dp[CD_BSCALE] = fmax(dp[CD_BSCALE], sqrt(fma(hk1, hk1, ss)));
+    for (int i = 1; i < k; ++i) {            // rotation i acts on rows i-1, i
+      const double c = ctl.Rd[i], sn = ctl.Rth[i];
+      const double a = s_col[i - 1], b = s_col[i];
+      s_col[i - 1] = c * a + sn * b;
+      s_col[i] = c * b - sn * a;
+    }
+    const double a = s_col[k - 1];
+    const double r = sqrt(fma(a, a, hk1 * hk1));
+    const double c = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? hk1 / r : 0.0;
+    ctl.Rd[k] = c;
+    ctl.Rth[k] = sn;
+    s_col[k - 1] = r;
+    const double gk = (k == 1) ? ctl.alpha[1] : ctl.Rphi[k];  // g_1 = ||r_0||
+    s_g[k] = c * gk;
+    ctl.Rphi[k] = c * gk;
+    ctl.Rphi[k + 1] = -sn * gk;
+    ctl.pres[k] = fabs(sn * gk);
+    dp[CD_PRES] = ctl.pres[k];
+  }
+  __syncthreads();
+  for (int i = lane; i < k; i += 64) col[i] = s_col[i];
+  // R u = g: u_j from the finished row j, then row j's column leaves the rows above
+  for (int j = k; j >= 1; --j) {
+    const double *cj = (j == k) ? s_col : ctl.hm + (long long)j * ctl.ldh;
+    const double rjj = cj[j - 1];
+    const double uj = rjj != 0.0 ? s_g[j] / rjj : 0.0;
+    for (int i = lane + 1; i < j; i += 64) s_g[i] = fma(-cj[i - 1], uj, s_g[i]);
+    if (lane == 0) ctl.u[j] = uj;
+    __syncthreads();
+  }
+}
+
+// rho_k = ||Y_k u_k - b||: partials of the squared norm, 4 rows per thread,
+// four columns of Y per step
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gm_resid(Ctl ctl, const T *__restrict__ Y, long long ld,
+                                                     const T *__restrict__ bv, long long m, double *partials) {
+  if (ctl.ip[CI_STOP]) return;
+  __shared__ double lds[kBlock / 64];
+  const int k = ctl.ip[CI_K];
+  const long long r0 = ((long long)blockIdx.x * kBlock + threadIdx.x) * RPT;
+  double acc[RPT];
+  load_quad(bv, r0, m, acc);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) acc[i] = -acc[i];
+  int j = 1;
+  for (; j + 3 <= k; j += 4) {
+    double y[4][RPT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) load_quad(Y + (long long)(j - 1 + q) * ld, r0, m, y[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double uq = ctl.u[j + q];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) acc[i] = fma(uq, y[q][i], acc[i]);
+    }
+  }
+  for (; j <= k; ++j) {
+    double y[RPT];
+    load_quad(Y + (long long)(j - 1) * ld, r0, m, y);
+    const double uj = ctl.u[j];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) acc[i] = fma(uj, y[i], acc[i]);
+  }
+  double ss = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) ss = fma(acc[i], acc[i], ss);
+  const double tot = block_sum<kBlock>(ss, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// the GMRES stopping decision of iteration k: the discrepancy principle and
+// residual norm stagnation on rho_k = ||A x_k - b||, then breakdown
+// (h_{k+1,k} below 100 eps times the largest Hessenberg column norm), then k_max
+__device__ inline void gm_stop_test(const Ctl &ctl, double rho) {
+  double *dp = ctl.dp;
+  const int k = ctl.ip[CI_K];
+  ctl.rho[k] = rho;
+  const double eta = dp[CD_ETAEPS] * dp[CD_BSCALE];
+  int reason = 0;
+  if (dp[CD_USEDP] != 0.0 && rho <= dp[CD_TAUE])
+    reason = 1;  // GKB_STOP_DP
+  else if (dp[CD_RNS] > 0.0 && k >= 2 && fabs(ctl.rho[k - 1] - rho) < dp[CD_RNS] * ctl.rho[k - 1])
+    reason = 6;  // GKB_STOP_RNS
+  else if (!(ctl.alpha[k + 1] > eta))
+    reason = 3;  // GKB_STOP_BREAKDOWN: the Krylov space is invariant
+  else if (k >= ctl.K)
+    reason = dp[CD_USEDP] != 0.0 ? 4 : 2;
   ctl.ip[CI_KSTOP] = k;
   if (reason) {
     ctl.ip[CI_REASON] = reason;
@@ -962,6 +1105,16 @@ void launch_rre(Ctl ctl, const T *x, const T *x_true, long long n, double *parti
 void launch_small_solve(Ctl ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl);
 }
+void launch_gm_hcol(Ctl ctl, int first, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(kBlock), 0, s, ctl, first);
+}
+void launch_gm_solve(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, ctl); }
+template <typename T>
+void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s) {
+  const int nb = vec_blocks(m);
+  hipLaunchKernelGGL(k_gm_resid<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Y, ld, b, m, partials);
+  launch_norm_finalize(ctl, partials, nb, NORM_GMRHO, ctl.ip + CI_STOP, s);
+}
 template <typename T>
 void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, hipStream_t s) {
   hipLaunchKernelGGL(k_solution<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, Q, ld, dim, out);
@@ -1060,6 +1213,7 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
+  template void launch_gm_resid<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t);  \
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
   template void launch_b_norm_finalize<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t); \
