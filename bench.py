@@ -137,25 +137,32 @@ def batch_bench(ctx):
     def sequential():
         return [gk.gkb_ba_solve(ctx, g, b, x, **o) for g, b, x, o in zip(geoms, bs, xs, opts)]
 
-    def batched():
-        return gk.gkb_batch_solve(ctx, gk.GKB_METHOD_BA, geoms, bs, xs, opts)
+    def batched(mode=gk.GKB_BATCH_LAUNCHES):
+        ctx.set_batch_mode(mode)
+        try:
+            return gk.gkb_batch_solve(ctx, gk.GKB_METHOD_BA, geoms, bs, xs, opts)
+        finally:
+            ctx.set_batch_mode(gk.GKB_BATCH_LAUNCHES)
+
+    def timed(f, *a):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f(*a)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
 
     sequential()
     batched()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rs = sequential()
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    rb = batched()
-    torch.cuda.synchronize()
-    t_bat = time.perf_counter() - t0
+    batched(gk.GKB_BATCH_GRAPH)
+    rs, t_seq = timed(sequential)
+    rb, t_bat = timed(batched)
+    rg, t_graph = timed(batched, gk.GKB_BATCH_GRAPH)
     ks = [r.k_stop for r in rb]
-    assert ks == [r.k_stop for r in rs]
+    assert ks == [r.k_stop for r in rs] == [r.k_stop for r in rg]
     ns = len(geoms)
     return {"workload": "64 parallel-beam slices, n 128..512, 180..720 views, 0.5-5% noise, BA-GKB, DP tau=1",
             "slices": ns, "s_per_slice_batched": t_bat / ns, "s_per_slice_sequential": t_seq / ns,
+            "s_per_slice_batched_graph": t_graph / ns,
             "batched_speedup": t_seq / t_bat, "iterations_mean": float(np.mean(ks)),
             "iterations_min": int(min(ks)), "iterations_max": int(max(ks)),
             "stopped_by_dp": sum(1 for r in rb if r.reason == gk.STOP_DP),

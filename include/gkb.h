@@ -215,6 +215,17 @@ typedef enum { GKB_METHOD_AB = 0, GKB_METHOD_BA = 1 } gkb_method;
 gkb_status gkb_batch_solve(gkb_ctx *ctx, int method, int n_slices, const gkb_geometry *geoms, int dtype,
                            const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info);
 
+/* How gkb_batch_solve issues its iterations on this context:
+ *   GKB_BATCH_LAUNCHES (default): every step of an iteration is one kernel
+ *     launch over all active slices;
+ *   GKB_BATCH_GRAPH: the same launches are captured once into a hipGraph
+ *     and replayed each iteration; the graph is captured again when slices
+ *     stop (and when the reorthogonalisation kernel's unroll changes, at
+ *     k = 17, 33, 65).  Capture runs on a stream the context creates.
+ * Results are bit for bit the same in both modes. */
+typedef enum { GKB_BATCH_LAUNCHES = 0, GKB_BATCH_GRAPH = 1 } gkb_batch_mode;
+gkb_status gkb_set_batch_mode(gkb_ctx *ctx, int mode);
+
 /* ---- Learned sinogram filter inside B (BA-GKB only) ----
  * BA-GKB (Alg. "BA-GKB") applies B and B^T only, so a linear filter F on
  * the sinogram side of B keeps the algorithm as it is: M = B F A,

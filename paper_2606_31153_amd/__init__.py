@@ -28,6 +28,7 @@ STOP_NONE, STOP_DP, STOP_KMAX, STOP_BREAKDOWN, STOP_DP_NOT_REACHED, STOP_FALLBAC
 GKB_PAR2D, GKB_FAN2D, GKB_CONE3D = 0, 1, 2
 GKB_F32, GKB_F64 = 0, 1
 GKB_METHOD_AB, GKB_METHOD_BA = 0, 1
+GKB_BATCH_LAUNCHES, GKB_BATCH_GRAPH = 0, 1
 
 STATUS_NAMES = {0: "GKB_OK", -1: "GKB_EINVAL", -2: "GKB_ENOMEM", -3: "GKB_EDEVICE", -4: "GKB_ENONFINITE",
                 -5: "GKB_EUNSUPPORTED"}
@@ -36,7 +37,7 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_only", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
             "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc",
-            "gkb_check_geometry", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve")
+            "gkb_check_geometry", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve", "gkb_set_batch_mode")
 NET_PARAMS = 19008
 GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
@@ -113,6 +114,7 @@ def lib() -> ctypes.CDLL:
         L.gkb_net_train_step.argtypes = [vp, vp, G, cp, vp, vp, cp, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_double)]
         L.gkb_check_geometry.argtypes = [G, cp, cp, ctypes.POINTER(CheckStats), ctypes.POINTER(cp)]
+        L.gkb_set_batch_mode.argtypes = [vp, cp]
         L.gkb_trace_enable.argtypes = [vp, cp]
         L.gkb_trace_only.argtypes = [vp, ctypes.c_char_p]
         L.gkb_trace_reset.argtypes = [vp]
@@ -186,6 +188,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_batch_mode(self, mode: int):
+        """GKB_BATCH_LAUNCHES or GKB_BATCH_GRAPH for gkb_batch_solve."""
+        _check(lib().gkb_set_batch_mode(self.handle, mode))
 
     def set_stream(self, stream: int):
         _check(lib().gkb_set_stream(self.handle, ctypes.c_void_p(stream)))

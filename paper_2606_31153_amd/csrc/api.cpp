@@ -689,6 +689,10 @@ struct gkb_ctx {
   hipEvent_t bpin_ev[2] = {nullptr, nullptr};
   // learned filter: activations, masks, filter output, training buffers
   DevBuf na0, na1, na2, nga, ngb, nmask, nout, ngout, nxh, nr, npart, nsums, nred, ny;
+  // batched solves: 1 = every iteration's launches captured in a hipGraph
+  // (re-captured when the set of active slices changes) and replayed
+  int batch_graph = 0;
+  hipStream_t cap_stream = nullptr;  // capture stream (created on first use)
   // tracing
   bool trace = false;
   std::string trace_only;  // non-empty: record only this kernel name
@@ -2306,7 +2310,10 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     const int L = 4;
     std::vector<hipEvent_t> evs(L, nullptr);
     for (auto &e : evs) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    for (int k = 1; k <= bl.kmax; ++k) {
+    // one iteration's launches over the active slices (the kernels read k
+    // from the slices' control blocks; on the host only the unroll of the
+    // fused CGS2 middle depends on it)
+    auto iteration = [&](int k) {
       // s~ <- M q_k - alpha_k/t_k s~, t_{k+1}, Y_k
       if (mode == MODE_BA) {
         opA(BS_Q_PREV, BS_Y_CUR, plain);
@@ -2331,6 +2338,42 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
         TraceScope ts(c, "residual");
         launch_b_resid<T>(bd, bl, st);
       }
+    };
+    // graph mode: the iteration is captured on the context's capture stream
+    // and the executable graph replayed on the solve's stream; a new active
+    // set (or unroll) is captured anew
+    hipGraphExec_t gexec = nullptr;
+    int set_version = 0, graph_key = -1;
+    auto release_graph = [&]() {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    };
+    for (int k = 1; k <= bl.kmax; ++k) {
+      if (c->batch_graph) {
+        const int key = set_version * 8 + (mid_unroll_bucket(k));
+        if (!gexec || key != graph_key) {
+          release_graph();
+          if (!c->cap_stream) HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+          const bool tr = c->trace;
+          c->trace = false;  // no event records inside the graph
+          HIPC(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+          st = c->cap_stream;
+          iteration(k);
+          st = c->stream;
+          c->trace = tr;
+          hipGraph_t gr = nullptr;
+          const hipError_t ce = hipStreamEndCapture(c->cap_stream, &gr);
+          if (ce != hipSuccess) return fail(GKB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+          const hipError_t ie = hipGraphInstantiate(&gexec, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          if (ie != hipSuccess) return fail(GKB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+          graph_key = key;
+        }
+        TraceScope ts(c, "iteration");
+        HIPC(hipGraphLaunch(gexec, st));
+      } else {
+        iteration(k);
+      }
       HIPC(hipEventRecord(evs[k % L], st));
       if (k >= L) {
         HIPC(hipEventSynchronize(evs[(k - L + 1) % L]));
@@ -2342,11 +2385,16 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
           active.swap(still);
           build_map(sh, active, mapbuf, bl);
           stt = upload_map(c, mapbuf);
-          if (stt != GKB_OK) return stt;
+          if (stt != GKB_OK) {
+            release_graph();
+            return stt;
+          }
           bd = BatchDev<T>{sd, c->bmap.as<const int>(), c->bmap.as<const int>() + bl.na, bl.na, 0};
+          ++set_version;
         }
       }
     }
+    release_graph();
     HIPC(hipGetLastError());
     // solutions of every slice that iterated: x = Q u (BA) or B (Q u) (AB)
     active = loop;
@@ -2458,6 +2506,7 @@ void gkb_destroy(gkb_ctx *c) {
   if (c->bpin) (void)hipHostFree(c->bpin);
   for (hipEvent_t e : c->bpin_ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -2718,6 +2767,13 @@ gkb_status gkb_net_train_step(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, i
   st = net_prepare(net, c->stream);
   if (st != GKB_OK) return st;
   HIPC(hipGetLastError());
+  return GKB_OK;
+}
+
+gkb_status gkb_set_batch_mode(gkb_ctx *c, int mode) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (mode != GKB_BATCH_LAUNCHES && mode != GKB_BATCH_GRAPH) return fail(GKB_EINVAL, "unknown batch mode");
+  c->batch_graph = mode == GKB_BATCH_GRAPH ? 1 : 0;
   return GKB_OK;
 }
 

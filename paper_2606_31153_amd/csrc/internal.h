@@ -363,6 +363,8 @@ __host__ __device__ constexpr int mid_max_k(int elem) {
   return (kMidLdsBytes / (kMidLd * elem) < kBlock ? kMidLdsBytes / (kMidLd * elem) : kBlock) - 1;
 }
 int mid_blocks(long long dim);
+// the fused CGS2 middle's register unroll at iteration k (a launch-time choice)
+int mid_unroll_bucket(int k);
 template <typename T>
 void launch_cgs_mid(Ctl ctl, const T *Q, long long ld, T *w, long long dim, double *partials, int k,
                     hipStream_t s);  // k: the iteration (columns 0..k-1)

@@ -1023,6 +1023,7 @@ __global__ void kb_set_k(BatchDev<T> bd, int k) {
 
 void launch_set_int(int *p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v); }
 
+int mid_unroll_bucket(int k) { return mid_unroll(k); }
 int vec_blocks(long long dim) {
   long long b = (dim + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
   return (int)std::max<long long>(b, 1);

@@ -128,6 +128,34 @@ def test_batch_equals_single_bitwise(ctx, method, dtype, kind):
     assert any(r.reason == gk.STOP_KMAX for r in rb)
 
 
+@pytest.mark.parametrize("method", [gk.GKB_METHOD_BA, gk.GKB_METHOD_AB])
+@pytest.mark.parametrize("kind", ["par", "fan"])
+def test_batch_graph_mode_equals_launch_mode(ctx, method, kind):
+    # the hipGraph-captured iteration replays the same launches: every slice
+    # bit for bit as in the launch-per-step mode, over a batch whose slices
+    # stop at different iterations (the graph is captured again each time the
+    # active set shrinks) and run past k = 17 and 33 (the fused CGS2 middle
+    # changes its unroll); the graph-mode batch is run twice, with eager work
+    # and synchronisations in between, and both runs compared
+    geoms, bs, opts = build(MIX if kind == "par" else FAN_MIX, 720)
+    opts = [dict(o, k_max=max(o["k_max"], 36)) if not o.get("use_dp") else o for o in opts]
+    note("batch graph vs launches %s %s" % (kind, method))
+    ref, xref = run_batch(ctx, method, geoms, bs, opts, torch.float32)
+    try:
+        ctx.set_batch_mode(gk.GKB_BATCH_GRAPH)
+        for rep in range(2):
+            rb, xb = run_batch(ctx, method, geoms, bs, opts, torch.float32)
+            for s in range(len(geoms)):
+                assert_same(rb[s], xb[s], ref[s], xref[s])
+            # eager work between the replays
+            r1, x1 = run_single(ctx, method, geoms[0], bs[0], opts[0], torch.float32)
+            assert_same(r1, x1, ref[0], xref[0])
+    finally:
+        ctx.set_batch_mode(gk.GKB_BATCH_LAUNCHES)
+    ks = sorted({r.k_stop for r in ref})
+    assert len(ks) >= 3 and ks[-1] > 33
+
+
 def test_batch_without_reorthogonalisation(ctx):
     geoms, bs, opts = build(MIX[:3], 710)
     opts = [dict(o, reorth=(i != 1)) for i, o in enumerate(opts)]
