@@ -215,6 +215,28 @@ typedef enum { GKB_METHOD_AB = 0, GKB_METHOD_BA = 1 } gkb_method;
 gkb_status gkb_batch_solve(gkb_ctx *ctx, int method, int n_slices, const gkb_geometry *geoms, int dtype,
                            const void *const *b, const gkb_solve_opts *opts, void *const *x, gkb_solve_info *info);
 
+/* Autotuning of launch shapes.  For a GKB_PAR2D geometry the parallel-beam
+ * A^T is launched with 1, 2 or 4 views per step of each thread (2 and 4 read
+ * every view's full candidate window so that the loads of the views are in
+ * flight together) and B with 4 or 8 views per step; the terms are added in
+ * the same order either way, so results do not change, only time.
+ * gkb_autotune times every choice on the device (mean of five launches after
+ * a warm-up, on a constant sinogram of the geometry), keeps the fastest in
+ * the context's tables for (g, dtype), where every later projector call and
+ * solve takes it from (a batch takes the choice of its slice with the most
+ * pixel-views), and returns the measured times in microseconds (0 where not
+ * run).  Other geometry kinds have no choices: the call returns the fixed
+ * ones.  gkb_set_tuning sets them directly.  Untuned geometries use 4 and 8.
+ * gkb_autotune is asynchronous to nothing: it synchronises on its events. */
+typedef struct {
+  int at_views_per_step;  /* 1, 2 or 4 */
+  int b_views_per_step;   /* 4 or 8 */
+  double at_us[3];        /* A^T with 1, 2, 4 views per step */
+  double b_us[2];         /* B with 4, 8 views per step */
+} gkb_tuning;
+gkb_status gkb_autotune(gkb_ctx *ctx, const gkb_geometry *g, int dtype, gkb_tuning *t);
+gkb_status gkb_set_tuning(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const gkb_tuning *t);
+
 /* How gkb_batch_solve issues its iterations on this context:
  *   GKB_BATCH_LAUNCHES (default): every step of an iteration is one kernel
  *     launch over all active slices;

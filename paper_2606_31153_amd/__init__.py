@@ -37,7 +37,8 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_batch_solve", "gkb_trace_enable", "gkb_trace_only", "gkb_trace_reset", "gkb_trace_get", "gkb_net_create",
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
             "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc",
-            "gkb_check_geometry", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve", "gkb_set_batch_mode")
+            "gkb_check_geometry", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve", "gkb_set_batch_mode",
+            "gkb_autotune", "gkb_set_tuning")
 NET_PARAMS = 19008
 GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
@@ -68,6 +69,11 @@ class SolveOpts(ctypes.Structure):
 class CheckStats(ctypes.Structure):
     _fields_ = [("units", ctypes.c_longlong), ("reads", ctypes.c_longlong), ("out_of_bounds", ctypes.c_longlong),
                 ("uncovered", ctypes.c_longlong), ("max_uncovered_weight", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("at_views_per_step", ctypes.c_int), ("b_views_per_step", ctypes.c_int),
+                ("at_us", ctypes.c_double * 3), ("b_us", ctypes.c_double * 2)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -115,6 +121,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(ctypes.c_double)]
         L.gkb_check_geometry.argtypes = [G, cp, cp, ctypes.POINTER(CheckStats), ctypes.POINTER(cp)]
         L.gkb_set_batch_mode.argtypes = [vp, cp]
+        L.gkb_autotune.argtypes = [vp, G, cp, ctypes.POINTER(Tuning)]
+        L.gkb_set_tuning.argtypes = [vp, G, cp, ctypes.POINTER(Tuning)]
         L.gkb_trace_enable.argtypes = [vp, cp]
         L.gkb_trace_only.argtypes = [vp, ctypes.c_char_p]
         L.gkb_trace_reset.argtypes = [vp]
@@ -257,6 +265,21 @@ def gkb_check_geometry(geom, dtype_code: int = GKB_F32, stride: int = 1):
     ok = ctypes.c_int()
     _check(lib().gkb_check_geometry(ctypes.byref(g), dtype_code, stride, st, ctypes.byref(ok)))
     return dict(zip(("A", "B", "At", "Bt"), st)), bool(ok.value)
+
+
+def gkb_autotune(ctx: Context, geom, dtype_code: int = GKB_F32) -> Tuning:
+    """Times the launch choices of geom on the device and keeps the fastest."""
+    g, keep = make_geometry(geom)
+    t = Tuning()
+    _check(lib().gkb_autotune(ctx.handle, ctypes.byref(g), dtype_code, ctypes.byref(t)))
+    return t
+
+
+def gkb_set_tuning(ctx: Context, geom, at_views: int, b_views: int, dtype_code: int = GKB_F32) -> None:
+    g, keep = make_geometry(geom)
+    t = Tuning()
+    t.at_views_per_step, t.b_views_per_step = at_views, b_views
+    _check(lib().gkb_set_tuning(ctx.handle, ctypes.byref(g), dtype_code, ctypes.byref(t)))
 
 
 @dataclass

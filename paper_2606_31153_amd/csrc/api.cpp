@@ -80,6 +80,9 @@ struct DevBuf {
 
 namespace gkb {
 
+// views per step of the parallel-beam A^T and B when a geometry is not tuned
+constexpr int kDefaultAtViews = 4, kDefaultBViews = 8;
+
 std::vector<double> view_angles(const gkb_geometry *g) {
   std::vector<double> a(g->n_views);
   for (int v = 0; v < g->n_views; ++v) a[v] = g->angles ? g->angles[v] : v * (g->angle_span / g->n_views);
@@ -314,6 +317,8 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     // checks every line)
     gd.fwd_seg = (g->src_dist * du <= 0.9) ? 1 : 0;
   }
+  gd.at_vu = kDefaultAtViews;
+  gd.b_vu = kDefaultBViews;
   gd.nc_bt = (int)std::floor(2.0 * hmax_bt) + 1;
   gd.nc_at = (int)std::floor(2.0 * hmax_at) + 1;
   gd.pad = gd.nc_bt + (int)std::ceil(hmax_bt) + 2;
@@ -973,6 +978,92 @@ gkb_status projector_call(gkb_ctx *c, const gkb_geometry *g, int dtype, const vo
   if (st != GKB_OK) return st;
   HIPC(hipSetDevice(c->device));
   return dtype == GKB_F32 ? apply_op<float>(c, *d, op, in, out) : apply_op<double>(c, *d, op, in, out);
+}
+
+// ----- autotuning of the launch choices -----
+// Parallel beam: A^T with 1, 2 and 4 views per step and B with 4 and 8 are
+// timed (HIP events, mean of five launches after one warm-up) on a constant
+// sinogram of the geometry, and the fastest of each is kept in the
+// geometry's tables, where every later call, solve and batch takes it from.
+// The choices change the order of loads, not of any sum.
+template <typename T>
+gkb_status autotune_impl(gkb_ctx *c, DevTables &d, gkb_tuning *out) {
+  GeomDev &g = d.gd;
+  gkb_tuning t{};
+  for (double &v : t.at_us) v = 0.0;
+  for (double &v : t.b_us) v = 0.0;
+  if (g.kind == GKB_PAR2D) {
+    const long long nb = std::max<long long>({(long long)ray_blocks(g), (long long)bt_blocks(g), (long long)pixel_blocks(g), 1LL});
+    gkb_status st = ensure_scratch(c, g, sizeof(T), nb);
+    if (st != GKB_OK) return st;
+    HIPC(c->tmp_m.ensure(sizeof(T) * (size_t)g.m));
+    HIPC(c->tmp_n.ensure(sizeof(T) * (size_t)g.n));
+    T *y = c->tmp_m.as<T>(), *x = c->tmp_n.as<T>(), *ypad = c->ypad.as<T>();
+    HIPC(hipMemsetAsync(y, 0x3c, sizeof(T) * (size_t)g.m, c->stream));
+    launch_pad_sino<T>(g, col<const T>(y), ypad, nullptr, c->stream);
+    hipEvent_t e0 = c->get_event(), e1 = c->get_event();
+    auto time_it = [&](auto launch) -> double {
+      launch();
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < 5; ++r) launch();
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      return 1e3 * ms / 5.0;
+    };
+    const Epi<T> e = plain_epi<T>();
+    const int at_cand[3] = {1, 2, 4}, b_cand[2] = {4, 8};
+    int best_at = g.at_vu, best_b = g.b_vu;
+    double bt = 1e300, bb = 1e300;
+    for (int i = 0; i < 3; ++i) {
+      g.at_vu = at_cand[i];
+      t.at_us[i] = time_it([&]() { launch_fwd_adj<T>(g, vt_of<T>(d), rt_of<T>(d), ypad, x, e, nullptr, c->stream); });
+      if (t.at_us[i] < bt) {
+        bt = t.at_us[i];
+        best_at = at_cand[i];
+      }
+    }
+    for (int i = 0; i < 2; ++i) {
+      g.b_vu = b_cand[i];
+      t.b_us[i] = time_it([&]() { launch_back<T>(g, vt_of<T>(d), ypad, x, e, nullptr, c->stream); });
+      if (t.b_us[i] < bb) {
+        bb = t.b_us[i];
+        best_b = b_cand[i];
+      }
+    }
+    c->event_pool.push_back(e0);
+    c->event_pool.push_back(e1);
+    HIPC(hipGetLastError());
+    g.at_vu = best_at;
+    g.b_vu = best_b;
+  }
+  t.at_views_per_step = g.at_vu;
+  t.b_views_per_step = g.b_vu;
+  if (out) *out = t;
+  return GKB_OK;
+}
+
+gkb_status autotune(gkb_ctx *c, const gkb_geometry *geom, int dtype, gkb_tuning *out) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  DevTables *d = nullptr;
+  gkb_status st = get_tables(c, geom, dtype, &d);
+  if (st != GKB_OK) return st;
+  HIPC(hipSetDevice(c->device));
+  return dtype == GKB_F32 ? autotune_impl<float>(c, *d, out) : autotune_impl<double>(c, *d, out);
+}
+
+gkb_status set_tuning(gkb_ctx *c, const gkb_geometry *geom, int dtype, const gkb_tuning *t) {
+  if (!c || !t) return fail(GKB_EINVAL, "NULL argument");
+  if (t->at_views_per_step != 1 && t->at_views_per_step != 2 && t->at_views_per_step != 4)
+    return fail(GKB_EINVAL, "A^T views per step must be 1, 2 or 4");
+  if (t->b_views_per_step != 4 && t->b_views_per_step != 8) return fail(GKB_EINVAL, "B views per step must be 4 or 8");
+  DevTables *d = nullptr;
+  gkb_status st = get_tables(c, geom, dtype, &d);
+  if (st != GKB_OK) return st;
+  d->gd.at_vu = t->at_views_per_step;
+  d->gd.b_vu = t->b_views_per_step;
+  return GKB_OK;
 }
 
 // ----- allocation-free back projection -----
@@ -2078,6 +2169,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
   bl.mid_kmax = -1;
   bl.any_plain = 0;
   size_t bytesT = 0, ndbl = (size_t)ns * CD_COUNT;
+  double best_pv = 0.0;
   for (int s = 0; s < ns; ++s) {
     DevTables *d = nullptr;
     gkb_status stt = get_tables(c, &geoms[s], dtype, &d);
@@ -2096,6 +2188,11 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.ldq = (h.dimq + 3) / 4 * 4;
     bl.nc_bt = std::max(bl.nc_bt, g.nc_bt);
     bl.nc_at = std::max(bl.nc_at, g.nc_at);
+    if (s == 0 || (double)g.n * g.nv > best_pv) {  // the tuned choices of the slice with the most pixel-views
+      best_pv = (double)g.n * g.nv;
+      bl.at_vu = g.at_vu;
+      bl.b_vu = g.b_vu;
+    }
     bl.kmax = std::max(bl.kmax, h.K);
     h.cnt[BF_RAY] = ray_blocks(g);
     h.cnt[BF_RAYBT] = bt_blocks(g);
@@ -2768,6 +2865,13 @@ gkb_status gkb_net_train_step(gkb_ctx *c, gkb_net *net, const gkb_geometry *g, i
   if (st != GKB_OK) return st;
   HIPC(hipGetLastError());
   return GKB_OK;
+}
+
+gkb_status gkb_autotune(gkb_ctx *c, const gkb_geometry *g, int dtype, gkb_tuning *t) {
+  return autotune(c, g, dtype, t);
+}
+gkb_status gkb_set_tuning(gkb_ctx *c, const gkb_geometry *g, int dtype, const gkb_tuning *t) {
+  return set_tuning(c, g, dtype, t);
 }
 
 gkb_status gkb_set_batch_mode(gkb_ctx *c, int mode) {

@@ -172,6 +172,9 @@ struct GeomDev {
   int bt_fast;         // fan B^T, float: series forms of the candidate weights (relative error <= 1e-6)
   int at_fast;         // fan A^T, float: first-order sine of the candidate angles (relative error <= 1e-6)
   int fwd_seg;         // A, float: adjacent rays cross a line less than a pixel apart (segment loads)
+  // tuned launch choices (see gkb_autotune): parallel-beam A^T views per step
+  // (1, 2 or 4) and B views per step (4 or 8); results do not depend on them
+  int at_vu, b_vu;
   // padded image: row-major region (ny lines of ldR = nx + 2 pad), then the
   // column-major region at offT (nx lines of ldT = ny + 2 pad)
   int pad, ldR, ldT;
@@ -291,6 +294,7 @@ struct BatchLaunch {
   int any_plain; // some slice's k_max exceeds mid_max_k (separate update and inner products)
   int fan;       // all slices fan beam (else all parallel beam)
   int nc_bt, nc_at;
+  int at_vu, b_vu;  // views per step of A^T and B: the tuned choices of the slice with the most pixel-views
 };
 
 // Epilogue selection of a batched projector launch (see Epi).

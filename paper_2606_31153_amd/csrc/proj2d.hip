@@ -525,9 +525,13 @@ __device__ inline T gather_view_groups(T acc) {
   return acc;
 }
 
-template <typename T, bool FAN>
+// Parallel beam: VU = 4 or 8 views per step (the loads of all in flight
+// together), summed into four accumulators by view index mod 4, so that both
+// choices add the same terms in the same order.
+template <typename T, bool FAN, int VU = 4>
 __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                  const Epi<T> &e, Blk b) {
+  static_assert(VU == 4 || VU == 8, "B: 4 or 8 views per step");
   int i, j;
   const int grp = tile_pixel(g, b.id, i, j);
   const bool valid = i < g.nx && j < g.ny;
@@ -544,6 +548,21 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
     if (!FAN) {
       T a[4] = {T(0), T(0), T(0), T(0)};
       int v = grp;
+      if (VU == 8) {
+        for (; v + 7 * VS < g.nv; v += 8 * VS) {
+          T u[8], fl[8];
+          typename Pair<T>::v2 p[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            u[q] = clampv(fma(px, vt.p0[v + q * VS], fma(py, vt.p1[v + q * VS], off)), ulo, uhi);
+            fl[q] = floor(u[q]);
+            p[q] = load_pair(ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)fl[q]));
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) a[q & 3] += fma(u[q] - fl[q], p[q].y - p[q].x, p[q].x);
+          roff += (unsigned)(8 * VS) * ldY;
+        }
+      }
       for (; v + 3 * VS < g.nv; v += 4 * VS) {
         T u[4], fl[4];
         typename Pair<T>::v2 p[4];
@@ -603,11 +622,11 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
   epilogue(e, own ? (long long)j * g.nx + i : 0, own, acc, xo, b);
 }
 
-template <typename T, bool FAN>
+template <typename T, bool FAN, int VU>
 __global__ __launch_bounds__(kBlock) void k_back(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
                                                  T *__restrict__ xo, Epi<T> e, const int *stop) {
   if (stop && *stop) return;
-  back_body<T, FAN>(g, vt, ypad, xo, e, Blk{blockIdx.x, gridDim.x});
+  back_body<T, FAN, VU>(g, vt, ypad, xo, e, Blk{blockIdx.x, gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -689,7 +708,11 @@ __device__ inline T at_fan_bins_lin(const typename Pair<T>::v2 *__restrict__ yw,
   return acc;
 }
 
-template <typename T, bool FAN, int NC>
+// Parallel beam: VU views per step.  With VU > 1 every view of a step reads
+// the full window of NC bins (the candidates past a view's own floor(2h) + 1
+// get zero weight), so that the loads of all VU views are in flight
+// together; the terms are added in the same order as with VU = 1.
+template <typename T, bool FAN, int NC, int VU = 1>
 __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, const T *__restrict__ ypad, T *xo,
                                     const Epi<T> &e, Blk b) {
   int i, j;
@@ -708,7 +731,39 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
   const T ulo = -T(g.uclamp_at), uhi = T(g.nu - 1) + T(g.uclamp_at);
   if (!FAN) {
     if (valid) {
-      for (int v = grp; v < g.nv; v += VS) {
+      int v = grp;
+      if (VU > 1) {
+        // a slice's padding is sized for its own candidate count (NC is the
+        // launch's largest): the bins past it are not read
+        const int ncs = min(g.nc_at, NC);
+        for (; v + (VU - 1) * VS < g.nv; v += VU * VS) {
+          T d0[VU], yv[VU][NC];
+#pragma unroll
+          for (int q = 0; q < VU; ++q) {
+            const int vq = v + q * VS;
+            const T u = clampv(fma(px, vt.p0[vq], fma(py, vt.p1[vq], off)), ulo, uhi);
+            const T k0f = ceil(u - vt.p4[vq]);
+            d0[q] = u - k0f;
+            const T *row = ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)k0f);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) yv[q][c] = c < ncs ? row[c] : T(0);
+          }
+#pragma unroll
+          for (int q = 0; q < VU; ++q) {
+            const int vq = v + q * VS;
+            const T slope = vt.p3[vq];
+            T part = T(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              const T wt = fma(-fabs(d0[q] - T(c)), slope, T(1));
+              part = fma(hat_clamp(wt), yv[q][c], part);
+            }
+            acc = fma(vt.p2[vq], part, acc);
+          }
+          roff += (unsigned)(VU * VS) * ldY;
+        }
+      }
+      for (; v < g.nv; v += VS) {
         T u = fma(px, vt.p0[v], fma(py, vt.p1[v], off));
         u = clampv(u, ulo, uhi);
         const T w = vt.p2[v], slope = vt.p3[v], h = vt.p4[v];
@@ -799,11 +854,11 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
   epilogue(e, own ? (long long)j * g.nx + i : 0, own, acc, xo, b);
 }
 
-template <typename T, bool FAN, int NC>
+template <typename T, bool FAN, int NC, int VU>
 __global__ __launch_bounds__(kBlock) void k_fwd_adj(GeomDev g, ViewTab<T> vt, const T *__restrict__ ypad,
                                                     T *__restrict__ xo, Epi<T> e, const int *stop) {
   if (stop && *stop) return;
-  fwd_adj_body<T, FAN, NC>(g, vt, ypad, xo, e, Blk{blockIdx.x, gridDim.x});
+  fwd_adj_body<T, FAN, NC, VU>(g, vt, ypad, xo, e, Blk{blockIdx.x, gridDim.x});
 }
 
 
@@ -881,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void kb_back_adj(BatchDev<T> bd, int out_se
   back_adj_body<T, FAN, NC>(g, rt, d.xpad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
 }
 
-template <typename T, bool FAN>
+template <typename T, bool FAN, int VU>
 __global__ __launch_bounds__(kBlock) void kb_back(BatchDev<T> bd, int out_sel, EpiCfg ec) {
   Blk b;
   const SliceDev<T> &d = slice_of(bd, BF_PIX, blockIdx.x, b);
@@ -889,10 +944,10 @@ __global__ __launch_bounds__(kBlock) void kb_back(BatchDev<T> bd, int out_sel, E
   const int k = d.ctl.ip[CI_K];
   const GeomDev g = d.g;
   const ViewTab<T> vt = d.vt;
-  back_body<T, FAN>(g, vt, d.ypad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
+  back_body<T, FAN, VU>(g, vt, d.ypad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
 }
 
-template <typename T, bool FAN, int NC>
+template <typename T, bool FAN, int NC, int VU>
 __global__ __launch_bounds__(kBlock) void kb_fwd_adj(BatchDev<T> bd, int out_sel, EpiCfg ec) {
   Blk b;
   const SliceDev<T> &d = slice_of(bd, BF_PIX, blockIdx.x, b);
@@ -900,7 +955,7 @@ __global__ __launch_bounds__(kBlock) void kb_fwd_adj(BatchDev<T> bd, int out_sel
   const int k = d.ctl.ip[CI_K];
   const GeomDev g = d.g;
   const ViewTab<T> vt = d.vt;
-  fwd_adj_body<T, FAN, NC>(g, vt, d.ypad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
+  fwd_adj_body<T, FAN, NC, VU>(g, vt, d.ypad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
 }
 
 }  // namespace
@@ -987,25 +1042,46 @@ template <typename T>
 void launch_back(const GeomDev &g, const ViewTab<T> &vt, const T *ypad, T *x, const Epi<T> &e, const int *stop,
                  hipStream_t s) {
   if (g.kind == 1)
-    hipLaunchKernelGGL((k_back<T, true>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
+    hipLaunchKernelGGL((k_back<T, true, 4>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
+  else if (g.b_vu == 8)
+    hipLaunchKernelGGL((k_back<T, false, 8>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
   else
-    hipLaunchKernelGGL((k_back<T, false>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
+    hipLaunchKernelGGL((k_back<T, false, 4>), dim3(pixel_blocks(g)), dim3(kBlock), 0, s, g, vt, ypad, x, e, stop);
   if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, pixel_blocks(g), NORM_T1, stop, s);
 }
+
+// views per step of the parallel-beam A^T actually launched: the tuned count
+// for windows of up to four bins, one view otherwise
+__host__ inline int at_views(int nc, int tuned) { return nc <= 4 ? tuned : 1; }
 
 template <typename T, bool FAN>
 static void fwd_adj_nc(const GeomDev &g, const ViewTab<T> &vt, const RayTab<T> &rt, const T *ypad, T *x,
                        const Epi<T> &e, const int *stop, hipStream_t s) {
   const dim3 grid(pixel_blocks(g)), blk(kBlock);
+  const int vu = FAN ? 1 : at_views(g.nc_at, g.at_vu);
+#define GKB_AT(NC, VU) hipLaunchKernelGGL((k_fwd_adj<T, FAN, NC, VU>), grid, blk, 0, s, g, vt, ypad, x, e, stop)
   switch (g.nc_at) {
-    case 2: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 2>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
-    case 3: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 3>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
-    case 4: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 4>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
-    case 5: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 5>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
-    case 6: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 6>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
-    case 7: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 7>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
-    default: hipLaunchKernelGGL((k_fwd_adj<T, FAN, 8>), grid, blk, 0, s, g, vt, ypad, x, e, stop); break;
+    case 2:
+      if (vu == 4) GKB_AT(2, 4);
+      else if (vu == 2) GKB_AT(2, 2);
+      else GKB_AT(2, 1);
+      break;
+    case 3:
+      if (vu == 4) GKB_AT(3, 4);
+      else if (vu == 2) GKB_AT(3, 2);
+      else GKB_AT(3, 1);
+      break;
+    case 4:
+      if (vu == 4) GKB_AT(4, 4);
+      else if (vu == 2) GKB_AT(4, 2);
+      else GKB_AT(4, 1);
+      break;
+    case 5: GKB_AT(5, 1); break;
+    case 6: GKB_AT(6, 1); break;
+    case 7: GKB_AT(7, 1); break;
+    default: GKB_AT(8, 1); break;
   }
+#undef GKB_AT
 }
 
 template <typename T>
@@ -1068,24 +1144,41 @@ template <typename T>
 void launch_b_back(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
   if (bl.tot[BF_PIX] <= 0) return;
   if (bl.fan)
-    hipLaunchKernelGGL((kb_back<T, true>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
+    hipLaunchKernelGGL((kb_back<T, true, 4>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  else if (bl.b_vu == 8)
+    hipLaunchKernelGGL((kb_back<T, false, 8>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
   else
-    hipLaunchKernelGGL((kb_back<T, false>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
+    hipLaunchKernelGGL((kb_back<T, false, 4>), dim3(bl.tot[BF_PIX]), dim3(kBlock), 0, s, bd, out_sel, ec);
   if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_PIX, NORM_T1, s);
 }
 
 template <typename T, bool FAN>
 static void b_fwd_adj_nc(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
   const dim3 grid(bl.tot[BF_PIX]), blk(kBlock);
+  const int vu = FAN ? 1 : at_views(bl.nc_at, bl.at_vu);
+#define GKB_AT(NC, VU) hipLaunchKernelGGL((kb_fwd_adj<T, FAN, NC, VU>), grid, blk, 0, s, bd, out_sel, ec)
   switch (bl.nc_at) {
-    case 2: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 2>), grid, blk, 0, s, bd, out_sel, ec); break;
-    case 3: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 3>), grid, blk, 0, s, bd, out_sel, ec); break;
-    case 4: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 4>), grid, blk, 0, s, bd, out_sel, ec); break;
-    case 5: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 5>), grid, blk, 0, s, bd, out_sel, ec); break;
-    case 6: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 6>), grid, blk, 0, s, bd, out_sel, ec); break;
-    case 7: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 7>), grid, blk, 0, s, bd, out_sel, ec); break;
-    default: hipLaunchKernelGGL((kb_fwd_adj<T, FAN, 8>), grid, blk, 0, s, bd, out_sel, ec); break;
+    case 2:
+      if (vu == 4) GKB_AT(2, 4);
+      else if (vu == 2) GKB_AT(2, 2);
+      else GKB_AT(2, 1);
+      break;
+    case 3:
+      if (vu == 4) GKB_AT(3, 4);
+      else if (vu == 2) GKB_AT(3, 2);
+      else GKB_AT(3, 1);
+      break;
+    case 4:
+      if (vu == 4) GKB_AT(4, 4);
+      else if (vu == 2) GKB_AT(4, 2);
+      else GKB_AT(4, 1);
+      break;
+    case 5: GKB_AT(5, 1); break;
+    case 6: GKB_AT(6, 1); break;
+    case 7: GKB_AT(7, 1); break;
+    default: GKB_AT(8, 1); break;
   }
+#undef GKB_AT
 }
 
 template <typename T>

@@ -330,14 +330,17 @@ void check_fwd_adj(const Geo2 &G, int stride, CheckStat &s) {
           u = clampT((T)ud, ulo, uhi);
         }
         const long long rs = (long long)v * g.ldY;
+        // parallel beam with several views per step reads every view's full
+        // window of the geometry's candidate count
+        const int nread = G.fan ? cnt : std::max(cnt, std::min(g.nc_at, NC));
         // reads (fan beam: the same indices in units of (w y, w) pairs)
         for (int sh = -1; sh <= 1; ++sh) {
           if (!G.fan && sh != 0) continue;
           const T us = G.fan ? clampT(T(u + T(sh) * T(1e-3)), ulo, uhi) : u;
           const int k0 = (int)std::ceil(us - H);
           add_read(s, rs + g.padY + k0, rs, rs + g.ldY);
-          add_read(s, rs + g.padY + k0 + cnt - 1, rs, rs + g.ldY);
-          s.reads += cnt - 2;
+          add_read(s, rs + g.padY + k0 + nread - 1, rs, rs + g.ldY);
+          s.reads += nread - 2;
           if (!valid) continue;
           // every bin whose ray passes within a pixel of p lies in the window
           const int a = std::max(0, (int)std::floor(ud) - NC - 4), b = std::min(g.nu - 1, (int)std::ceil(ud) + NC + 4);

@@ -196,3 +196,42 @@ def test_library_work_is_ordered_with_torch_on_the_default_stream(ctx):
         s2 = y2.double().sum()
         torch.cuda.synchronize()
         assert torch.isfinite(s1) and abs(float(s2) - 2.0 * float(s1)) <= 1e-6 * abs(float(s2))
+
+
+@pytest.mark.parametrize("gname", ["par_ragged", "par64", "par_pitch", "par_tiny"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_tuning_choices_give_identical_results(ctx, gname, dtype):
+    # A^T with 1, 2 or 4 views per step and B with 4 or 8 add the same terms
+    # in the same order: equal bit for bit, and within the projector bounds of
+    # the oracle; the autotuner keeps one of the choices
+    geom = GEOMS[gname]
+    dev = torch.device("cuda:0")
+    code = gk.GKB_F32 if dtype == torch.float32 else gk.GKB_F64
+    y = np.random.default_rng(41).standard_normal(geom.m)
+    yd = torch.tensor(y, dtype=dtype, device=dev)
+    outs = {}
+    for at_v in (1, 2, 4):
+        for b_v in (4, 8):
+            note("tuning %s at=%d b=%d" % (gname, at_v, b_v))
+            gk.gkb_set_tuning(ctx, geom, at_v, b_v, code)
+            xa = torch.empty(geom.n, dtype=dtype, device=dev)
+            xb = torch.empty(geom.n, dtype=dtype, device=dev)
+            gk.gkb_forward_adjoint(ctx, geom, yd, xa)
+            gk.gkb_back(ctx, geom, yd, xb)
+            torch.cuda.synchronize()
+            outs[(at_v, b_v)] = (xa.cpu().numpy(), xb.cpu().numpy())
+    ref_a, ref_b = outs[(1, 4)]
+    for key, (a, b) in outs.items():
+        assert np.array_equal(a, ref_a), key
+        assert np.array_equal(b, ref_b), key
+    op = oracle.Operator(geom)
+    tol = 1e-5 if dtype == torch.float32 else 1e-12
+    assert np.linalg.norm(ref_a - op.At(y).reshape(-1)) <= tol * np.linalg.norm(op.At(y))
+    assert np.linalg.norm(ref_b - op.B(y).reshape(-1)) <= tol * np.linalg.norm(op.B(y))
+    t = gk.gkb_autotune(ctx, geom, code)
+    note("autotune %s: A^T %s us -> %d, B %s us -> %d" % (gname, list(t.at_us), t.at_views_per_step,
+                                                         list(t.b_us), t.b_views_per_step))
+    assert t.at_views_per_step in (1, 2, 4) and t.b_views_per_step in (4, 8)
+    assert all(v > 0 for v in t.at_us) and all(v > 0 for v in t.b_us)
+    assert t.at_us[(1, 2, 4).index(t.at_views_per_step)] == min(t.at_us)
+    gk.gkb_set_tuning(ctx, geom, 1, 4, code)
