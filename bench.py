@@ -151,6 +151,15 @@ def batch_bench(ctx):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
+    # launch shapes with the library's defaults, then autotuned per slice
+    # geometry (the tuning itself is not timed)
+    for g in geoms:
+        gk.gkb_set_tuning(ctx, g, 1, 4)
+    batched()
+    _, t_untuned = timed(batched)
+    t0 = time.perf_counter()
+    tunes = [gk.gkb_autotune(ctx, g) for g in geoms]
+    t_tune = time.perf_counter() - t0
     sequential()
     batched()
     batched(gk.GKB_BATCH_GRAPH)
@@ -163,6 +172,10 @@ def batch_bench(ctx):
     return {"workload": "64 parallel-beam slices, n 128..512, 180..720 views, 0.5-5% noise, BA-GKB, DP tau=1",
             "slices": ns, "s_per_slice_batched": t_bat / ns, "s_per_slice_sequential": t_seq / ns,
             "s_per_slice_batched_graph": t_graph / ns,
+            "s_per_slice_batched_one_view_per_step": t_untuned / ns,
+            "autotune": {"seconds": t_tune,
+                         "at_views_per_step": [t.at_views_per_step for t in tunes],
+                         "b_views_per_step": [t.b_views_per_step for t in tunes]},
             "batched_speedup": t_seq / t_bat, "iterations_mean": float(np.mean(ks)),
             "iterations_min": int(min(ks)), "iterations_max": int(max(ks)),
             "stopped_by_dp": sum(1 for r in rb if r.reason == gk.STOP_DP),
@@ -350,15 +363,58 @@ def learned_main(args):
     print(json.dumps(out))
 
 
-def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int):
+def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int, runs: int):
     import oracle
     op = oracle.Operator(geom)
-    t0 = time.perf_counter()
-    res = oracle.gkb(op, oracle.MODE_BA, b_host, iters, use_dp=True, tau=1.0, noise_norm=enorm)
-    dt = time.perf_counter() - t0
-    return {"value": res.k_stop / dt, "unit": "GKB iters/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "FP64 CPU oracle, BA-GKB, %d iterations of the same fan-beam 512^2/720/1024 problem "
-                      "(residual evaluated literally), %.1f s" % (res.k_stop, dt)}
+    rates = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        res = oracle.gkb(op, oracle.MODE_BA, b_host, iters)
+        rates.append(res.k_stop / (time.perf_counter() - t0))
+    return {"value": float(np.mean(rates)), "unit": "GKB iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "median": float(np.median(rates)), "runs": runs,
+            "sample": "FP64 CPU oracle (OpenMP, all host threads), BA-GKB, %d runs of %d iterations of the same "
+                      "fan-beam 512^2/720/1024 problem, each iteration with its residual ||A x_k - b|| evaluated "
+                      "literally (one more A and a Q u product); value = mean and median over the runs of "
+                      "iterations/s; a 150-iteration run takes minutes, so the sample is short" % (runs, iters)}
+
+
+def par512_point(ctx, iters: int):
+    """AB- and BA-GKB iterations/s on the 512x512 parallel-beam workload
+    (720 views over 180 degrees, 725 bins), the second image size of the
+    timing experiments (context beside the fan-beam headline)."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    from paper_2606_31153_amd import synth
+    geom = synth.workload_par512()
+    _, b, enorm = make_problem(geom, 2000, 0.005)
+    x = torch.zeros(geom.n, dtype=torch.float32, device=b.device)
+    gk.gkb_autotune(ctx, geom)
+    out = {"workload": "parallel beam 512x512, 720 views over 180 deg, 725 bins; %d iterations" % iters}
+    for name, fn in (("ba", gk.gkb_ba_solve), ("ab", gk.gkb_ab_solve)):
+        fn(ctx, geom, b, x, iters)
+        torch.cuda.synchronize()
+        r = fn(ctx, geom, b, x, iters)
+        torch.cuda.synchronize()
+        out["%s_iters_per_s" % name] = iters / r.seconds
+    return out
+
+
+def gmres_point(ctx, geom, b, iters: int):
+    """The paper's comparison methods on the benchmark workload (context)."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    x = torch.zeros(geom.n, dtype=torch.float32, device=b.device)
+    out = {"workload": "fan-beam 512x512 as above; %d iterations" % iters}
+    for name, fn in (("ba_gmres", gk.gkb_ba_gmres_solve), ("ab_gmres", gk.gkb_ab_gmres_solve)):
+        fn(ctx, geom, b, x, iters)
+        torch.cuda.synchronize()
+        r = fn(ctx, geom, b, x, iters)
+        torch.cuda.synchronize()
+        out["%s_iters_per_s" % name] = iters / r.seconds
+    return out
 
 
 def main():
@@ -367,7 +423,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=K_ITERS)
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cone", action="store_true", help="measure the 512^3 cone-beam workload instead")
@@ -460,8 +517,13 @@ def main():
         comp = 4.0 * (geom.n + geom.m) / t / 1e9
         oper = units[k] * OPERAND_BYTES_PER_UNIT / t / 1e9
         gbps[k] = {"avg_us": v["avg_ms"] * 1e3, "units": units[k], "compulsory_GBs": comp,
-                   "compulsory_pct_hbm": 100 * comp / HBM_PEAK_GBS, "operand_GBs": oper,
-                   "operand_pct_hbm": 100 * oper / HBM_PEAK_GBS}
+                   "compulsory_pct_hbm": 100 * comp / HBM_PEAK_GBS,
+                   # two FP32 taps per unit, served from L1/LDS/L2: a cache-bandwidth figure, not HBM
+                   "operand_cache_GBs": oper}
+        if k in MEASURED_TRAFFIC:
+            hb = MEASURED_TRAFFIC[k] / t / 1e9
+            gbps[k]["measured_hbm_GBs"] = hb
+            gbps[k]["measured_hbm_pct"] = 100 * hb / HBM_PEAK_GBS
 
     iters = 2 * args.iters * args.steps
     out = {
@@ -491,12 +553,16 @@ def main():
         "kernels": kernels,
         "kernels_source": "one untimed step with every kernel bracketed by HIP events",
     }
+    print("bench: parallel-beam 512 point", file=sys.stderr, flush=True)
+    out["par512"] = par512_point(ctx, args.iters)
+    print("bench: GMRES on the benchmark workload", file=sys.stderr, flush=True)
+    out["gmres"] = gmres_point(ctx, geom, b, args.iters)
     if not args.no_batch:
         print("bench: 64-slice batched workload", file=sys.stderr, flush=True)
         out["s_per_slice_to_discrepancy"] = batch_bench(ctx)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(geom, b.double().cpu().numpy(), enorm, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(geom, b.double().cpu().numpy(), enorm, args.cpu_iters, args.cpu_runs)
     ctx.close()
     print(json.dumps(out))
 
