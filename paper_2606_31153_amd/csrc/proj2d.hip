@@ -467,10 +467,14 @@ __device__ inline void back_adj_body(const GeomDev &g, const RayTab<T> &rt, cons
   const int cnt = min(wave_max(valid ? (int)floor(T(2) * hr) + 1 : 0), NC);
   T acc = T(0);
   if (valid) {
+    // the three largest counts have straight-line code; the generic count
+    // guards every tap with a branch
     if (cnt == NC)
       acc = back_adj_ray<T, FAN, NC, NC>(g, rt, pad, r, hr, cnt, half);
     else if (cnt == NC - 1)
       acc = back_adj_ray<T, FAN, NC - 1, NC>(g, rt, pad, r, hr, cnt, half);
+    else if (NC > 3 && cnt == NC - 2)
+      acc = back_adj_ray<T, FAN, (NC > 3 ? NC - 2 : 0), NC>(g, rt, pad, r, hr, cnt, half);
     else
       acc = back_adj_ray<T, FAN, 0, NC>(g, rt, pad, r, hr, cnt, half);
   }
@@ -823,6 +827,7 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
             acc = cnt == NC       ? at_fan_bins_lin<T, NC, NC>(yw, dc1, c1, cnt, acc)
                   : cnt == NC - 1 ? at_fan_bins_lin<T, NC - 1, NC>(yw, dc1, c1, cnt, acc)
                   : cnt == NC - 2 ? at_fan_bins_lin<T, (NC > 2 ? NC - 2 : 0), NC>(yw, dc1, c1, cnt, acc)
+                  : cnt == NC - 3 ? at_fan_bins_lin<T, (NC > 3 ? NC - 3 : 0), NC>(yw, dc1, c1, cnt, acc)
                                   : at_fan_bins_lin<T, 0, NC>(yw, dc1, c1, cnt, acc);
           } else {
             const T c3 = c1 * dg * dg * T(-1.0 / 6.0);
