@@ -9,7 +9,9 @@ arithmetic.
 ``oracle.c`` (ctypes) holds the projectors, the GKB driver and the Jacobi
 SVD; ``dense.py`` holds an independent NumPy builder of the dense projector
 matrices from their weight formulas (a second implementation for tiny
-sizes); ``learned.py`` holds the learned-preconditioner reference.
+sizes); ``learned.py`` holds the learned-preconditioner reference;
+``hybrid.py`` holds hybrid regularisation (lambda_k chosen on the projected
+problem) and the enlarged-subspace TSVD on top of the GKB driver.
 """
 from __future__ import annotations
 

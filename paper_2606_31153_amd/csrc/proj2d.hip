@@ -39,7 +39,10 @@ namespace gkb {
 namespace {
 
 // atan of |z| <= 0.5: z * P(z^2), P a degree-5 polynomial fitted to atan(z)/z
-// on [0, 0.5] (relative error 5.4e-9, below float rounding).
+// on [0, 0.5] by iteratively reweighted least squares on Chebyshev nodes (a
+// near-minimax fit of the relative error).  With the coefficients as printed
+// the relative error is at most 7.1e-9 in exact arithmetic, below float
+// rounding.
 __device__ inline float atan_poly(float z) {
   const float t = z * z;
   float p = -0.05129426f;
