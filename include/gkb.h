@@ -198,6 +198,44 @@ gkb_status gkb_ab_gmres_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, co
 gkb_status gkb_ba_gmres_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b,
                               const gkb_solve_opts *o, void *x, gkb_solve_info *info);
 
+/* Hybrid regularisation and the enlarged-subspace TSVD on AB-/BA-GKB.  The
+ * paper names both (a regularisation parameter chosen inside the Krylov
+ * subspace, on the projected problem: Sec. 1, Sec. 6; an enlarged subspace
+ * truncated back to rank k: Sec. 3.1) but fixes no rule; the rules here:
+ *   lambda_rule GKB_LAMBDA_DP: iteration k solves min ||C_k u - t_1 e_1||^2 +
+ *     lambda_k^2 ||u||^2 with lambda_k such that ||C_k u - t_1 e_1|| =
+ *     tau_proj * eta_proj, eta_proj the noise norm in the projected
+ *     residual's space (AB-GKB: ||e||; BA-GKB: ||B e||); lambda_k = 0 while
+ *     the residual at lambda = 0 is at least that level;
+ *   lambda_rule GKB_LAMBDA_GCV: lambda_k minimises ||C_k u - t_1 e_1||^2 /
+ *     trace(I - C_k (C_k^T C_k + lambda^2 I)^-1 C_k^T)^2;
+ *   both search [1e-10 s, 10 s], s = max_i ||C_k e_i||, and take a root or
+ *   minimum outside it at the range's end.  rho_k = ||A x_k - b|| is formed
+ *   from the stored A-images (m x k_max extra values of the vector type, as
+ *   for GMRES) and the options' stopping rules act on it;
+ *   tsvd_rank r >= 1 (lambda_rule GKB_LAMBDA_FIXED, lambda 0): the plain
+ *   iteration runs to its stop (k_max, or earlier by a stopping rule or a
+ *   breakdown), then x = Q_K u (B Q_K u) with u the rank-r truncated SVD
+ *   solution of min ||C_K u - t_1 e_1|| (one-sided Jacobi in FP64, K x K and
+ *   (K+1) x K doubles of workspace); info->residual is ||A x - b|| of that x.
+ * lambda_history (HOST, k_max entries, may be NULL) receives lambda_k.
+ * Errors: GKB_EINVAL for a rule outside the enum, neither a rule nor a rank,
+ * both, a rank outside [1, k_max], a negative or non-finite tau_proj or
+ * eta_proj, lambda != 0, or k_max > 1024; GKB_EUNSUPPORTED for a learned
+ * filter (precond). */
+typedef enum { GKB_LAMBDA_FIXED = 0, GKB_LAMBDA_DP = 1, GKB_LAMBDA_GCV = 2 } gkb_lambda_rule;
+typedef struct {
+  int lambda_rule;         /* gkb_lambda_rule */
+  double tau_proj;         /* discrepancy rule: level tau_proj * eta_proj */
+  double eta_proj;
+  int tsvd_rank;           /* 0: off */
+  double *lambda_history;  /* HOST, k_max entries, or NULL */
+} gkb_hybrid_opts;
+gkb_status gkb_ab_hybrid_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b,
+                               const gkb_solve_opts *o, const gkb_hybrid_opts *h, void *x, gkb_solve_info *info);
+gkb_status gkb_ba_hybrid_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const void *b,
+                               const gkb_solve_opts *o, const gkb_hybrid_opts *h, void *x, gkb_solve_info *info);
+
 /* Batched multi-slice solve: n_slices independent problems, each with its own
  * geometry, b, options (k_max, lambda, tau, noise_norm, reorth, histories)
  * and discrepancy stop, solved by AB-GKB (method GKB_METHOD_AB) or BA-GKB

@@ -29,6 +29,7 @@ GKB_PAR2D, GKB_FAN2D, GKB_CONE3D = 0, 1, 2
 GKB_F32, GKB_F64 = 0, 1
 GKB_METHOD_AB, GKB_METHOD_BA = 0, 1
 GKB_BATCH_LAUNCHES, GKB_BATCH_GRAPH = 0, 1
+GKB_LAMBDA_FIXED, GKB_LAMBDA_DP, GKB_LAMBDA_GCV = 0, 1, 2
 
 STATUS_NAMES = {0: "GKB_OK", -1: "GKB_EINVAL", -2: "GKB_ENOMEM", -3: "GKB_EDEVICE", -4: "GKB_ENONFINITE",
                 -5: "GKB_EUNSUPPORTED"}
@@ -38,7 +39,7 @@ EXPORTED = ("gkb_create", "gkb_destroy", "gkb_set_stream", "gkb_last_error", "gk
             "gkb_net_destroy", "gkb_net_set_weights", "gkb_net_get_weights", "gkb_net_save", "gkb_net_load",
             "gkb_net_apply", "gkb_net_frozen_apply", "gkb_net_grad", "gkb_net_train_step", "gkb_back_noalloc",
             "gkb_check_geometry", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve", "gkb_set_batch_mode",
-            "gkb_autotune", "gkb_set_tuning")
+            "gkb_autotune", "gkb_set_tuning", "gkb_ab_hybrid_solve", "gkb_ba_hybrid_solve")
 NET_PARAMS = 19008
 GKB_NET_FBP, GKB_NET_FROZEN = 0, 1
 
@@ -55,6 +56,11 @@ class Geometry(ctypes.Structure):
                 ("angle_span", ctypes.c_double), ("n_det_u", ctypes.c_int), ("n_det_v", ctypes.c_int),
                 ("det_pitch_u", ctypes.c_double), ("det_pitch_v", ctypes.c_double),
                 ("src_dist", ctypes.c_double), ("src_det_dist", ctypes.c_double)]
+
+
+class HybridOpts(ctypes.Structure):
+    _fields_ = [("lambda_rule", ctypes.c_int), ("tau_proj", ctypes.c_double), ("eta_proj", ctypes.c_double),
+                ("tsvd_rank", ctypes.c_int), ("lambda_history", ctypes.POINTER(ctypes.c_double))]
 
 
 class SolveOpts(ctypes.Structure):
@@ -104,6 +110,9 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [vp, G, cp, vp, vp]
         for name in ("gkb_ab_solve", "gkb_ba_solve", "gkb_gkb_solve", "gkb_ab_gmres_solve", "gkb_ba_gmres_solve"):
             getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo)]
+        for name in ("gkb_ab_hybrid_solve", "gkb_ba_hybrid_solve"):
+            getattr(L, name).argtypes = [vp, G, cp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(HybridOpts), vp,
+                                         ctypes.POINTER(SolveInfo)]
         L.gkb_batch_solve.argtypes = [vp, cp, cp, G, cp, ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                                       ctypes.POINTER(vp), ctypes.POINTER(SolveInfo)]
         L.gkb_net_create.argtypes = [vp, ctypes.POINTER(vp), cp, cp, cp, ctypes.c_ulonglong]
@@ -295,11 +304,12 @@ class SolveResult:
     alpha: np.ndarray
     t: np.ndarray
     rre: Optional[np.ndarray] = None  # RRE(x_k), k = 1..k_stop, when x_true was given
+    lam: Optional[np.ndarray] = None  # lambda_k, k = 1..k_stop (hybrid solves)
 
 
 def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, use_dp: bool = False,
            tau: float = 1.0, noise_norm: float = 0.0, reorth: bool = True, precond=None,
-           rns_eps: float = 0.0, x_true=None) -> SolveResult:
+           rns_eps: float = 0.0, x_true=None, hybrid: Optional[HybridOpts] = None) -> SolveResult:
     g, keep = make_geometry(geom)
     code = _dtype_code(b)
     if x.dtype != b.dtype:
@@ -319,7 +329,8 @@ def _solve(name: str, ctx: Context, geom, b, x, k_max: int, lam: float = 0.0, us
                   None if x_true is None else _dev_ptr(x_true, geom.n).value,
                   None if rre is None else rre.ctypes.data_as(P))
     info = SolveInfo()
-    _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(b, geom.m), ctypes.byref(o),
+    extra = () if hybrid is None else (ctypes.byref(hybrid),)
+    _check(getattr(lib(), name)(ctx.handle, ctypes.byref(g), code, _dev_ptr(b, geom.m), ctypes.byref(o), *extra,
                                 _dev_ptr(x, geom.n), ctypes.byref(info)))
     k = info.k_stop
     return SolveResult(k_stop=k, reason=info.reason, residual=info.residual, proj_residual=info.proj_residual,
@@ -351,6 +362,27 @@ def gkb_ab_gmres_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResul
 def gkb_ba_gmres_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
     """BA-GMRES (B as left preconditioner): x = Q_k u_k."""
     return _solve("gkb_ba_gmres_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def _hybrid(name: str, ctx: Context, geom, b, x, k_max: int, rule: int = GKB_LAMBDA_FIXED, tau_proj: float = 1.0,
+            eta_proj: float = 0.0, tsvd_rank: int = 0, **kw) -> SolveResult:
+    lam = np.zeros(max(k_max, 1))
+    h = HybridOpts(rule, tau_proj, eta_proj, tsvd_rank, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    r = _solve(name, ctx, geom, b, x, k_max, hybrid=h, **kw)
+    r.lam = lam[:r.k_stop] if rule != GKB_LAMBDA_FIXED else None
+    return r
+
+
+def gkb_ab_hybrid_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """Hybrid AB-GKB (rule GKB_LAMBDA_DP with tau_proj, eta_proj = ||e||, or
+    GKB_LAMBDA_GCV), or the enlarged-subspace TSVD (tsvd_rank)."""
+    return _hybrid("gkb_ab_hybrid_solve", ctx, geom, b, x, k_max, **kw)
+
+
+def gkb_ba_hybrid_solve(ctx: Context, geom, b, x, k_max: int, **kw) -> SolveResult:
+    """Hybrid BA-GKB (rule GKB_LAMBDA_DP with eta_proj = ||B e||, or
+    GKB_LAMBDA_GCV), or the enlarged-subspace TSVD (tsvd_rank)."""
+    return _hybrid("gkb_ba_hybrid_solve", ctx, geom, b, x, k_max, **kw)
 
 
 def _opts(k_max: int, lam: float = 0.0, use_dp: bool = False, tau: float = 1.0, noise_norm: float = 0.0,

@@ -682,7 +682,8 @@ struct gkb_ctx {
   DevBuf ywpad;  // fan-beam A^T input as (w y, w) pairs, apart from ypad so that neither layout overwrites the other's pads
   // solve workspace
   DevBuf Q, yk, rdbl, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
-  DevBuf gm_y, gm_h;  // GMRES: the A-images Y and the Hessenberg columns
+  DevBuf gm_y, gm_h;  // GMRES and hybrid GKB: the A-images Y; GMRES: the Hessenberg columns
+  DevBuf hy_w;        // enlarged-subspace TSVD: Jacobi workspace (W, V)
   int *host_flag = nullptr;      // host-mapped
   int *host_flag_dev = nullptr;  // its device address
   // batched solves: vectors, control blocks, slice descriptors, launch maps
@@ -1413,7 +1414,7 @@ struct Solver {
     HIPC(c->w.ensure(sizeof(T) * (size_t)dimq));
     HIPC(c->tmp_n.ensure(sizeof(T) * (size_t)n));
     HIPC(c->tmp_m.ensure(sizeof(T) * (size_t)m));
-    const size_t nd = CD_COUNT + 10 * (size_t)(K + 2);
+    const size_t nd = CD_COUNT + 11 * (size_t)(K + 2);
     HIPC(c->ctl_d.ensure(sizeof(double) * nd));
     HIPC(c->ctl_i.ensure(sizeof(int) * CI_COUNT));
     const long long vb = std::max<long long>(
@@ -1441,7 +1442,8 @@ struct Solver {
     ctl.ip = c->ctl_i.as<int>();
     ctl.dp = dp;
     dp += CD_COUNT;
-    double **arrs[] = {&ctl.alpha, &ctl.t, &ctl.rho, &ctl.pres, &ctl.u, &ctl.Rd, &ctl.Rth, &ctl.Rphi, &ctl.c, &ctl.rre};
+    double **arrs[] = {&ctl.alpha, &ctl.t, &ctl.rho, &ctl.pres, &ctl.u,   &ctl.Rd,
+                       &ctl.Rth,   &ctl.Rphi, &ctl.c, &ctl.rre,  &ctl.lamh};
     for (double **a : arrs) {
       *a = dp;
       dp += K + 2;
@@ -1501,18 +1503,20 @@ struct Solver {
   }
   // the four projectors; `tag` names the input (TAG_NONE: unknown), and the
   // padding kernel is skipped when the padded buffer already holds it
-  void A(Col<const T> in, Col<T> out, const Epi<T> &e, int tag = TAG_NONE) {
+  // stp: the stop flag the launches test (nullptr: run unconditionally)
+  void A(Col<const T> in, Col<T> out, const Epi<T> &e, const int *stp, int tag) {
     if (cone()) {
-      launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stop, st);
+      launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stp, st);
       TraceScope ts(c, "fwd");
-      launch_cone_fwd<T>(g, ct_of<T>(d), xpad, out, e, stop, st);
+      launch_cone_fwd<T>(g, ct_of<T>(d), xpad, out, e, stp, st);
       return;
     }
-    if (tag == TAG_NONE || tag_x != tag) launch_pad_image<T>(g, in, xpad, d.has_coldom, stop, st);
+    if (tag == TAG_NONE || tag_x != tag) launch_pad_image<T>(g, in, xpad, d.has_coldom, stp, st);
     tag_x = tag;
     TraceScope ts(c, "fwd");
-    launch_fwd<T>(g, rt_of<T>(d), xpad, out, e, stop, st);
+    launch_fwd<T>(g, rt_of<T>(d), xpad, out, e, stp, st);
   }
+  void A(Col<const T> in, Col<T> out, const Epi<T> &e, int tag = TAG_NONE) { A(in, out, e, stop, tag); }
   void Bt(Col<const T> in, Col<T> out, const Epi<T> &e, int tag = TAG_NONE) {
     if (cone()) {
       launch_cone_pad_volume<T>(g, in, xpad, d.has_xdom, d.has_ydom, stop, st);
@@ -1763,11 +1767,40 @@ struct Solver {
       launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st);
     }
   }
+
+  // ----- hybrid regularisation: lambda_k on C_k each iteration -----
+  // The residual recurrence of the plain solve assumes one lambda for all
+  // iterations, so rho_k = ||Y_k u_k - b|| is formed from the A-images of
+  // the basis (as for GMRES: BA: A q_i; AB: A B q_i).
+  gkb_status hy_alloc() {
+    ldy = (m + 3) / 4 * 4;
+    HIPC(c->gm_y.ensure(sizeof(T) * (size_t)ldy * K));
+    Y = c->gm_y.as<T>();
+    return GKB_OK;
+  }
+
+  void hy_iteration(bool reorth, int k, const T *b) {
+    T *keep = yk;
+    yk = Y + (size_t)(k - 1) * (size_t)ldy;  // the A-image of q_k is column k - 1 of Y
+    apply_M();
+    yk = keep;
+    apply_Mt(false);
+    reorth_and_normalize_impl(reorth, k);
+    {
+      TraceScope ts(c, "small_solve");
+      launch_hy_lambda(ctl, st);
+      launch_hy_solve(ctl, st);
+    }
+    {
+      TraceScope ts(c, "residual");
+      launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st, NORM_RHO);
+    }
+  }
 };
 
 template <typename T>
 gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const void *bv, const gkb_solve_opts *o,
-                      void *xv, gkb_solve_info *info, int mode) {
+                      void *xv, gkb_solve_info *info, int mode, const gkb_hybrid_opts *hy = nullptr) {
   auto t_start = std::chrono::steady_clock::now();
   DevTables *d = nullptr;
   gkb_status stt = get_tables(c, geom, dtype, &d);
@@ -1775,6 +1808,19 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   Solver<T> S(c, *d, mode, o->k_max);
   stt = S.alloc();
   if (stt != GKB_OK) return stt;
+  // hybrid regularisation (lambda_k on C_k) or the enlarged-subspace TSVD
+  const bool hyb = hy && hy->lambda_rule != GKB_LAMBDA_FIXED;
+  const int tsvd_rank = hy ? hy->tsvd_rank : 0;
+  double *tsvd_w = nullptr;
+  if (hyb) {
+    stt = S.hy_alloc();
+    if (stt != GKB_OK) return stt;
+  }
+  if (tsvd_rank > 0) {
+    const size_t K = (size_t)o->k_max;
+    HIPC(c->hy_w.ensure(sizeof(double) * ((K + 1) * K + K * K)));
+    tsvd_w = c->hy_w.as<double>();
+  }
   if (o->precond) {
     S.net = o->precond;
     net_shape(geom, S.nrows, S.nL);
@@ -1795,6 +1841,8 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   hdp[CD_USEDP] = o->use_dp ? 1.0 : 0.0;
   hdp[CD_KMAX] = o->k_max;
   hdp[CD_RNS] = o->rns_eps;
+  hdp[CD_HRULE] = hyb ? hy->lambda_rule : HY_FIXED;
+  hdp[CD_HTARGET] = (hyb && hy->lambda_rule == GKB_LAMBDA_DP) ? hy->tau_proj * hy->eta_proj : 0.0;
   HIPC(hipMemcpyAsync(S.ctl.ip, hip_, sizeof hip_, hipMemcpyHostToDevice, st));
   HIPC(hipMemcpyAsync(S.ctl.dp, hdp, sizeof hdp, hipMemcpyHostToDevice, st));
   *c->host_flag = 0;
@@ -1856,7 +1904,10 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     if (x_true) launch_norm_to<T>(S.ctl, x_true, g.n, NORM_XTRUE, S.partials, st);
     int launched = 0;
     for (int k = 1; k <= o->k_max; ++k) {
-      S.iteration(reorth, k);
+      if (hyb)
+        S.hy_iteration(reorth, k, b);
+      else
+        S.iteration(reorth, k);
       if (x_true) S.rre_step(x_true);
       HIPC(hipEventRecord(evs[k % L], st));
       ++launched;
@@ -1868,12 +1919,18 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
     HIPC(hipGetLastError());
     // launches queued after the stop did not run: no padded copy is known
     S.forget_pads();
+    // enlarged-subspace TSVD: u from the rank-r truncated SVD of C_K
+    if (tsvd_rank > 0) launch_tsvd(S.ctl, tsvd_w, tsvd_w + (size_t)(o->k_max + 1) * o->k_max, tsvd_rank, st);
     // solution x = Q_k u_k (BA, matched) or B (Q_k u_k) (AB)
     if (mode == MODE_AB) {
       launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, S.tm, st);
       S.B(col<const T>(S.tm), x, plain_epi<T>(), nullptr);
     } else {
       launch_solution<T>(S.ctl, S.Q, S.ldq, S.dimq, x, st);
+    }
+    if (tsvd_rank > 0) {  // ||A x - b|| of the truncated solution
+      S.A(col<const T>(x), col<T>(S.tm), plain_epi<T>(), nullptr, Solver<T>::TAG_NONE);
+      launch_final_residual<T>(S.ctl, S.tm, b, g.m, S.partials, st);
     }
     HIPC(hipGetLastError());
     int hi[CI_COUNT];
@@ -1893,6 +1950,27 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
       std::vector<double> rre(o->k_max + 2);
       HIPC(hipMemcpy(rre.data(), S.ctl.rre, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
       for (int k = 1; k <= k_stop; ++k) o->rre_history[k - 1] = rre[k];
+    }
+    if (hyb && hy->lambda_history) {
+      std::vector<double> lh(o->k_max + 2);
+      HIPC(hipMemcpy(lh.data(), S.ctl.lamh, sizeof(double) * (o->k_max + 2), hipMemcpyDeviceToHost));
+      for (int k = 1; k <= o->k_max; ++k) hy->lambda_history[k - 1] = (k <= k_stop) ? lh[k] : 0.0;
+    }
+    if (tsvd_rank > 0) {
+      // ||A x - b|| of the returned x, and ||C_K u - t_1 e_1|| of its u
+      const int K = k_stop;
+      std::vector<double> al(K + 2), tt(K + 2), uu(K + 2);
+      HIPC(hipMemcpy(&inf.residual, S.ctl.dp + CD_FINALRES, sizeof(double), hipMemcpyDeviceToHost));
+      HIPC(hipMemcpy(al.data(), S.ctl.alpha, sizeof(double) * (K + 2), hipMemcpyDeviceToHost));
+      HIPC(hipMemcpy(tt.data(), S.ctl.t, sizeof(double) * (K + 2), hipMemcpyDeviceToHost));
+      HIPC(hipMemcpy(uu.data(), S.ctl.u, sizeof(double) * (K + 2), hipMemcpyDeviceToHost));
+      double pr = 0.0;
+      for (int i = 1; i <= K + 1; ++i) {
+        double r = (i <= K ? al[i] * uu[i] : 0.0) + (i >= 2 ? tt[i] * uu[i - 1] : 0.0);
+        if (i == 1) r -= tt[1];
+        pr += r * r;
+      }
+      inf.proj_residual = std::sqrt(pr);
     }
     (void)launched;
   }
@@ -2061,6 +2139,31 @@ gkb_status gm_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b,
   HIPC(hipSetDevice(c->device));
   return dtype == GKB_F32 ? gm_solve_impl<float>(c, g, dtype, b, o, x, info, mode)
                           : gm_solve_impl<double>(c, g, dtype, b, o, x, info, mode);
+}
+
+gkb_status hy_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                    const gkb_hybrid_opts *h, void *x, gkb_solve_info *info, int mode) {
+  if (!c) return fail(GKB_EINVAL, "context is NULL");
+  if (!o || !h) return fail(GKB_EINVAL, "options are NULL");
+  if (!b || !x) return fail(GKB_EINVAL, "data pointer is NULL");
+  gkb_status st = validate_geom(g, dtype);
+  if (st != GKB_OK) return st;
+  st = validate_opts(o);
+  if (st != GKB_OK) return st;
+  if (o->precond) return fail(GKB_EUNSUPPORTED, "hybrid solves take no learned filter");
+  if (o->k_max > kHyMaxK) return fail(GKB_EINVAL, "hybrid and TSVD solves: k_max must be <= 1024");
+  if (o->lambda != 0.0) return fail(GKB_EINVAL, "hybrid and TSVD solves choose lambda themselves (lambda must be 0)");
+  if (h->lambda_rule < GKB_LAMBDA_FIXED || h->lambda_rule > GKB_LAMBDA_GCV)
+    return fail(GKB_EINVAL, "lambda_rule must be GKB_LAMBDA_FIXED, GKB_LAMBDA_DP or GKB_LAMBDA_GCV");
+  if ((h->lambda_rule == GKB_LAMBDA_FIXED) == (h->tsvd_rank == 0))
+    return fail(GKB_EINVAL, "give either a lambda rule or a TSVD rank");
+  if (h->tsvd_rank < 0 || h->tsvd_rank > o->k_max) return fail(GKB_EINVAL, "tsvd_rank must be in [1, k_max]");
+  if (h->lambda_rule == GKB_LAMBDA_DP &&
+      (!(h->tau_proj >= 0.0) || !std::isfinite(h->tau_proj) || !(h->eta_proj >= 0.0) || !std::isfinite(h->eta_proj)))
+    return fail(GKB_EINVAL, "tau_proj and eta_proj must be finite and >= 0");
+  HIPC(hipSetDevice(c->device));
+  return dtype == GKB_F32 ? solve_impl<float>(c, g, dtype, b, o, x, info, mode, h)
+                          : solve_impl<double>(c, g, dtype, b, o, x, info, mode, h);
 }
 
 gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
@@ -2281,6 +2384,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       dp += h.K + 2;
     }
     ctl.rre = nullptr;  // no reconstruction-error histories in batched solves
+    ctl.lamh = nullptr;
     ctl.aw = wsD + h.ores;
     ctl.r = ctl.aw + (h.m + 3) / 4 * 4;
     ctl.K = h.K;
@@ -2686,6 +2790,16 @@ gkb_status gkb_ab_gmres_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, cons
 gkb_status gkb_ba_gmres_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
                               void *x, gkb_solve_info *info) {
   return gm_entry(c, g, dtype, b, o, x, info, MODE_BA);
+}
+
+gkb_status gkb_ab_hybrid_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                               const gkb_hybrid_opts *h, void *x, gkb_solve_info *info) {
+  return hy_entry(c, g, dtype, b, o, h, x, info, MODE_AB);
+}
+
+gkb_status gkb_ba_hybrid_solve(gkb_ctx *c, const gkb_geometry *g, int dtype, const void *b, const gkb_solve_opts *o,
+                               const gkb_hybrid_opts *h, void *x, gkb_solve_info *info) {
+  return hy_entry(c, g, dtype, b, o, h, x, info, MODE_BA);
 }
 
 gkb_status gkb_batch_solve(gkb_ctx *c, int method, int n_slices, const gkb_geometry *geoms, int dtype,

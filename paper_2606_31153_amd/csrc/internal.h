@@ -41,7 +41,10 @@ enum CtlDbl : int {
   CD_BNORM = 12,   // ||b||
   CD_RNS = 13,     // residual norm stagnation tolerance (0 = off)
   CD_XTNORM = 14,  // ||x_true|| for the relative reconstruction error
-  CD_COUNT = 16
+  CD_HRULE = 15,   // hybrid solves: rule choosing lambda_k on C_k (1 discrepancy, 2 GCV)
+  CD_HTARGET = 16, // hybrid discrepancy rule: tau * eta of the projected residual
+  CD_FINALRES = 17,  // ||A x - b|| of a solution formed after the iteration (TSVD)
+  CD_COUNT = 20
 };
 
 // Views into the control block (device memory).  Arrays indexed 1-based by
@@ -59,6 +62,7 @@ struct Ctl {
   double *Rphi;   // rotated right-hand side
   double *c;      // CGS coefficients [K+1]
   double *rre;    // [K+2] RRE(x_k) at rre[k] (single-slice solves with x_true; else null)
+  double *lamh;   // [K+2] lambda_k at lamh[k] (hybrid solves; else null)
   double *aw;     // [m] A-image of the last column of W = Q R^{-1}
   double *r;      // [m] r_k = A x_k - b
   int *host_stop; // host-mapped mirror of ip[CI_STOP] (may be null)
@@ -436,7 +440,7 @@ void launch_net_scale(float *r, long long n, const double *sums, int batch, hipS
 // targets of the finalising reductions: t[k+1], alpha[k+1], dp[CD_BNORM] =
 // ||b||, and rho[k] = ||r_k|| with the stopping decision of iteration k
 enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO = 3, NORM_XTRUE = 4, NORM_RRE = 5,
-                        NORM_GMRHO = 6 };
+                        NORM_GMRHO = 6, NORM_FINAL = 7 };
 
 // ---- GMRES (Algs. "AB-GMRES", "BA-GMRES") on the same vectors and reductions ----
 constexpr int kGmMaxK = 1024;  // k_max limit of the GMRES solves
@@ -449,7 +453,21 @@ void launch_gm_solve(Ctl ctl, hipStream_t s);
 // rho_k = ||Y_k u_k - b|| (Y: the A-images, ld a multiple of 4) and the
 // stopping decision of iteration k
 template <typename T>
-void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s);
+void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s,
+                     int which = NORM_GMRHO);
+
+// hybrid regularisation (lambda_k chosen on C_k) and the enlarged-subspace
+// TSVD: k_max at most kHyMaxK
+constexpr int kHyMaxK = 1024;
+enum HybridRule : int { HY_FIXED = 0, HY_DP = 1, HY_GCV = 2 };
+void launch_hy_lambda(Ctl ctl, hipStream_t s);
+void launch_hy_solve(Ctl ctl, hipStream_t s);
+// rank-r truncated SVD solution of the projected problem at k_stop into u;
+// W: (K+1) K doubles, V: K K doubles of workspace
+void launch_tsvd(Ctl ctl, double *W, double *V, int rank, hipStream_t s);
+// ||ax - b|| into CD_FINALRES
+template <typename T>
+void launch_final_residual(Ctl ctl, const T *ax, const T *b, long long m, double *partials, hipStream_t s);
 
 // ---- batched launchers: one launch covers every active slice ----
 template <typename T>

@@ -439,6 +439,7 @@ __device__ inline void norm_finalize_body(const Ctl &ctl, const double *__restri
       case NORM_XTRUE: ctl.dp[CD_XTNORM] = sqrt(tot); break;
       case NORM_RRE: ctl.rre[ctl.ip[CI_KSTOP]] = sqrt(tot) / ctl.dp[CD_XTNORM]; break;
       case NORM_GMRHO: gm_stop_test(ctl, sqrt(tot)); break;
+      case NORM_FINAL: ctl.dp[CD_FINALRES] = sqrt(tot); break;
       default: stop_test(ctl, sqrt(tot)); break;  // NORM_RHO
     }
   }
@@ -489,12 +490,9 @@ __global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restri
 constexpr int kSolveThreads = 256;
 constexpr int kMaxKLds = 4096;
 
+__device__ inline void finish_solve(const Ctl &ctl, int k);
+
 __device__ inline void small_solve_body(const Ctl &ctl) {
-  __shared__ double s_u[kMaxKLds + 2];
-  __shared__ double s_rd[kMaxKLds + 2];
-  __shared__ double s_rth[kMaxKLds + 2];
-  __shared__ double s_rphi[kMaxKLds + 2];
-  __shared__ double s_red[kSolveThreads / 64];
   const int k = ctl.ip[CI_K];
   double *dp = ctl.dp;
   if (threadIdx.x == 0) {
@@ -529,6 +527,17 @@ __device__ inline void small_solve_body(const Ctl &ctl) {
     dp[CD_PHIBAR] = -s * phibar;
   }
   __syncthreads();
+  finish_solve(ctl, k);
+}
+
+// u_k from R (Rd, Rth) and Rphi, and the projected residual ||C_k u - t_1 e_1||
+__device__ inline void finish_solve(const Ctl &ctl, int k) {
+  __shared__ double s_u[kMaxKLds + 2];
+  __shared__ double s_rd[kMaxKLds + 2];
+  __shared__ double s_rth[kMaxKLds + 2];
+  __shared__ double s_rphi[kMaxKLds + 2];
+  __shared__ double s_red[kSolveThreads / 64];
+  double *dp = ctl.dp;
   // reciprocals of the diagonal, formed in parallel, so that the serial
   // back substitution below multiplies instead of dividing
   for (int i = 1 + threadIdx.x; i <= k; i += kSolveThreads) {
@@ -803,6 +812,296 @@ __global__ __launch_bounds__(kBlock) void k_resid_init(Ctl ctl, const T *__restr
 __global__ __launch_bounds__(kSolveThreads) void k_small_solve(Ctl ctl) {
   if (ctl.ip[CI_STOP]) return;
   small_solve_body(ctl);
+}
+
+// ---- hybrid regularisation: lambda_k chosen on C_k ------------------------------
+// One pass of the damped reduction of [C_k; lambda I] (as in the projected
+// solve, from column 1) carries three sums forward, so that one thread
+// evaluates the rules at one lambda with O(k) work and no stored arrays:
+//  * the residual of the damped problem, phibar_{k+1}^2 + sum psi_i^2 (psi_i
+//    the parts rotated into the lambda rows);
+//  * ||u||^2 = ||R^-1 f||^2: rotations from the right turn the upper
+//    bidiagonal R into a lower bidiagonal L (the rotation that clears
+//    R_{i,i+1} leaves delta_{i+1} = sn rho_{i+1} below the diagonal and
+//    -cs rho_{i+1} on it), and ||R^-1 f|| = ||L^-1 f||, solved forward;
+//  * ||R^-1||_F^2 = sum_j c_j, c_j = (1 + theta_j^2 c_{j-1}) / rho_j^2: column j
+//    of R^-1 is e_j / rho_j plus -theta_j / rho_j times column j - 1.
+// Then ||C_k u - t_1 e_1||^2 = damped residual^2 - lambda^2 ||u||^2 and, as
+// R^T R = C_k^T C_k + lambda^2 I, trace(I_{k+1} - H(lambda)) = 1 + lambda^2 ||R^-1||_F^2.
+struct HyVal {
+  double phi2;  // ||C_k u_lambda - t_1 e_1||^2
+  double tr;    // trace(I_{k+1} - H(lambda))
+};
+
+__device__ inline HyVal hy_eval(const double *__restrict__ a, const double *__restrict__ t, int k, double lam) {
+  const double l2 = lam * lam;
+  double rhobar = a[1], phibar = t[1], psi2 = 0.0;
+  double zprev = 0.0, zz = 0.0, u2 = 0.0, cprev = 0.0, csum = 0.0, thprev = 0.0, cs2 = 1.0, sn2 = 0.0;
+  for (int i = 1; i <= k; ++i) {
+    double rhat = rhobar;
+    if (lam > 0.0) {  // [rhobar; lambda] -> [rhat; 0]
+      const double h2 = fma(rhobar, rhobar, l2);
+      const double inv = rsqrt(h2);
+      rhat = h2 * inv;
+      psi2 = fma(l2 * inv * inv, phibar * phibar, psi2);
+      phibar *= rhobar * inv;
+    }
+    // [rhat; t_{i+1}] -> [rho_i; 0]; R_{i,i+1} = theta = s alpha_{i+1}
+    const double ti = t[i + 1];
+    const double r2 = fma(rhat, rhat, ti * ti);
+    const double irho = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double rho = r2 * irho;
+    const double c = rhat * irho, sv = ti * irho;
+    const double phi = c * phibar;
+    phibar *= sv;
+    double theta = 0.0;
+    if (i < k) {
+      theta = sv * a[i + 1];
+      rhobar = -c * a[i + 1];
+    }
+    const double ci = fma(thprev * thprev, cprev, 1.0) * irho * irho;
+    csum += ci;
+    cprev = ci;
+    const double gb = (i == 1) ? rho : -cs2 * rho;
+    const double dl = (i == 1) ? 0.0 : sn2 * rho;
+    const double rhs = fma(-dl, zprev, phi);
+    if (i < k) {
+      const double g2 = fma(gb, gb, theta * theta);
+      const double ig = g2 > 0.0 ? rsqrt(g2) : 0.0;
+      cs2 = g2 > 0.0 ? gb * ig : 1.0;
+      sn2 = theta * ig;
+      zprev = rhs * ig;
+      zz = fma(zprev, zprev, zz);
+    } else {
+      const double zb = gb != 0.0 ? rhs / gb : 0.0;
+      u2 = fma(zb, zb, zz);
+    }
+    thprev = theta;
+  }
+  HyVal v;
+  v.phi2 = fmax(fma(phibar, phibar, psi2) - l2 * u2, 0.0);
+  v.tr = fma(l2, csum, 1.0);
+  return v;
+}
+
+// lambda_k on C_k: kHyPasses passes of kSolveThreads values of ln(lambda),
+// equally spaced, first over [ln(1e-10 s), ln(10 s)] (s = max_i ||C_k e_i||),
+// then over the bracket the previous pass found.
+//  discrepancy: F = ||C_k u - t_1 e_1|| - tau eta grows with lambda; lambda = 0
+//    when F(0) >= 0, the range's end where F has one sign over it, else the
+//    first grid value with F >= 0 and its predecessor bracket the root, and
+//    the last pass interpolates F linearly in ln(lambda);
+//  GCV: G = ||C_k u - t_1 e_1||^2 / trace(I - H)^2; the grid minimum and its
+//    neighbours bracket the next pass, and the last takes the vertex of the
+//    parabola through the minimum and its neighbours.
+constexpr int kHyPasses = 3;
+
+__global__ __launch_bounds__(kSolveThreads) void k_hy_lambda(Ctl ctl) {
+  if (ctl.ip[CI_STOP]) return;
+  __shared__ double s_a[kHyMaxK + 2], s_t[kHyMaxK + 2];
+  __shared__ double s_v[kSolveThreads];
+  __shared__ double s_z[2], s_lam;
+  __shared__ int s_done;
+  const int k = ctl.ip[CI_K];
+  const int tid = threadIdx.x;
+  for (int i = 1 + tid; i <= k + 1; i += kSolveThreads) {
+    s_a[i] = ctl.alpha[i];
+    s_t[i] = ctl.t[i];
+  }
+  double sc = 0.0;
+  for (int i = 1 + tid; i <= k; i += kSolveThreads) sc = fmax(sc, ctl.alpha[i] * ctl.alpha[i] + ctl.t[i + 1] * ctl.t[i + 1]);
+  s_v[tid] = sc;
+  __syncthreads();
+  const int rule = (int)ctl.dp[CD_HRULE];
+  const double target = ctl.dp[CD_HTARGET];
+  if (tid == 0) {
+    double m = 0.0;
+    for (int j = 0; j < kSolveThreads; ++j) m = fmax(m, s_v[j]);
+    m = sqrt(m);
+    s_z[0] = log(1e-10 * m);
+    s_z[1] = log(10.0 * m);
+    s_done = 0;
+    s_lam = 0.0;
+    if (!(m > 0.0)) {
+      s_done = 1;  // C_k = 0: nothing to regularise
+    } else if (rule == HY_DP && sqrt(hy_eval(s_a, s_t, k, 0.0).phi2) >= target) {
+      s_done = 1;  // the subspace cannot fit the data to the level yet
+    }
+  }
+  __syncthreads();
+  constexpr int N = kSolveThreads;
+  for (int pass = 0; pass < kHyPasses && !s_done; ++pass) {
+    const double za = s_z[0], zb = s_z[1];
+    const double h = (zb - za) / (N - 1);
+    const double z = za + h * tid;
+    const HyVal v = hy_eval(s_a, s_t, k, exp(z));
+    s_v[tid] = rule == HY_DP ? sqrt(v.phi2) - target : v.phi2 / (v.tr * v.tr);
+    __syncthreads();
+    if (tid == 0) {
+      const bool last = pass == kHyPasses - 1;
+      if (rule == HY_DP) {
+        int j0 = N;
+        for (int j = 0; j < N; ++j)
+          if (s_v[j] >= 0.0) {
+            j0 = j;
+            break;
+          }
+        if (j0 == 0 || j0 == N) {
+          s_lam = exp(j0 == 0 ? za : zb);  // the root lies outside the range (first pass only)
+          s_done = 1;
+        } else {
+          const double z0 = za + h * (j0 - 1), fa = s_v[j0 - 1], fb = s_v[j0];
+          if (last) {
+            s_lam = exp(z0 + h * fa / (fa - fb));
+          } else {
+            s_z[0] = z0;
+            s_z[1] = z0 + h;
+          }
+        }
+      } else {
+        int jm = 0;
+        for (int j = 1; j < N; ++j)
+          if (s_v[j] < s_v[jm]) jm = j;
+        const int lo = jm > 0 ? jm - 1 : 0, hi = jm < N - 1 ? jm + 1 : N - 1;
+        if (last) {
+          double zm = za + h * jm;
+          if (jm > 0 && jm < N - 1) {
+            const double d2 = s_v[jm + 1] - 2.0 * s_v[jm] + s_v[jm - 1];
+            if (d2 > 0.0) zm -= 0.5 * h * (s_v[jm + 1] - s_v[jm - 1]) / d2;
+          }
+          s_lam = exp(zm);
+        } else {
+          s_z[0] = za + h * lo;
+          s_z[1] = za + h * hi;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ctl.dp[CD_LAMBDA] = s_lam;
+    ctl.lamh[k] = s_lam;
+  }
+}
+
+// the projected Tikhonov solution at lambda_k: [C_k; lambda I] reduced from
+// column 1 (thread 0; Rth[i + 1] = R_{i,i+1}), then u and the projected residual
+__global__ __launch_bounds__(kSolveThreads) void k_hy_solve(Ctl ctl) {
+  if (ctl.ip[CI_STOP]) return;
+  const int k = ctl.ip[CI_K];
+  if (threadIdx.x == 0) {
+    const double lam = ctl.dp[CD_LAMBDA];
+    double rhobar = ctl.alpha[1], phibar = ctl.t[1];
+    for (int i = 1; i <= k; ++i) {
+      double rhat = rhobar;
+      if (lam > 0.0) {
+        rhat = sqrt(rhobar * rhobar + lam * lam);
+        phibar *= rhobar / rhat;
+      }
+      const double ti = ctl.t[i + 1];
+      const double rho = sqrt(rhat * rhat + ti * ti);
+      const double c = rhat / rho, sv = ti / rho;
+      ctl.Rd[i] = rho;
+      ctl.Rphi[i] = c * phibar;
+      phibar *= sv;
+      if (i < k) {
+        ctl.Rth[i + 1] = sv * ctl.alpha[i + 1];
+        rhobar = -c * ctl.alpha[i + 1];
+      }
+    }
+  }
+  __syncthreads();
+  finish_solve(ctl, k);
+}
+
+// ---- enlarged-subspace TSVD: one-sided Jacobi SVD of C_K (K = k_stop) -----------
+// W = C_K (column-major, ld K + 1) and V = I; sweeps of rotations over all
+// column pairs (round-robin: K/2 disjoint pairs per round, one thread each)
+// make the columns of W orthogonal, W = U Sigma, C_K = W V^T.  Then
+// u = sum over the `rank` largest sigma_i of (t_1 W_{1i} / sigma_i^2) v_i.
+constexpr int kJacobiSweeps = 60;
+
+__global__ __launch_bounds__(kSolveThreads) void k_tsvd(Ctl ctl, double *__restrict__ W, double *__restrict__ V,
+                                                        int rank) {
+  __shared__ double s_sig[kHyMaxK + 2];
+  __shared__ double s_coef[kHyMaxK + 2];
+  __shared__ int s_rot;
+  const int K = ctl.ip[CI_KSTOP];
+  const int tid = threadIdx.x;
+  const long long ldw = K + 1;
+  for (long long e = tid; e < ldw * K; e += kSolveThreads) {
+    const int j = (int)(e / ldw), i = (int)(e - (long long)j * ldw);
+    W[e] = i == j ? ctl.alpha[j + 1] : (i == j + 1 ? ctl.t[j + 2] : 0.0);
+  }
+  for (long long e = tid; e < (long long)K * K; e += kSolveThreads) V[e] = (e / K == e % K) ? 1.0 : 0.0;
+  __syncthreads();
+  const int P = K + (K & 1);  // players of the round robin (one idle when K is odd)
+  for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < P - 1; ++r) {
+      for (int p = tid; p < P / 2; p += kSolveThreads) {
+        int i = p == 0 ? P - 1 : (r + p) % (P - 1);
+        int j = p == 0 ? r : (r - p + P - 1) % (P - 1);
+        if (i >= K || j >= K) continue;
+        if (i > j) {
+          const int tmp = i;
+          i = j;
+          j = tmp;
+        }
+        double *wi = W + (long long)i * ldw, *wj = W + (long long)j * ldw;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int q = 0; q <= K; ++q) {
+          al = fma(wi[q], wi[q], al);
+          be = fma(wj[q], wj[q], be);
+          ga = fma(wi[q], wj[q], ga);
+        }
+        if (!(fabs(ga) > 1e-15 * sqrt(al * be))) continue;
+        s_rot = 1;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double tn = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
+        for (int q = 0; q <= K; ++q) {
+          const double a = wi[q], b = wj[q];
+          wi[q] = cs * a - sn * b;
+          wj[q] = sn * a + cs * b;
+        }
+        double *vi = V + (long long)i * K, *vj = V + (long long)j * K;
+        for (int q = 0; q < K; ++q) {
+          const double a = vi[q], b = vj[q];
+          vi[q] = cs * a - sn * b;
+          vj[q] = sn * a + cs * b;
+        }
+      }
+      __syncthreads();
+    }
+    if (!s_rot) break;
+    __syncthreads();
+  }
+  for (int i = tid; i < K; i += kSolveThreads) {
+    double ss = 0.0;
+    for (int q = 0; q <= K; ++q) ss = fma(W[(long long)i * ldw + q], W[(long long)i * ldw + q], ss);
+    s_sig[i] = ss;  // sigma_i^2
+    s_coef[i] = 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // the rank largest sigma (ties by index); a zero sigma takes no part
+    for (int r = 0; r < rank; ++r) {
+      int best = -1;
+      for (int i = 0; i < K; ++i)
+        if (s_coef[i] == 0.0 && s_sig[i] > 0.0 && (best < 0 || s_sig[i] > s_sig[best])) best = i;
+      if (best < 0) break;
+      s_coef[best] = ctl.t[1] * W[(long long)best * ldw] / s_sig[best];
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < K; q += kSolveThreads) {
+    double acc = 0.0;
+    for (int i = 0; i < K; ++i)
+      if (s_coef[i] != 0.0) acc = fma(s_coef[i], V[(long long)i * K + q], acc);
+    ctl.u[q + 1] = acc;
+  }
 }
 
 // ---- out = sum_{i=1..k_stop} u_i Q[:, i-1] -------------------------------------
@@ -1111,10 +1410,24 @@ void launch_gm_hcol(Ctl ctl, int first, hipStream_t s) {
 }
 void launch_gm_solve(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, ctl); }
 template <typename T>
-void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s) {
+void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s,
+                     int which) {
   const int nb = vec_blocks(m);
   hipLaunchKernelGGL(k_gm_resid<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Y, ld, b, m, partials);
-  launch_norm_finalize(ctl, partials, nb, NORM_GMRHO, ctl.ip + CI_STOP, s);
+  launch_norm_finalize(ctl, partials, nb, which, ctl.ip + CI_STOP, s);
+}
+void launch_hy_lambda(Ctl ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_hy_lambda, dim3(1), dim3(kSolveThreads), 0, s, ctl);
+}
+void launch_hy_solve(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_hy_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl); }
+void launch_tsvd(Ctl ctl, double *W, double *V, int rank, hipStream_t s) {
+  hipLaunchKernelGGL(k_tsvd, dim3(1), dim3(kSolveThreads), 0, s, ctl, W, V, rank);
+}
+template <typename T>
+void launch_final_residual(Ctl ctl, const T *ax, const T *b, long long m, double *partials, hipStream_t s) {
+  const int nb = vec_blocks(m);
+  hipLaunchKernelGGL(k_diff_norm<T>, dim3(nb), dim3(kBlock), 0, s, ax, b, m, partials);
+  launch_norm_finalize(ctl, partials, nb, NORM_FINAL, nullptr, s);
 }
 template <typename T>
 void launch_solution(Ctl ctl, const T *Q, long long ld, long long dim, T *out, hipStream_t s) {
@@ -1214,7 +1527,8 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
-  template void launch_gm_resid<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t);  \
+  template void launch_gm_resid<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t, int); \
+  template void launch_final_residual<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);       \
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
   template void launch_b_norm_finalize<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t); \

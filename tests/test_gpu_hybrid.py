@@ -1,0 +1,163 @@
+"""GPU hybrid regularisation and enlarged-subspace TSVD (through the C ABI)
+against the oracle (oracle/hybrid.py; readings of Sec. 1, Sec. 3.1 and
+Sec. 6 stated there).
+
+The GPU evaluates the lambda rules by a one-pass recurrence per lambda over
+three refining grids, solves the projected problem by Givens rotations and
+takes the TSVD by one-sided Jacobi; the oracle takes NumPy's SVD of C_k,
+bisects the discrepancy rule to rounding and minimises GCV on a fine grid
+with golden-section refinement.  FP64 path: the same stopping iteration and
+reason; lambda_k within 1e-9 and x, rho_k within 1e-8 for the discrepancy
+rule (a root, resolved to rounding on both sides); lambda_k, x and rho_k
+within 1e-6 for GCV (a flat minimum, which each side locates to about 1e-8
+in lambda, and x moves with it).  FP32/FP64 split: the same discrepancy stop
+and x within 1e-4.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import hybrid as hy
+from paper_2606_31153_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2606_31153_amd as gk  # noqa: E402
+
+DEV = torch.device("cuda:0")
+MODES = {"ab": (oracle.MODE_AB, gk.gkb_ab_hybrid_solve), "ba": (oracle.MODE_BA, gk.gkb_ba_hybrid_solve)}
+RULES = {"dp": (hy.RULE_DP, gk.GKB_LAMBDA_DP), "gcv": (hy.RULE_GCV, gk.GKB_LAMBDA_GCV)}
+GEOMS = {"par64_v89": lambda: synth.par2d(64, 89, 91), "fan_ragged": lambda: synth.fan2d(45, 33, 70)}
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gk.Context(0)
+    yield c
+    c.close()
+
+
+def problem(geom, seed, nu):
+    op = oracle.Operator(geom)
+    x_true = synth.rasterize_ellipses(synth.ellipse_params(seed), geom.nx, geom.ny)
+    ax = op.A(x_true).reshape(-1)
+    b, en = synth.add_noise(ax, synth.noise_direction(geom.m, seed), nu)
+    return op, x_true, b, en, b - ax
+
+
+def eta_proj(op, mode, e):
+    # the noise norm in the projected residual's space: ||e|| (AB), ||B e|| (BA)
+    return float(np.linalg.norm(e)) if mode == oracle.MODE_AB else float(np.linalg.norm(op.B(e)))
+
+
+def gpu(ctx, geom, fn, b, dtype, k_max, **kw):
+    bd = torch.tensor(np.asarray(b, dtype=np.float64), dtype=dtype, device=DEV)
+    xd = torch.full((geom.n,), float("nan"), dtype=dtype, device=DEV)
+    res = fn(ctx, geom, bd, xd, k_max, **kw)
+    torch.cuda.synchronize()
+    return res, xd.cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("rname", list(RULES))
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("gname", list(GEOMS))
+def test_hybrid_fp64_matches_oracle(ctx, gname, mode, rname):
+    geom = GEOMS[gname]()
+    op, xt, b, en, e = problem(geom, 1200, 0.02)
+    om, fn = MODES[mode]
+    orule, grule = RULES[rname]
+    eta = eta_proj(op, om, e)
+    K = 25
+    ref = hy.hybrid(op, om, b, K, orule, 1.0, eta)
+    note("hybrid fp64 %s %s %s: oracle k=%d reason %d, lambda_K %.3e" % (gname, mode, rname, ref.k_stop,
+                                                                         ref.reason, ref.lam[-1]))
+    res, x = gpu(ctx, geom, fn, b, torch.float64, K, rule=grule, tau_proj=1.0, eta_proj=eta)
+    assert (res.k_stop, res.reason) == (ref.k_stop, ref.reason)
+    lam_tol = 1e-9 if rname == "dp" else 1e-6
+    nz = ref.lam > 0
+    assert np.array_equal(res.lam > 0, nz)
+    lam_err = float(np.max(np.abs(res.lam[nz] / ref.lam[nz] - 1.0))) if nz.any() else 0.0
+    note("  lambda rel %.2e, x rel %.2e, rho rel %.2e" % (lam_err, rel(x, ref.x.reshape(-1)),
+                                                          float(np.max(np.abs(res.rho / ref.rho - 1.0)))))
+    assert lam_err <= lam_tol
+    # GCV: x and rho move with lambda, which each side resolves to about 1e-8
+    # at a flat minimum; the discrepancy root is resolved to rounding
+    tol = 1e-8 if rname == "dp" else 1e-6
+    assert rel(x, ref.x.reshape(-1)) <= tol
+    assert np.allclose(res.rho, ref.rho, rtol=tol)
+    assert res.proj_residual == pytest.approx(ref.pres[-1], rel=tol)
+
+
+@pytest.mark.parametrize("rname", list(RULES))
+@pytest.mark.parametrize("mode", list(MODES))
+def test_hybrid_fp32_discrepancy_stop_matches_oracle(ctx, mode, rname):
+    geom = synth.fan2d(96, 143, 160)
+    op, xt, b, en, e = problem(geom, 2201, 0.02)
+    b32 = np.float32(b).astype(np.float64)
+    om, fn = MODES[mode]
+    orule, grule = RULES[rname]
+    eta = eta_proj(op, om, b32 - op.A(xt).reshape(-1))
+    ref = hy.hybrid(op, om, b32, 40, orule, 1.0, eta, use_dp=True, tau=1.02, noise_norm=en)
+    res, x = gpu(ctx, geom, fn, b32, torch.float32, 40, rule=grule, tau_proj=1.0, eta_proj=eta, use_dp=True,
+                 tau=1.02, noise_norm=en)
+    note("hybrid fp32 %s %s: gpu k=%d reason %d, oracle k=%d reason %d, x rel %.2e" % (
+        mode, rname, res.k_stop, res.reason, ref.k_stop, ref.reason, rel(x, ref.x.reshape(-1))))
+    assert (res.k_stop, res.reason) == (ref.k_stop, ref.reason)
+    assert rel(x, ref.x.reshape(-1)) <= 1e-4
+    assert np.allclose(res.rho, ref.rho, rtol=1e-4)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_tsvd_matches_oracle(ctx, mode, dtype):
+    geom = synth.par2d(64, 89, 91)
+    op, xt, b, en, e = problem(geom, 1300, 0.02)
+    if dtype == torch.float32:
+        b = np.float32(b).astype(np.float64)
+    om, fn = MODES[mode]
+    K = 24
+    for r in (1, 8, 24):
+        ref = hy.tsvd(op, om, b, K, r).reshape(-1)
+        res, x = gpu(ctx, geom, fn, b, dtype, K, tsvd_rank=r)
+        tol = 1e-8 if dtype == torch.float64 else 1e-4
+        note("tsvd %s %s K=%d r=%d: x rel %.2e" % (mode, "f64" if dtype == torch.float64 else "f32", K, r,
+                                                    rel(x, ref)))
+        assert res.k_stop == K
+        assert rel(x, ref) <= tol
+        assert res.residual == pytest.approx(np.linalg.norm(op.A(ref).reshape(-1) - b), rel=10 * tol)
+
+
+def test_hybrid_errors_and_degenerate_input(ctx):
+    geom = synth.par2d(32, 20)
+    bd = torch.ones(geom.m, dtype=torch.float32, device=DEV)
+    xd = torch.zeros(geom.n, dtype=torch.float32, device=DEV)
+    bad = [dict(rule=7), dict(rule=gk.GKB_LAMBDA_FIXED), dict(rule=gk.GKB_LAMBDA_GCV, tsvd_rank=3),
+           dict(tsvd_rank=11), dict(rule=gk.GKB_LAMBDA_DP, eta_proj=-1.0), dict(rule=gk.GKB_LAMBDA_GCV, lam=0.1)]
+    for kw in bad:
+        with pytest.raises(gk.GkbError) as ei:
+            gk.gkb_ba_hybrid_solve(ctx, geom, bd, xd, 10, **kw)
+        assert ei.value.status == gk.GKB_EINVAL, kw
+    with pytest.raises(gk.GkbError) as ei:
+        gk.gkb_ab_hybrid_solve(ctx, geom, bd, xd, 2000, rule=gk.GKB_LAMBDA_GCV)
+    assert ei.value.status == gk.GKB_EINVAL
+    # zero right-hand side: breakdown at k = 0, x = 0
+    res, x = gpu(ctx, geom, gk.gkb_ba_hybrid_solve, np.zeros(geom.m), torch.float32, 10, rule=gk.GKB_LAMBDA_GCV)
+    assert res.k_stop == 0 and res.reason == gk.STOP_BREAKDOWN and not x.any()
+    # the discrepancy rule with eta = 0 never regularises: plain GKB
+    b = np.random.default_rng(3).standard_normal(geom.m)
+    res, x = gpu(ctx, geom, gk.gkb_ba_hybrid_solve, b, torch.float64, 12, rule=gk.GKB_LAMBDA_DP, eta_proj=0.0)
+    plain, xp = gpu(ctx, geom, gk.gkb_ba_solve, b, torch.float64, 12)
+    assert np.all(res.lam == 0.0)
+    assert rel(x, xp) <= 1e-10

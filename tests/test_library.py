@@ -41,12 +41,16 @@ def test_struct_layouts_match_header(tmp_path):
     # compile the header with the host C compiler and compare the struct sizes
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "gkb.h"\n'
-                   'int main(void){printf("%zu %zu %zu", sizeof(gkb_geometry), sizeof(gkb_solve_opts),'
-                   ' sizeof(gkb_solve_info)); return 0;}\n')
+                   '#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu", sizeof(gkb_geometry), sizeof(gkb_solve_opts),'
+                   ' sizeof(gkb_solve_info), sizeof(gkb_hybrid_opts), offsetof(gkb_hybrid_opts, tsvd_rank),'
+                   ' offsetof(gkb_hybrid_opts, lambda_history), sizeof(gkb_tuning)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     sizes = [int(v) for v in subprocess.check_output([str(exe)]).split()]
-    assert sizes == [ctypes.sizeof(gk.Geometry), ctypes.sizeof(gk.SolveOpts), ctypes.sizeof(gk.SolveInfo)]
+    assert sizes == [ctypes.sizeof(gk.Geometry), ctypes.sizeof(gk.SolveOpts), ctypes.sizeof(gk.SolveInfo),
+                     ctypes.sizeof(gk.HybridOpts), gk.HybridOpts.tsvd_rank.offset,
+                     gk.HybridOpts.lambda_history.offset, ctypes.sizeof(gk.Tuning)]
 
 
 def test_last_error_is_a_string():
