@@ -417,6 +417,27 @@ def gmres_point(ctx, geom, b, iters: int):
     return out
 
 
+def hybrid_point(ctx, geom, b, iters: int):
+    """Hybrid BA-GKB (lambda_k on C_k by the projected discrepancy rule or GCV)
+    and the enlarged-subspace TSVD on the benchmark workload: iterations/s
+    beside plain BA-GKB, the same number of iterations."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    x = torch.zeros(geom.n, dtype=torch.float32, device=b.device)
+    out = {"workload": "fan-beam 512x512 as above; BA-GKB, %d iterations" % iters}
+    for name, kw in (("plain", None), ("hybrid_dp", dict(rule=gk.GKB_LAMBDA_DP, eta_proj=1.0)),
+                     ("hybrid_gcv", dict(rule=gk.GKB_LAMBDA_GCV)), ("tsvd_rank100", dict(tsvd_rank=100))):
+        fn = gk.gkb_ba_solve if kw is None else gk.gkb_ba_hybrid_solve
+        kw = kw or {}
+        fn(ctx, geom, b, x, iters, **kw)
+        torch.cuda.synchronize()
+        r = fn(ctx, geom, b, x, iters, **kw)
+        torch.cuda.synchronize()
+        out["%s_iters_per_s" % name] = iters / r.seconds
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -557,6 +578,8 @@ def main():
     out["par512"] = par512_point(ctx, args.iters)
     print("bench: GMRES on the benchmark workload", file=sys.stderr, flush=True)
     out["gmres"] = gmres_point(ctx, geom, b, args.iters)
+    print("bench: hybrid regularisation and TSVD on the benchmark workload", file=sys.stderr, flush=True)
+    out["hybrid"] = hybrid_point(ctx, geom, b, args.iters)
     if not args.no_batch:
         print("bench: 64-slice batched workload", file=sys.stderr, flush=True)
         out["s_per_slice_to_discrepancy"] = batch_bench(ctx)

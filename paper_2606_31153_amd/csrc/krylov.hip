@@ -1016,31 +1016,42 @@ __global__ __launch_bounds__(kSolveThreads) void k_hy_solve(Ctl ctl) {
 
 // ---- enlarged-subspace TSVD: one-sided Jacobi SVD of C_K (K = k_stop) -----------
 // W = C_K (column-major, ld K + 1) and V = I; sweeps of rotations over all
-// column pairs (round-robin: K/2 disjoint pairs per round, one thread each)
-// make the columns of W orthogonal, W = U Sigma, C_K = W V^T.  Then
+// column pairs (round-robin: K/2 disjoint pairs per round) make the columns of
+// W orthogonal, W = U Sigma, C_K = W V^T.  One wavefront takes one pair at a
+// time: its lanes hold rows lane, lane + 64, ... of the two columns, the
+// three inner products are reduced across the wavefront in a fixed order, and
+// the rotation updates the rows in place.  Then
 // u = sum over the `rank` largest sigma_i of (t_1 W_{1i} / sigma_i^2) v_i.
 constexpr int kJacobiSweeps = 60;
+constexpr int kTsvdThreads = 1024;
 
-__global__ __launch_bounds__(kSolveThreads) void k_tsvd(Ctl ctl, double *__restrict__ W, double *__restrict__ V,
-                                                        int rank) {
+__device__ inline double wave_sum_all(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kTsvdThreads) void k_tsvd(Ctl ctl, double *__restrict__ W, double *__restrict__ V,
+                                                       int rank) {
   __shared__ double s_sig[kHyMaxK + 2];
   __shared__ double s_coef[kHyMaxK + 2];
   __shared__ int s_rot;
   const int K = ctl.ip[CI_KSTOP];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = kTsvdThreads / 64;
   const long long ldw = K + 1;
-  for (long long e = tid; e < ldw * K; e += kSolveThreads) {
+  for (long long e = tid; e < ldw * K; e += kTsvdThreads) {
     const int j = (int)(e / ldw), i = (int)(e - (long long)j * ldw);
     W[e] = i == j ? ctl.alpha[j + 1] : (i == j + 1 ? ctl.t[j + 2] : 0.0);
   }
-  for (long long e = tid; e < (long long)K * K; e += kSolveThreads) V[e] = (e / K == e % K) ? 1.0 : 0.0;
+  for (long long e = tid; e < (long long)K * K; e += kTsvdThreads) V[e] = (e / K == e % K) ? 1.0 : 0.0;
   __syncthreads();
   const int P = K + (K & 1);  // players of the round robin (one idle when K is odd)
   for (int sweep = 0; sweep < kJacobiSweeps; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int r = 0; r < P - 1; ++r) {
-      for (int p = tid; p < P / 2; p += kSolveThreads) {
+      for (int p = wave; p < P / 2; p += NW) {
         int i = p == 0 ? P - 1 : (r + p) % (P - 1);
         int j = p == 0 ? r : (r - p + P - 1) % (P - 1);
         if (i >= K || j >= K) continue;
@@ -1051,23 +1062,26 @@ __global__ __launch_bounds__(kSolveThreads) void k_tsvd(Ctl ctl, double *__restr
         }
         double *wi = W + (long long)i * ldw, *wj = W + (long long)j * ldw;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int q = 0; q <= K; ++q) {
+        for (int q = lane; q <= K; q += 64) {
           al = fma(wi[q], wi[q], al);
           be = fma(wj[q], wj[q], be);
           ga = fma(wi[q], wj[q], ga);
         }
+        al = wave_sum_all(al);
+        be = wave_sum_all(be);
+        ga = wave_sum_all(ga);
         if (!(fabs(ga) > 1e-15 * sqrt(al * be))) continue;
-        s_rot = 1;
+        if (lane == 0) s_rot = 1;
         const double zeta = (be - al) / (2.0 * ga);
         const double tn = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + tn * tn), sn = cs * tn;
-        for (int q = 0; q <= K; ++q) {
+        for (int q = lane; q <= K; q += 64) {
           const double a = wi[q], b = wj[q];
           wi[q] = cs * a - sn * b;
           wj[q] = sn * a + cs * b;
         }
         double *vi = V + (long long)i * K, *vj = V + (long long)j * K;
-        for (int q = 0; q < K; ++q) {
+        for (int q = lane; q < K; q += 64) {
           const double a = vi[q], b = vj[q];
           vi[q] = cs * a - sn * b;
           vj[q] = sn * a + cs * b;
@@ -1078,7 +1092,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_tsvd(Ctl ctl, double *__restr
     if (!s_rot) break;
     __syncthreads();
   }
-  for (int i = tid; i < K; i += kSolveThreads) {
+  for (int i = tid; i < K; i += kTsvdThreads) {
     double ss = 0.0;
     for (int q = 0; q <= K; ++q) ss = fma(W[(long long)i * ldw + q], W[(long long)i * ldw + q], ss);
     s_sig[i] = ss;  // sigma_i^2
@@ -1096,7 +1110,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_tsvd(Ctl ctl, double *__restr
     }
   }
   __syncthreads();
-  for (int q = tid; q < K; q += kSolveThreads) {
+  for (int q = tid; q < K; q += kTsvdThreads) {
     double acc = 0.0;
     for (int i = 0; i < K; ++i)
       if (s_coef[i] != 0.0) acc = fma(s_coef[i], V[(long long)i * K + q], acc);
@@ -1421,7 +1435,7 @@ void launch_hy_lambda(Ctl ctl, hipStream_t s) {
 }
 void launch_hy_solve(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_hy_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl); }
 void launch_tsvd(Ctl ctl, double *W, double *V, int rank, hipStream_t s) {
-  hipLaunchKernelGGL(k_tsvd, dim3(1), dim3(kSolveThreads), 0, s, ctl, W, V, rank);
+  hipLaunchKernelGGL(k_tsvd, dim3(1), dim3(kTsvdThreads), 0, s, ctl, W, V, rank);
 }
 template <typename T>
 void launch_final_residual(Ctl ctl, const T *ax, const T *b, long long m, double *partials, hipStream_t s) {

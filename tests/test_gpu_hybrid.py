@@ -161,3 +161,29 @@ def test_hybrid_errors_and_degenerate_input(ctx):
     plain, xp = gpu(ctx, geom, gk.gkb_ba_solve, b, torch.float64, 12)
     assert np.all(res.lam == 0.0)
     assert rel(x, xp) <= 1e-10
+
+
+def test_paper_shape_hybrid_discrepancy_damps_semiconvergence(ctx):
+    # Example 1's shape (Sec. 5: 128^2 image, 65 views, 128 bins, 4 % noise).
+    # Plain BA-GKB and AB-GKB semiconverge: past k_DP their error grows
+    # (Sec. 5's RRE curves).  With lambda_k from the projected discrepancy
+    # rule the error stays near its best as k grows: the motivation the paper
+    # gives for regularising inside the subspace (Sec. 1).
+    geom = synth.par2d(128, 65, 128)
+    op, xt, b, en, e = problem(geom, 6000, 0.04)
+    bd = torch.tensor(b, dtype=torch.float32, device=DEV)
+    xtd = torch.tensor(xt.reshape(-1), dtype=torch.float32, device=DEV)
+    K = 80
+    for mode, fp, fh in (("ba", gk.gkb_ba_solve, gk.gkb_ba_hybrid_solve), ("ab", gk.gkb_ab_solve,
+                                                                             gk.gkb_ab_hybrid_solve)):
+        eta = eta_proj(op, MODES[mode][0], e)
+        x = torch.zeros(geom.n, dtype=torch.float32, device=DEV)
+        plain = fp(ctx, geom, bd, x, K, x_true=xtd)
+        hyb = fh(ctx, geom, bd, x, K, x_true=xtd, rule=gk.GKB_LAMBDA_DP, tau_proj=1.0, eta_proj=eta)
+        torch.cuda.synchronize()
+        best = float(plain.rre.min())
+        note("paper shape %s: plain RRE min %.4f, at k=%d %.4f; hybrid-DP at k=%d %.4f" % (
+            mode, best, K, plain.rre[-1], K, hyb.rre[-1]))
+        assert plain.rre[-1] >= 1.5 * best
+        assert hyb.rre[-1] <= 1.1 * best
+        assert np.all(hyb.rre[20:] <= 1.1 * best)
