@@ -308,7 +308,10 @@ def learned_main(args):
     tg, eg = synth.par2d(256, 360), synth.par2d(512, 720)
     t0 = time.perf_counter()
     log("training set (%d samples)" % args.train_samples)
-    bd, xd, _ = learned.make_set(ctx, tg, range(4_000_000, 4_000_000 + args.train_samples), 0.01, 0.05, 4_000_000)
+    bd, xd, tn = learned.make_set(ctx, tg, range(4_000_000, 4_000_000 + args.train_samples), 0.01, 0.05, 4_000_000)
+    if args.targets == "gkb":
+        log("targets: plain BA-GKB discrepancy solutions")
+        xd = learned.gkb_targets(ctx, tg, bd, tn)
     if args.textures > 0:
         log("texture samples (%d)" % args.textures)
         bt, xt = learned.make_textures(ctx, tg, args.textures, 4_200_000, 0.01, 0.05)
@@ -345,12 +348,13 @@ def learned_main(args):
            "data": "synthetic: seeded ellipse phantoms, 1-5% Gaussian noise",
            "config": {"workload": "train 256^2/360 views/363 bins, %d samples, %d epochs, batch %d, lr %g; "
                                   "evaluate 16 slices 512^2/720 views/725 bins, DP tau=1, k_max 150; "
-                                  "%d random-texture samples; init %s + %g He noise; objective %s"
+                                  "%d random-texture samples; init %s + %g He noise; objective %s; targets %s"
                                   % (args.train_samples, args.epochs, args.batch, args.lr, args.textures, args.init,
-                                     args.init_noise, args.objective)},
+                                     args.init_noise, args.objective, args.targets)},
            "training": {"seconds_data": t_data, "seconds_train": t_train, "steps": steps,
                         "ms_per_step": 1e3 * t_train / max(steps, 1), "loss_per_epoch": losses},
            "plain": ev["plain"], "learned": ev["learned"],
+           "learned_over_plain_s_per_slice": ev["learned"]["s_per_slice"] / ev["plain"]["s_per_slice"],
            "ramlak_control": {"filter": evc["learned"], "speedup_s_per_slice": evc["speedup_s_per_slice"],
                               "plain": evc["plain"]},
            "learned_min_residual_over_e": [r["learned_free"]["min_res_over_e"] for r in ev["slices"]],
@@ -457,6 +461,8 @@ def main():
     ap.add_argument("--objective", choices=("fbp", "frozen"), default="frozen")
     ap.add_argument("--init-noise", type=float, default=0.1)
     ap.add_argument("--epochs", type=int, default=5)
+    ap.add_argument("--targets", choices=("truth", "gkb"), default="truth",
+                    help="training targets: the phantoms, or plain BA-GKB discrepancy solutions")
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-4)
     args = ap.parse_args()

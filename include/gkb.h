@@ -296,9 +296,12 @@ gkb_status gkb_set_batch_mode(gkb_ctx *ctx, int mode);
  * after layers 1-3; with the ReLU masks of b frozen, F is linear, F b = N(b),
  * and F^T is its exact transpose.  The discrepancy test stays on
  * ||A x - b||.  Set gkb_solve_opts.precond to a network to use it (GKB_F32,
- * gkb_ba_solve); if the learned solve does not reach the discrepancy level by
- * k_max, breaks down before iteration 3 or meets a non-finite value, the
- * plain BA-GKB result is returned with reason GKB_STOP_FALLBACK.
+ * gkb_ba_solve); if the learned solve does not reach the discrepancy level
+ * (by k_max; the attempt ends earlier once its residual, falling at its mean
+ * rate of the last five iterations, would still be above the level at
+ * k_max), breaks down before iteration 3 or meets a non-finite value, the
+ * plain BA-GKB result is returned with reason GKB_STOP_FALLBACK
+ * (info->seconds then covers both solves).
  *
  * Weights: FP32 master copy of 19008 values, W1 [32][1][9], W2 [32][32][9],
  * W3 [32][32][9], W4 [1][32][9] ([out][in][tap], concatenated); every layer

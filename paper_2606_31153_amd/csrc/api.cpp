@@ -1841,6 +1841,7 @@ gkb_status solve_impl(gkb_ctx *c, const gkb_geometry *geom, int dtype, const voi
   hdp[CD_USEDP] = o->use_dp ? 1.0 : 0.0;
   hdp[CD_KMAX] = o->k_max;
   hdp[CD_RNS] = o->rns_eps;
+  hdp[CD_REACH] = (o->precond && o->use_dp) ? 1.0 : 0.0;
   hdp[CD_HRULE] = hyb ? hy->lambda_rule : HY_FIXED;
   hdp[CD_HTARGET] = (hyb && hy->lambda_rule == GKB_LAMBDA_DP) ? hy->tau_proj * hy->eta_proj : 0.0;
   HIPC(hipMemcpyAsync(S.ctl.ip, hip_, sizeof hip_, hipMemcpyHostToDevice, st));
@@ -2183,7 +2184,11 @@ gkb_status solve_entry(gkb_ctx *c, const gkb_geometry *g, int dtype, const void 
     if (st != GKB_OK) return st;
     // learned solve; plain BA-GKB is the fallback when the learned one does
     // not reach the discrepancy level, breaks down early or meets a
-    // non-finite value
+    // non-finite value.  With the discrepancy principle on, the attempt also
+    // ends once its residual, at its mean decrease over the last five
+    // iterations, would still be above the level at k_max: a residual that
+    // levels off above the level then costs the iterations up to that point
+    // instead of k_max before the fallback.
     gkb_solve_info li{};
     st = solve_impl<float>(c, g, dtype, b, o, x, &li, mode);
     // with the discrepancy principle on, the learned solution is kept only if

@@ -44,6 +44,7 @@ enum CtlDbl : int {
   CD_HRULE = 15,   // hybrid solves: rule choosing lambda_k on C_k (1 discrepancy, 2 GCV)
   CD_HTARGET = 16, // hybrid discrepancy rule: tau * eta of the projected residual
   CD_FINALRES = 17,  // ||A x - b|| of a solution formed after the iteration (TSVD)
+  CD_REACH = 18,   // 1: stop once the residual cannot reach tau ||e|| by k_max at its recent rate
   CD_COUNT = 20
 };
 

@@ -573,6 +573,8 @@ __device__ inline void finish_solve(const Ctl &ctl, int k) {
   }
 }
 
+constexpr int kReachWindow = 5;
+
 // ---- the discrepancy residual rho_k = ||r_k|| (kept by the recurrences above)
 // and the stopping decision of iteration k (thread 0 of a finalising kernel) ----
 __device__ inline void stop_test(const Ctl &ctl, double rho) {
@@ -589,6 +591,10 @@ __device__ inline void stop_test(const Ctl &ctl, double rho) {
     reason = 1;  // GKB_STOP_DP
   else if (dp[CD_RNS] > 0.0 && k >= 2 && fabs(ctl.rho[k - 1] - rho) < dp[CD_RNS] * ctl.rho[k - 1])
     reason = 6;  // GKB_STOP_RNS (eq. RNS): the relative change of the residual norm fell below the tolerance
+  else if (dp[CD_REACH] != 0.0 && k > kReachWindow &&
+           !(fma((ctl.rho[k - kReachWindow] - rho) / kReachWindow, (double)(ctl.K - k), dp[CD_TAUE]) >= rho))
+    reason = 6;  // out of reach: at the mean decrease of the last kReachWindow iterations the residual
+                 // would still be above tau ||e|| at k_max (a stop for the learned attempt)
   else if (!(tk1 > eta))
     reason = 3;  // GKB_STOP_BREAKDOWN
   else if (k >= ctl.K)

@@ -63,6 +63,24 @@ def make_set(ctx, geom, seeds, nu_lo: float, nu_hi: float, key: int, workers: in
     return bd, xd, e.double().norm(dim=1).cpu().numpy()
 
 
+def gkb_targets(ctx, geom, bd, enorms, k_max: int = 150):
+    """Training targets from plain BA-GKB: the discrepancy-principle solution
+    (tau = 1, the sample's own ||e_i||) of every sample, [N, n] FP32 on the
+    device (the smallest-residual iterate where the level is not reached)."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    N = bd.shape[0]
+    out = torch.empty(N, geom.n, dtype=torch.float32, device=bd.device)
+    for i in range(N):
+        r = gk.gkb_ba_solve(ctx, geom, bd[i], out[i], k_max, use_dp=True, tau=1.0, noise_norm=float(enorms[i]))
+        if r.reason != gk.STOP_DP and r.rho.size:
+            kb = int(np.argmin(r.rho)) + 1
+            gk.gkb_ba_solve(ctx, geom, bd[i], out[i], kb)
+    torch.cuda.synchronize()
+    return out
+
+
 def ramlak(K: int = 9) -> np.ndarray:
     """The Ram-Lak (ramp) filter of filtered back projection for unit bin
     pitch, truncated to K taps: h(0) = 1/4, h(k) = -1/(pi k)^2 for odd k,

@@ -236,6 +236,44 @@ def test_learned_stop_above_the_discrepancy_level_falls_back(ctx):
     net.close()
 
 
+def test_failing_learned_attempt_ends_at_stagnation(ctx):
+    # With the discrepancy principle on, a learned attempt whose residual
+    # levels off above the level ends at the first k > 5 at which the mean
+    # decrease of the last five iterations, continued to k_max, would leave
+    # it above tau ||e||, instead of running to k_max; the plain result is
+    # returned (reason FALLBACK).  tau = 0.5 is out of reach (the residual of
+    # this overdetermined problem stays above about sqrt((m - n) / m) ||e||).
+    geom = synth.par2d(48, 60)
+    net = gk.Net(ctx, seed=7)  # He-initialised random network
+    op = oracle.Operator(geom)
+    x = synth.rasterize_ellipses(synth.ellipse_params(962), geom.nx, geom.ny)
+    b, en = synth.add_noise(op.A(x).reshape(-1), synth.noise_direction(geom.m, 962), 0.02)
+    bd = dev32(b)
+    K = 150
+    x1 = torch.zeros(geom.n, dtype=torch.float32, device=DEV)
+    x2 = torch.zeros(geom.n, dtype=torch.float32, device=DEV)
+    free = gk.gkb_ba_solve(ctx, geom, bd, x2, K, precond=net)
+    rho, level, W = free.rho, 0.5 * en, 5
+    k_stall = next(k for k in range(W + 1, K + 1)
+                   if not (rho[k - 1 - W] - rho[k - 1]) / W * (K - k) + level >= rho[k - 1])
+    kw = dict(use_dp=True, tau=0.5, noise_norm=en)
+    r1 = gk.gkb_ba_solve(ctx, geom, bd, x1, K, **kw)
+    ctx.trace_reset()
+    ctx.trace_enable(True)
+    r2 = gk.gkb_ba_solve(ctx, geom, bd, x2, K, precond=net, **kw)
+    torch.cuda.synchronize()
+    ctx.trace_enable(False)
+    n_ft, _ = ctx.trace_get("filter_t")
+    note("learned stall: k_stall %d of %d, F^T launches %d" % (k_stall, K, n_ft))
+    assert k_stall < K // 2
+    # one F^T per iteration and one at start-up; up to four iterations are
+    # queued before the host sees the stop
+    assert k_stall + 1 <= n_ft <= k_stall + 5
+    assert r2.reason == gk.STOP_FALLBACK and r2.k_stop == r1.k_stop
+    assert torch.equal(x1, x2)
+    net.close()
+
+
 LEARNED_GEOMS = {
     "par": synth.par2d(20, 16, 29),
     "fan": synth.fan2d(20, 18, 40),
