@@ -21,6 +21,7 @@ and once as one batched call, after an untimed pass of each that builds the
 geometry tables.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+                  [--only-headline | --only-batch | --cone | --learned]
 """
 from __future__ import annotations
 
@@ -48,8 +49,8 @@ OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each
 # scaled by the plain-copy calibration), profiles/fan512_gkb_hbm_traffic.txt.
 # An entry must be removed when its kernel changes.
-MEASURED_TRAFFIC = {"fwd": (14860.3 * 1.9910 + 8750.9) * 1024.0, "back": (8316.0 * 1.9910 + 2952.5) * 1024.0,
-                    "fwd_adj": (22176.4 * 1.9910 + 2062.7) * 1024.0, "back_adj": (21653.9 * 1.9910 + 5939.8) * 1024.0}
+MEASURED_TRAFFIC = {"fwd": (14858.4 * 1.9904 + 8750.7) * 1024.0, "back": (8322.9 * 1.9904 + 2952.3) * 1024.0,
+                    "fwd_adj": (22217.7 * 1.9904 + 2062.4) * 1024.0, "back_adj": (21656.5 * 1.9904 + 5938.4) * 1024.0}
 
 
 def joseph_crossings(geom) -> int:
@@ -452,6 +453,9 @@ def main():
     ap.add_argument("--cpu-runs", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the timed fan-beam steps and kernel table only (for profiling its kernels)")
+    ap.add_argument("--only-batch", action="store_true", help="the 64-slice batched workload only (profiling)")
     ap.add_argument("--cone", action="store_true", help="measure the 512^3 cone-beam workload instead")
     ap.add_argument("--cone-iters", type=int, default=60)
     ap.add_argument("--learned", action="store_true", help="train and evaluate the learned filter instead")
@@ -475,6 +479,15 @@ def main():
         return
     if args.learned:
         learned_main(args)
+        return
+    if args.only_batch:  # the batched workload alone (profiling)
+        import paper_2606_31153_amd as gk
+        ctx = gk.Context(0)
+        res = batch_bench(ctx)
+        ctx.close()
+        print(json.dumps({"metric": "s/slice to discrepancy, 64-slice batched workload",
+                          "value": res["s_per_slice_batched"], "unit": "s/slice", "higher_is_better": False,
+                          "n_gpus": 1, "s_per_slice_to_discrepancy": res}))
         return
 
     import torch
@@ -580,6 +593,10 @@ def main():
         "kernels": kernels,
         "kernels_source": "one untimed step with every kernel bracketed by HIP events",
     }
+    if args.only_headline:  # profiling the headline kernels alone
+        ctx.close()
+        print(json.dumps(out))
+        return
     print("bench: parallel-beam 512 point", file=sys.stderr, flush=True)
     out["par512"] = par512_point(ctx, args.iters)
     print("bench: GMRES on the benchmark workload", file=sys.stderr, flush=True)
