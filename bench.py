@@ -376,8 +376,16 @@ def cpu_baseline(geom, b_host: np.ndarray, enorm: float, iters: int, runs: int):
         t0 = time.perf_counter()
         res = oracle.gkb(op, oracle.MODE_BA, b_host, iters)
         rates.append(res.k_stop / (time.perf_counter() - t0))
-    return {"value": float(np.mean(rates)), "unit": "GKB iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # the same problem on one thread: 2 iterations
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    res1 = oracle.gkb(op, oracle.MODE_BA, b_host, 2)
+    one = res1.k_stop / (time.perf_counter() - t0)
+    oracle.set_threads(cores)
+    return {"value": float(np.mean(rates)), "unit": "GKB iters/s", "cores": cores, "kind": "oracle",
             "median": float(np.median(rates)), "runs": runs,
+            "single_thread": {"value": one, "iterations": 2},
             "sample": "FP64 CPU oracle (OpenMP, all host threads), BA-GKB, %d runs of %d iterations of the same "
                       "fan-beam 512^2/720/1024 problem, each iteration with its residual ||A x_k - b|| evaluated "
                       "literally (one more A and a Q u product); value = mean and median over the runs of "
