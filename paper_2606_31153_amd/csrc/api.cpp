@@ -684,6 +684,7 @@ struct gkb_ctx {
   DevBuf Q, yk, rdbl, s, w, tmp_n, tmp_m, ctl_d, ctl_i;
   DevBuf gm_y, gm_h;  // GMRES and hybrid GKB: the A-images Y; GMRES: the Hessenberg columns
   DevBuf hy_w;        // enlarged-subspace TSVD: Jacobi workspace (W, V)
+  DevBuf gram;        // Gram matrix of the Krylov basis (delayed second Gram-Schmidt round)
   int *host_flag = nullptr;      // host-mapped
   int *host_flag_dev = nullptr;  // its device address
   // batched solves: vectors, control blocks, slice descriptors, launch maps
@@ -1417,12 +1418,12 @@ struct Solver {
     const size_t nd = CD_COUNT + 11 * (size_t)(K + 2);
     HIPC(c->ctl_d.ensure(sizeof(double) * nd));
     HIPC(c->ctl_i.ensure(sizeof(int) * CI_COUNT));
+    HIPC(c->gram.ensure(sizeof(double) * (size_t)(K + 1) * (size_t)(K + 1)));
     const long long vb = std::max<long long>(
         {(long long)vec_blocks(dimq), (long long)vec_blocks(m), (long long)vec_blocks(dims)});
     const long long pb = std::max<long long>(
-        {(long long)ray_blocks(g), (long long)bt_blocks(g), (long long)pixel_blocks(g), vb * (K + 2),
-         (long long)upd_blocks(dimq),
-         (long long)mid_blocks(dimq) * (K + 2)});
+        {(long long)ray_blocks(g), (long long)bt_blocks(g), (long long)pixel_blocks(g), 2 * vb * (K + 2),
+         (long long)upd_blocks(dimq)});
     gkb_status stt = ensure_scratch(c, g, sizeof(T), pb);
     if (stt != GKB_OK) return stt;
     if (!c->host_flag) {
@@ -1450,6 +1451,7 @@ struct Solver {
     }
     ctl.aw = c->rdbl.as<double>();
     ctl.r = ctl.aw + (m + 3) / 4 * 4;  // 32-byte aligned quads
+    ctl.gram = c->gram.as<double>();
     ctl.K = K;
     ctl.host_stop = c->host_flag_dev;
     partials = c->partials.as<double>();
@@ -1656,14 +1658,12 @@ struct Solver {
   // k: the iteration (the columns q_1..q_k of Q)
   void reorth_and_normalize_impl(bool reorth, int k) {
     TraceScope ts(c, "reorth");
+    (void)k;
     if (reorth) {
-      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
-      if (K <= mid_max_k(sizeof(T))) {
-        launch_cgs_mid<T>(ctl, Q, ldq, w, dimq, partials, k, st);
-      } else {
-        launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, st);
-        launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
-      }
+      // two classical rounds, the second from the Gram matrix (one read of Q
+      // for the inner products, one for the update)
+      launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+      launch_dcgs_coef(ctl, st);
       launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
     } else {
       // no reorthogonalisation: only the norm alpha_{k+1} = ||w|| (no columns)
@@ -1742,15 +1742,10 @@ struct Solver {
   // summed into column k of H; h_{k+1,k} = ||w|| into alpha[k+1]; q_{k+1}
   void gm_orthogonalise(int k) {
     TraceScope ts(c, "reorth");
-    launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
-    launch_gm_hcol(ctl, 1, st);
-    if (K <= mid_max_k(sizeof(T))) {
-      launch_cgs_mid<T>(ctl, Q, ldq, w, dimq, partials, k, st);
-    } else {
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 0, partials, st);
-      launch_cgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
-    }
-    launch_gm_hcol(ctl, 0, st);
+    (void)k;
+    launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+    launch_dcgs_coef(ctl, st);
+    launch_gm_hcol(ctl, 1, st);  // h_{1..k,k}: both rounds' coefficients
     launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
     normalize();
   }
@@ -2230,7 +2225,7 @@ struct SliceHost {
   size_t oQ, oyk, os, ow, otn, otm, oxp, oyp;
   // element offsets into the double workspace (control arrays, residual
   // vectors Aw and r, partials)
-  size_t oarr, ores, opart;
+  size_t oarr, ores, opart, ogram;
 };
 
 // Launch map of the slices in `active` (slice ids): the active list followed
@@ -2274,8 +2269,6 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
   bl.nc_bt = 2;
   bl.nc_at = 2;
   bl.kmax = 1;
-  bl.mid_kmax = -1;
-  bl.any_plain = 0;
   size_t bytesT = 0, ndbl = (size_t)ns * CD_COUNT;
   double best_pv = 0.0;
   for (int s = 0; s < ns; ++s) {
@@ -2307,12 +2300,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     h.cnt[BF_PIX] = pixel_blocks(g);
     h.cnt[BF_VQ] = vec_blocks(h.dimq);
     h.cnt[BF_VQU] = upd_blocks(h.dimq);
-    const bool mid = h.K <= mid_max_k(sizeof(T));
-    h.cnt[BF_VQM] = mid ? mid_blocks(h.dimq) : 0;
-    if (mid)
-      bl.mid_kmax = std::max(bl.mid_kmax, h.K);
-    else
-      bl.any_plain = 1;
+    h.cnt[BF_VQD] = dots_blocks(h.dimq);
     h.cnt[BF_VM] = vec_blocks(g.m);
     h.cnt[BF_PADR] = (int)std::min<long long>(((long long)g.ny * g.ldR + 255) / 256, 2048);
     h.cnt[BF_PADC] = d->has_coldom ? ((g.ldT + 31) / 32) * ((g.nx + 31) / 32) : 0;
@@ -2335,10 +2323,13 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     ndbl = (ndbl + 31) / 32 * 32;
     h.ores = ndbl;
     ndbl += 2 * (size_t)((g.m + 3) / 4 * 4);
+    h.ogram = ndbl;
+    ndbl += (size_t)(h.K + 1) * (size_t)(h.K + 1);
+    ndbl = (ndbl + 31) / 32 * 32;
     h.opart = ndbl;
     ndbl += (size_t)std::max<long long>(
-        {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_RAYBT], (long long)h.cnt[BF_PIX], (long long)h.cnt[BF_VQ] * (h.K + 2),
-         (long long)h.cnt[BF_VQU], (long long)h.cnt[BF_VQM] * (h.K + 2),
+        {(long long)h.cnt[BF_RAY], (long long)h.cnt[BF_RAYBT], (long long)h.cnt[BF_PIX], 2LL * h.cnt[BF_VQD] * (h.K + 2),
+         (long long)h.cnt[BF_VQU],
          (long long)h.cnt[BF_VM] * (h.K + 2), 1024LL});
     ndbl = (ndbl + 31) / 32 * 32;
   }
@@ -2390,6 +2381,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     }
     ctl.rre = nullptr;  // no reconstruction-error histories in batched solves
     ctl.lamh = nullptr;
+    ctl.gram = wsD + h.ogram;
     ctl.aw = wsD + h.ores;
     ctl.r = ctl.aw + (h.m + 3) / 4 * 4;
     ctl.K = h.K;
@@ -2531,8 +2523,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
       apply_Mt(false);
       {
         TraceScope ts(c, "reorth");
-        launch_b_cgs_dots<T>(bd, bl, st);
-        launch_b_cgs_second<T>(bd, bl, k, st);
+        launch_b_dcgs<T>(bd, bl, st);
         launch_b_cgs_update<T>(bd, bl, 1, st);
         launch_b_normalize<T>(bd, bl, st);
       }
@@ -2556,7 +2547,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     };
     for (int k = 1; k <= bl.kmax; ++k) {
       if (c->batch_graph) {
-        const int key = set_version * 8 + (mid_unroll_bucket(k));
+        const int key = set_version;
         if (!gexec || key != graph_key) {
           release_graph();
           if (!c->cap_stream) HIPC(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));

@@ -73,6 +73,10 @@ struct Ctl {
   // rotated right-hand side in Rphi[1..k+1].  Null for GKB.
   double *hm;
   long long ldh;
+  // Gram matrix of the stored basis, G = Q^T Q ((K+1) x (K+1), FP64, row-major,
+  // ld K + 1): row k-1 is completed at iteration k by the delayed second
+  // Gram-Schmidt round (null where the classical two-round form runs)
+  double *gram;
 };
 
 // A vector selected by the device-side iteration counter:
@@ -276,7 +280,7 @@ enum BlockFam : int {
   BF_PADC,     // column-major image padding (32x32 tiles)
   BF_PADS,     // sinogram padding
   BF_VQU,      // CGS update over Q's dimension (upd_blocks)
-  BF_VQM,      // fused CGS2 middle over Q's dimension (mid_blocks; slices with k_max <= mid_max_k)
+  BF_VQD,      // inner products of the delayed CGS round over Q's dimension (dots_blocks)
   BF_RAYBT,    // B^T: bt_blocks
   BF_COUNT
 };
@@ -295,8 +299,6 @@ struct BatchLaunch {
   int na;
   int tot[BF_COUNT];
   int kmax;      // largest k_max over the slices
-  int mid_kmax;  // largest k_max over the slices that take the fused CGS2 middle (-1: none)
-  int any_plain; // some slice's k_max exceeds mid_max_k (separate update and inner products)
   int fan;       // all slices fan beam (else all parallel beam)
   int nc_bt, nc_at;
   int at_vu, b_vu;  // views per step of A^T and B: the tuned choices of the slice with the most pixel-views
@@ -362,28 +364,17 @@ int cone_voxel_blocks(const GeomDev &g);
 // ---- Krylov vector kernels (krylov.hip) ----
 int vec_blocks(long long dim);
 int upd_blocks(long long dim);  // workgroups of the CGS update
-// Fused middle of CGS2 (w -= Q c, then the inner products of the new w with
-// the same columns, from one read of Q): a workgroup takes kMidSub sub-blocks
-// of 64 rows and holds a sub-block's columns in LDS (kMidLd entries each,
-// within kMidLdsBytes).  Solves whose k_max exceeds mid_max_k use the separate
-// update and inner-product kernels.
-constexpr int kMidSub = 8, kMidLd = 65, kMidLdsBytes = 58 * 1024;  // + 4.5 KB static LDS
-__host__ __device__ constexpr int mid_max_k(int elem) {
-  return (kMidLdsBytes / (kMidLd * elem) < kBlock ? kMidLdsBytes / (kMidLd * elem) : kBlock) - 1;
-}
-int mid_blocks(long long dim);
-// the fused CGS2 middle's register unroll at iteration k (a launch-time choice)
-int mid_unroll_bucket(int k);
-template <typename T>
-void launch_cgs_mid(Ctl ctl, const T *Q, long long ld, T *w, long long dim, double *partials, int k,
-                    hipStream_t s);  // k: the iteration (columns 0..k-1)
+int dots_blocks(long long dim);  // row blocks of the delayed CGS inner products
 template <typename T>
 void launch_copy(const T *src, T *dst, long long n, hipStream_t s);
 template <typename T>
 void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *partials, hipStream_t s);
+// delayed two-round Gram-Schmidt: one read of Q gives c1 = Q^T w and the
+// Gram row of the newest column q_k; then c = c1 + (c1 - G c1) in ctl.c, for
+// launch_cgs_update (partials: 2 (K+2) doubles per row block)
 template <typename T>
-void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
-                     hipStream_t s);
+void launch_dcgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials, hipStream_t s);
+void launch_dcgs_coef(Ctl ctl, hipStream_t s);
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        hipStream_t s, int reorth = 1);
@@ -490,13 +481,9 @@ void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int
 template <typename T>
 void launch_b_norm_finalize(const BatchDev<T> &bd, const BatchLaunch &bl, int fam, int which, hipStream_t s);
 template <typename T>
-void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
+void launch_b_dcgs(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s);
-// second CGS2 round up to its coefficients: the fused middle for slices with
-// k_max <= mid_max_k, update + inner products for the others
-template <typename T>
-void launch_b_cgs_second(const BatchDev<T> &bd, const BatchLaunch &bl, int k, hipStream_t s);
 template <typename T>
 void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s);
 template <typename T>

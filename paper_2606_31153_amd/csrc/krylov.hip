@@ -40,31 +40,6 @@ constexpr int CH = 4;   // columns per workgroup in the multi-dot kernels
 constexpr int UCH = 16; // columns per unrolled step of the update loops
 constexpr int RPT = 4;  // rows per thread (one 4-wide vector load)
 constexpr int ROWS_PER_BLOCK = kBlock * RPT;
-// fused CGS2 middle (cgs_mid_body): rows per sub-block (one per lane), LDS
-// column stride (odd, so that the threads of the inner products, one column
-// each, read distinct banks)
-constexpr int MID_ROWS = 64, MID_LD = kMidLd, MID_SUB = kMidSub;
-static_assert(MID_LD == MID_ROWS + 1, "odd column stride");
-
-// Sum CH values over the block; results valid in threads 0..CH-1 (value j in thread j).
-__device__ inline double block_sum_vec(double (&v)[CH], double *lds /* [4][CH] */) {
-#pragma unroll
-  for (int j = 0; j < CH; ++j) v[j] = wave_sum(v[j]);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-#pragma unroll
-    for (int j = 0; j < CH; ++j) lds[wid * CH + j] = v[j];
-  }
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x < CH) {
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) r += lds[w * CH + threadIdx.x];
-  }
-  return r;
-}
-
 // Rows r..r+3 of a column (zeros past dim).  Columns are stored with a
 // leading dimension that is a multiple of 4, so full quads are aligned.
 template <typename T>
@@ -99,66 +74,141 @@ __device__ inline void store_quad(T *__restrict__ p, long long r, long long dim,
   }
 }
 
-// ---- partial inner products: workgroup (x, y) covers rows [x*1024, x*1024+1024)
-// and columns [CH y, CH y + CH) of Q (columns 0..ncol-1), against w.
-// Result: partials[x * ldp + column].
+// ---- delayed second round of classical Gram-Schmidt ---------------------------
+// The second round's coefficients are Q^T (w - Q c1) = c1 - G c1, with G = Q^T Q
+// the Gram matrix of the stored (rounded) basis, so that round needs no second
+// read of Q: one pass forms c1 = Q^T w together with the Gram row of the newest
+// column, Q^T q_k, and one pass subtracts Q (c1 + c2).  In exact arithmetic
+// G = I and c2 = 0; with rounding, c2 = (I - G) c1 removes what the stored
+// basis has lost of its orthogonality, as the second classical round does.
+// Partials: row block bx at bx * 2 (K+2): c1 terms at column j, Gram terms at
+// K + 2 + j.
+template <int N>
+__device__ inline double block_sum_vec_n(double (&v)[N], double *lds /* [4][N] */) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) lds[wid * N + j] = v[j];
+  }
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x < N) {
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) r += lds[w * N + threadIdx.x];
+  }
+  return r;
+}
+
+// A workgroup takes CH2 columns over kDotsQuads x 1024 rows: the block sums,
+// whose cost does not depend on the rows, are spread over four times the rows
+// of the other vector kernels.
+constexpr int CH2 = 4, kDotsQuads = 4;
 template <typename T>
-__device__ inline void dots_body(const Ctl &ctl, const T *__restrict__ V, long long ld, const T *__restrict__ w,
-                                 long long dim, double *partials, unsigned bx, unsigned by, int ncol) {
+__device__ inline void dots2_body(const Ctl &ctl, const T *__restrict__ V, long long ld, const T *__restrict__ w,
+                                  long long dim, double *partials, unsigned bx, unsigned by, int ncol) {
+  constexpr int CH = CH2;
   const int c0 = by * CH;
   if (c0 >= ncol) return;
-  __shared__ double lds[(kBlock / 64) * CH];
-  const T *__restrict__ wv = w;
-  const long long r = ((long long)bx * kBlock + threadIdx.x) * RPT;
-  double wq[RPT];
-  load_quad(wv, r, dim, wq);
-  double acc[CH];
+  __shared__ double lds[(kBlock / 64) * 2 * CH];
+  double acc[2 * CH];
 #pragma unroll
-  for (int j = 0; j < CH; ++j) {
-    acc[j] = 0.0;
-    if (c0 + j < ncol) {
-      double q[RPT];
-      load_quad(V + (long long)(c0 + j) * ld, r, dim, q);
+  for (int j = 0; j < 2 * CH; ++j) acc[j] = 0.0;
+  const T *__restrict__ qk = V + (long long)(ncol - 1) * ld;  // q_k, the newest column
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) acc[j] = fma(q[i], wq[i], acc[j]);
+  for (int qd = 0; qd < kDotsQuads; ++qd) {
+    const long long r = (((long long)bx * kDotsQuads + qd) * kBlock + threadIdx.x) * RPT;
+    if (r >= dim) break;
+    double wq[RPT], nq[RPT];
+    load_quad(w, r, dim, wq);
+    load_quad(qk, r, dim, nq);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      if (c0 + j < ncol) {
+        double q[RPT];
+        load_quad(V + (long long)(c0 + j) * ld, r, dim, q);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          acc[j] = fma(q[i], wq[i], acc[j]);
+          acc[CH + j] = fma(q[i], nq[i], acc[CH + j]);
+        }
+      }
     }
   }
-  const double sum = block_sum_vec(acc, lds);
-  if (threadIdx.x < CH && c0 + (int)threadIdx.x < ncol)
-    partials[(long long)bx * (ctl.K + 2) + c0 + threadIdx.x] = sum;
+  const double sum = block_sum_vec_n<2 * CH>(acc, lds);
+  const int t = threadIdx.x;
+  const long long ldp = ctl.K + 2;
+  if (t < 2 * CH) {
+    const int j = t < CH ? t : t - CH;
+    if (c0 + j < ncol) partials[(long long)bx * 2 * ldp + (t < CH ? 0 : ldp) + c0 + j] = sum;
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dots(Ctl ctl, const T *__restrict__ V, long long ld,
-                                                 const T *__restrict__ w, long long dim, double *partials) {
+__global__ __launch_bounds__(kBlock) void k_dots2(Ctl ctl, const T *__restrict__ V, long long ld,
+                                                  const T *__restrict__ w, long long dim, double *partials) {
   if (ctl.ip[CI_STOP]) return;
-  dots_body(ctl, V, ld, w, dim, partials, blockIdx.x, blockIdx.y, ctl.ip[CI_K]);
+  dots2_body(ctl, V, ld, w, dim, partials, blockIdx.x, blockIdx.y, ctl.ip[CI_K]);
 }
 
-// ---- column sums of the per-workgroup partials: c[col] (col < ncol), one
-// workgroup per column ----
-__device__ inline void reduce_cols_body(const Ctl &ctl, const double *__restrict__ partials, int nb, int col,
-                                        int ncol) {
+// column sums of the two partial sets; workgroup col < K + 1 sums c1[col],
+// col - (K + 1) the Gram entry (q_col, q_k), which fills row and column k - 1
+// of G
+__device__ inline void reduce_cols2_body(const Ctl &ctl, const double *__restrict__ partials, int nb, int col,
+                                         int ncol) {
   __shared__ double lds[kBlock / 64];
-  if (col >= ncol) return;
-  const int ldp = ctl.K + 2;
-  // four independent sums keep four strided loads in flight per thread
+  const int set = col > ctl.K ? 1 : 0;
+  const int j = col - set * (ctl.K + 1);
+  if (j >= ncol) return;
+  const long long ldp = ctl.K + 2, st = 2 * ldp, off = set * ldp + j;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int b = threadIdx.x;
   for (; b + 3 * kBlock < nb; b += 4 * kBlock) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] += partials[(long long)(b + u * kBlock) * ldp + col];
+    for (int u = 0; u < 4; ++u) acc[u] += partials[(long long)(b + u * kBlock) * st + off];
   }
-  if (b < nb) acc[0] += partials[(long long)b * ldp + col];
-  if (b + kBlock < nb) acc[1] += partials[(long long)(b + kBlock) * ldp + col];
-  if (b + 2 * kBlock < nb) acc[2] += partials[(long long)(b + 2 * kBlock) * ldp + col];
+  if (b < nb) acc[0] += partials[(long long)b * st + off];
+  if (b + kBlock < nb) acc[1] += partials[(long long)(b + kBlock) * st + off];
+  if (b + 2 * kBlock < nb) acc[2] += partials[(long long)(b + 2 * kBlock) * st + off];
   const double tot = block_sum<kBlock>((acc[0] + acc[1]) + (acc[2] + acc[3]), lds);
-  if (threadIdx.x == 0) ctl.c[col] = tot;
+  if (threadIdx.x == 0) {
+    if (set == 0) {
+      ctl.c[j] = tot;
+    } else {
+      const long long ldg = ctl.K + 1, kk = ncol - 1;
+      ctl.gram[kk * ldg + j] = tot;
+      ctl.gram[(long long)j * ldg + kk] = tot;
+    }
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_cols(Ctl ctl, const double *__restrict__ partials, int nb) {
+__global__ __launch_bounds__(kBlock) void k_reduce_cols2(Ctl ctl, const double *__restrict__ partials, int nb) {
   if (ctl.ip[CI_STOP]) return;
-  reduce_cols_body(ctl, partials, nb, blockIdx.x, ctl.ip[CI_K]);
+  reduce_cols2_body(ctl, partials, nb, blockIdx.x, ctl.ip[CI_K]);
+}
+
+// c = c1 + (c1 - G c1) over the k columns, in one workgroup (c1 is staged in
+// LDS before any c_i is written; each row's product is summed in column order)
+constexpr int kCoefMaxLds = 4096;
+__device__ inline void dcgs_coef_body(const Ctl &ctl, int k) {
+  __shared__ double s_c1[kCoefMaxLds];
+  for (int j = threadIdx.x; j < k; j += kBlock) s_c1[j] = ctl.c[j];
+  __syncthreads();
+  // G is symmetric: thread i walks column i, so that the lanes of a
+  // wavefront read neighbouring entries of one row at each step
+  const long long ldg = ctl.K + 1;
+  for (int i = threadIdx.x; i < k; i += kBlock) {
+    double t = 0.0;
+    for (int j = 0; j < k; ++j) t = fma(ctl.gram[(long long)j * ldg + i], s_c1[j], t);
+    ctl.c[i] = s_c1[i] + (s_c1[i] - t);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dcgs_coef(Ctl ctl) {
+  if (ctl.ip[CI_STOP]) return;
+  dcgs_coef_body(ctl, ctl.ip[CI_K]);
 }
 
 // Wavefronts that share the rows of a CGS update workgroup (and split its
@@ -274,142 +324,6 @@ __device__ __attribute__((always_inline)) inline void cgs_update_body(const Ctl 
     cgs_update_split(ctl, Q, ld, w, dim, last, partials, b, ncols);
   else
     cgs_update_rows(ctl, Q, ld, w, dim, last, partials, b, ncols);
-}
-
-// ---- the middle of CGS2 from one read of Q: w -= Q[:, 0..ncols-1] c with the
-// first round's coefficients c, then the partial inner products of the new w
-// with the same columns (the second round's c).  A workgroup takes MID_SUB
-// consecutive sub-blocks of 64 rows.  Per sub-block, wavefront v loads the
-// columns v, v + 4, ... (one row per lane) into LDS, accumulating its share
-// of Q c on the way; w and the four shares are added in a fixed order, the
-// new rows of w are stored, and the threads of column j sum it against them
-// from LDS.  With ncols <= 4 U every wavefront holds its columns of a sub-block in
-// registers, and the loads of the next sub-block are issued before this one
-// is used, so that they are in flight during the LDS work; otherwise the
-// columns are loaded U at a time.  The workgroup writes one partial per
-// column: partials[blk * (K + 2) + j].  qs (dynamic LDS) holds cap columns of
-// MID_LD entries; ncols <= cap <= kBlock.
-template <typename T, int U>
-__device__ __attribute__((always_inline)) inline void cgs_mid_body(const Ctl &ctl, const T *__restrict__ Q,
-                                                                   long long ld, T *__restrict__ w, long long dim,
-                                                                   double *__restrict__ partials, unsigned blk,
-                                                                   int ncols, T *__restrict__ qs) {
-  constexpr int NW = kBlock / 64;
-  __shared__ double part[NW][MID_ROWS];
-  __shared__ double wsh[MID_ROWS];
-  __shared__ double csh[kBlock];
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if ((int)threadIdx.x < ncols) csh[threadIdx.x] = ctl.c[threadIdx.x];
-  // inner products: tpc threads per column (a power of two: all threads busy
-  // when the columns are few), each over 64 / tpc rows of a sub-block
-  const int tpc = ncols <= NW * U ? kBlock / (NW * U) : 1;
-  const int jd = threadIdx.x / tpc, part_id = threadIdx.x % tpc, nr = MID_ROWS / tpc;
-  // this lane's row in sub-block sb; a row past dim loads from row 0 and counts as 0
-  auto row = [&](int sb) { return ((long long)blk * MID_SUB + sb) * MID_ROWS + lane; };
-  // add the four shares and w, store the new rows of w, then the inner products
-  double dacc = 0.0;
-  auto finish = [&](long long r, T w0, double acc) {
-    const bool in = r < dim;
-    part[wid][lane] = acc;
-    __syncthreads();
-    if (wid == 0) {
-      double v = (in ? (double)w0 : 0.0) + part[0][lane];
-#pragma unroll
-      for (int u = 1; u < NW; ++u) v += part[u][lane];
-      const T out = (T)v;
-      if (in) w[r] = out;
-      wsh[lane] = in ? (double)out : 0.0;
-    }
-    __syncthreads();
-    if (jd < ncols) {
-      const T *__restrict__ col = qs + jd * MID_LD + part_id * nr;
-      const double *__restrict__ ws = wsh + part_id * nr;
-#pragma unroll 4
-      for (int i = 0; i < nr; ++i) dacc = fma((double)col[i], ws[i], dacc);
-    }
-    __syncthreads();  // qs, part and wsh are reused by the next sub-block
-  };
-  __syncthreads();  // csh
-  if (ncols <= NW * U) {
-    T qn[U] = {}, wn = T(0);
-    auto issue = [&](int sb) {
-      const long long r = row(sb);
-      const long long rc = r < dim ? r : 0LL;
-      wn = w[rc];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j = min(wid + NW * u, ncols - 1);
-        qn[u] = Q[(long long)j * ld + rc];
-      }
-    };
-    if (ncols > 0) issue(0);
-#pragma unroll
-    for (int sb = 0; sb < MID_SUB; ++sb) {
-      const long long r = row(sb);
-      const bool in = r < dim;
-      T q[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) q[u] = qn[u];
-      T w0 = ncols > 0 ? wn : (in ? w[r] : T(0));
-      if (sb + 1 < MID_SUB && ncols > 0) issue(sb + 1);
-      double acc = 0.0;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j = wid + NW * u;
-        if (j < ncols) {
-          const T qv = in ? q[u] : T(0);
-          qs[j * MID_LD + lane] = qv;
-          acc = fma(-csh[j], (double)qv, acc);
-        }
-      }
-      finish(r, w0, acc);
-    }
-  } else {
-    for (int sb = 0; sb < MID_SUB; ++sb) {
-      const long long r = row(sb);
-      const bool in = r < dim;
-      const T w0 = w[in ? r : 0LL];
-      double acc = 0.0;
-      const T *__restrict__ qr = Q + (in ? r : 0LL);
-      for (int j0 = wid; j0 < ncols; j0 += NW * U) {
-        T q[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int j = min(j0 + NW * u, ncols - 1);
-          q[u] = qr[(long long)j * ld];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int j = j0 + NW * u;
-          if (j < ncols) {
-            const T qv = in ? q[u] : T(0);
-            qs[j * MID_LD + lane] = qv;
-            acc = fma(-csh[j], (double)qv, acc);
-          }
-        }
-      }
-      finish(r, w0, acc);
-    }
-  }
-  // the tpc parts of a column (adjacent lanes) meet in a fixed-order butterfly
-  for (int o = 1; o < tpc; o <<= 1) dacc += __shfl_xor(dacc, o);
-  if (jd < ncols && part_id == 0) partials[(long long)blk * (ctl.K + 2) + jd] = dacc;
-}
-
-// columns per wavefront held in registers by the fused CGS2 middle at
-// iteration k (k columns, four wavefronts).  Past 128 columns the loads go 32
-// at a time without the prefetch: 64 columns per wavefront in registers spill
-// and were slower.
-inline int mid_unroll(int k) { return k <= 16 ? 4 : k <= 32 ? 8 : k <= 64 ? 16 : 32; }
-
-template <typename T, int U>
-__global__ __launch_bounds__(kBlock) void k_cgs_mid(Ctl ctl, const T *__restrict__ Q, long long ld,
-                                                    T *__restrict__ w, long long dim, double *partials, int cap) {
-  if (ctl.ip[CI_STOP]) return;
-  extern __shared__ __align__(16) unsigned char mid_lds[];
-  cgs_mid_body<T, U>(ctl, Q, ld, w, dim, partials, blockIdx.x, min(ctl.ip[CI_K], cap),
-                     reinterpret_cast<T *>(mid_lds));
 }
 
 // reorth == 0: no columns, only the partials of ||w||^2 (with last == 1)
@@ -1223,31 +1137,35 @@ __global__ __launch_bounds__(kBlock) void kb_norm_finalize(BatchDev<T> bd, int f
   norm_finalize_body(d.ctl, d.partials, (unsigned)(pre[a + 1] - pre[a]), which);
 }
 
-// Q^T w for reorthogonalisation (no columns when the slice does not
-// reorthogonalise)
-// slice takes the fused CGS2 middle
 template <typename T>
-__device__ inline bool mid_slice(const SliceDev<T> &d) {
-  return d.ctl.K <= mid_max_k(sizeof(T));
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void kb_dots(BatchDev<T> bd, int plain_only) {
+__global__ __launch_bounds__(kBlock) void kb_dots2(BatchDev<T> bd) {
   Blk b;
-  const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
-  if (skip(bd, d) || (plain_only && mid_slice(d))) return;
+  const SliceDev<T> &d = slice_of(bd, BF_VQD, blockIdx.x, b);
+  if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
-  dots_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, d.partials, b.id, blockIdx.y, d.reorth ? k : 0);
+  dots2_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, d.partials, b.id, blockIdx.y, d.reorth ? k : 0);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void kb_reduce_cols(BatchDev<T> bd, int after_mid) {
+__global__ __launch_bounds__(kBlock) void kb_reduce_cols2(BatchDev<T> bd) {
   const int a = blockIdx.y;
   const SliceDev<T> &d = bd.sd[bd.active[a]];
   if (skip(bd, d)) return;
-  const int *pre = bd.pre + (after_mid && mid_slice(d) ? BF_VQM : BF_VQ) * (bd.na + 1);
+  const int *pre = bd.pre + BF_VQD * (bd.na + 1);
   const int k = d.ctl.ip[CI_K];
-  reduce_cols_body(d.ctl, d.partials, pre[a + 1] - pre[a], blockIdx.x, d.reorth ? k : 0);
+  // the launch covers 2 (kmax + 1) columns; this slice's two sets start at 0
+  // and K + 1 of its own
+  const int kmax1 = gridDim.x / 2;
+  const int set = blockIdx.x >= (unsigned)kmax1 ? 1 : 0, j = blockIdx.x - set * kmax1;
+  if (j > d.ctl.K) return;
+  reduce_cols2_body(d.ctl, d.partials, pre[a + 1] - pre[a], set * (d.ctl.K + 1) + j, d.reorth ? k : 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void kb_dcgs_coef(BatchDev<T> bd) {
+  const SliceDev<T> &d = bd.sd[bd.active[blockIdx.x]];
+  if (skip(bd, d) || !d.reorth) return;
+  dcgs_coef_body(d.ctl, d.ctl.ip[CI_K]);
 }
 
 template <typename T>
@@ -1267,24 +1185,12 @@ __global__ __launch_bounds__(kBlock) void kb_resid_init(BatchDev<T> bd) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void kb_cgs_update(BatchDev<T> bd, int last, int plain_only) {
+__global__ __launch_bounds__(kBlock) void kb_cgs_update(BatchDev<T> bd, int last) {
   Blk b;
   const SliceDev<T> &d = slice_of(bd, BF_VQU, blockIdx.x, b);
-  if (skip(bd, d) || (plain_only && mid_slice(d))) return;
+  if (skip(bd, d)) return;
   const int k = d.ctl.ip[CI_K];
   cgs_update_body<T>(d.ctl, d.Q, d.ldq, d.w, d.dimq, last, d.partials, b, d.reorth ? k : 0);
-}
-
-// cap: LDS columns, at least k_max + 1 of every slice in the family
-template <typename T, int U>
-__global__ __launch_bounds__(kBlock) void kb_cgs_mid(BatchDev<T> bd, int cap) {
-  Blk b;
-  const SliceDev<T> &d = slice_of(bd, BF_VQM, blockIdx.x, b);
-  if (skip(bd, d)) return;
-  extern __shared__ __align__(16) unsigned char mid_lds[];
-  const int k = d.ctl.ip[CI_K];
-  cgs_mid_body<T, U>(d.ctl, d.Q, d.ldq, d.w, d.dimq, d.partials, b.id, min(d.reorth ? k : 0, cap),
-                     reinterpret_cast<T *>(mid_lds));
 }
 
 template <typename T>
@@ -1342,13 +1248,12 @@ __global__ void kb_set_k(BatchDev<T> bd, int k) {
 
 void launch_set_int(int *p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v); }
 
-int mid_unroll_bucket(int k) { return mid_unroll(k); }
 int vec_blocks(long long dim) {
   long long b = (dim + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
   return (int)std::max<long long>(b, 1);
 }
-int mid_blocks(long long dim) {
-  const long long rows = (long long)MID_ROWS * MID_SUB;
+int dots_blocks(long long dim) {
+  const long long rows = (long long)kBlock * RPT * kDotsQuads;
   return (int)std::max<long long>((dim + rows - 1) / rows, 1);
 }
 int upd_blocks(long long dim) {
@@ -1370,29 +1275,14 @@ void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *parti
   launch_norm_finalize(ctl, partials, nb, which, ctl.ip + CI_STOP, s);
 }
 template <typename T>
-void launch_cgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
-                     hipStream_t s) {
-  const int nb = vec_blocks(dim);
-  const dim3 grid(nb, (ctl.K + CH) / CH);
-  hipLaunchKernelGGL(k_dots<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials);
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 1), dim3(kBlock), 0, s, ctl, (const double *)partials, nb);
+void launch_dcgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
+                      hipStream_t s) {
+  const int nb = dots_blocks(dim);
+  const dim3 grid(nb, (ctl.K + CH2) / CH2);
+  hipLaunchKernelGGL(k_dots2<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials);
+  hipLaunchKernelGGL(k_reduce_cols2, dim3(2 * (ctl.K + 1)), dim3(kBlock), 0, s, ctl, (const double *)partials, nb);
 }
-template <typename T>
-void launch_cgs_mid(Ctl ctl, const T *Q, long long ld, T *w, long long dim, double *partials, int k,
-                    hipStream_t s) {
-  const int nb = mid_blocks(dim);
-  const int cap = ctl.K + 1;  // columns 0..k-1 with k <= K
-  const size_t lds = (size_t)cap * MID_LD * sizeof(T);
-  switch (mid_unroll(k)) {
-#define GKB_MID(U)                                                                                           \
-  case U:                                                                                                    \
-    hipLaunchKernelGGL((k_cgs_mid<T, U>), dim3(nb), dim3(kBlock), lds, s, ctl, Q, ld, w, dim, partials, cap); \
-    break;
-    GKB_MID(4) GKB_MID(8) GKB_MID(16) GKB_MID(32)
-#undef GKB_MID
-  }
-  hipLaunchKernelGGL(k_reduce_cols, dim3(ctl.K + 1), dim3(kBlock), 0, s, ctl, (const double *)partials, nb);
-}
+void launch_dcgs_coef(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(kBlock), 0, s, ctl); }
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        hipStream_t s, int reorth) {
@@ -1470,37 +1360,17 @@ void launch_b_norm_to(const BatchDev<T> &bd, const BatchLaunch &bl, int sel, int
   launch_b_norm_finalize(bd, bl, fam, which, s);
 }
 template <typename T>
-void launch_b_cgs_dots(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
+void launch_b_dcgs(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
   if (bl.tot[BF_VQ] <= 0) return;
-  hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VQ], (bl.kmax + CH) / CH), dim3(kBlock), 0, s, bd, 0);
-  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 1, bl.na), dim3(kBlock), 0, s, bd, 0);
+  hipLaunchKernelGGL(kb_dots2<T>, dim3(bl.tot[BF_VQD], (bl.kmax + CH2) / CH2), dim3(kBlock), 0, s, bd);
+  hipLaunchKernelGGL(kb_reduce_cols2<T>, dim3(2 * (bl.kmax + 1), bl.na), dim3(kBlock), 0, s, bd);
+  hipLaunchKernelGGL(kb_dcgs_coef<T>, dim3(bl.na), dim3(kBlock), 0, s, bd);
 }
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s) {
   if (bl.tot[BF_VQU] <= 0) return;
-  hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQU]), dim3(kBlock), 0, s, bd, last, 0);
+  hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQU]), dim3(kBlock), 0, s, bd, last);
   if (last) launch_b_norm_finalize(bd, bl, BF_VQU, NORM_ALPHA1, s);
-}
-template <typename T>
-void launch_b_cgs_second(const BatchDev<T> &bd, const BatchLaunch &bl, int k, hipStream_t s) {
-  if (bl.tot[BF_VQ] <= 0) return;
-  if (bl.tot[BF_VQM] > 0) {
-    const int cap = bl.mid_kmax + 1;
-    const size_t lds = (size_t)cap * MID_LD * sizeof(T);
-    switch (mid_unroll(k)) {
-#define GKB_MID(U)                                                                                \
-  case U:                                                                                         \
-    hipLaunchKernelGGL((kb_cgs_mid<T, U>), dim3(bl.tot[BF_VQM]), dim3(kBlock), lds, s, bd, cap); \
-    break;
-      GKB_MID(4) GKB_MID(8) GKB_MID(16) GKB_MID(32)
-#undef GKB_MID
-    }
-  }
-  if (bl.any_plain) {
-    hipLaunchKernelGGL(kb_cgs_update<T>, dim3(bl.tot[BF_VQU]), dim3(kBlock), 0, s, bd, 0, 1);
-    hipLaunchKernelGGL(kb_dots<T>, dim3(bl.tot[BF_VQ], (bl.kmax + CH) / CH), dim3(kBlock), 0, s, bd, 1);
-  }
-  hipLaunchKernelGGL(kb_reduce_cols<T>, dim3(bl.kmax + 1, bl.na), dim3(kBlock), 0, s, bd, 1);
 }
 template <typename T>
 void launch_b_normalize(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) {
@@ -1538,10 +1408,8 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
 #define GKB_INST(T)                                                                                         \
   template void launch_copy<T>(const T *, T *, long long, hipStream_t);                                    \
   template void launch_norm_to<T>(Ctl, const T *, long long, int, double *, hipStream_t);                  \
-  template void launch_cgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t); \
   template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, hipStream_t, \
                                      int);                                                                  \
-  template void launch_cgs_mid<T>(Ctl, const T *, long long, T *, long long, double *, int, hipStream_t);   \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t, PadOut<T>);               \
   template void launch_resid<T>(Ctl, const T *, long long, double *, hipStream_t);                         \
   template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
@@ -1552,9 +1420,9 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
   template void launch_b_norm_finalize<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t); \
-  template void launch_b_cgs_dots<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                \
+  template void launch_b_dcgs<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                    \
+  template void launch_dcgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t); \
   template void launch_b_cgs_update<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);         \
-  template void launch_b_cgs_second<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);         \
   template void launch_b_normalize<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);               \
   template void launch_b_resid<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                   \
   template void launch_b_resid_init<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);              \

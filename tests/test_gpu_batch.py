@@ -134,8 +134,7 @@ def test_batch_graph_mode_equals_launch_mode(ctx, method, kind):
     # the hipGraph-captured iteration replays the same launches: every slice
     # bit for bit as in the launch-per-step mode, over a batch whose slices
     # stop at different iterations (the graph is captured again each time the
-    # active set shrinks) and run past k = 17 and 33 (the fused CGS2 middle
-    # changes its unroll); the graph-mode batch is run twice, with eager work
+    # active set shrinks); the graph-mode batch is run twice, with eager work
     # and synchronisations in between, and both runs compared
     geoms, bs, opts = build(MIX if kind == "par" else FAN_MIX, 720)
     opts = [dict(o, k_max=max(o["k_max"], 36)) if not o.get("use_dp") else o for o in opts]
@@ -183,12 +182,12 @@ def test_batch_with_stagnation_stops(ctx, method):
 
 
 @pytest.mark.parametrize("method", [gk.GKB_METHOD_BA, gk.GKB_METHOD_AB])
-def test_batch_mixes_fused_and_separate_cgs(ctx, method):
-    # FP64 slices with k_max 113 (second CGS round as one fused pass over Q)
-    # and 114 (separate update and inner-product kernels) in one batch
+def test_batch_mixes_k_max(ctx, method):
+    # FP64 slices with k_max 113, 114 and 20 in one batch (Gram matrices and
+    # inner-product partials of three sizes), each bit for bit as alone
     geoms, bs, opts = build(MIX[:3], 730)
     opts = [dict(o, k_max=k) for o, k in zip(opts, (113, 114, 20))]
-    note("batch fused/separate CGS %s" % method)
+    note("batch mixed k_max %s" % method)
     rb, xb = run_batch(ctx, method, geoms, bs, opts, torch.float64)
     for s in range(3):
         rs, xs = run_single(ctx, method, geoms[s], bs[s], opts[s], torch.float64)
