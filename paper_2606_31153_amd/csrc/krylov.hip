@@ -190,23 +190,43 @@ __global__ __launch_bounds__(kBlock) void k_reduce_cols2(Ctl ctl, const double *
 }
 
 // c = c1 + (c1 - G c1) over the k columns, in one workgroup (c1 is staged in
-// LDS before any c_i is written; each row's product is summed in column order)
-constexpr int kCoefMaxLds = 4096;
+// LDS before any c_i is written; each row's product is summed in column order
+// within each of a fixed number of column slices, the slices in order)
+constexpr int kCoefMaxLds = 4096, kCoefThreads = 1024, kCoefWaves = kCoefThreads / 64;
 __device__ inline void dcgs_coef_body(const Ctl &ctl, int k) {
   __shared__ double s_c1[kCoefMaxLds];
-  for (int j = threadIdx.x; j < k; j += kBlock) s_c1[j] = ctl.c[j];
+  __shared__ double s_part[kCoefWaves][64];
+  for (int j = threadIdx.x; j < k; j += kCoefThreads) s_c1[j] = ctl.c[j];
   __syncthreads();
-  // G is symmetric: thread i walks column i, so that the lanes of a
-  // wavefront read neighbouring entries of one row at each step
+  // G is symmetric: lane i walks column i, so that the lanes of a wavefront
+  // read neighbouring entries of one row at each step
   const long long ldg = ctl.K + 1;
-  for (int i = threadIdx.x; i < k; i += kBlock) {
+  const int nic = (k + 63) / 64;  // 64-row chunks of the result
+  if (nic <= kCoefWaves) {
+    // nic * S wavefronts: S of them split the sum of each chunk, and their
+    // shares are added in a fixed order
+    const int S = kCoefWaves / nic, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ic = wv / S, sl = wv - ic * S, i = ic * 64 + lane;
+    const int per = (k + S - 1) / S, j0 = sl * per, j1 = min(k, j0 + per);
+    double t = 0.0;
+    if (ic < nic && i < k)
+      for (int j = j0; j < j1; ++j) t = fma(ctl.gram[(long long)j * ldg + i], s_c1[j], t);
+    s_part[wv][lane] = t;
+    __syncthreads();
+    if (ic < nic && sl == 0 && i < k) {
+      for (int v = 1; v < S; ++v) t += s_part[wv + v][lane];
+      ctl.c[i] = s_c1[i] + (s_c1[i] - t);
+    }
+    return;
+  }
+  for (int i = threadIdx.x; i < k; i += kCoefThreads) {
     double t = 0.0;
     for (int j = 0; j < k; ++j) t = fma(ctl.gram[(long long)j * ldg + i], s_c1[j], t);
     ctl.c[i] = s_c1[i] + (s_c1[i] - t);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_dcgs_coef(Ctl ctl) {
+__global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(Ctl ctl) {
   if (ctl.ip[CI_STOP]) return;
   dcgs_coef_body(ctl, ctl.ip[CI_K]);
 }
@@ -1162,7 +1182,7 @@ __global__ __launch_bounds__(kBlock) void kb_reduce_cols2(BatchDev<T> bd) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void kb_dcgs_coef(BatchDev<T> bd) {
+__global__ __launch_bounds__(kCoefThreads) void kb_dcgs_coef(BatchDev<T> bd) {
   const SliceDev<T> &d = bd.sd[bd.active[blockIdx.x]];
   if (skip(bd, d) || !d.reorth) return;
   dcgs_coef_body(d.ctl, d.ctl.ip[CI_K]);
@@ -1282,7 +1302,7 @@ void launch_dcgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long d
   hipLaunchKernelGGL(k_dots2<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials);
   hipLaunchKernelGGL(k_reduce_cols2, dim3(2 * (ctl.K + 1)), dim3(kBlock), 0, s, ctl, (const double *)partials, nb);
 }
-void launch_dcgs_coef(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(kBlock), 0, s, ctl); }
+void launch_dcgs_coef(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(kCoefThreads), 0, s, ctl); }
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        hipStream_t s, int reorth) {
@@ -1364,7 +1384,7 @@ void launch_b_dcgs(const BatchDev<T> &bd, const BatchLaunch &bl, hipStream_t s) 
   if (bl.tot[BF_VQ] <= 0) return;
   hipLaunchKernelGGL(kb_dots2<T>, dim3(bl.tot[BF_VQD], (bl.kmax + CH2) / CH2), dim3(kBlock), 0, s, bd);
   hipLaunchKernelGGL(kb_reduce_cols2<T>, dim3(2 * (bl.kmax + 1), bl.na), dim3(kBlock), 0, s, bd);
-  hipLaunchKernelGGL(kb_dcgs_coef<T>, dim3(bl.na), dim3(kBlock), 0, s, bd);
+  hipLaunchKernelGGL(kb_dcgs_coef<T>, dim3(bl.na), dim3(kCoefThreads), 0, s, bd);
 }
 template <typename T>
 void launch_b_cgs_update(const BatchDev<T> &bd, const BatchLaunch &bl, int last, hipStream_t s) {

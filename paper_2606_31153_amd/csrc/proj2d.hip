@@ -38,21 +38,41 @@ namespace gkb {
 
 namespace {
 
-// atan of |z| <= 0.5: z * P(z^2), P a degree-5 polynomial fitted to atan(z)/z
-// on [0, 0.5] by iteratively reweighted least squares on Chebyshev nodes (a
-// near-minimax fit of the relative error).  With the coefficients as printed
-// the relative error is at most 7.1e-9 in exact arithmetic, below float
-// rounding.
+// atan of |z| <= 0.5: z * P(z^2), P of degree 5 with P(0) = 1, fitted to the
+// relative error of atan by Lawson's iteratively reweighted least squares on
+// Chebyshev nodes, its coefficients rounded to float one at a time with the
+// higher ones refitted (fit_angle_poly.py beside this file).  With the
+// coefficients as printed the relative error is at most 5.4e-9 in exact
+// arithmetic, below float rounding.
 __device__ inline float atan_poly(float z) {
   const float t = z * z;
-  float p = -0.05129426f;
-  p = fmaf(p, t, 0.10156788f);
-  p = fmaf(p, t, -0.14173856f);
-  p = fmaf(p, t, 0.19994047f);
-  p = fmaf(p, t, -0.33333223f);
+  float p = -0.05125048f;
+  p = fmaf(p, t, 0.10155799f);
+  p = fmaf(p, t, -0.14174211f);
+  p = fmaf(p, t, 0.19994168f);
+  p = fmaf(p, t, -0.33333233f);
   p = fmaf(p, t, 1.0f);
   return z * p;
 }
+
+// The same for asin(s) = s * Q(s^2), |s| <= 1/sqrt(5) (the sine of an angle of
+// tangent 0.5): relative error at most 1.1e-9.  The struct holds Q's
+// coefficients times a scale, and eval(s, off) = off + scale * asin(s).
+struct AsinScaled {
+  float c[6];
+  __device__ explicit AsinScaled(float scale) {
+    const float q[6] = {1.0f, 0.16666691f, 0.074983247f, 0.04501405f, 0.026861863f, 0.036772124f};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) c[j] = q[j] * scale;
+  }
+  __device__ float eval(float s, float off) const {
+    const float t = s * s;
+    float p = c[5];
+#pragma unroll
+    for (int j = 4; j >= 0; --j) p = fmaf(p, t, c[j]);
+    return fmaf(s, p, off);
+  }
+};
 
 // Fan angle of a pixel from its coordinates (a along, b across the central ray).
 template <typename T>
@@ -800,14 +820,40 @@ __device__ inline void fwd_adj_body(const GeomDev &g, const ViewTab<T> &vt, cons
     const int lane = threadIdx.x & 63;
     const T *__restrict__ ht = vt.htile + (long long)b.id * g.nv;
     const int nvg = (g.nv - grp + VS - 1) / VS;  // views of this group
+    // float with the fast angle and the first-order sine: the pixel's sine
+    // s = b / |p - S| comes from the reciprocal square root that |p - S| needs
+    // anyway, and its angle in bins from the scaled asin polynomial
+    const bool sine_path = fast && g.at_fast;
+    const AsinScaled asn((float)inv_dg);
     for (int t0 = 0; t0 < nvg; t0 += 64) {
       const T hl = (t0 + lane < nvg) ? ht[grp + VS * (t0 + lane)] : T(0);
+      const int cl = min((int)floor(T(2) * hl) + 1, NC);  // the candidate count of each lane's view
       const int tend = min(nvg, t0 + 64);
       for (int t = t0; t < tend; ++t) {
         const int v = grp + VS * t;
         const T H = lane_value(hl, t - t0);
-        const int cnt = min((int)floor(T(2) * H) + 1, NC);
+        const int cnt = __builtin_amdgcn_readlane(cl, t - t0);
         const T cb = vt.p0[v], sb = vt.p1[v];
+        if constexpr (sizeof(T) == 4) {
+          if (sine_path) {
+            const T a = fma(-px, cb, fma(-py, sb, D));
+            const T bb = fma(px, sb, -py * cb);
+            const T r2 = fma(a, a, bb * bb);
+            const T rs = fast_rsq(r2);
+            const T up = clampv(asn.eval(bb * rs, off), ulo, uhi);
+            const T k0f = ceil(up - H);
+            const T c1 = r2 * rs * T(g.du);
+            const T dc1 = (up - k0f) * c1;
+            const auto *yw = reinterpret_cast<const typename Pair<T>::v2 *>(ypad) + (roff + (unsigned)(int)k0f);
+            acc = cnt == NC       ? at_fan_bins_lin<T, NC, NC>(yw, dc1, c1, cnt, acc)
+                  : cnt == NC - 1 ? at_fan_bins_lin<T, NC - 1, NC>(yw, dc1, c1, cnt, acc)
+                  : cnt == NC - 2 ? at_fan_bins_lin<T, (NC > 2 ? NC - 2 : 0), NC>(yw, dc1, c1, cnt, acc)
+                  : cnt == NC - 3 ? at_fan_bins_lin<T, (NC > 3 ? NC - 3 : 0), NC>(yw, dc1, c1, cnt, acc)
+                                  : at_fan_bins_lin<T, 0, NC>(yw, dc1, c1, cnt, acc);
+            roff += (unsigned)VS * ldY;
+            continue;
+          }
+        }
         const T a = D - fma(px, cb, py * sb);
         const T bb = fma(px, sb, -py * cb);
         T up = fma(fan_angle<T>(bb, a, fast), inv_dg, off);
