@@ -202,9 +202,9 @@ __device__ inline void dcgs_coef_body(const Ctl &ctl, int k) {
   // read neighbouring entries of one row at each step
   const long long ldg = ctl.K + 1;
   const int nic = (k + 63) / 64;  // 64-row chunks of the result
-  if (nic <= kCoefWaves) {
-    // nic * S wavefronts: S of them split the sum of each chunk, and their
-    // shares are added in a fixed order
+  if (2 * nic <= kCoefWaves) {
+    // nic * S wavefronts, S >= 2: S of them split the sum of each chunk, and
+    // their shares are added in a fixed order
     const int S = kCoefWaves / nic, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ic = wv / S, sl = wv - ic * S, i = ic * 64 + lane;
     const int per = (k + S - 1) / S, j0 = sl * per, j1 = min(k, j0 + per);
@@ -219,6 +219,7 @@ __device__ inline void dcgs_coef_body(const Ctl &ctl, int k) {
     }
     return;
   }
+  // more than 512 rows: one thread per row, in rounds of kCoefThreads rows
   for (int i = threadIdx.x; i < k; i += kCoefThreads) {
     double t = 0.0;
     for (int j = 0; j < k; ++j) t = fma(ctl.gram[(long long)j * ldg + i], s_c1[j], t);

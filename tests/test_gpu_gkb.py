@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import dense
 from paper_2606_31153_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -248,6 +249,34 @@ def test_fp32_long_run_does_not_depend_on_k_max(ctx, mode):
     assert np.array_equal(r1.t[:151], r2.t[:151])
     ref = oracle.gkb(op, MODES[mode][0], b32, 150)
     assert rel(x1, ref.x.reshape(-1)) <= 1e-4
+
+
+# Past 512 columns the reorthogonalisation's coefficient kernel gives each
+# thread a row, and past 1024 it takes the rows in several rounds.  On a
+# 33x33 image with 61 views (M of full rank n = 1089, no rotation symmetry)
+# n iterations fill the whole space, so x_n is the full-space solution,
+# computed here from the oracle's dense A and B: BA, (BA)^-1 B b; AB, B z with
+# z the least-norm minimiser of ||A B z - b||.  BA-GKB must also break down
+# at k = n: t_{n+1} is then what rounding leaves of a vector orthogonalised
+# against a complete orthonormal basis (6e-12 against the 4e-11 threshold,
+# and 5e-5 one step earlier); a basis that lost orthogonality runs on.  (AB's
+# last step, from n to n + 1, divides by an alpha_{n+1} of about 1e-9 and is
+# left out: its x moves by 1e-6.)
+@pytest.mark.parametrize("mode", ["ba", "ab"])
+def test_fp64_fills_the_space_past_1024_columns(ctx, mode):
+    geom = synth.par2d(33, 61)
+    op, xt, b, en = problem(geom, 1006, 0.01)
+    A, B = dense.dense_A(geom), dense.dense_B(geom)
+    if mode == "ba":
+        xs = np.linalg.solve(B @ A, B @ b)
+    else:
+        xs = B @ np.linalg.lstsq(A @ B, b, rcond=None)[0]
+    note("fp64 full space %s, n=%d" % (mode, geom.n))
+    res, x = gpu_solve(ctx, geom, mode, b, torch.float64, 1200 if mode == "ba" else geom.n)
+    note("  k_stop %d reason %d, x rel %.2e" % (res.k_stop, res.reason, rel(x, xs)))
+    assert res.k_stop == geom.n
+    assert res.reason == (gk.STOP_BREAKDOWN if mode == "ba" else gk.STOP_KMAX)
+    assert rel(x, xs) <= 1e-8
 
 
 # FP32 projectors and vectors, FP64 reductions and projected solve, against
