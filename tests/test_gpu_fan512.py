@@ -26,10 +26,17 @@ d ||b|| / ||e|| = 200 d relative.  So:
   iteration lies within three times the FP32 path's own residual deviation
   from the oracle over the ten iterations before it.
 * The same workload with 719 views (no exact symmetry), 40 FP32 iterations:
-  x within 1e-5 (measured 2.4e-6 BA, 8e-7 AB), alpha and t within 1e-4 over
-  the first 10 iterations (measured 2e-7 BA, 1e-5 AB) and rho_40 within 1e-3
-  (near-repeated singular values leave the middle of the alpha, t histories
-  undetermined here too).
+  x within 1e-5 (measured 2.4e-6 BA, 1e-6 AB), alpha and t within 1e-5 over
+  the first 8 iterations (measured 3e-7) and rho_40 within 1e-3.  The
+  geometry is one view away from the symmetric one, so its singular values
+  come in near-repeated pairs, and from k of about 9 the individual alpha_k,
+  t_k respond to perturbations of the operator at the level of the float
+  projectors' own deviation from the FP64 operators (2-3e-5 relative on
+  random data: a detector coordinate near 1000 bins carries up to 6e-5 bins
+  of float rounding).  Changing only how the float A^T rounds that
+  coordinate (its deviation staying at 2.8e-5) moved the deviation of AB's
+  alpha_10 from 8e-6 to 2e-4, of BA's alpha_12 from 2e-4 to 9e-3, while x
+  moved by less than 1e-6.
 """
 import os
 import sys
@@ -178,10 +185,10 @@ def test_fan512_719_views_fp32_matches_oracle(ctx, mode):
     K = int(z["k_max"])
     res, x = solve(ctx, geom, mode, b, torch.float32, K)
     e = rel(x, z["it_x"].astype(np.float64))
-    a_rel = np.max(np.abs(res.alpha[:10] / z["it_alpha"][:10] - 1.0))
-    t_rel = np.max(np.abs(res.t[:10] / z["it_t"][:10] - 1.0))
+    a_rel = np.max(np.abs(res.alpha[:8] / z["it_alpha"][:8] - 1.0))
+    t_rel = np.max(np.abs(res.t[:8] / z["it_t"][:8] - 1.0))
     r_rel = abs(res.rho[-1] / z["it_rho"][-1] - 1.0)
-    note("fan512 719 views %s f32, %d its: x rel %.2e; first 10: alpha %.1e t %.1e; rho_%d %.1e" % (
+    note("fan512 719 views %s f32, %d its: x rel %.2e; first 8: alpha %.1e t %.1e; rho_%d %.1e" % (
         mode, K, e, a_rel, t_rel, K, r_rel))
     assert e <= 1e-5
-    assert a_rel <= 1e-4 and t_rel <= 1e-4 and r_rel <= 1e-3
+    assert a_rel <= 1e-5 and t_rel <= 1e-5 and r_rel <= 1e-3
