@@ -273,6 +273,19 @@ def cone_main(args):
     r = gk.gkb_ba_solve(ctx, geom, bd, x, iters, use_dp=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # BA-GKB with a sinogram filter inside B applied per detector row (M = B F A,
+    # F the Ram-Lak filter carried exactly by the learned-filter network and its
+    # kernels): the cost per iteration of the per-row F at this size
+    print("bench: cone BA-GKB with a per-row filter", file=sys.stderr, flush=True)
+    from paper_2606_31153_amd import learned
+    net = gk.Net(ctx)
+    net.set_weights(learned.linear_pair_weights(learned.ramlak()))
+    fiters = max(1, min(iters, args.cone_filter_iters))
+    t0 = time.perf_counter()
+    rf = gk.gkb_ba_solve(ctx, geom, bd, x, fiters, use_dp=False, precond=net)
+    torch.cuda.synchronize()
+    elf = time.perf_counter() - t0
+    net.close()
     print("bench: cone units", file=sys.stderr, flush=True)
     units = cone_units(geom)
     pv = geom.n * geom.n_views
@@ -286,6 +299,9 @@ def cone_main(args):
            "config": {"workload": "cone beam 512^3, 720 views over 360 deg, 1024x768 flat detector, D=1024, "
                                   "SDD=2048; BA-GKB %d iterations" % iters},
            "kernels": kernels, "units": {"joseph_samples": units, "voxel_views": pv},
+           "per_row_filter": {"filter": "Ram-Lak (9 taps) through the learned-filter network, per detector row "
+                                        "(720 x 768 rows of 1024 bins), inside B", "iterations": rf.k_stop,
+                              "iters_per_s": rf.k_stop / elf, "plain_iters_per_s": r.k_stop / el},
            "roofline": {"bound": "alu", "kernel": dom, "achieved": ach, "peak": VALU_FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": ach / VALU_FP32_PEAK_TFLOPS,
                         "work_per_launch": "%d units x 8 flop (bilinear: 3 lerps + accumulate)" % u[dom]}}
@@ -466,6 +482,8 @@ def main():
     ap.add_argument("--only-batch", action="store_true", help="the 64-slice batched workload only (profiling)")
     ap.add_argument("--cone", action="store_true", help="measure the 512^3 cone-beam workload instead")
     ap.add_argument("--cone-iters", type=int, default=60)
+    ap.add_argument("--cone-filter-iters", type=int, default=10,
+                    help="iterations of the cone solve with the per-row filter")
     ap.add_argument("--learned", action="store_true", help="train and evaluate the learned filter instead")
     ap.add_argument("--train-samples", type=int, default=20000)
     ap.add_argument("--textures", type=int, default=0, help="extra random-texture training samples")
