@@ -96,7 +96,9 @@ typedef struct {
   int use_dp;               /* 1: stop at the first k with ||A x_k - b|| <= tau*noise_norm (eq. DP) */
   double tau;               /* > 0 when use_dp; the paper uses 1 */
   double noise_norm;        /* ||e||, the noise norm the discrepancy principle compares against */
-  int reorth;               /* 1 = one-sided reorthogonalisation of q (two classical Gram-Schmidt passes); 0 = none */
+  int reorth;               /* 1 = one-sided reorthogonalisation of q: two classical Gram-Schmidt rounds, the
+                               second's inner products taken from the Gram matrix of the stored basis
+                               ((k_max+1)^2 doubles of device workspace); 0 = none */
   const gkb_net *precond;   /* BA only: learned sinogram filter F inside B (M = B F A); NULL = plain */
   double *residual_history; /* optional HOST [k_max]: ||A x_k - b||, k = 1..k_stop */
   double *alpha_history;    /* optional HOST [k_max+1]: alpha_1.. */
@@ -178,8 +180,9 @@ gkb_status gkb_gkb_solve(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const v
  *     preconditioner; Arnoldi basis in R^n from r_0 = B b; x_k = Q_k u_k.
  * u_k = argmin ||H_k u - ||r_0|| e_1|| (eq. proj) with the (k+1) x k upper
  * Hessenberg H_k of the Arnoldi relation M Q_k = Q_{k+1} H_k (eq. Arn iter).
- * The Arnoldi vectors are orthogonalised by two classical Gram-Schmidt passes
- * (the coefficients of both passes form H_k's column; the paper prints one
+ * The Arnoldi vectors are orthogonalised by two classical Gram-Schmidt rounds,
+ * the second's inner products taken from the Gram matrix of the stored basis
+ * (the coefficients of both rounds form H_k's column; the paper prints one
  * modified pass, equal up to rounding), and u_k comes from a Givens QR of
  * H_k updated once per iteration (the paper uses the SVD).  The stopping
  * rules are those of the GKB solves on ||A x_k - b|| (eqs. DP and RNS), which
@@ -280,8 +283,7 @@ gkb_status gkb_set_tuning(gkb_ctx *ctx, const gkb_geometry *g, int dtype, const 
  *     launch over all active slices;
  *   GKB_BATCH_GRAPH: the same launches are captured once into a hipGraph
  *     and replayed each iteration; the graph is captured again when slices
- *     stop (and when the reorthogonalisation kernel's unroll changes, at
- *     k = 17, 33, 65).  Capture runs on a stream the context creates.
+ *     stop.  Capture runs on a stream the context creates.
  * Results are bit for bit the same in both modes. */
 typedef enum { GKB_BATCH_LAUNCHES = 0, GKB_BATCH_GRAPH = 1 } gkb_batch_mode;
 gkb_status gkb_set_batch_mode(gkb_ctx *ctx, int mode);

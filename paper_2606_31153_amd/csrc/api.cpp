@@ -1738,7 +1738,8 @@ struct Solver {
     }
   }
 
-  // Arnoldi step: CGS2 of w against q_1..q_k, the two rounds' coefficients
+  // Arnoldi step: two classical Gram-Schmidt rounds of w against q_1..q_k
+  // (the second's inner products from the Gram matrix), their coefficients
   // summed into column k of H; h_{k+1,k} = ||w|| into alpha[k+1]; q_{k+1}
   void gm_orthogonalise(int k) {
     TraceScope ts(c, "reorth");
@@ -2509,8 +2510,7 @@ gkb_status batch_impl(gkb_ctx *c, int mode, int ns, const gkb_geometry *geoms, i
     std::vector<hipEvent_t> evs(L, nullptr);
     for (auto &e : evs) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // one iteration's launches over the active slices (the kernels read k
-    // from the slices' control blocks; on the host only the unroll of the
-    // fused CGS2 middle depends on it)
+    // from the slices' control blocks; the launches do not depend on it)
     auto iteration = [&](int k) {
       // s~ <- M q_k - alpha_k/t_k s~, t_{k+1}, Y_k
       if (mode == MODE_BA) {

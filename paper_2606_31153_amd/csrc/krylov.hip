@@ -547,7 +547,7 @@ __device__ inline void stop_test(const Ctl &ctl, double rho) {
 }
 
 // ---- GMRES (Algs. "AB-GMRES" and "BA-GMRES") -----------------------------------
-// Arnoldi (eq. (Arn iter)) uses the CGS2 kernels above: the two rounds'
+// Arnoldi (eq. (Arn iter)) uses the reorthogonalisation kernels above: the two rounds'
 // coefficients add up to the Hessenberg column, h_{k+1,k} = ||w|| is
 // alpha[k+1] and q_{k+1} = w / alpha[k+1] (alpha[1] = ||r_0||).  The
 // projected problem (eq. proj) min ||H_k u - ||r_0|| e_1|| is solved by
