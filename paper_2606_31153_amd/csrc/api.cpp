@@ -1644,7 +1644,7 @@ struct Solver {
   void iteration(bool reorth, int k) {
     apply_M();
     apply_Mt(false);
-    reorth_and_normalize_impl(reorth, k);
+    reorth_and_normalize_impl(reorth);
     {
       TraceScope ts(c, "small_solve");
       launch_small_solve(ctl, st);
@@ -1655,10 +1655,10 @@ struct Solver {
     }
   }
 
-  // k: the iteration (the columns q_1..q_k of Q)
-  void reorth_and_normalize_impl(bool reorth, int k) {
+  // reorthogonalise w against the columns q_1..q_k of Q (the kernels read k
+  // from the control block), then alpha_{k+1} and q_{k+1}
+  void reorth_and_normalize_impl(bool reorth) {
     TraceScope ts(c, "reorth");
-    (void)k;
     if (reorth) {
       // two classical rounds, the second from the Gram matrix (one read of Q
       // for the inner products, one for the update)
@@ -1741,19 +1741,18 @@ struct Solver {
   // Arnoldi step: two classical Gram-Schmidt rounds of w against q_1..q_k
   // (the second's inner products from the Gram matrix), their coefficients
   // summed into column k of H; h_{k+1,k} = ||w|| into alpha[k+1]; q_{k+1}
-  void gm_orthogonalise(int k) {
+  void gm_orthogonalise() {
     TraceScope ts(c, "reorth");
-    (void)k;
     launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
     launch_dcgs_coef(ctl, st);
-    launch_gm_hcol(ctl, 1, st);  // h_{1..k,k}: both rounds' coefficients
+    launch_gm_hcol(ctl, st);  // h_{1..k,k}: both rounds' coefficients
     launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
     normalize();
   }
 
   void gm_iteration(int k, const T *b) {
     gm_apply_M();
-    gm_orthogonalise(k);
+    gm_orthogonalise();
     {
       TraceScope ts(c, "small_solve");
       launch_gm_solve(ctl, st);
@@ -1781,7 +1780,7 @@ struct Solver {
     apply_M();
     yk = keep;
     apply_Mt(false);
-    reorth_and_normalize_impl(reorth, k);
+    reorth_and_normalize_impl(reorth);
     {
       TraceScope ts(c, "small_solve");
       launch_hy_lambda(ctl, st);

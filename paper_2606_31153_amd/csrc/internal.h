@@ -438,7 +438,7 @@ enum NormTarget : int { NORM_T1 = 0, NORM_ALPHA1 = 1, NORM_BNORM = 2, NORM_RHO =
 constexpr int kGmMaxK = 1024;  // k_max limit of the GMRES solves
 // Hessenberg column k, rows 0..k-1, from the CGS coefficients ctl.c (first
 // round: set; second round: added)
-void launch_gm_hcol(Ctl ctl, int first, hipStream_t s);
+void launch_gm_hcol(Ctl ctl, hipStream_t s);
 // Givens QR update of H_k with column k (h_{k+1,k} = alpha[k+1]), u_k by back
 // substitution, projected residual into pres[k]
 void launch_gm_solve(Ctl ctl, hipStream_t s);

@@ -557,11 +557,12 @@ __device__ inline void stop_test(const Ctl &ctl, double rho) {
 // right-hand side g gains one entry, and u_k solves the k x k triangular
 // system R u = g.  |g_{k+1}| is the projected residual.
 
-__global__ __launch_bounds__(kBlock) void k_gm_hcol(Ctl ctl, int first) {
+// h_{1..k,k}: the reorthogonalisation coefficients of both rounds (c1 + c2)
+__global__ __launch_bounds__(kBlock) void k_gm_hcol(Ctl ctl) {
   if (ctl.ip[CI_STOP]) return;
   const int k = ctl.ip[CI_K];
   double *col = ctl.hm + (long long)k * ctl.ldh;
-  for (int i = threadIdx.x; i < k; i += kBlock) col[i] = first ? ctl.c[i] : col[i] + ctl.c[i];
+  for (int i = threadIdx.x; i < k; i += kBlock) col[i] = ctl.c[i];
 }
 
 // One wavefront.  The serial rotation steps run in lane 0 on a copy of the
@@ -1336,8 +1337,8 @@ void launch_rre(Ctl ctl, const T *x, const T *x_true, long long n, double *parti
 void launch_small_solve(Ctl ctl, hipStream_t s) {
   hipLaunchKernelGGL(k_small_solve, dim3(1), dim3(kSolveThreads), 0, s, ctl);
 }
-void launch_gm_hcol(Ctl ctl, int first, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(kBlock), 0, s, ctl, first);
+void launch_gm_hcol(Ctl ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_hcol, dim3(1), dim3(kBlock), 0, s, ctl);
 }
 void launch_gm_solve(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, ctl); }
 template <typename T>
