@@ -55,6 +55,24 @@ __device__ inline float atan_poly(float z) {
   return z * p;
 }
 
+// atan_poly with P's coefficients times a scale: eval(z, off) = off +
+// scale * atan(z) with one multiply fewer than fma(atan_poly(z), scale, off).
+struct AtanScaled {
+  float c[6];
+  __device__ explicit AtanScaled(float scale) {
+    const float q[6] = {1.0f, -0.33333233f, 0.19994168f, -0.14174211f, 0.10155799f, -0.05125048f};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) c[j] = q[j] * scale;
+  }
+  __device__ float eval(float z, float off) const {
+    const float t = z * z;
+    float p = c[5];
+#pragma unroll
+    for (int j = 4; j >= 0; --j) p = fmaf(p, t, c[j]);
+    return fmaf(z, p, off);
+  }
+};
+
 // The same for asin(s) = s * Q(s^2), |s| <= 1/sqrt(5) (the sine of an angle of
 // tangent 0.5): relative error at most 1.1e-9.  The struct holds Q's
 // coefficients times a scale, and eval(s, off) = off + scale * asin(s).
@@ -614,6 +632,21 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
     } else {
       const T D = T(g.D), inv_dg = T(g.inv_du);
       const bool fast = g.fast_atan != 0;
+      const AtanScaled atn((float)inv_dg);
+      // the pixel's detector coordinate in view (cb, sb); float with the fast
+      // angle: the atan polynomial yields bins directly
+      auto u_of = [&](T cb, T sb) -> T {
+        if constexpr (sizeof(T) == 4) {
+          if (fast) {
+            const T a = fma(-px, cb, fma(-py, sb, D));
+            const T bb = fma(px, sb, -py * cb);
+            return clampv(T(atn.eval(bb * fast_rcp(a), off)), ulo, uhi);
+          }
+        }
+        const T a = D - fma(px, cb, py * sb);
+        const T bb = fma(px, sb, -py * cb);
+        return clampv(T(fma(fan_angle<T>(bb, a, fast), inv_dg, off)), ulo, uhi);
+      };
       T a0 = T(0), a1 = T(0);
       int v = grp;
       for (; v + VS < g.nv; v += 2 * VS) {
@@ -621,10 +654,7 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
         typename Pair<T>::v2 p[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const T cb = vt.p0[v + q * VS], sb = vt.p1[v + q * VS];
-          const T a = D - fma(px, cb, py * sb);
-          const T bb = fma(px, sb, -py * cb);
-          u[q] = clampv(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo, uhi);
+          u[q] = u_of(vt.p0[v + q * VS], vt.p1[v + q * VS]);
           fl[q] = floor(u[q]);
           p[q] = load_pair(ypad + (roff + (unsigned)(q * VS) * ldY + (unsigned)(int)fl[q]));
         }
@@ -633,10 +663,7 @@ __device__ inline void back_body(const GeomDev &g, const ViewTab<T> &vt, const T
         roff += (unsigned)(2 * VS) * ldY;
       }
       if (v < g.nv) {
-        const T cb = vt.p0[v], sb = vt.p1[v];
-        const T a = D - fma(px, cb, py * sb);
-        const T bb = fma(px, sb, -py * cb);
-        const T u = clampv(fma(fan_angle<T>(bb, a, fast), inv_dg, off), ulo, uhi);
+        const T u = u_of(vt.p0[v], vt.p1[v]);
         const T fl = floor(u);
         const auto p = load_pair(ypad + (roff + (unsigned)(int)fl));
         a0 += fma(u - fl, p.y - p.x, p.x);
