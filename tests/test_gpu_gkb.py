@@ -361,12 +361,19 @@ def test_invalid_options_rejected(ctx):
     dev = torch.device("cuda:0")
     b = torch.ones(geom.m, dtype=torch.float32, device=dev)
     x = torch.zeros(geom.n, dtype=torch.float32, device=dev)
-    with pytest.raises(gk.GkbError) as e:
-        gk.gkb_ba_solve(ctx, geom, b, x, 0)
-    assert e.value.status == gk.GKB_EINVAL
+    for k_max in (0, 4097):  # k_max in [1, 4096]
+        with pytest.raises(gk.GkbError) as e:
+            gk.gkb_ba_solve(ctx, geom, b, x, k_max)
+        assert e.value.status == gk.GKB_EINVAL
     with pytest.raises(gk.GkbError) as e:
         gk.gkb_ba_solve(ctx, geom, b, x, 5, use_dp=True, tau=0.0, noise_norm=1.0)
     assert e.value.status == gk.GKB_EINVAL
+    # the largest k_max allocates its basis and Gram matrix ((k_max + 1)^2
+    # doubles) and launches the reorthogonalisation with grids for all its columns; a
+    # discrepancy level above ||b|| stops the solve at k = 1
+    res = gk.gkb_ba_solve(ctx, geom, b, x, 4096, use_dp=True, tau=1.0, noise_norm=1e30)
+    torch.cuda.synchronize()
+    assert (res.k_stop, res.reason) == (1, gk.STOP_DP) and torch.isfinite(x).all()
 
 
 def test_dp_not_reached(ctx):
