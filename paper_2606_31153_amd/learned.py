@@ -27,6 +27,39 @@ def _phantom(args):
     return synth.ellipse_phantom(n, seed).astype(np.float32)
 
 
+def _texture(args):
+    n, seed = args
+    return synth.gaussian_texture(n, seed).astype(np.float32)
+
+
+def _noisy(ctx, geom, xd, seeds, nus):
+    """b_i = A x_i + e_i for the device images xd [N, n]: A x_i by the
+    library's forward projector, then, on the host in float64, the noise of
+    sample seeds[i] (synth.noise_direction) at level nus[i] relative to
+    ||A x_i|| (synth.add_noise).  Returns device b [N, m] (FP32) and ||e_i||."""
+    import torch
+
+    import paper_2606_31153_amd as gk
+    N, m = xd.shape[0], geom.m
+    bd = torch.empty(N, m, dtype=torch.float32, device=xd.device)
+    enorm = np.zeros(N)
+    chunk = max(1, (1 << 27) // m)
+    tmp = torch.empty(min(N, chunk), m, dtype=torch.float32, device=xd.device)
+    for c0 in range(0, N, chunk):
+        c1 = min(N, c0 + chunk)
+        for i in range(c0, c1):
+            gk.gkb_forward(ctx, geom, xd[i], tmp[i - c0])
+        torch.cuda.synchronize()
+        bt = tmp[:c1 - c0].cpu().numpy()
+        out = np.empty_like(bt)
+        for i in range(c0, c1):
+            b, enorm[i] = synth.add_noise(bt[i - c0], synth.noise_direction(m, int(seeds[i])), float(nus[i]))
+            out[i - c0] = b
+        bd[c0:c1].copy_(torch.from_numpy(out))
+    torch.cuda.synchronize()
+    return bd, enorm
+
+
 def phantoms(n: int, seeds, workers: int = 16) -> np.ndarray:
     """[len(seeds), n*n] float32 phantoms, generated in a pool of processes
     (spawned, so that no child inherits a GPU context)."""
@@ -40,27 +73,17 @@ def phantoms(n: int, seeds, workers: int = 16) -> np.ndarray:
 
 def make_set(ctx, geom, seeds, nu_lo: float, nu_hi: float, key: int, workers: int = 16):
     """Device tensors b [N, m], x [N, n] (FP32) and the noise norms ||e_i||.
-    Noise levels from the Philox stream keyed (key, batch); noise directions
-    from torch's generator seeded with key (drawn on the GPU)."""
+    Noise levels from the Philox stream keyed (key, batch); each sample's
+    noise direction from its own seed (synth.noise_direction)."""
     import torch
 
-    import paper_2606_31153_amd as gk
     dev = torch.device("cuda:0")
+    seeds = list(seeds)
     X = phantoms(geom.nx, seeds, workers)
-    N = X.shape[0]
     xd = torch.from_numpy(X).to(dev)
-    bd = torch.empty(N, geom.m, dtype=torch.float32, device=dev)
-    for i in range(N):
-        gk.gkb_forward(ctx, geom, xd[i], bd[i])
-    nus = synth.rng(key, synth.PURPOSE_BATCH).uniform(nu_lo, nu_hi, N)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(int(key))
-    e = torch.randn(N, geom.m, generator=gen, device=dev, dtype=torch.float32)
-    scale = torch.tensor(nus, device=dev, dtype=torch.float32) * bd.norm(dim=1) / e.norm(dim=1)
-    e *= scale[:, None]
-    bd += e
-    torch.cuda.synchronize()
-    return bd, xd, e.double().norm(dim=1).cpu().numpy()
+    nus = synth.rng(key, synth.PURPOSE_BATCH).uniform(nu_lo, nu_hi, len(seeds))
+    bd, enorm = _noisy(ctx, geom, xd, seeds, nus)
+    return bd, xd, enorm
 
 
 def gkb_targets(ctx, geom, bd, enorms, k_max: int = 150):
@@ -135,36 +158,23 @@ def rescale_output(ctx, net, geom, bd, xd, count: int = 16):
     net.set_weights(w * np.float32((num / den) ** 0.25))
 
 
-def make_textures(ctx, geom, count: int, key: int, nu_lo: float, nu_hi: float):
+def make_textures(ctx, geom, count: int, key: int, nu_lo: float, nu_hi: float, workers: int = 16):
     """Random-texture training samples: Gaussian random fields with a random
-    correlation length (2 to 24 pixels), shifted and scaled to the density
-    range of the phantoms, drawn with torch's generator seeded with key;
-    b = A z + noise as in make_set.  Returns device b [count, m], z [count, n]."""
+    correlation length (synth.gaussian_texture, seeds key + i), b = A z +
+    noise as in make_set.  Returns device b [count, m], z [count, n]."""
     import torch
 
-    import paper_2606_31153_amd as gk
     dev = torch.device("cuda:0")
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(int(key))
-    n = geom.nx
-    fy = torch.fft.fftfreq(n, device=dev)[:, None]
-    fx = torch.fft.fftfreq(n, device=dev)[None, :]
-    f2 = fy * fy + fx * fx
-    ls = torch.exp(torch.empty(count, device=dev).uniform_(np.log(2.0), np.log(24.0), generator=gen))
-    zs = torch.empty(count, n * n, dtype=torch.float32, device=dev)
-    for i in range(count):
-        w = torch.randn(n, n, generator=gen, device=dev)
-        z = torch.fft.ifft2(torch.fft.fft2(w) * torch.exp(-2.0 * (np.pi ** 2) * f2 * ls[i] ** 2)).real
-        z = (z - z.mean()) / (z.std() + 1e-12)
-        zs[i] = (0.3 + 0.15 * z).reshape(-1)
-    bd = torch.empty(count, geom.m, dtype=torch.float32, device=dev)
-    for i in range(count):
-        gk.gkb_forward(ctx, geom, zs[i], bd[i])
+    seeds = [key + i for i in range(count)]
+    args = [(geom.nx, s) for s in seeds]
+    if workers <= 1 or count < 64:
+        Z = np.stack([_texture(a).reshape(-1) for a in args])
+    else:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            Z = np.stack([z.reshape(-1) for z in pool.map(_texture, args, chunksize=max(1, count // (4 * workers)))])
+    zs = torch.from_numpy(Z).to(dev)
     nus = synth.rng(key, synth.PURPOSE_BATCH).uniform(nu_lo, nu_hi, count)
-    e = torch.randn(count, geom.m, generator=gen, device=dev, dtype=torch.float32)
-    e *= (torch.tensor(nus, device=dev, dtype=torch.float32) * bd.norm(dim=1) / e.norm(dim=1))[:, None]
-    bd += e
-    torch.cuda.synchronize()
+    bd, _ = _noisy(ctx, geom, zs, seeds, nus)
     return bd, zs
 
 

@@ -187,6 +187,21 @@ def ellipse_phantom(n: int, seed: int, count: int = 8) -> np.ndarray:
     return rasterize_ellipses(ellipse_params(seed, count), n)
 
 
+def gaussian_texture(n: int, seed: int) -> np.ndarray:
+    """n x n Gaussian random field (float64, row-major): white noise filtered
+    by a Gaussian of correlation length ell drawn log-uniformly from [2, 24]
+    pixels, standardised, then shifted and scaled to the phantoms' density
+    range (mean 0.3, standard deviation 0.15)."""
+    g = rng(seed, PURPOSE_PHANTOM)
+    ell = math.exp(g.uniform(math.log(2.0), math.log(24.0)))
+    w = g.standard_normal((n, n))
+    f = np.fft.fftfreq(n)
+    f2 = f[:, None] ** 2 + f[None, :] ** 2
+    z = np.fft.ifft2(np.fft.fft2(w) * np.exp(-2.0 * math.pi ** 2 * f2 * ell ** 2)).real
+    z = (z - z.mean()) / (z.std() + 1e-12)
+    return 0.3 + 0.15 * z
+
+
 def ellipsoid_params(seed: int, count: int = 8) -> np.ndarray:
     """Rows (cx, cy, cz, a, b, c, q0, q1, q2, q3, rho): random centre at
     radius 0.5*U^(1/3) in a uniform direction, semi-axes U[0.1, 0.45],
