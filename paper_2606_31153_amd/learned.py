@@ -152,8 +152,8 @@ def rescale_output(ctx, net, geom, bd, xd, count: int = 16):
         gk.gkb_net_apply(ctx, net, geom, bd[i], y)
         gk.gkb_back(ctx, geom, y, xb)
         torch.cuda.synchronize()
-        num += float(xd[i].double().norm())
-        den += float(xb.double().norm())
+        num += float(np.linalg.norm(xd[i].cpu().numpy().astype(np.float64)))
+        den += float(np.linalg.norm(xb.cpu().numpy().astype(np.float64)))
     w = net.get_weights()
     net.set_weights(w * np.float32((num / den) ** 0.25))
 
@@ -221,7 +221,8 @@ def evaluate(ctx, net, geom, bd, xd, enorms, k_max: int = 150):
             r = gk.gkb_ba_solve(ctx, geom, bd[i], x, k_max, use_dp=True, tau=1.0, noise_norm=target, precond=pc)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            rre = float((x.double() - xd[i].double()).norm() / xd[i].double().norm())
+            xh, th = x.cpu().numpy().astype(np.float64), xd[i].cpu().numpy().astype(np.float64)
+            rre = float(np.linalg.norm(xh - th) / np.linalg.norm(th))
             res[name] = {"k": r.k_stop, "reason": r.reason, "seconds": dt, "residual": r.residual, "rre": rre,
                          "res_over_e": r.residual / float(enorms[i])}
         # the learned recurrence without a stop: smallest residual and where
