@@ -233,9 +233,12 @@ __global__ __launch_bounds__(kCoefThreads) void k_dcgs_coef(Ctl ctl) {
 }
 
 // Wavefronts that share the rows of a CGS update workgroup (and split its
-// columns): 4 for vectors of up to 2^19 entries, whose workgroups would
-// otherwise be too few to keep HBM busy, else 1.
-__host__ __device__ inline int upd_split(long long dim) { return dim <= (1LL << 19) ? 4 : 1; }
+// columns): 4 for vectors of up to 2^19 entries and 2 up to 2^21, whose
+// workgroups would otherwise be too few to keep HBM busy (a 737280-entry
+// vector gives 720 workgroups of 1024 rows for 256 CUs), else 1.
+__host__ __device__ inline int upd_split(long long dim) {
+  return dim <= (1LL << 19) ? 4 : (dim <= (1LL << 21) ? 2 : 1);
+}
 
 // ---- w -= Q[:, 0..ncols-1] c (FP64 per element); last == 1: partials of
 // ||w||^2 (alpha[k+1] = ||w|| by the finalising kernel).  The four wavefronts
