@@ -375,8 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T
 // line: n = CNT, or the wave-uniform runtime count `nrt` (at most MAXC) when
 // CNT == 0.
 // kBtLines lines per step, the taps of all of them loaded before any is
-// weighted.
-constexpr int kBtLines = 6;
+// weighted: 8 for parallel rays, 6 for fan rays (whose kernel would need 110
+// instead of 94 VGPRs with 8, four waves per SIMD instead of five).
+template <bool FAN>
+constexpr int kBtLines = FAN ? 6 : 8;
 template <typename T, bool FAN, int CNT, int MAXC>
 __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, long long r,
                                  T hr, int nrt, int half) {
@@ -464,14 +466,15 @@ __device__ inline T back_adj_ray(const GeomDev &g, const RayTab<T> &rt, const T 
   };
   T acc = T(0);
   int j = lo;
-  for (; j + kBtLines - 1 <= hi; j += kBtLines) {
-    T d0[kBtLines], v[kBtLines][NQ];
+  constexpr int NL = kBtLines<FAN>;
+  for (; j + NL - 1 <= hi; j += NL) {
+    T d0[NL], v[NL][NQ];
 #pragma unroll
-    for (int i = 0; i < kBtLines; ++i) taps(jf + T(i), off + (unsigned)(i * ld), d0[i], v[i]);
+    for (int i = 0; i < NL; ++i) taps(jf + T(i), off + (unsigned)(i * ld), d0[i], v[i]);
 #pragma unroll
-    for (int i = 0; i < kBtLines; ++i) weigh(jf + T(i), d0[i], v[i], acc);
-    jf += T(kBtLines);
-    off += (unsigned)(kBtLines * ld);
+    for (int i = 0; i < NL; ++i) weigh(jf + T(i), d0[i], v[i], acc);
+    jf += T(NL);
+    off += (unsigned)(NL * ld);
   }
   for (; j <= hi; ++j) {
     T d0a, va[NQ];
