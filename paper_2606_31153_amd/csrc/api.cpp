@@ -1664,12 +1664,11 @@ struct Solver {
       // for the inner products, one for the update)
       launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
       launch_dcgs_coef(ctl, st);
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
+      update_normalize(1);
     } else {
       // no reorthogonalisation: only the norm alpha_{k+1} = ||w|| (no columns)
-      launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st, 0);
+      update_normalize(0);
     }
-    normalize();
   }
 
   // RRE(x_k) = ||x_k - x_true|| / ||x_true|| (eq. RE) after iteration k: x_k
@@ -1695,6 +1694,22 @@ struct Solver {
       return;
     }
     launch_normalize<T>(ctl, w, Q, ldq, dimq, st, mode == MODE_AB ? pad_sino_out() : pad_image_out());
+    if (mode == MODE_AB)
+      wrote_sino(TAG_Q);
+    else
+      wrote_image(TAG_Q);
+  }
+
+  // w -= Q c over the reorthogonalisation columns (reorth_cols = 0: none),
+  // then q_{k+1} = w / alpha_{k+1} with alpha_{k+1} summed from the update's
+  // partials inside the normalisation
+  void update_normalize(int reorth_cols) {
+    if (!fusing()) {
+      launch_update_normalize<T>(ctl, Q, ldq, w, dimq, partials, st, reorth_cols);
+      return;
+    }
+    launch_update_normalize<T>(ctl, Q, ldq, w, dimq, partials, st, reorth_cols,
+                               mode == MODE_AB ? pad_sino_out() : pad_image_out());
     if (mode == MODE_AB)
       wrote_sino(TAG_Q);
     else
@@ -1746,8 +1761,7 @@ struct Solver {
     launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
     launch_dcgs_coef(ctl, st);
     launch_gm_hcol(ctl, st);  // h_{1..k,k}: both rounds' coefficients
-    launch_cgs_update<T>(ctl, Q, ldq, w, dimq, 1, partials, st);
-    normalize();
+    update_normalize(1);
   }
 
   void gm_iteration(int k, const T *b) {

@@ -381,6 +381,11 @@ void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, i
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s,
                       PadOut<T> pout = PadOut<T>{});
+// w -= Q c (reorth != 0) with the partials of ||w||^2, then q_{k+1} = w / alpha_{k+1},
+// alpha_{k+1} formed from those partials inside the normalisation
+template <typename T>
+void launch_update_normalize(Ctl ctl, T *Q, long long ld, T *w, long long dim, double *partials, hipStream_t s,
+                             int reorth, PadOut<T> pout = PadOut<T>{});
 template <typename T>
 void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream_t s);
 // rre[k_stop] = ||x - x_true|| / dp[CD_XTNORM] (eq. RE); runs after a stop too

@@ -392,9 +392,9 @@ __global__ __launch_bounds__(kBlock) void k_norm_finalize(Ctl ctl, const double 
 // ---- Q[:, k] = w / alpha[k+1] ------------------------------------------------
 template <typename T>
 __device__ inline void normalize_body(const Ctl &ctl, const T *__restrict__ w, T *__restrict__ Q, long long ld,
-                                      long long dim, unsigned blk, const PadOut<T> &pout) {
+                                      long long dim, unsigned blk, const PadOut<T> &pout, double alpha) {
   const int k = ctl.ip[CI_K];
-  const double inv = 1.0 / ctl.alpha[k + 1];
+  const double inv = 1.0 / alpha;
   T *q = Q + (long long)k * ld;
   const long long r = ((long long)blk * kBlock + threadIdx.x) * RPT;
   if (r >= dim) return;
@@ -416,7 +416,26 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_normalize(Ctl ctl, const T *__restrict__ w, T *__restrict__ Q,
                                                       long long ld, long long dim, PadOut<T> pout) {
   if (ctl.ip[CI_STOP]) return;
-  normalize_body(ctl, w, Q, ld, dim, blockIdx.x, pout);
+  normalize_body(ctl, w, Q, ld, dim, blockIdx.x, pout, ctl.alpha[ctl.ip[CI_K] + 1]);
+}
+
+// The same with alpha[k+1] = sqrt of the sum of the nb partials of ||w||^2,
+// which every workgroup forms in the finalising kernel's order (the same
+// value); workgroup 0 stores it.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_normalize_fin(Ctl ctl, const T *__restrict__ w, T *__restrict__ Q,
+                                                          long long ld, long long dim, PadOut<T> pout,
+                                                          const double *__restrict__ partials, int nb) {
+  if (ctl.ip[CI_STOP]) return;
+  __shared__ double lds[kBlock / 64];
+  __shared__ double s_alpha;
+  const double tot = partial_total<kBlock>(partials, (unsigned)nb, 1, lds);  // valid in thread 0
+  if (threadIdx.x == 0) {
+    s_alpha = sqrt(tot);
+    if (blockIdx.x == 0) ctl.alpha[ctl.ip[CI_K] + 1] = s_alpha;
+  }
+  __syncthreads();
+  normalize_body(ctl, w, Q, ld, dim, blockIdx.x, pout, s_alpha);
 }
 
 // ---- projected solve, discrepancy test, advance --------------------------------
@@ -1223,7 +1242,7 @@ __global__ __launch_bounds__(kBlock) void kb_normalize(BatchDev<T> bd) {
   Blk b;
   const SliceDev<T> &d = slice_of(bd, BF_VQ, blockIdx.x, b);
   if (skip(bd, d)) return;
-  normalize_body<T>(d.ctl, d.w, d.Q, d.ldq, d.dimq, b.id, PadOut<T>{});
+  normalize_body<T>(d.ctl, d.w, d.Q, d.ldq, d.dimq, b.id, PadOut<T>{}, d.ctl.alpha[d.ctl.ip[CI_K] + 1]);
 }
 
 template <typename T>
@@ -1318,6 +1337,14 @@ void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, i
 template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s, PadOut<T> pout) {
   hipLaunchKernelGGL(k_normalize<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim, pout);
+}
+template <typename T>
+void launch_update_normalize(Ctl ctl, T *Q, long long ld, T *w, long long dim, double *partials, hipStream_t s,
+                             int reorth, PadOut<T> pout) {
+  const int nb = upd_blocks(dim);
+  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, 1, partials, reorth);
+  hipLaunchKernelGGL(k_normalize_fin<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim, pout,
+                     (const double *)partials, nb);
 }
 template <typename T>
 void launch_resid_init(Ctl ctl, const T *b, long long m, double *partials, hipStream_t s) {
@@ -1436,6 +1463,7 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, hipStream_t, \
                                      int);                                                                  \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t, PadOut<T>);               \
+  template void launch_update_normalize<T>(Ctl, T *, long long, T *, long long, double *, hipStream_t, int, PadOut<T>); \
   template void launch_resid<T>(Ctl, const T *, long long, double *, hipStream_t);                         \
   template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
