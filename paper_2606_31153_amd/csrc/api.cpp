@@ -327,6 +327,8 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   gd.offT = (long long)ny * gd.ldR;
   // 64 elements of slack: A's segment loads read up to 62 past the end of a padded line
   gd.pad_elems = gd.offT + (long long)nx * gd.ldT + 64;
+  // A's segment path addresses the padded image with 32-bit element offsets
+  if (gd.pad_elems >= (1LL << 31)) gd.fwd_seg = 0;
   gd.uclamp_at = hmax_at + 1.0;
   gd.padY = std::max(4, gd.nc_at + (int)std::ceil(2.0 * hmax_at) + 3);
   gd.ldY = nu + 2 * gd.padY;

@@ -14,6 +14,12 @@ constexpr int kBlock = 256;
 // g, g + kViewGroups, ...; the groups' sums meet in LDS.
 constexpr int kPixTileX = 32, kPixTileY = 2, kViewGroups = 4;
 static_assert(kPixTileX * kPixTileY * kViewGroups == kBlock, "pixel tile must fill the workgroup");
+// FP32 A from line segments: stage four lines' 64-element segments per
+// 16-byte load through the wavefront's LDS (true), or load one element per
+// lane and line and exchange it between lanes (false).
+constexpr bool kFwdSegStage = true;
+// lines per step of the staged form (a multiple of 4)
+constexpr int kFwdStageLines = 8;
 
 // Integer fields of the device control block.
 enum CtlInt : int {

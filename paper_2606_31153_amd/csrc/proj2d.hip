@@ -247,6 +247,78 @@ __device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, c
   const int lane = threadIdx.x & 63;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
   int j = wlo;
+  if constexpr (kFwdSegStage) {
+    // kFwdStageLines lines per step.  Lanes 16 q' .. 16 q' + 15 load four
+    // consecutive elements each of line 4 h + q' of the step (one 16-byte
+    // load per lane covers the 64-element segments of four lines) into this
+    // wavefront's LDS rows; a lane then reads its two taps from the row.
+    // The rays of a wavefront cross every line in the same order (that of
+    // their bins, or the reverse), so a segment starts at the crossing of
+    // lane 0 or of lane 63, whichever lies first at the middle line; a line
+    // where some lane falls outside its segment gathers instead.
+    __shared__ __align__(16) float stage[kBlock / 64][kFwdStageLines * 64];
+    float *__restrict__ rows = stage[threadIdx.x >> 6];
+    const int sub = lane >> 4, e4 = (lane & 15) * 4;
+    // lane masks of the quarter-wavefronts 1, 2, 3 (a branch-free choice of
+    // each lane's segment start)
+    const int m1 = sub == 1 ? -1 : 0, m2 = sub == 2 ? -1 : 0, m3 = sub == 3 ? -1 : 0;
+    const float b0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, base), 0));
+    const float b63 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, base), 63));
+    const int lead = b0 <= b63 ? 0 : 63;
+    // element offsets from pad (never negative: a crossing's floor is at
+    // least -2 and every line has pad >= 2 leading elements)
+    const unsigned lbase = (unsigned)((rowdom ? 0LL : g.offT) + g.pad);
+    const unsigned lane_off = (unsigned)(sub * ld + e4);
+    constexpr int NL = kFwdStageLines;
+    float jm = float(j) - mid;  // line coordinate relative to the middle line (exact)
+    for (; j <= whi - (NL - 1); j += NL, jm += float(NL)) {
+      float c[NL], f[NL];
+      int fi[NL], s0[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        c[q] = clampv(fmaf(q == 0 ? jm : jm + float(q), slope, base), clo, chi);
+        f[q] = floorf(c[q]);
+        fi[q] = (int)f[q];
+        s0[q] = __builtin_amdgcn_readlane(fi[q], lead);
+      }
+      const unsigned rowj = lbase + (unsigned)(j * ld);
+      float4 v[NL / 4];
+#pragma unroll
+      for (int h = 0; h < NL / 4; ++h) {
+        int s = s0[4 * h];
+        s = (m1 & s0[4 * h + 1]) | (~m1 & s);
+        s = (m2 & s0[4 * h + 2]) | (~m2 & s);
+        s = (m3 & s0[4 * h + 3]) | (~m3 & s);
+        v[h] = *reinterpret_cast<const float4 *>(pad + (rowj + (unsigned)(4 * h * ld) + lane_off + (unsigned)s));
+      }
+#pragma unroll
+      for (int h = 0; h < NL / 4; ++h) *reinterpret_cast<float4 *>(rows + (4 * h + sub) * 64 + e4) = v[h];
+      __builtin_amdgcn_wave_barrier();
+      float sv[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int dl = fi[q] - s0[q];
+        float t0, t1;
+        if (__ballot((unsigned)dl > 62u) == 0) {
+          t0 = rows[q * 64 + dl];
+          t1 = rows[q * 64 + dl + 1];
+        } else {
+          const auto p = load_pair(pad + (rowj + (unsigned)(q * ld) + (unsigned)fi[q]));
+          t0 = p.x;
+          t1 = p.y;
+        }
+        sv[q] = fmaf(c[q] - f[q], t1 - t0, t0);
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int q = 0; q < NL; q += 4) {
+        a0 += sv[q];
+        a1 += sv[q + 1];
+        a2 += sv[q + 2];
+        a3 += sv[q + 3];
+      }
+    }
+  }
   for (; j <= whi - 7; j += 8) {
     float s[8];
 #pragma unroll

@@ -125,6 +125,13 @@ void check_fwd(const Geo2 &G, int stride, CheckStat &s) {
         const float mid = rd ? 0.5f * float(g.ny - 1) : 0.5f * float(g.nx - 1);
         const long long line0 = (rd ? 0LL : g.offT) + g.pad;
         const float clo = -1.5f, chi = float(len) + 0.5f;
+        // the staged form takes whole blocks of kFwdStageLines lines from wlo,
+        // its segment starting at the crossing of the lead lane (0 or 63,
+        // whichever has the smaller crossing at the middle line); the lines
+        // after the last block exchange taps between lanes, the segment
+        // starting at the smaller of lanes 0 and 63
+        const int nstaged = kFwdSegStage ? ((whi - wlo + 1) / kFwdStageLines) * kFwdStageLines : 0;
+        const int lead = (float)t.base[r0] <= (float)t.base[r0 + 63] ? 0 : 63;
         for (int j = wlo; j <= whi; ++j) {
           int fi[64];
           float cc[64];
@@ -133,7 +140,7 @@ void check_fwd(const Geo2 &G, int stride, CheckStat &s) {
             cc[lane] = clampT(std::fma(float(j) - mid, (float)t.slope[r], (float)t.base[r]), clo, chi);
             fi[lane] = (int)std::floor(cc[lane]);
           }
-          const int s0 = std::min(fi[0], fi[63]);
+          const int s0 = j - wlo < nstaged ? fi[lead] : std::min(fi[0], fi[63]);
           const long long ls = line0 + (long long)j * ld;  // element 0 of the line
           bool gather = false;
           for (int lane = 0; lane < 64; ++lane) {
