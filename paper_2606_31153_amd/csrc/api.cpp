@@ -316,6 +316,11 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
     // rays of a wavefront usually cross a line within 64 pixels (the kernel
     // checks every line)
     gd.fwd_seg = (g->src_dist * du <= 0.9) ? 1 : 0;
+  } else if (kFwdSegStage) {
+    // parallel beam: adjacent rays cross a line at most sqrt(2) du apart, so
+    // the 64 rays of a wavefront fit a 128-element segment while 63 sqrt(2) du
+    // stays below 126 (the staged form; the kernel checks every line)
+    gd.fwd_seg = (63.0 * std::sqrt(2.0) * du <= 124.0) ? 2 : 0;
   }
   gd.at_vu = kDefaultAtViews;
   gd.b_vu = kDefaultBViews;
@@ -325,8 +330,8 @@ void build_tables(const gkb_geometry *g, HostTables &t) {
   gd.ldR = nx + 2 * gd.pad;
   gd.ldT = ny + 2 * gd.pad;
   gd.offT = (long long)ny * gd.ldR;
-  // 64 elements of slack: A's segment loads read up to 62 past the end of a padded line
-  gd.pad_elems = gd.offT + (long long)nx * gd.ldT + 64;
+  // 128 elements of slack: A's segment loads read up to 126 past the end of a padded line
+  gd.pad_elems = gd.offT + (long long)nx * gd.ldT + 128;
   // A's segment path addresses the padded image with 32-bit element offsets
   if (gd.pad_elems >= (1LL << 31)) gd.fwd_seg = 0;
   gd.uclamp_at = hmax_at + 1.0;

@@ -231,8 +231,13 @@ __device__ inline float seg_lerp(const float *__restrict__ line, float c, int la
 // A for a wavefront of 64 valid rays that all step along the same axis: one
 // loop over the lines any of them crosses (a ray's crossings outside its own
 // range fall into the zero padding and add nothing), eight lines per step.
+
+// SW: segment width in elements, 64 (fan beam: adjacent rays cross a line
+// under a pixel apart) or 128 (parallel beam: up to sqrt(2) pixels apart).
+template <int SW>
 __device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, const float *__restrict__ pad,
                                     long long r) {
+  static_assert(SW == 64 || SW == 128, "segment width");
   const int meta = rt.meta[r];
   const int lo = meta & 0x7fff, hi = (meta >> 15) & 0x7fff;
   const bool rowdom = (meta >> 30) & 1;
@@ -248,20 +253,25 @@ __device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, c
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
   int j = wlo;
   if constexpr (kFwdSegStage) {
-    // kFwdStageLines lines per step.  Lanes 16 q' .. 16 q' + 15 load four
-    // consecutive elements each of line 4 h + q' of the step (one 16-byte
-    // load per lane covers the 64-element segments of four lines) into this
-    // wavefront's LDS rows; a lane then reads its two taps from the row.
-    // The rays of a wavefront cross every line in the same order (that of
-    // their bins, or the reverse), so a segment starts at the crossing of
-    // lane 0 or of lane 63, whichever lies first at the middle line; a line
-    // where some lane falls outside its segment gathers instead.
-    __shared__ __align__(16) float stage[kBlock / 64][kFwdStageLines * 64];
+    // kFwdStageLines lines per step.  LPL = SW / 4 lanes load line
+    // h * LPS + q' of the step (q' = lane / LPL), four consecutive elements
+    // each, so that one 16-byte load per lane covers the SW-element segments
+    // of LPS = 64 / LPL lines, into this wavefront's LDS rows; a lane then
+    // reads its two taps from the row.  The rays of a wavefront cross every
+    // line in the same order (that of their bins, or the reverse), so a
+    // segment starts at the crossing of lane 0 or of lane 63, whichever lies
+    // first at the middle line; a line where some lane falls outside its
+    // segment gathers instead.
+    constexpr int LPL = SW / 4, LPS = 64 / LPL, NL = kFwdStageLines;
+    static_assert(NL % LPS == 0, "whole loads per step");
+    __shared__ __align__(16) float stage[kBlock / 64][NL * SW];
     float *__restrict__ rows = stage[threadIdx.x >> 6];
-    const int sub = lane >> 4, e4 = (lane & 15) * 4;
-    // lane masks of the quarter-wavefronts 1, 2, 3 (a branch-free choice of
+    const int sub = lane / LPL, e4 = (lane % LPL) * 4;
+    // lane masks of the line groups 1 .. LPS - 1 (a branch-free choice of
     // each lane's segment start)
-    const int m1 = sub == 1 ? -1 : 0, m2 = sub == 2 ? -1 : 0, m3 = sub == 3 ? -1 : 0;
+    int msk[LPS];
+#pragma unroll
+    for (int u = 1; u < LPS; ++u) msk[u] = sub == u ? -1 : 0;
     const float b0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, base), 0));
     const float b63 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, base), 63));
     const int lead = b0 <= b63 ? 0 : 63;
@@ -269,7 +279,6 @@ __device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, c
     // least -2 and every line has pad >= 2 leading elements)
     const unsigned lbase = (unsigned)((rowdom ? 0LL : g.offT) + g.pad);
     const unsigned lane_off = (unsigned)(sub * ld + e4);
-    constexpr int NL = kFwdStageLines;
     float jm = float(j) - mid;  // line coordinate relative to the middle line (exact)
     for (; j <= whi - (NL - 1); j += NL, jm += float(NL)) {
       float c[NL], f[NL];
@@ -282,26 +291,25 @@ __device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, c
         s0[q] = __builtin_amdgcn_readlane(fi[q], lead);
       }
       const unsigned rowj = lbase + (unsigned)(j * ld);
-      float4 v[NL / 4];
+      float4 v[NL / LPS];
 #pragma unroll
-      for (int h = 0; h < NL / 4; ++h) {
-        int s = s0[4 * h];
-        s = (m1 & s0[4 * h + 1]) | (~m1 & s);
-        s = (m2 & s0[4 * h + 2]) | (~m2 & s);
-        s = (m3 & s0[4 * h + 3]) | (~m3 & s);
-        v[h] = *reinterpret_cast<const float4 *>(pad + (rowj + (unsigned)(4 * h * ld) + lane_off + (unsigned)s));
+      for (int h = 0; h < NL / LPS; ++h) {
+        int s = s0[LPS * h];
+#pragma unroll
+        for (int u = 1; u < LPS; ++u) s = (msk[u] & s0[LPS * h + u]) | (~msk[u] & s);
+        v[h] = *reinterpret_cast<const float4 *>(pad + (rowj + (unsigned)(LPS * h * ld) + lane_off + (unsigned)s));
       }
 #pragma unroll
-      for (int h = 0; h < NL / 4; ++h) *reinterpret_cast<float4 *>(rows + (4 * h + sub) * 64 + e4) = v[h];
+      for (int h = 0; h < NL / LPS; ++h) *reinterpret_cast<float4 *>(rows + (LPS * h + sub) * SW + e4) = v[h];
       __builtin_amdgcn_wave_barrier();
       float sv[NL];
 #pragma unroll
       for (int q = 0; q < NL; ++q) {
         const int dl = fi[q] - s0[q];
         float t0, t1;
-        if (__ballot((unsigned)dl > 62u) == 0) {
-          t0 = rows[q * 64 + dl];
-          t1 = rows[q * 64 + dl + 1];
+        if (__ballot((unsigned)dl > unsigned(SW - 2)) == 0) {
+          t0 = rows[q * SW + dl];
+          t1 = rows[q * SW + dl + 1];
         } else {
           const auto p = load_pair(pad + (rowj + (unsigned)(q * ld) + (unsigned)fi[q]));
           t0 = p.x;
@@ -342,7 +350,9 @@ __device__ inline float fwd_ray_seg(const GeomDev &g, const RayTab<float> &rt, c
   return ((a0 + a1) + (a2 + a3)) * rt.w[r];
 }
 
-template <typename T>
+// SW: the segment width the launch was built for (64 fan beam, 128 parallel
+// beam); a geometry flagged for the other width takes the per-ray gathers.
+template <typename T, int SW>
 __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *__restrict__ pad, T *yo,
                                 const Epi<T> &e, Blk b) {
   const unsigned wg = rt.order_fwd ? (unsigned)rt.order_fwd[b.id] : b.id;
@@ -351,12 +361,12 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
   T acc = T(0);
   bool seg = false;
   if constexpr (sizeof(T) == 4) {
-    if (g.fwd_seg) {
+    if (g.fwd_seg == (SW == 128 ? 2 : 1)) {
       // every lane a ray, all stepping along the same axis
       const bool rd = valid && ((rt.meta[r] >> 30) & 1);
       seg = __ballot(!valid) == 0 && (__ballot(rd) == 0 || __ballot(!rd) == 0);
     }
-    if (seg) acc = fwd_ray_seg(g, rt, pad, r);
+    if (seg) acc = fwd_ray_seg<SW>(g, rt, pad, r);
   }
   if (valid && !seg) {
     const int meta = rt.meta[r];
@@ -425,11 +435,11 @@ __device__ inline void fwd_body(const GeomDev &g, const RayTab<T> &rt, const T *
   epilogue(e, r, valid, acc, yo, b);
 }
 
-template <typename T>
+template <typename T, int SW>
 __global__ __launch_bounds__(kBlock) void k_fwd(GeomDev g, RayTab<T> rt, const T *__restrict__ pad, Col<T> yc,
                                                 Epi<T> e, const int *stop) {
   if (stop && *stop) return;
-  fwd_body(g, rt, pad, yc.get(), e, Blk{blockIdx.x, gridDim.x});
+  fwd_body<T, SW>(g, rt, pad, yc.get(), e, Blk{blockIdx.x, gridDim.x});
 }
 
 // ---------------------------------------------------------------------------
@@ -1070,7 +1080,7 @@ __global__ __launch_bounds__(256) void kb_pad_sino(BatchDev<T> bd, int in_sel, i
     pad_sino_body(y, d.ypad, d.g.nv, d.g.nu, d.g.padY, d.g.ldY, b);
 }
 
-template <typename T>
+template <typename T, int SW>
 __global__ __launch_bounds__(kBlock) void kb_fwd(BatchDev<T> bd, int out_sel, EpiCfg ec) {
   Blk b;
   const SliceDev<T> &d = slice_of(bd, BF_RAY, blockIdx.x, b);
@@ -1078,7 +1088,7 @@ __global__ __launch_bounds__(kBlock) void kb_fwd(BatchDev<T> bd, int out_sel, Ep
   const int k = d.ctl.ip[CI_K];
   const GeomDev g = d.g;
   const RayTab<T> rt = d.rt;
-  fwd_body(g, rt, d.xpad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
+  fwd_body<T, SW>(g, rt, d.xpad, resolve(d, out_sel, k), make_epi(d, ec, k), b);
 }
 
 template <typename T, bool FAN, int NC>
@@ -1165,7 +1175,10 @@ void launch_pad_sino_adj(const GeomDev &g, const RayTab<T> &rt, Col<const T> y, 
 template <typename T>
 void launch_fwd(const GeomDev &g, const RayTab<T> &rt, const T *pad, Col<T> y, const Epi<T> &e, const int *stop,
                 hipStream_t s) {
-  hipLaunchKernelGGL(k_fwd<T>, dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, pad, y, e, stop);
+  if (g.fwd_seg == 2)
+    hipLaunchKernelGGL((k_fwd<T, 128>), dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, pad, y, e, stop);
+  else
+    hipLaunchKernelGGL((k_fwd<T, 64>), dim3(ray_blocks(g)), dim3(kBlock), 0, s, g, rt, pad, y, e, stop);
   if (e.norm_to_t) launch_norm_finalize(e.ctl, e.partials, ray_blocks(g), NORM_T1, stop, s);
 }
 
@@ -1268,7 +1281,10 @@ void launch_b_pad_sino(const BatchDev<T> &bd, const BatchLaunch &bl, int in_sel,
 template <typename T>
 void launch_b_fwd(const BatchDev<T> &bd, const BatchLaunch &bl, int out_sel, EpiCfg ec, hipStream_t s) {
   if (bl.tot[BF_RAY] <= 0) return;
-  hipLaunchKernelGGL(kb_fwd<T>, dim3(bl.tot[BF_RAY]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  if (bl.fan)
+    hipLaunchKernelGGL((kb_fwd<T, 64>), dim3(bl.tot[BF_RAY]), dim3(kBlock), 0, s, bd, out_sel, ec);
+  else
+    hipLaunchKernelGGL((kb_fwd<T, 128>), dim3(bl.tot[BF_RAY]), dim3(kBlock), 0, s, bd, out_sel, ec);
   if (ec.norm_to_t) launch_b_norm_finalize(bd, bl, BF_RAY, NORM_T1, s);
 }
 

@@ -140,13 +140,15 @@ void check_fwd(const Geo2 &G, int stride, CheckStat &s) {
             cc[lane] = clampT(std::fma(float(j) - mid, (float)t.slope[r], (float)t.base[r]), clo, chi);
             fi[lane] = (int)std::floor(cc[lane]);
           }
-          const int s0 = j - wlo < nstaged ? fi[lead] : std::min(fi[0], fi[63]);
+          const bool staged = j - wlo < nstaged;
+          // segment width: 128 (parallel beam, staged form) or 64
+          const int sw = staged && g.fwd_seg == 2 ? 128 : 64;
+          const int s0 = staged ? fi[lead] : std::min(fi[0], fi[63]);
           const long long ls = line0 + (long long)j * ld;  // element 0 of the line
           bool gather = false;
-          for (int lane = 0; lane < 64; ++lane) {
-            add_read(s, ls + s0 + lane, 0, g.pad_elems);
-            if ((unsigned)(fi[lane] - s0) > 62u) gather = true;
-          }
+          for (int e = 0; e < sw; ++e) add_read(s, ls + s0 + e, 0, g.pad_elems);
+          for (int lane = 0; lane < 64; ++lane)
+            if ((unsigned)(fi[lane] - s0) > unsigned(sw - 2)) gather = true;
           for (int lane = 0; lane < 64; ++lane) {
             if (gather) {
               add_read(s, ls + fi[lane], ls - g.pad, ls - g.pad + ld);

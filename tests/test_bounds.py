@@ -86,6 +86,18 @@ def test_fan_segment_loads_are_replayed():
     assert s32["A"].reads != s64["A"].reads
 
 
+def test_parallel_segment_loads_are_replayed():
+    # float parallel beam with a detector pitch near one pixel takes the
+    # 128-element segment path of A; a coarse pitch (1.7 pixels: 64 rays span
+    # more than 128 elements of a line) keeps the per-ray gathers
+    for name, seg in (("par128_v179", True), ("par_pitch", False)):
+        g = GEOMS_2D[name]
+        s32, _ = gk.gkb_check_geometry(g, gk.GKB_F32, 1)
+        s64, _ = gk.gkb_check_geometry(g, gk.GKB_F64, 1)
+        assert s32["A"].units == s64["A"].units == g.m
+        assert (s32["A"].reads != s64["A"].reads) == seg, name
+
+
 @pytest.mark.parametrize("name,stride", [("fan512", 31), ("par512", 31)])
 def test_full_size_2d_launches_replay_clean(name, stride):
     g = synth.workload_fan512() if name == "fan512" else synth.workload_par512()
