@@ -49,8 +49,8 @@ OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each
 # scaled by the plain-copy calibration), profiles/fan512_gkb_hbm_traffic.txt.
 # An entry must be removed when its kernel changes.
-MEASURED_TRAFFIC = {"back": (8315.5 * 1.9855 + 2952.6) * 1024.0,
-                    "fwd_adj": (22201.1 * 1.9855 + 2062.8) * 1024.0, "back_adj": (21656.2 * 1.9855 + 5938.6) * 1024.0}
+MEASURED_TRAFFIC = {"fwd": (14860.1 * 1.9855 + 8785.9) * 1024.0, "back": (8322.4 * 1.9855 + 2952.5) * 1024.0,
+                    "fwd_adj": (22201.5 * 1.9855 + 2061.6) * 1024.0, "back_adj": (21661.9 * 1.9855 + 5938.5) * 1024.0}
 
 
 def joseph_crossings(geom) -> int:
