@@ -209,7 +209,9 @@ __global__ __launch_bounds__(256) void k_pad_sino_w(Col<const T> yc, const T *__
 // exchange them, so the texture path sees one contiguous load instead of 64
 // scattered pairs.  Where some lane's pair is not inside the segment (the
 // rays spread over more than 63 pixels, or are not ordered) the pair is
-// gathered instead; the test is uniform over the wavefront.
+// gathered instead; the test is uniform over the wavefront.  The staged form
+// below takes whole blocks of lines; this one takes the lines after the last
+// block (all of them with the staged form switched off).
 __device__ inline float seg_lerp(const float *__restrict__ line, float c, int lane) {
   const float f = floorf(c);
   const int fi = (int)f;
@@ -230,7 +232,8 @@ __device__ inline float seg_lerp(const float *__restrict__ line, float c, int la
 
 // A for a wavefront of 64 valid rays that all step along the same axis: one
 // loop over the lines any of them crosses (a ray's crossings outside its own
-// range fall into the zero padding and add nothing), eight lines per step.
+// range fall into the zero padding and add nothing), in blocks of
+// kFwdStageLines (or eight) lines, then line by line.
 
 // SW: segment width in elements, 64 (fan beam: adjacent rays cross a line
 // under a pixel apart) or 128 (parallel beam: up to sqrt(2) pixels apart).
