@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_cone_weight(Col<const T> yc, ConeTab<T>
 // ---------------------------------------------------------------------------
 // A: Joseph forward, one thread per ray
 // ---------------------------------------------------------------------------
-constexpr int kConeFwdPlanes = 8;  // planes whose tap loads are in flight together
+constexpr int kConeFwdPlanes = 12;  // planes whose tap loads are in flight together
 
 template <typename T>
 __device__ inline void cone_fwd_body(const GeomDev &g, const ConeTab<T> &ct, const T *__restrict__ pad, T *yo,
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_cone_fwd(GeomDev g, ConeTab<T> ct, c
 // coordinate can reach r at the depths of those columns.
 // ---------------------------------------------------------------------------
 constexpr int kConeBtRows = 4;    // most rows of the uniform window
-constexpr int kConeBtPlanes = 4;  // planes whose loads are in flight together
+constexpr int kConeBtPlanes = 6;  // planes whose loads are in flight together
 
 // Generic form: the exact candidate columns and rows of every plane, with
 // data-dependent loops.  Used where the uniform windows would be too large.
