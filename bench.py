@@ -350,8 +350,8 @@ def learned_main(args):
     log("evaluation set")
     eb, ex, en = learned.make_set(ctx, eg, range(4_100_000, 4_100_016), 0.01, 0.05, 4_100_000)
     ev = learned.evaluate(ctx, net, eg, eb, ex, en)
-    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        net.save(os.path.join(ROOT, "gpurun_out", "learned_filter.bin"))
+    if args.save_filter:
+        net.save(args.save_filter)
     # control: the same kernels with the network set to the analytic Ram-Lak
     # filter (a linear filter, exactly, whatever the masks)
     log("Ram-Lak control")
@@ -486,6 +486,7 @@ def main():
                     help="iterations of the cone solve with the per-row filter")
     ap.add_argument("--learned", action="store_true", help="train and evaluate the learned filter instead")
     ap.add_argument("--train-samples", type=int, default=20000)
+    ap.add_argument("--save-filter", default="", help="with --learned: write the trained network's weights to this file")
     ap.add_argument("--textures", type=int, default=0, help="extra random-texture training samples")
     ap.add_argument("--init", choices=("identity", "ramlak"), default="identity")
     ap.add_argument("--objective", choices=("fbp", "frozen"), default="frozen")
