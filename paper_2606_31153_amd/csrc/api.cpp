@@ -1669,7 +1669,7 @@ struct Solver {
     if (reorth) {
       // two classical rounds, the second from the Gram matrix (one read of Q
       // for the inner products, one for the update)
-      launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+      launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st, q_streams());
       launch_dcgs_coef(ctl, st);
       update_normalize(1);
     } else {
@@ -1707,16 +1707,23 @@ struct Solver {
       wrote_image(TAG_Q);
   }
 
+  // the stored basis (K + 1 columns of ldq) larger than the last-level cache:
+  // its reorthogonalisation passes stream it with nontemporal loads, which
+  // keeps the projectors' data in that cache (a basis that fits is read with
+  // ordinary loads, so that the update pass finds what the inner products
+  // brought in)
+  bool q_streams() const { return (long long)(ctl.K + 1) * ldq * (long long)sizeof(T) > kLlcBytes; }
+
   // w -= Q c over the reorthogonalisation columns (reorth_cols = 0: none),
   // then q_{k+1} = w / alpha_{k+1} with alpha_{k+1} summed from the update's
   // partials inside the normalisation
   void update_normalize(int reorth_cols) {
     if (!fusing()) {
-      launch_update_normalize<T>(ctl, Q, ldq, w, dimq, partials, st, reorth_cols);
+      launch_update_normalize<T>(ctl, Q, ldq, w, dimq, partials, st, reorth_cols, PadOut<T>{}, q_streams());
       return;
     }
     launch_update_normalize<T>(ctl, Q, ldq, w, dimq, partials, st, reorth_cols,
-                               mode == MODE_AB ? pad_sino_out() : pad_image_out());
+                               mode == MODE_AB ? pad_sino_out() : pad_image_out(), q_streams());
     if (mode == MODE_AB)
       wrote_sino(TAG_Q);
     else
@@ -1765,7 +1772,7 @@ struct Solver {
   // summed into column k of H; h_{k+1,k} = ||w|| into alpha[k+1]; q_{k+1}
   void gm_orthogonalise() {
     TraceScope ts(c, "reorth");
-    launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st);
+    launch_dcgs_dots<T>(ctl, Q, ldq, w, dimq, partials, st, q_streams());
     launch_dcgs_coef(ctl, st);
     launch_gm_hcol(ctl, st);  // h_{1..k,k}: both rounds' coefficients
     update_normalize(1);

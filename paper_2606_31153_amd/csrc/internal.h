@@ -20,6 +20,9 @@ static_assert(kPixTileX * kPixTileY * kViewGroups == kBlock, "pixel tile must fi
 constexpr bool kFwdSegStage = true;
 // lines per step of the staged form (a multiple of 4)
 constexpr int kFwdStageLines = 8;
+// Last-level cache (Infinity Cache) of the MI355X: a stored basis larger than
+// this is read with nontemporal loads in the reorthogonalisation passes.
+constexpr long long kLlcBytes = 256LL << 20;
 
 // Integer fields of the device control block.
 enum CtlInt : int {
@@ -379,7 +382,8 @@ void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *parti
 // Gram row of the newest column q_k; then c = c1 + (c1 - G c1) in ctl.c, for
 // launch_cgs_update (partials: 2 (K+2) doubles per row block)
 template <typename T>
-void launch_dcgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials, hipStream_t s);
+void launch_dcgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials, hipStream_t s,
+                      bool nt = false);
 void launch_dcgs_coef(Ctl ctl, hipStream_t s);
 template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
@@ -388,10 +392,11 @@ template <typename T>
 void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hipStream_t s,
                       PadOut<T> pout = PadOut<T>{});
 // w -= Q c (reorth != 0) with the partials of ||w||^2, then q_{k+1} = w / alpha_{k+1},
-// alpha_{k+1} formed from those partials inside the normalisation
+// alpha_{k+1} formed from those partials inside the normalisation; nt: Q's
+// columns with nontemporal loads (both passes take the same choice)
 template <typename T>
 void launch_update_normalize(Ctl ctl, T *Q, long long ld, T *w, long long dim, double *partials, hipStream_t s,
-                             int reorth, PadOut<T> pout = PadOut<T>{});
+                             int reorth, PadOut<T> pout = PadOut<T>{}, bool nt = false);
 template <typename T>
 void launch_resid(Ctl ctl, const T *yk, long long m, double *partials, hipStream_t s);
 // rre[k_stop] = ||x - x_true|| / dp[CD_XTNORM] (eq. RE); runs after a stop too

@@ -57,6 +57,25 @@ __device__ inline void load_quad(const T *__restrict__ p, long long r, long long
   }
 }
 
+// A column of the stored basis, read once per pass; nt: with nontemporal
+// loads, for a basis larger than the last-level cache, which would otherwise
+// push out what the other kernels of the iteration read from it
+template <typename T>
+__device__ inline void load_quad_q(const T *__restrict__ p, long long r, long long dim, double (&q)[RPT], bool nt) {
+  if (nt) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    if (r + RPT <= dim) {
+      const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4 *>(p + r));
+      q[0] = (double)v.x;
+      q[1] = (double)v.y;
+      q[2] = (double)v.z;
+      q[3] = (double)v.w;
+      return;
+    }
+  }
+  load_quad(p, r, dim, q);
+}
+
 template <typename T>
 __device__ inline void store_quad(T *__restrict__ p, long long r, long long dim, const T (&q)[RPT]) {
   typedef T v4 __attribute__((ext_vector_type(4)));
@@ -108,7 +127,8 @@ __device__ inline double block_sum_vec_n(double (&v)[N], double *lds /* [4][N] *
 constexpr int CH2 = 4, kDotsQuads = 4;
 template <typename T>
 __device__ inline void dots2_body(const Ctl &ctl, const T *__restrict__ V, long long ld, const T *__restrict__ w,
-                                  long long dim, double *partials, unsigned bx, unsigned by, int ncol) {
+                                  long long dim, double *partials, unsigned bx, unsigned by, int ncol,
+                                  bool nt = false) {
   constexpr int CH = CH2;
   const int c0 = by * CH;
   if (c0 >= ncol) return;
@@ -128,7 +148,7 @@ __device__ inline void dots2_body(const Ctl &ctl, const T *__restrict__ V, long 
     for (int j = 0; j < CH; ++j) {
       if (c0 + j < ncol) {
         double q[RPT];
-        load_quad(V + (long long)(c0 + j) * ld, r, dim, q);
+        load_quad_q(V + (long long)(c0 + j) * ld, r, dim, q, nt);
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
           acc[j] = fma(q[i], wq[i], acc[j]);
@@ -148,9 +168,10 @@ __device__ inline void dots2_body(const Ctl &ctl, const T *__restrict__ V, long 
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dots2(Ctl ctl, const T *__restrict__ V, long long ld,
-                                                  const T *__restrict__ w, long long dim, double *partials) {
+                                                  const T *__restrict__ w, long long dim, double *partials,
+                                                  int nt) {
   if (ctl.ip[CI_STOP]) return;
-  dots2_body(ctl, V, ld, w, dim, partials, blockIdx.x, blockIdx.y, ctl.ip[CI_K]);
+  dots2_body(ctl, V, ld, w, dim, partials, blockIdx.x, blockIdx.y, ctl.ip[CI_K], nt != 0);
 }
 
 // column sums of the two partial sets; workgroup col < K + 1 sums c1[col],
@@ -248,7 +269,8 @@ __host__ __device__ inline int upd_split(long long dim) {
 template <typename T>
 __device__ __attribute__((always_inline)) inline void cgs_update_split(const Ctl &ctl, const T *__restrict__ Q,
                                                                       long long ld, T *__restrict__ w, long long dim,
-                                                                      int last, double *partials, Blk b, int ncols) {
+                                                                      int last, double *partials, Blk b, int ncols,
+                                                                      bool nt) {
   constexpr int NW = kBlock / 64;
   __shared__ double part[NW - 1][64 * RPT];
   __shared__ double lds[NW];
@@ -267,7 +289,7 @@ __device__ __attribute__((always_inline)) inline void cgs_update_split(const Ctl
     for (int j = 0; j < UCH; ++j) {
       if (c0 + j < j1) {
         double q[RPT];
-        load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
+        load_quad_q(Q + (long long)(c0 + j) * ld, r, dim, q, nt);
         const double cj = cc[c0 + j];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) acc[i] = fma(-cj, q[i], acc[i]);
@@ -308,7 +330,8 @@ __device__ __attribute__((always_inline)) inline void cgs_update_split(const Ctl
 template <typename T>
 __device__ __attribute__((always_inline)) inline void cgs_update_rows(const Ctl &ctl, const T *__restrict__ Q,
                                                                       long long ld, T *__restrict__ w, long long dim,
-                                                                      int last, double *partials, Blk b, int ncols) {
+                                                                      int last, double *partials, Blk b, int ncols,
+                                                                      bool nt) {
   __shared__ double lds[kBlock / 64];
   const double *__restrict__ cc = ctl.c;
   const long long r = ((long long)b.id * kBlock + threadIdx.x) * RPT;
@@ -319,7 +342,7 @@ __device__ __attribute__((always_inline)) inline void cgs_update_rows(const Ctl 
     for (int j = 0; j < UCH; ++j) {
       if (c0 + j < ncols) {
         double q[RPT];
-        load_quad(Q + (long long)(c0 + j) * ld, r, dim, q);
+        load_quad_q(Q + (long long)(c0 + j) * ld, r, dim, q, nt);
         const double cj = cc[c0 + j];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) acc[i] = fma(-cj, q[i], acc[i]);
@@ -343,20 +366,22 @@ __device__ __attribute__((always_inline)) inline void cgs_update_rows(const Ctl 
 template <typename T>
 __device__ __attribute__((always_inline)) inline void cgs_update_body(const Ctl &ctl, const T *__restrict__ Q,
                                                                       long long ld, T *__restrict__ w, long long dim,
-                                                                      int last, double *partials, Blk b, int ncols) {
+                                                                      int last, double *partials, Blk b, int ncols,
+                                                                      bool nt = false) {
   if (upd_split(dim) > 1)
-    cgs_update_split(ctl, Q, ld, w, dim, last, partials, b, ncols);
+    cgs_update_split(ctl, Q, ld, w, dim, last, partials, b, ncols, nt);
   else
-    cgs_update_rows(ctl, Q, ld, w, dim, last, partials, b, ncols);
+    cgs_update_rows(ctl, Q, ld, w, dim, last, partials, b, ncols, nt);
 }
 
 // reorth == 0: no columns, only the partials of ||w||^2 (with last == 1)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cgs_update(Ctl ctl, const T *__restrict__ Q, long long ld,
                                                        T *__restrict__ w, long long dim, int last,
-                                                       double *partials, int reorth) {
+                                                       double *partials, int reorth, int nt) {
   if (ctl.ip[CI_STOP]) return;
-  cgs_update_body(ctl, Q, ld, w, dim, last, partials, Blk{blockIdx.x, gridDim.x}, reorth ? ctl.ip[CI_K] : 0);
+  cgs_update_body(ctl, Q, ld, w, dim, last, partials, Blk{blockIdx.x, gridDim.x}, reorth ? ctl.ip[CI_K] : 0,
+                  nt != 0);
 }
 
 // ---- finalising kernel: t[k+1] (which == NORM_T1) or alpha[k+1]
@@ -1320,10 +1345,10 @@ void launch_norm_to(Ctl ctl, const T *v, long long dim, int which, double *parti
 }
 template <typename T>
 void launch_dcgs_dots(Ctl ctl, const T *Q, long long ld, const T *w, long long dim, double *partials,
-                      hipStream_t s) {
+                      hipStream_t s, bool nt) {
   const int nb = dots_blocks(dim);
   const dim3 grid(nb, (ctl.K + CH2) / CH2);
-  hipLaunchKernelGGL(k_dots2<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials);
+  hipLaunchKernelGGL(k_dots2<T>, grid, dim3(kBlock), 0, s, ctl, Q, ld, w, dim, partials, (int)nt);
   hipLaunchKernelGGL(k_reduce_cols2, dim3(2 * (ctl.K + 1)), dim3(kBlock), 0, s, ctl, (const double *)partials, nb);
 }
 void launch_dcgs_coef(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_dcgs_coef, dim3(1), dim3(kCoefThreads), 0, s, ctl); }
@@ -1331,7 +1356,7 @@ template <typename T>
 void launch_cgs_update(Ctl ctl, const T *Q, long long ld, T *w, long long dim, int last, double *partials,
                        hipStream_t s, int reorth) {
   const int nb = upd_blocks(dim);
-  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, reorth);
+  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, last, partials, reorth, 0);
   if (last) launch_norm_finalize(ctl, partials, nb, NORM_ALPHA1, ctl.ip + CI_STOP, s);
 }
 template <typename T>
@@ -1340,9 +1365,10 @@ void launch_normalize(Ctl ctl, const T *w, T *Q, long long ld, long long dim, hi
 }
 template <typename T>
 void launch_update_normalize(Ctl ctl, T *Q, long long ld, T *w, long long dim, double *partials, hipStream_t s,
-                             int reorth, PadOut<T> pout) {
+                             int reorth, PadOut<T> pout, bool nt) {
   const int nb = upd_blocks(dim);
-  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, 1, partials, reorth);
+  hipLaunchKernelGGL(k_cgs_update<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Q, ld, w, dim, 1, partials, reorth,
+                     (int)nt);
   hipLaunchKernelGGL(k_normalize_fin<T>, dim3(vec_blocks(dim)), dim3(kBlock), 0, s, ctl, w, Q, ld, dim, pout,
                      (const double *)partials, nb);
 }
@@ -1463,7 +1489,8 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_cgs_update<T>(Ctl, const T *, long long, T *, long long, int, double *, hipStream_t, \
                                      int);                                                                  \
   template void launch_normalize<T>(Ctl, const T *, T *, long long, long long, hipStream_t, PadOut<T>);               \
-  template void launch_update_normalize<T>(Ctl, T *, long long, T *, long long, double *, hipStream_t, int, PadOut<T>); \
+  template void launch_update_normalize<T>(Ctl, T *, long long, T *, long long, double *, hipStream_t, int, PadOut<T>, \
+                                           bool);                                                                  \
   template void launch_resid<T>(Ctl, const T *, long long, double *, hipStream_t);                         \
   template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
@@ -1474,7 +1501,7 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
   template void launch_b_norm_finalize<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t); \
   template void launch_b_dcgs<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                    \
-  template void launch_dcgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t); \
+  template void launch_dcgs_dots<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t, bool); \
   template void launch_b_cgs_update<T>(const BatchDev<T> &, const BatchLaunch &, int, hipStream_t);         \
   template void launch_b_normalize<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);               \
   template void launch_b_resid<T>(const BatchDev<T> &, const BatchLaunch &, hipStream_t);                   \
