@@ -1713,6 +1713,9 @@ struct Solver {
   // ordinary loads, so that the update pass finds what the inner products
   // brought in)
   bool q_streams() const { return (long long)(ctl.K + 1) * ldq * (long long)sizeof(T) > kLlcBytes; }
+  // the same for the stored A-images Y (GMRES and hybrid solves: K columns of
+  // ldy), which the residual reads in full every iteration
+  bool y_streams() const { return (long long)ctl.K * ldy * (long long)sizeof(T) > kLlcBytes; }
 
   // w -= Q c over the reorthogonalisation columns (reorth_cols = 0: none),
   // then q_{k+1} = w / alpha_{k+1} with alpha_{k+1} summed from the update's
@@ -1787,7 +1790,7 @@ struct Solver {
     }
     {
       TraceScope ts(c, "residual");
-      launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st);
+      launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st, NORM_GMRHO, y_streams());
     }
   }
 
@@ -1816,7 +1819,7 @@ struct Solver {
     }
     {
       TraceScope ts(c, "residual");
-      launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st, NORM_RHO);
+      launch_gm_resid<T>(ctl, Y, ldy, b, m, partials, st, NORM_RHO, y_streams());
     }
   }
 };

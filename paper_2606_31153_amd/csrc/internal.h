@@ -462,7 +462,7 @@ void launch_gm_solve(Ctl ctl, hipStream_t s);
 // stopping decision of iteration k
 template <typename T>
 void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s,
-                     int which = NORM_GMRHO);
+                     int which = NORM_GMRHO, bool nt = false);
 
 // hybrid regularisation (lambda_k chosen on C_k) and the enlarged-subspace
 // TSVD: k_max at most kHyMaxK

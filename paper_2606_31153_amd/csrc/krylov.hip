@@ -670,10 +670,11 @@ __global__ __launch_bounds__(64) void k_gm_solve(Ctl ctl) {
 }
 
 // rho_k = ||Y_k u_k - b||: partials of the squared norm, 4 rows per thread,
-// four columns of Y per step
+// four columns of Y per step; nt: Y's columns with nontemporal loads
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gm_resid(Ctl ctl, const T *__restrict__ Y, long long ld,
-                                                     const T *__restrict__ bv, long long m, double *partials) {
+                                                     const T *__restrict__ bv, long long m, double *partials,
+                                                     int nt) {
   if (ctl.ip[CI_STOP]) return;
   __shared__ double lds[kBlock / 64];
   const int k = ctl.ip[CI_K];
@@ -686,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_resid(Ctl ctl, const T *__restric
   for (; j + 3 <= k; j += 4) {
     double y[4][RPT];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) load_quad(Y + (long long)(j - 1 + q) * ld, r0, m, y[q]);
+    for (int q = 0; q < 4; ++q) load_quad_q(Y + (long long)(j - 1 + q) * ld, r0, m, y[q], nt != 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double uq = ctl.u[j + q];
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(kBlock) void k_gm_resid(Ctl ctl, const T *__restric
   }
   for (; j <= k; ++j) {
     double y[RPT];
-    load_quad(Y + (long long)(j - 1) * ld, r0, m, y);
+    load_quad_q(Y + (long long)(j - 1) * ld, r0, m, y, nt != 0);
     const double uj = ctl.u[j];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) acc[i] = fma(uj, y[i], acc[i]);
@@ -1399,9 +1400,9 @@ void launch_gm_hcol(Ctl ctl, hipStream_t s) {
 void launch_gm_solve(Ctl ctl, hipStream_t s) { hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(64), 0, s, ctl); }
 template <typename T>
 void launch_gm_resid(Ctl ctl, const T *Y, long long ld, const T *b, long long m, double *partials, hipStream_t s,
-                     int which) {
+                     int which, bool nt) {
   const int nb = vec_blocks(m);
-  hipLaunchKernelGGL(k_gm_resid<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Y, ld, b, m, partials);
+  hipLaunchKernelGGL(k_gm_resid<T>, dim3(nb), dim3(kBlock), 0, s, ctl, Y, ld, b, m, partials, (int)nt);
   launch_norm_finalize(ctl, partials, nb, which, ctl.ip + CI_STOP, s);
 }
 void launch_hy_lambda(Ctl ctl, hipStream_t s) {
@@ -1495,7 +1496,8 @@ void launch_b_report(const SliceDev<T> *sd, int ns, int phase, double *out, hipS
   template void launch_rre<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);                \
   template void launch_resid_init<T>(Ctl, const T *, long long, double *, hipStream_t);                    \
   template void launch_solution<T>(Ctl, const T *, long long, long long, T *, hipStream_t);                  \
-  template void launch_gm_resid<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t, int); \
+  template void launch_gm_resid<T>(Ctl, const T *, long long, const T *, long long, double *, hipStream_t, int,  \
+                                    bool);                                                                        \
   template void launch_final_residual<T>(Ctl, const T *, const T *, long long, double *, hipStream_t);       \
   template void launch_b_copy<T>(const BatchDev<T> &, const BatchLaunch &, int, int, hipStream_t);          \
   template void launch_b_norm_to<T>(const BatchDev<T> &, const BatchLaunch &, int, int, int, hipStream_t);  \
