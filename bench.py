@@ -49,8 +49,8 @@ OPERAND_BYTES_PER_UNIT = 8.0  # two FP32 taps
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each
 # scaled by the plain-copy calibration), profiles/fan512_gkb_hbm_traffic.txt.
 # An entry must be removed when its kernel changes.
-MEASURED_TRAFFIC = {"fwd": (14859.4 * 1.9855 + 8786.6) * 1024.0, "back": (8322.4 * 1.9855 + 2952.5) * 1024.0,
-                    "fwd_adj": (22200.2 * 1.9855 + 2061.6) * 1024.0, "back_adj": (21661.8 * 1.9855 + 5938.7) * 1024.0}
+MEASURED_TRAFFIC = {"fwd": (14860.2 * 1.9855 + 8785.3) * 1024.0, "back": (8322.4 * 1.9855 + 2952.5) * 1024.0,
+                    "fwd_adj": (22211.3 * 1.9855 + 2062.2) * 1024.0, "back_adj": (21661.7 * 1.9855 + 5938.4) * 1024.0}
 
 
 def joseph_crossings(geom) -> int:
